@@ -1,0 +1,337 @@
+"""Seeded synthetic scenes for the many-light direct-lighting workloads.
+
+This module only makes inputs: emissive triangles, their emission, occluder
+boxes, shading points with normals, and the method parameters each workload
+runs with.  It holds none of the method's arithmetic; the GPU library and the
+CPU oracle both take these arrays as they are.
+
+The paper's scenes (a bathroom with Cornell boxes lit by a sky dome and area
+lights, and a sky-lit architectural interior) are not available, so these
+scenes stand in for them:
+
+* ``tiny``     - 1,024 random triangles in a ceiling band over a unit box,
+                 4,096 random points with cosine-distributed normals about +y,
+                 64 random boxes; an 8^3 dense grid, cut size 16, 16 spp,
+                 8 static frames.
+* ``static``   - 65,536 triangles in 256 Gaussian clusters (sigma 0.02) under
+                 the ceiling of a unit room, 4,096 box occluders, and the
+                 1920x1080 primary hits of a pinhole camera in that room;
+                 64^3 hashed cells, cut size 64, 1 spp, 32 frames.  The room
+                 full of boxes plays the visibility-dominated interior.
+* ``dynamic``  - 16 walled compartments (4x4), each with its own cluster of
+                 65,536 triangles under its ceiling (1,048,576 in total),
+                 1,048,576 points on floors and walls, 16,384 wall bricks;
+                 emission per cluster animated as Le * (1 + sin(2 pi f t +
+                 phi)), f ~ U[0.1, 1] cycles per frame, phi ~ U[0, 2 pi).
+                 The compartments stand in for the paper's Cornell boxes, each
+                 lit only by its own light.
+
+Every array is float32 (uint32 for indices) and C-contiguous.
+"""
+from __future__ import annotations
+
+import dataclasses
+import math
+from typing import Callable, Optional
+
+import numpy as np
+
+# Seeds: 19111021700 + workload number.
+SEED_BASE = 19111021700
+
+DEFAULT_PARAMS = dict(
+    M=16,
+    alpha=0.1,
+    T=2.0,
+    eps=0.05,
+    fx_shift=32,
+    reward_max=65536.0,
+    t_lo=1e-4,
+    reward_mode=0,
+    two_sided=1,
+    albedo=0.7,
+    grid_lo=(0.0, 0.0, 0.0),
+    grid_hi=(1.0, 1.0, 1.0),
+    grid_dims=(8, 8, 8),
+    hashed=0,
+    capacity=0,
+    adapt=1,
+    temporal=1,
+    scene_id=0,
+    seed=SEED_BASE + 1,
+    spp=1,
+    frames=1,
+)
+
+
+@dataclasses.dataclass
+class Scene:
+    name: str
+    tri: np.ndarray        # (N, 9) v0 v1 v2
+    emit: np.ndarray       # (N, 3) RGB emission
+    boxes: np.ndarray      # (K, 6) min xyz, max xyz
+    pos: np.ndarray        # (P, 3) shading points
+    nrm: np.ndarray        # (P, 3) unit normals
+    params: dict
+    emission_at: Optional[Callable[[int], np.ndarray]] = None  # frame -> (N, 3)
+    image_size: Optional[tuple] = None
+
+    @property
+    def N(self) -> int:
+        return int(self.tri.shape[0])
+
+    @property
+    def K(self) -> int:
+        return int(self.boxes.shape[0])
+
+    @property
+    def P(self) -> int:
+        return int(self.pos.shape[0])
+
+
+def _f32(a) -> np.ndarray:
+    return np.ascontiguousarray(np.asarray(a, dtype=np.float32))
+
+
+def _cosine_normals(rng: np.random.Generator, n: int) -> np.ndarray:
+    """Unit normals distributed as cos(theta) about +y."""
+    u1 = rng.random(n)
+    u2 = rng.random(n)
+    r = np.sqrt(u1)
+    phi = 2.0 * np.pi * u2
+    v = np.stack([r * np.cos(phi), np.sqrt(np.maximum(0.0, 1.0 - u1)), r * np.sin(phi)], axis=1)
+    v /= np.linalg.norm(v, axis=1, keepdims=True)
+    return _f32(v)
+
+
+def _random_boxes(rng, k, centre_lo, centre_hi, side_lo=0.02, side_hi=0.1) -> np.ndarray:
+    c = rng.uniform(centre_lo, centre_hi, size=(k, 3))
+    h = 0.5 * rng.uniform(side_lo, side_hi, size=(k, 3))
+    return _f32(np.concatenate([c - h, c + h], axis=1))
+
+
+def params_for(**overrides) -> dict:
+    p = dict(DEFAULT_PARAMS)
+    p.update(overrides)
+    return p
+
+
+# --------------------------------------------------------------------------
+# tiny: the small plain-method workload
+# --------------------------------------------------------------------------
+def make_tiny(n_lights=1024, n_points=4096, n_boxes=64, M=16, spp=16, frames=8,
+              seed=SEED_BASE + 1, **overrides) -> Scene:
+    rng = np.random.default_rng(seed)
+    v = rng.uniform([0.0, 0.9, 0.0], [1.0, 1.0, 1.0], size=(n_lights, 3, 3))
+    tri = _f32(v.reshape(n_lights, 9))
+    emit = _f32(rng.random((n_lights, 3)))
+    pos = _f32(rng.random((n_points, 3)))
+    nrm = _cosine_normals(rng, n_points)
+    boxes = _random_boxes(rng, n_boxes, 0.0, 1.0) if n_boxes else np.zeros((0, 6), np.float32)
+    params = params_for(M=M, spp=spp, frames=frames, grid_dims=(8, 8, 8), hashed=0,
+                        seed=seed)
+    params.update(overrides)
+    return Scene("tiny", tri, emit, boxes, pos, nrm, params)
+
+
+# --------------------------------------------------------------------------
+# Primary hits of a pinhole camera in a unit room with box occluders.
+# --------------------------------------------------------------------------
+def _primary_hits(boxes: np.ndarray, width: int, height: int, cam=(0.5, 0.45, 0.02),
+                  vfov_deg=60.0, room_lo=(0.0, 0.0, 0.0), room_hi=(1.0, 1.0, 1.0),
+                  extra_walls=None):
+    """Cast one ray through every pixel centre, camera looking down +z.
+
+    Returns float32 positions snapped onto the face that was hit and the
+    axis-aligned face normal pointing back towards the camera.  Pixels are in
+    row-major order, top row first.
+    """
+    o = np.asarray(cam, dtype=np.float64)
+    tan_h = math.tan(math.radians(vfov_deg) * 0.5)
+    aspect = width / height
+    px = (np.arange(width) + 0.5) / width * 2.0 - 1.0
+    py = 1.0 - (np.arange(height) + 0.5) / height * 2.0
+    dx = np.broadcast_to(px[None, :] * tan_h * aspect, (height, width)).reshape(-1)
+    dy = np.broadcast_to(py[:, None] * tan_h, (height, width)).reshape(-1)
+    d = np.stack([dx, dy, np.ones_like(dx)], axis=1)
+    d /= np.linalg.norm(d, axis=1, keepdims=True)
+    n_pix = d.shape[0]
+    inv = 1.0 / d
+
+    # room walls (inside faces); the camera is inside the room
+    lo = np.asarray(room_lo, np.float64)
+    hi = np.asarray(room_hi, np.float64)
+    t_best = np.full(n_pix, np.inf)
+    axis_best = np.zeros(n_pix, np.int64)
+    plane_best = np.zeros(n_pix)
+    for a in range(3):
+        with np.errstate(divide="ignore", invalid="ignore"):
+            t_hi = np.where(d[:, a] > 0, (hi[a] - o[a]) * inv[:, a], np.inf)
+            t_lo = np.where(d[:, a] < 0, (lo[a] - o[a]) * inv[:, a], np.inf)
+        for t, plane in ((t_hi, hi[a]), (t_lo, lo[a])):
+            better = t < t_best
+            t_best = np.where(better, t, t_best)
+            axis_best = np.where(better, a, axis_best)
+            plane_best = np.where(better, plane, plane_best)
+
+    # boxes: test each box against the pixels inside its screen-space bound
+    bx = boxes.astype(np.float64)
+    if extra_walls is not None:
+        bx = np.concatenate([bx, extra_walls.astype(np.float64)], axis=0)
+    corners = np.stack([np.stack([bx[:, 0 if (c & 1) == 0 else 3],
+                                  bx[:, 1 if (c & 2) == 0 else 4],
+                                  bx[:, 2 if (c & 4) == 0 else 5]], axis=1) for c in range(8)], axis=1)
+    rel = corners - o[None, None, :]
+    zc = rel[:, :, 2]
+    front = np.all(zc > 1e-6, axis=1)
+    for b in np.nonzero(front)[0]:
+        sx = rel[b, :, 0] / zc[b] / (tan_h * aspect)
+        sy = rel[b, :, 1] / zc[b] / tan_h
+        c0 = int(max(0, math.floor((sx.min() + 1.0) * 0.5 * width) - 1))
+        c1 = int(min(width, math.ceil((sx.max() + 1.0) * 0.5 * width) + 1))
+        r0 = int(max(0, math.floor((1.0 - sy.max()) * 0.5 * height) - 1))
+        r1 = int(min(height, math.ceil((1.0 - sy.min()) * 0.5 * height) + 1))
+        if c0 >= c1 or r0 >= r1:
+            continue
+        idx = (np.arange(r0, r1)[:, None] * width + np.arange(c0, c1)[None, :]).reshape(-1)
+        dd = d[idx]
+        iv = inv[idx]
+        tn = np.zeros(idx.size)
+        tf = np.full(idx.size, np.inf)
+        ax = np.zeros(idx.size, np.int64)
+        pl = np.zeros(idx.size)
+        for a in range(3):
+            t0 = (bx[b, a] - o[a]) * iv[:, a]
+            t1 = (bx[b, 3 + a] - o[a]) * iv[:, a]
+            near = np.minimum(t0, t1)
+            enter_plane = np.where(dd[:, a] > 0, bx[b, a], bx[b, 3 + a])
+            upd = near > tn
+            tn = np.where(upd, near, tn)
+            ax = np.where(upd, a, ax)
+            pl = np.where(upd, enter_plane, pl)
+            tf = np.minimum(tf, np.maximum(t0, t1))
+        hit = (tn < tf) & (tn > 0) & (tn < t_best[idx])
+        sel = idx[hit]
+        t_best[sel] = tn[hit]
+        axis_best[sel] = ax[hit]
+        plane_best[sel] = pl[hit]
+
+    p = o[None, :] + t_best[:, None] * d
+    nrm = np.zeros_like(p)
+    rows = np.arange(n_pix)
+    p[rows, axis_best] = plane_best
+    nrm[rows, axis_best] = -np.sign(d[rows, axis_best])
+    return _f32(p), _f32(nrm)
+
+
+def _clustered_lights(rng, n_clusters, per_cluster, centre_lo, centre_hi, sigma=0.02, half=0.005):
+    centres = rng.uniform(centre_lo, centre_hi, size=(n_clusters, 3))
+    cen = centres[:, None, :] + sigma * rng.standard_normal((n_clusters, per_cluster, 3))
+    verts = cen[:, :, None, :] + rng.uniform(-half, half, size=(n_clusters, per_cluster, 3, 3))
+    tri = _f32(verts.reshape(n_clusters * per_cluster, 9))
+    le_cluster = rng.random((n_clusters, 3))
+    emit = _f32(np.repeat(le_cluster, per_cluster, axis=0))
+    return tri, emit, centres, le_cluster
+
+
+# --------------------------------------------------------------------------
+# static: the large static workload (the headline throughput measurement)
+# --------------------------------------------------------------------------
+def make_static(width=1920, height=1080, n_clusters=256, per_cluster=256, n_boxes=4096,
+                M=64, spp=1, frames=32, seed=SEED_BASE + 2, capacity=1 << 19, **overrides) -> Scene:
+    rng = np.random.default_rng(seed)
+    tri, emit, _, _ = _clustered_lights(rng, n_clusters, per_cluster,
+                                        [0.05, 0.90, 0.05], [0.95, 0.98, 0.95])
+    boxes = _random_boxes(rng, n_boxes, [0.0, 0.0, 0.1], [1.0, 0.85, 1.0])
+    pos, nrm = _primary_hits(boxes, width, height)
+    params = params_for(M=M, spp=spp, frames=frames, grid_dims=(64, 64, 64), hashed=1,
+                        capacity=capacity, seed=seed)
+    params.update(overrides)
+    return Scene("static", tri, emit, boxes, pos, nrm, params, image_size=(height, width))
+
+
+# --------------------------------------------------------------------------
+# dynamic: walled compartments, each with its own animated light
+# --------------------------------------------------------------------------
+def make_dynamic(n_points=1 << 20, per_cluster=65536, grid=4, bricks_per_axis=None, M=64, spp=1,
+                 frames=60, seed=SEED_BASE + 3, capacity=1 << 19, **overrides) -> Scene:
+    rng = np.random.default_rng(seed)
+    n_comp = grid * grid
+    cw = 1.0 / grid
+    # lights: one cluster per compartment, centred under its ceiling
+    cx = (np.arange(grid) + 0.5) * cw
+    centres = np.array([[cx[i], 0.93, cx[j]] for j in range(grid) for i in range(grid)], np.float64)
+    cen = centres[:, None, :] + np.array([0.15 * cw, 0.01, 0.15 * cw]) * rng.standard_normal((n_comp, per_cluster, 3))
+    verts = cen[:, :, None, :] + rng.uniform(-0.002, 0.002, size=(n_comp, per_cluster, 3, 3))
+    tri = _f32(verts.reshape(n_comp * per_cluster, 9))
+    base = rng.random((n_comp, 3))
+    freq = rng.uniform(0.1, 1.0, size=n_comp)
+    phase = rng.uniform(0.0, 2.0 * np.pi, size=n_comp)
+
+    def emission_at(frame: int) -> np.ndarray:
+        s = 1.0 + np.sin(2.0 * np.pi * freq * float(frame) + phase)
+        return _f32(np.repeat(base * s[:, None], per_cluster, axis=0))
+
+    emit = emission_at(0)
+    # walls: 16,384 bricks along the interior partition planes (x = k/grid and
+    # z = k/grid for k = 1..grid-1), floor to ceiling
+    n_planes = 2 * (grid - 1)
+    total_bricks = 16384
+    per_plane = total_bricks // n_planes
+    rows = int(round(math.sqrt(per_plane)))
+    cols = per_plane // rows
+    bricks = []
+    th = 0.01
+    for axis in (0, 2):
+        for k in range(1, grid):
+            w = k * cw
+            for r in range(rows):
+                y0, y1 = r / rows, (r + 1) / rows
+                for cidx in range(cols):
+                    u0, u1 = cidx / cols, (cidx + 1) / cols
+                    if axis == 0:
+                        bricks.append([w - th, y0, u0, w + th, y1, u1])
+                    else:
+                        bricks.append([u0, y0, w - th, u1, y1, w + th])
+    while len(bricks) < total_bricks:  # pad with tiny boxes hugging the floor
+        bricks.append([0.0, -0.02, 0.0, 0.001, -0.01, 0.001])
+    boxes = _f32(np.array(bricks[:total_bricks]))
+    # points: floors (half) and the four walls of each compartment (half)
+    n_floor = n_points // 2
+    comp = rng.integers(0, n_comp, size=n_points)
+    ci = comp % grid
+    cj = comp // grid
+    pos = np.zeros((n_points, 3))
+    nrm = np.zeros((n_points, 3))
+    u = rng.random(n_points)
+    v = rng.random(n_points)
+    inner_lo_x = ci * cw + (th if True else 0.0)
+    inner_lo_z = cj * cw + th
+    span = cw - 2 * th
+    pos[:n_floor, 0] = inner_lo_x[:n_floor] + u[:n_floor] * span
+    pos[:n_floor, 1] = 0.0
+    pos[:n_floor, 2] = inner_lo_z[:n_floor] + v[:n_floor] * span
+    nrm[:n_floor, 1] = 1.0
+    side = rng.integers(0, 4, size=n_points)
+    wall = slice(n_floor, n_points)
+    s = side[wall]
+    h = v[wall] * 0.9
+    t = inner_lo_x[wall] * 0 + u[wall] * span
+    px = np.where(s == 0, inner_lo_x[wall], np.where(s == 1, inner_lo_x[wall] + span, inner_lo_x[wall] + t))
+    pz = np.where(s == 2, inner_lo_z[wall], np.where(s == 3, inner_lo_z[wall] + span, inner_lo_z[wall] + t))
+    pos[wall, 0] = px
+    pos[wall, 1] = h
+    pos[wall, 2] = pz
+    nrm[wall, 0] = np.where(s == 0, 1.0, np.where(s == 1, -1.0, 0.0))
+    nrm[wall, 2] = np.where(s == 2, 1.0, np.where(s == 3, -1.0, 0.0))
+    params = params_for(M=M, spp=spp, frames=frames, grid_dims=(64, 64, 64), hashed=1,
+                        capacity=capacity, seed=seed)
+    params.update(overrides)
+    return Scene("dynamic", tri, emit, boxes, _f32(pos), _f32(nrm), params, emission_at=emission_at)
+
+
+WORKLOADS = {"tiny": make_tiny, "static": make_static, "dynamic": make_dynamic}
+
+
+def make(name: str, **kw) -> Scene:
+    return WORKLOADS[name](**kw)

@@ -1,0 +1,181 @@
+"""Pins of the oracle's learning steps: Eq. 1 (in its per-pass batch form),
+Eq. 2, and one split-collapse step (section 3, Fig. 1)."""
+import itertools
+import math
+
+import numpy as np
+import pytest
+
+from paper_1911_10217_amd import scenes
+
+FX = 32
+
+
+def _fixed(r):
+    return np.array([int(round(x * 2**FX)) for x in r], np.uint64)
+
+
+@pytest.mark.parametrize("n", [1, 2, 3, 7, 64, 1000])
+def test_ema_equal_rewards_closed_form(orc, n):
+    # n equal rewards r: Q <- a^n Q + (1 - a^n) r
+    alpha, Q0, r = 0.1, 0.3, 0.25
+    out = orc.ema([Q0], [n * int(r * 2**FX)], [n], alpha, FX)[0]
+    a = float(np.float32(1.0) - np.float32(alpha))
+    want = a**n * Q0 + (1 - a**n) * r
+    assert abs(out - want) <= 4e-7 * max(1.0, abs(want))
+
+
+def test_ema_single_sample_is_eq1(orc):
+    alpha = np.float32(0.1)
+    for Q0, r in [(0.0, 0.5), (1.5, 0.25), (0.75, 3.0)]:
+        out = orc.ema([Q0], _fixed([r]), [1], float(alpha), FX)[0]
+        want = (1 - float(alpha)) * Q0 + float(alpha) * r  # Eq. 1
+        assert abs(out - want) <= 2e-7 * max(1.0, want)
+
+
+@pytest.mark.parametrize("n", [2, 3, 4, 5, 6])
+def test_ema_batch_equals_order_average(orc, n):
+    # the batch form equals the average of sequential Eq. 1 over all n! orders
+    rng = np.random.default_rng(n)
+    alpha = float(np.float32(0.1))
+    a = float(np.float32(1.0) - np.float32(alpha))
+    r = np.round(rng.random(n) * 2**20) / 2**20  # exact in fixed point
+    Q0 = 0.4
+    acc = 0.0
+    perms = list(itertools.permutations(range(n)))
+    for p in perms:
+        q = Q0
+        for i in p:
+            q = a * q + (1 - a) * r[i]
+        acc += q
+    want = acc / len(perms)
+    out = orc.ema([Q0], [int(_fixed(r).sum())], [n], alpha, FX)[0]
+    assert abs(out - want) <= 1e-6 * max(1.0, want)
+
+
+def test_ema_untouched_slot_unchanged(orc):
+    out = orc.ema([0.7, 0.2], [0, 5 << FX], [0, 5], 0.1, FX)
+    assert out[0] == np.float32(0.7)
+
+
+def test_cdf_uniform_when_q_is_zero(orc):
+    Qt, C = orc.cdf(np.zeros(16), 0.05)
+    assert np.all(Qt == 1.0) and C.tolist() == list(range(1, 17))
+
+
+def test_cdf_eq2_without_floor(orc):
+    Q = np.array([3, 0, 1, 4, 1, 5, 9, 2], np.float32)  # integers: sums exact
+    Qt, C = orc.cdf(Q, 0.0)
+    np.testing.assert_array_equal(Qt, Q)
+    np.testing.assert_array_equal(C, np.cumsum(Q.astype(np.float64)).astype(np.float32))
+
+
+def test_cdf_floor_and_normalisation(orc):
+    rng = np.random.default_rng(3)
+    Q = rng.random(64).astype(np.float32)
+    Q[::7] = 0.0
+    eps = 0.05
+    Qt, C = orc.cdf(Q, eps)
+    S = float(np.sum(Q.astype(np.float64)))
+    np.testing.assert_allclose(Qt, Q + eps * S / 64, rtol=1e-6)
+    assert np.all(Qt > 0)
+    assert np.all(np.diff(C) > 0)
+    p = Qt.astype(np.float64) / float(C[-1])
+    assert abs(p.sum() - 1.0) < 1e-5
+
+
+# --------------------------------------------------------------------------
+# split-collapse (section 3 and Fig. 1)
+# --------------------------------------------------------------------------
+def _balanced(orc, N, M, T=2.0):
+    pts = np.zeros((N, 3))
+    pts[:, 0] = (np.arange(N) + 0.25) / N
+    pts[:, 1:] = 0.5
+    tri = np.concatenate([pts, pts + [1e-5, 0, 0], pts + [0, 0, 1e-5]], axis=1).astype(np.float32)
+    p = scenes.params_for(M=M, T=T)
+    return orc.Oracle(p, tri, np.ones((N, 3), np.float32))
+
+
+def _ranges(o, node):
+    t = o.tree()
+    return [(int(t["first"][n]), int(t["last"][n])) for n in node]
+
+
+def test_fig1_split_one_leaf_collapse_one_parent(orc):
+    # 8 lights, depth 3; balanced 4-node cut A,B (under P1) and C,D (under P2)
+    o = _balanced(orc, 8, 4)
+    node, _ = o.template()
+    assert _ranges(o, node) == [(0, 1), (2, 3), (4, 5), (6, 7)]
+    changed, n2, q2 = o.split_collapse(node, [5.0, 1.0, 1.0, 1.0])
+    assert changed
+    # A splits into its two leaves, C and D collapse into P2
+    assert _ranges(o, n2) == [(0, 0), (1, 1), (2, 3), (4, 7)]
+    assert q2.tolist() == [2.5, 2.5, 1.0, 2.0]
+
+
+def test_split_needs_strictly_more_than_T_times_parent(orc):
+    o = _balanced(orc, 8, 4)
+    node, _ = o.template()
+    changed, n2, q2 = o.split_collapse(node, [4.0, 1.0, 1.0, 1.0])
+    assert not changed and n2.tolist() == node.tolist() and q2.tolist() == [4.0, 1.0, 1.0, 1.0]
+
+
+def test_pair_containing_lmax_is_not_collapsed(orc):
+    o = _balanced(orc, 8, 4)
+    node, _ = o.template()
+    changed, n2, q2 = o.split_collapse(node, [1.0, 5.0, 1.0, 1.0])
+    assert changed
+    assert _ranges(o, n2) == [(0, 1), (2, 2), (3, 3), (4, 7)]
+    assert q2.tolist() == [1.0, 2.5, 2.5, 2.0]
+
+
+def test_ties_take_smallest_slot(orc):
+    o = _balanced(orc, 16, 8)
+    node, _ = o.template()
+    assert _ranges(o, node) == [(2 * i, 2 * i + 1) for i in range(8)]
+    changed, n2, q2 = o.split_collapse(node, [9, 1, 1, 1, 1, 1, 1, 1])
+    assert changed
+    # argmin over equal pair sums (2,3), (4,5), (6,7) picks (2,3)
+    assert _ranges(o, n2) == [(0, 0), (1, 1), (2, 3), (4, 7), (8, 9), (10, 11), (12, 13), (14, 15)]
+    assert q2.tolist() == [4.5, 4.5, 1, 2, 1, 1, 1, 1]
+    # argmax tie: slots 0 and 1 equal -> slot 0 splits; pair (0,1) is excluded
+    changed, n3, q3 = o.split_collapse(node, [3, 3, 0.5, 0.5, 1, 1, 1, 1])
+    assert changed
+    assert _ranges(o, n3)[:4] == [(0, 0), (1, 1), (2, 3), (4, 7)]
+    assert q3.tolist() == [1.5, 1.5, 3, 1, 1, 1, 1, 1]
+
+
+def test_single_light_leaves_cannot_split(orc):
+    o = _balanced(orc, 8, 8)
+    node, _ = o.template()
+    changed, _, _ = o.split_collapse(node, [100, 0, 0, 0, 0, 0, 0, 0])
+    assert not changed
+
+
+def test_split_collapse_preserves_size_and_mass(orc):
+    o = _balanced(orc, 256, 16)
+    node, _ = o.template()
+    rng = np.random.default_rng(11)
+    t = o.tree()
+    q = rng.random(16).astype(np.float32)
+    for _ in range(200):
+        changed, node2, q2 = o.split_collapse(node, q)
+        assert node2.size == 16
+        assert abs(float(q2.astype(np.float64).sum()) - float(q.astype(np.float64).sum())) <= 1e-5
+        # the cut stays a partition of the lights in range order
+        f = t["first"][node2]
+        l = t["last"][node2]
+        assert f[0] == 0 and l[-1] == 255 and np.all(f[1:] == l[:-1] + 1)
+        node = node2
+        q = (q2 * rng.uniform(0.5, 1.5, 16)).astype(np.float32)
+
+
+def test_pair_holding_lmax_as_right_child_is_excluded(orc):
+    # with T < 1 the pair (A, B) that holds l_max = B could win the argmin;
+    # it is not a candidate, so (C, D) collapses
+    o = _balanced(orc, 8, 4, T=0.5)
+    node, _ = o.template()
+    changed, n2, q2 = o.split_collapse(node, [0.1, 1.0, 0.6, 0.6])
+    assert changed
+    assert _ranges(o, n2) == [(0, 1), (2, 2), (3, 3), (4, 7)]
+    assert q2.tolist() == [np.float32(0.1), 0.5, 0.5, np.float32(0.6) + np.float32(0.6)]
