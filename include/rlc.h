@@ -1,0 +1,178 @@
+/*
+ * rlc.h - C ABI of librlc, a HIP (gfx950) implementation of the per-frame
+ * hot path of Reinforcement Lightcuts Learning (J. Pantaleoni, "Importance
+ * Sampling of Many Lights with Reinforcement Lightcuts Learning",
+ * arXiv:1911.10217).
+ *
+ * The calls follow the paper's statement of the method (section 3):
+ *   build the reference light tree          rlc_build_light_tree
+ *   place occluders for shadow rays          rlc_set_occluders
+ *   sample a cluster and a light per point   rlc_sample
+ *   shade: shadow ray, contribution, estimate rlc_shade
+ *   learn: Eq. 1 statistics per cluster      rlc_learn
+ *   adapt cuts: Eq. 1, split-collapse, Eq. 2 rlc_adapt_cuts
+ *   all of the above for one frame            rlc_frame
+ *
+ * Conventions
+ *  - Every pointer named d_* is DEVICE memory owned by the caller (e.g. a
+ *    torch tensor's data_ptr()); it must stay valid until the work enqueued
+ *    on the context's stream has completed.  Pointers named h_* are host
+ *    memory.  The library owns every internal buffer.
+ *  - All calls only enqueue work on the context's stream (a hipStream_t,
+ *    passed as void*), except where a call says it synchronises.
+ *  - Return value: RLC_OK (0) or a negative error code; rlc_last_error()
+ *    gives a message.  Errors detected on the device (hash table full,
+ *    non-finite contributions) are latched and reported by the next call
+ *    that synchronises (rlc_sync, the dump calls).  No C++ exception crosses
+ *    this interface.  A context must not be used from two threads at once.
+ *  - Arrays of 3-vectors are packed float triples (x y z), row-major.
+ */
+#ifndef RLC_H
+#define RLC_H
+
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+#define RLC_OK 0
+#define RLC_EINVAL (-1)    /* bad argument, non-finite input, N == 0 ... */
+#define RLC_ENOMEM (-2)    /* device allocation failed */
+#define RLC_EHIP (-3)      /* a HIP runtime call failed */
+#define RLC_ECAPACITY (-4) /* the cell hash table overflowed */
+#define RLC_ESTATE (-5)    /* calls out of order (e.g. sample before build) */
+
+#define RLC_MMAX 256u      /* largest supported cut size */
+
+typedef struct rlc_ctx rlc_ctx;
+
+/* Parameters of the method.  M, alpha and T are the paper's (section 3:
+ * cut size, learning rate of Eq. 1, split-collapse threshold); the rest fix
+ * the readings of points the paper leaves open. */
+typedef struct rlc_config {
+    uint32_t M;            /* cut size, 1..RLC_MMAX */
+    float alpha;           /* Eq. 1 learning rate */
+    float T;               /* split when Q(l_max) > T * Q(p_min) */
+    float eps;             /* Q~ = Q + eps * sum(Q) / M before Eq. 2 */
+    uint32_t fx_shift;     /* a reward r enters the sums as rint(min(r, reward_max) * 2^fx_shift) */
+    float reward_max;
+    float t_lo;            /* shadow rays cover t in (t_lo, 1 - t_lo) of x -> y */
+    uint32_t reward_mode;  /* 0: reward |c_l|; 1: |c_l| * cluster size */
+    uint32_t two_sided;    /* 1: emitters radiate from both faces */
+    float albedo;          /* Lambertian receivers, f_r = albedo / pi */
+    float grid_lo[3];      /* cell grid box; points outside clamp to the border */
+    float grid_hi[3];
+    uint32_t grid_dims[3];
+    uint32_t hashed;       /* 0: dense grid table; 1: open-addressing hash */
+    uint32_t capacity;     /* hash capacity in cells (rounded up to 2^k) */
+    uint32_t adapt;        /* 1: split-collapse at the end of every pass */
+    uint32_t temporal;     /* 0: every pass restarts from the initial cut */
+    uint32_t scene_id;     /* upper key bits and RNG stream of this scene */
+    uint32_t occ_grid_res; /* 0: test every box per shadow ray; n: n^3 grid */
+    uint32_t reserved;
+    uint64_t seed;         /* Philox4x32-10 key */
+} rlc_config;
+
+/* Per-sample records of rlc_sample (device arrays of n = P * spp entries,
+ * sample i = point * spp + k).  Any member may be NULL where the later steps
+ * do not need it (cell, slot, light and inv_pdf feed rlc_shade/rlc_learn). */
+typedef struct rlc_samples {
+    uint64_t* d_key;       /* cell key: (scene_id << 32) | linear cell index */
+    uint32_t* d_cell;      /* internal table slot of the cell (0xFFFFFFFF: none) */
+    uint32_t* d_ready;     /* 1 if the cell's learned table was used */
+    uint32_t* d_slot;      /* cluster s drawn from the cell's cdf */
+    uint32_t* d_light;     /* light index in tree order */
+    float* d_inv_pdf;      /* 1 / p(light) */
+    float* d_y;            /* point on the light, 3 floats per sample */
+} rlc_samples;
+
+/* Create a context whose work goes to `stream` (hipStream_t).  Allocates
+ * the cell tables: capacity * M * 32 bytes plus 12 bytes per cell. */
+int rlc_create(const rlc_config* cfg, void* stream, rlc_ctx** out);
+int rlc_destroy(rlc_ctx* ctx);
+
+/* Section 3 / 3.1: sort the N emissive triangles (d_tri: N x 9 floats,
+ * v0 v1 v2; d_emit: N x 3 RGB) by the Morton code of their vertex sums and
+ * build the binary radix tree over them, then the breadth-first initial cut
+ * of min(M, N) nodes.  Resets every cell.  Synchronises (validates input). */
+int rlc_build_light_tree(rlc_ctx* ctx, const float* d_tri, const float* d_emit, uint32_t N);
+
+/* Replace the emission of every light (d_emit: N x 3, input order); the tree
+ * and the cuts are kept.  Used for animated lights. */
+int rlc_set_emission(rlc_ctx* ctx, const float* d_emit, uint32_t N);
+
+/* Occluders for the shadow rays: K axis-aligned boxes (d_aabb: K x 6, min
+ * xyz then max xyz).  With occ_grid_res > 0 a uniform grid over the boxes is
+ * built on the device.  Synchronises (validates input). */
+int rlc_set_occluders(rlc_ctx* ctx, const float* d_aabb, uint32_t K);
+
+/* Section 3: for every sample, locate (or create) the cell of the point,
+ * draw a cluster from the cell's cdf C by binary search (cells created in
+ * this pass use the initial cut, all clusters equally likely), a light
+ * uniformly inside it, and a uniform point on that light. */
+int rlc_sample(rlc_ctx* ctx, const float* d_pos, const float* d_nrm, uint32_t P, uint32_t spp,
+               uint32_t frame, const rlc_samples* out);
+
+/* Shadow ray, contribution c_l = Le f_r G A V and estimate c_l / p(l) for
+ * every sample.  d_radiance (P x 3) receives the mean estimate per point;
+ * d_contrib (n x 3, may be NULL) c_l; d_reward (n, may be NULL) the scalar
+ * reward |c_l| (times the cluster size in reward_mode 1). */
+int rlc_shade(rlc_ctx* ctx, const float* d_pos, const float* d_nrm, uint32_t P, uint32_t spp,
+              const rlc_samples* in, float* d_radiance, float* d_contrib, float* d_reward);
+
+/* Eq. 1 statistics: add every sample's fixed-point reward and a count to its
+ * (cell, cluster) in integer arithmetic (order-independent). */
+int rlc_learn(rlc_ctx* ctx, const rlc_samples* in, const float* d_reward, uint32_t n);
+
+/* End of a rendering pass (section 3): for every cell that received samples,
+ * Q <- (1-alpha)^n Q + (1 - (1-alpha)^n) mean(r) per cluster (Eq. 1 over the
+ * pass), one split-collapse step, Q~ and the cdf C by Eq. 2; clears the
+ * statistics. */
+int rlc_adapt_cuts(rlc_ctx* ctx);
+
+/* One whole pass: sample, shade and learn fused in one kernel, then
+ * rlc_adapt_cuts.  d_radiance: P x 3. */
+int rlc_frame(rlc_ctx* ctx, const float* d_pos, const float* d_nrm, uint32_t P, uint32_t spp,
+              uint32_t frame, float* d_radiance);
+
+/* Shadow-ray test only: d_vis[i] = 1 if the segment d_x[i] -> d_y[i] is
+ * unoccluded over t in (t_lo, 1 - t_lo). */
+int rlc_visible(rlc_ctx* ctx, const float* d_x, const float* d_y, uint32_t n, uint8_t* d_vis);
+
+/* Cell keys of points (d_keys: n entries, device). */
+int rlc_cell_keys(rlc_ctx* ctx, const float* d_pos, uint32_t n, uint64_t* d_keys);
+
+/* Error statistics of an image against a reference, FP64 on the device:
+ * h_out[0..4] = mean(img), variance(img), MSE, mean relative squared error
+ * (over entries with ref != 0), max abs error; n = number of floats. */
+int rlc_image_error(rlc_ctx* ctx, const float* d_img, const float* d_ref, uint32_t n, double* h_out);
+
+/* ---- inspection, checkpoint and parity interface (synchronise) ---- */
+int rlc_sync(rlc_ctx* ctx);
+const char* rlc_last_error(const rlc_ctx* ctx);
+int rlc_num_cells(rlc_ctx* ctx, uint32_t* h_n);
+int rlc_meff(rlc_ctx* ctx, uint32_t* h_meff);
+/* All cells in increasing key order; per-cell arrays have Meff columns;
+ * any pointer may be NULL; `max_cells` bounds the rows written. */
+int rlc_dump_cells(rlc_ctx* ctx, uint32_t max_cells, uint64_t* h_keys, uint32_t* h_ready,
+                   uint32_t* h_node, uint32_t* h_end, float* h_Q, float* h_Qt, float* h_C,
+                   uint64_t* h_sum, uint32_t* h_cnt);
+/* Tree arrays: perm[N] (tree order -> input index), left/right[N-1],
+ * parent/first/last[2N-1] (internal nodes 0..N-2, leaf j is N-1+j),
+ * rec[N x 16] = v0 v1 v2 Le area normal per light in tree order. */
+int rlc_dump_tree(rlc_ctx* ctx, uint32_t* h_perm, uint32_t* h_left, uint32_t* h_right,
+                  uint32_t* h_parent, uint32_t* h_first, uint32_t* h_last, float* h_rec);
+int rlc_get_template(rlc_ctx* ctx, uint32_t* h_node, uint32_t* h_end, uint32_t* h_meff);
+
+/* Per-kernel timing with HIP events on the context's stream: while enabled,
+ * rlc_frame records the fused kernel and the adapt kernel separately.
+ * rlc_get_timing synchronises and returns the summed milliseconds and the
+ * number of frames since the last call. */
+int rlc_set_timing(rlc_ctx* ctx, int enable);
+int rlc_get_timing(rlc_ctx* ctx, double* h_ms_fused, double* h_ms_adapt, uint32_t* h_frames);
+
+#ifdef __cplusplus
+}
+#endif
+#endif /* RLC_H */

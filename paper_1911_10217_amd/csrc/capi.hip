@@ -1,0 +1,723 @@
+// C ABI of librlc (declared in include/rlc.h): argument checks, ownership of
+// the library's device buffers, and the order of kernel launches for each
+// call.  No exception leaves this file.
+#include <algorithm>
+#include <cmath>
+#include <cstdarg>
+#include <cstdio>
+#include <cstring>
+#include <new>
+#include <vector>
+
+#include "rlc_internal.h"
+
+using namespace rlc;
+
+struct rlc_ctx {
+    rlc_config cfg;
+    hipStream_t stream = nullptr;
+    char msg[512] = {0};
+
+    // reference tree and initial cut
+    bool tree_built = false;
+    uint32_t N = 0, Meff = 0;
+    float4* rec = nullptr;
+    uint32_t* perm = nullptr;
+    uint32_t* morton = nullptr;
+    uint32_t* left = nullptr;
+    uint32_t* right = nullptr;
+    uint32_t* parent = nullptr;
+    uint32_t* first = nullptr;
+    uint32_t* last = nullptr;
+    uint32_t* tmpl_node = nullptr;
+    uint32_t* tmpl_end = nullptr;
+    float* tmpl_Qt = nullptr;
+    float* tmpl_C = nullptr;
+
+    // occluders
+    bool occ_set = false;
+    uint32_t K = 0;
+    float4* box = nullptr;
+    uint32_t* occ_off = nullptr;
+    uint32_t* occ_ref = nullptr;
+    DevOcc occ{};
+
+    // cells
+    DevCells cells{};
+    uint32_t* d_err = nullptr;
+    double* d_partial = nullptr;
+
+    // derived constants
+    float inv_cell[3] = {0, 0, 0};
+    float f_r = 0.0f;
+    float fx_scale = 1.0f, fx_inv = 1.0f;
+
+    // per-kernel timing
+    bool timing = false;
+    std::vector<hipEvent_t> pending;   // 3 per timed frame
+    std::vector<hipEvent_t> spare;
+};
+
+namespace {
+
+int fail(rlc_ctx* c, int code, const char* fmt, ...) {
+    if (c) {
+        va_list ap;
+        va_start(ap, fmt);
+        vsnprintf(c->msg, sizeof(c->msg), fmt, ap);
+        va_end(ap);
+    }
+    return code;
+}
+
+#define RLC_HIP(ctx, call)                                                                         \
+    do {                                                                                           \
+        hipError_t e_ = (call);                                                                    \
+        if (e_ != hipSuccess) return fail((ctx), RLC_EHIP, "%s: %s", #call, hipGetErrorString(e_)); \
+    } while (0)
+
+template <class T>
+int dalloc(rlc_ctx* c, T** p, size_t n) {
+    *p = nullptr;
+    if (n == 0) n = 1;
+    hipError_t e = hipMalloc((void**)p, sizeof(T) * n);
+    if (e != hipSuccess) {
+        *p = nullptr;
+        (void)hipGetLastError();
+        return fail(c, RLC_ENOMEM, "hipMalloc of %zu bytes failed: %s", sizeof(T) * n, hipGetErrorString(e));
+    }
+    return RLC_OK;
+}
+
+template <class T>
+void dfree(T*& p) {
+    if (p) (void)hipFree((void*)p);
+    p = nullptr;
+}
+
+#define RLC_TRY(expr)            \
+    do {                         \
+        int r_ = (expr);         \
+        if (r_ != RLC_OK) return r_; \
+    } while (0)
+
+bool finite_f(float v) { return std::isfinite(v); }
+
+uint32_t blocks_for(size_t n, uint32_t b = 256) { return (uint32_t)((n + b - 1) / b); }
+
+int reset_cells(rlc_ctx* c) {
+    DevCells& d = c->cells;
+    size_t rows = (size_t)d.capacity * d.M;
+    RLC_HIP(c, launch_fill_u64(d.keys, RLC_EMPTY_KEY, d.capacity, c->stream));
+    RLC_HIP(c, launch_fill_u32(d.ready, 0u, d.capacity, c->stream));
+    RLC_HIP(c, launch_fill_u64(d.sum, 0ull, rows, c->stream));
+    RLC_HIP(c, launch_fill_u32(d.cnt, 0u, rows, c->stream));
+    RLC_HIP(c, launch_fill_u32(d.n_live, 0u, 1, c->stream));
+    return RLC_OK;
+}
+
+void free_tree(rlc_ctx* c) {
+    dfree(c->rec);
+    dfree(c->perm);
+    dfree(c->morton);
+    dfree(c->left);
+    dfree(c->right);
+    dfree(c->parent);
+    dfree(c->first);
+    dfree(c->last);
+    dfree(c->tmpl_node);
+    dfree(c->tmpl_end);
+    dfree(c->tmpl_Qt);
+    dfree(c->tmpl_C);
+    c->tree_built = false;
+}
+
+void free_occ(rlc_ctx* c) {
+    dfree(c->box);
+    dfree(c->occ_off);
+    dfree(c->occ_ref);
+    c->occ = DevOcc{};
+    c->occ_set = false;
+    c->K = 0;
+}
+
+DevTree dev_tree(const rlc_ctx* c) {
+    DevTree t;
+    t.rec = c->rec;
+    t.left = c->left;
+    t.right = c->right;
+    t.parent = c->parent;
+    t.first = c->first;
+    t.last = c->last;
+    t.N = c->N;
+    return t;
+}
+
+DevCut dev_tmpl(const rlc_ctx* c) {
+    DevCut t;
+    t.node = c->tmpl_node;
+    t.end = c->tmpl_end;
+    t.Qt = c->tmpl_Qt;
+    t.C = c->tmpl_C;
+    t.Meff = c->Meff;
+    return t;
+}
+
+FrameParams frame_params(const rlc_ctx* c) {
+    FrameParams fp;
+    fp.tree = dev_tree(c);
+    fp.tmpl = dev_tmpl(c);
+    fp.cells = c->cells;
+    fp.occ = c->occ;
+    fp.occ.K = c->occ_set ? c->K : 0u;
+    for (int a = 0; a < 3; ++a) {
+        fp.grid_lo[a] = c->cfg.grid_lo[a];
+        fp.inv_cell[a] = c->inv_cell[a];
+        fp.dims[a] = c->cfg.grid_dims[a];
+    }
+    fp.scene_id = c->cfg.scene_id;
+    fp.seed_lo = (uint32_t)(c->cfg.seed & 0xFFFFFFFFull);
+    fp.seed_hi = (uint32_t)(c->cfg.seed >> 32);
+    fp.f_r = c->f_r;
+    fp.t_lo = c->cfg.t_lo;
+    fp.reward_max = c->cfg.reward_max;
+    fp.fx_scale = c->fx_scale;
+    fp.reward_mode = c->cfg.reward_mode;
+    fp.two_sided = c->cfg.two_sided;
+    fp.err = c->d_err;
+    return fp;
+}
+
+AdaptParams adapt_params(const rlc_ctx* c) {
+    AdaptParams ap;
+    ap.tree = dev_tree(c);
+    ap.tmpl = dev_tmpl(c);
+    ap.cells = c->cells;
+    ap.alpha = c->cfg.alpha;
+    ap.T = c->cfg.T;
+    ap.eps = c->cfg.eps;
+    ap.fx_inv = c->fx_inv;
+    ap.adapt = c->cfg.adapt;
+    ap.temporal = c->cfg.temporal;
+    return ap;
+}
+
+int need_tree(rlc_ctx* c) {
+    if (!c) return RLC_EINVAL;
+    if (!c->tree_built) return fail(c, RLC_ESTATE, "the light tree has not been built");
+    return RLC_OK;
+}
+
+int check_frame_args(rlc_ctx* c, const void* pos, uint32_t P, uint32_t spp) {
+    RLC_TRY(need_tree(c));
+    if (P == 0) return RLC_OK;
+    if (!pos) return fail(c, RLC_EINVAL, "null point array");
+    if (spp == 0) return fail(c, RLC_EINVAL, "spp must be >= 1");
+    if ((uint64_t)P * spp > 0xFFFFFFFFull) return fail(c, RLC_EINVAL, "P * spp exceeds 2^32 - 1");
+    return RLC_OK;
+}
+
+hipEvent_t take_event(rlc_ctx* c) {
+    if (!c->spare.empty()) {
+        hipEvent_t e = c->spare.back();
+        c->spare.pop_back();
+        return e;
+    }
+    hipEvent_t e = nullptr;
+    if (hipEventCreate(&e) != hipSuccess) return nullptr;
+    return e;
+}
+
+int read_device_errors(rlc_ctx* c) {
+    uint32_t err = 0;
+    RLC_HIP(c, hipMemcpyAsync(&err, c->d_err, sizeof(uint32_t), hipMemcpyDeviceToHost, c->stream));
+    RLC_HIP(c, hipStreamSynchronize(c->stream));
+    if (err) {
+        RLC_HIP(c, launch_fill_u32(c->d_err, 0u, 1, c->stream));
+        RLC_HIP(c, hipStreamSynchronize(c->stream));
+        if (err & RLC_DERR_CAPACITY)
+            return fail(c, RLC_ECAPACITY, "cell table full (capacity %u); some samples were not learned from",
+                        c->cells.capacity);
+        if (err & RLC_DERR_INPUT) return fail(c, RLC_EINVAL, "non-finite or inverted input");
+        if (err & RLC_DERR_NONFINITE) return fail(c, RLC_EINVAL, "non-finite contribution");
+    }
+    return RLC_OK;
+}
+
+}  // namespace
+
+extern "C" {
+
+const char* rlc_last_error(const rlc_ctx* ctx) { return ctx ? ctx->msg : "null context"; }
+
+int rlc_create(const rlc_config* cfg, void* stream, rlc_ctx** out) {
+    if (!out) return RLC_EINVAL;
+    *out = nullptr;
+    if (!cfg) return RLC_EINVAL;
+    const rlc_config& k = *cfg;
+    bool ok = k.M >= 1 && k.M <= RLC_MMAX && finite_f(k.alpha) && k.alpha >= 0.0f && k.alpha <= 1.0f &&
+              finite_f(k.T) && k.T >= 0.0f && finite_f(k.eps) && k.eps >= 0.0f && k.fx_shift <= 40 &&
+              finite_f(k.reward_max) && k.reward_max > 0.0f && finite_f(k.t_lo) && k.t_lo >= 0.0f &&
+              k.t_lo < 0.5f && k.reward_mode <= 1 && finite_f(k.albedo) && k.albedo >= 0.0f &&
+              k.occ_grid_res <= 1024;
+    for (int a = 0; a < 3; ++a)
+        ok = ok && finite_f(k.grid_lo[a]) && finite_f(k.grid_hi[a]) && k.grid_hi[a] > k.grid_lo[a] &&
+             k.grid_dims[a] >= 1 && k.grid_dims[a] <= (1u << 20);
+    if (!ok) return RLC_EINVAL;
+    uint64_t dense = (uint64_t)k.grid_dims[0] * k.grid_dims[1] * k.grid_dims[2];
+    if (dense > 0xFFFFFFFFull) return RLC_EINVAL;
+    uint64_t capacity;
+    if (k.hashed) {
+        if (k.capacity == 0 || k.capacity > (1u << 30)) return RLC_EINVAL;
+        capacity = 64;
+        while (capacity < k.capacity) capacity <<= 1;
+    } else {
+        if (dense > (1u << 28)) return RLC_EINVAL;
+        capacity = dense;
+    }
+    rlc_ctx* c = new (std::nothrow) rlc_ctx();
+    if (!c) return RLC_ENOMEM;
+    c->cfg = k;
+    c->stream = (hipStream_t)stream;
+    for (int a = 0; a < 3; ++a) c->inv_cell[a] = (float)k.grid_dims[a] / (k.grid_hi[a] - k.grid_lo[a]);
+    c->f_r = (float)((double)k.albedo / 3.14159265358979323846);
+    c->fx_scale = ldexpf(1.0f, (int)k.fx_shift);
+    c->fx_inv = ldexpf(1.0f, -(int)k.fx_shift);
+    DevCells& d = c->cells;
+    d.capacity = (uint32_t)capacity;
+    d.hashed = k.hashed ? 1u : 0u;
+    d.M = k.M;
+    size_t rows = (size_t)capacity * k.M;
+    int r = RLC_OK;
+    if (r == RLC_OK) r = dalloc(c, &d.keys, capacity);
+    if (r == RLC_OK) r = dalloc(c, &d.ready, capacity);
+    if (r == RLC_OK) r = dalloc(c, &d.node, rows);
+    if (r == RLC_OK) r = dalloc(c, &d.end, rows);
+    if (r == RLC_OK) r = dalloc(c, &d.Q, rows);
+    if (r == RLC_OK) r = dalloc(c, &d.Qt, rows);
+    if (r == RLC_OK) r = dalloc(c, &d.C, rows);
+    if (r == RLC_OK) r = dalloc(c, &d.sum, rows);
+    if (r == RLC_OK) r = dalloc(c, &d.cnt, rows);
+    if (r == RLC_OK) r = dalloc(c, &d.live, capacity);
+    if (r == RLC_OK) r = dalloc(c, &d.n_live, 1);
+    if (r == RLC_OK) r = dalloc(c, &c->d_err, 1);
+    if (r == RLC_OK) r = dalloc(c, &c->d_partial, 6 * 1024);
+    if (r == RLC_OK) r = reset_cells(c);
+    if (r == RLC_OK) {
+        hipError_t e = launch_fill_u32(c->d_err, 0u, 1, c->stream);
+        if (e == hipSuccess) e = hipStreamSynchronize(c->stream);
+        if (e != hipSuccess) r = RLC_EHIP;
+    }
+    if (r != RLC_OK) {
+        rlc_destroy(c);
+        return r;
+    }
+    *out = c;
+    return RLC_OK;
+}
+
+int rlc_destroy(rlc_ctx* c) {
+    if (!c) return RLC_OK;
+    if (c->stream || true) (void)hipStreamSynchronize(c->stream);
+    free_tree(c);
+    free_occ(c);
+    DevCells& d = c->cells;
+    dfree(d.keys);
+    dfree(d.ready);
+    dfree(d.node);
+    dfree(d.end);
+    dfree(d.Q);
+    dfree(d.Qt);
+    dfree(d.C);
+    dfree(d.sum);
+    dfree(d.cnt);
+    dfree(d.live);
+    dfree(d.n_live);
+    dfree(c->d_err);
+    dfree(c->d_partial);
+    for (hipEvent_t e : c->pending) (void)hipEventDestroy(e);
+    for (hipEvent_t e : c->spare) (void)hipEventDestroy(e);
+    delete c;
+    return RLC_OK;
+}
+
+int rlc_build_light_tree(rlc_ctx* c, const float* d_tri, const float* d_emit, uint32_t N) {
+    if (!c) return RLC_EINVAL;
+    if (!d_tri || !d_emit) return fail(c, RLC_EINVAL, "null triangle or emission array");
+    if (N == 0) return fail(c, RLC_EINVAL, "N must be >= 1");
+    if (N > (1u << 30)) return fail(c, RLC_EINVAL, "too many lights");
+    RLC_HIP(c, hipStreamSynchronize(c->stream));
+    free_tree(c);
+    const uint32_t nn = 2u * N - 1u;
+    const uint32_t M = c->cfg.M;
+    RLC_TRY(dalloc(c, &c->rec, 4 * (size_t)N));
+    RLC_TRY(dalloc(c, &c->perm, N));
+    RLC_TRY(dalloc(c, &c->morton, N));
+    RLC_TRY(dalloc(c, &c->left, N > 1 ? N - 1 : 1));
+    RLC_TRY(dalloc(c, &c->right, N > 1 ? N - 1 : 1));
+    RLC_TRY(dalloc(c, &c->parent, nn));
+    RLC_TRY(dalloc(c, &c->first, nn));
+    RLC_TRY(dalloc(c, &c->last, nn));
+    RLC_TRY(dalloc(c, &c->tmpl_node, M));
+    RLC_TRY(dalloc(c, &c->tmpl_end, M));
+    RLC_TRY(dalloc(c, &c->tmpl_Qt, M));
+    RLC_TRY(dalloc(c, &c->tmpl_C, M));
+    // temporaries
+    float* sums = nullptr;
+    float* part = nullptr;
+    float* bbox = nullptr;
+    uint32_t* ktmp = nullptr;
+    uint32_t* vtmp = nullptr;
+    uint32_t* hist = nullptr;
+    uint32_t nb = std::min<uint32_t>(1024u, blocks_for(N));
+    int r = RLC_OK;
+    if (r == RLC_OK) r = dalloc(c, &sums, 3 * (size_t)N);
+    if (r == RLC_OK) r = dalloc(c, &part, 6 * (size_t)nb);
+    if (r == RLC_OK) r = dalloc(c, &bbox, 9);
+    if (r == RLC_OK) r = dalloc(c, &ktmp, N);
+    if (r == RLC_OK) r = dalloc(c, &vtmp, N);
+    if (r == RLC_OK) r = dalloc(c, &hist, radix_sort_hist_entries(N));
+    hipError_t e = hipSuccess;
+    auto step = [&](hipError_t x) {
+        if (e == hipSuccess) e = x;
+    };
+    if (r == RLC_OK) {
+        step(launch_fill_u32(c->d_err, 0u, 1, c->stream));
+        step(launch_tri_prep(d_tri, N, sums, part, part + 3 * nb, nb, c->d_err, c->stream));
+        step(launch_check_finite(d_emit, 3 * N, c->d_err, c->stream));
+        step(launch_bbox_final(part, part + 3 * nb, nb, bbox, c->stream));
+        step(launch_morton(sums, bbox, N, c->morton, c->perm, c->stream));
+        step(radix_sort_pairs(c->morton, c->perm, ktmp, vtmp, hist, N, 30, c->stream));
+        step(launch_gather_records(d_tri, d_emit, c->perm, N, c->rec, c->stream));
+        step(launch_radix_tree(c->morton, c->perm, N, c->left, c->right, c->parent, c->first, c->last, c->stream));
+        c->N = N;
+        c->Meff = std::min(M, N);
+        step(launch_initial_cut(dev_tree(c), M, c->tmpl_node, c->tmpl_end, c->tmpl_Qt, c->tmpl_C, c->stream));
+        step(hipStreamSynchronize(c->stream));
+    }
+    dfree(sums);
+    dfree(part);
+    dfree(bbox);
+    dfree(ktmp);
+    dfree(vtmp);
+    dfree(hist);
+    if (r != RLC_OK) return r;
+    if (e != hipSuccess) return fail(c, RLC_EHIP, "light tree build: %s", hipGetErrorString(e));
+    RLC_TRY(read_device_errors(c));
+    c->tree_built = true;
+    RLC_TRY(reset_cells(c));
+    RLC_HIP(c, hipStreamSynchronize(c->stream));
+    return RLC_OK;
+}
+
+int rlc_set_emission(rlc_ctx* c, const float* d_emit, uint32_t N) {
+    RLC_TRY(need_tree(c));
+    if (!d_emit) return fail(c, RLC_EINVAL, "null emission array");
+    if (N != c->N) return fail(c, RLC_EINVAL, "emission for %u lights, tree has %u", N, c->N);
+    RLC_HIP(c, launch_scatter_emission(d_emit, c->perm, N, c->rec, c->stream));
+    return RLC_OK;
+}
+
+int rlc_set_occluders(rlc_ctx* c, const float* d_aabb, uint32_t K) {
+    if (!c) return RLC_EINVAL;
+    if (K && !d_aabb) return fail(c, RLC_EINVAL, "null box array");
+    RLC_HIP(c, hipStreamSynchronize(c->stream));
+    free_occ(c);
+    if (K == 0) {
+        c->occ_set = true;
+        return RLC_OK;
+    }
+    uint32_t nb = std::min<uint32_t>(1024u, blocks_for(K));
+    float* part = nullptr;
+    RLC_TRY(dalloc(c, &c->box, 2 * (size_t)K));
+    RLC_TRY(dalloc(c, &part, 6 * (size_t)nb));
+    RLC_HIP(c, launch_fill_u32(c->d_err, 0u, 1, c->stream));
+    RLC_HIP(c, launch_pack_boxes(d_aabb, K, c->box, part, part + 3 * nb, nb, c->d_err, c->stream));
+    std::vector<float> hpart(6 * (size_t)nb);
+    RLC_HIP(c, hipMemcpyAsync(hpart.data(), part, sizeof(float) * hpart.size(), hipMemcpyDeviceToHost, c->stream));
+    RLC_HIP(c, hipStreamSynchronize(c->stream));
+    dfree(part);
+    int r = read_device_errors(c);
+    if (r != RLC_OK) return r;
+    DevOcc& o = c->occ;
+    o.box = c->box;
+    o.K = K;
+    o.res = c->cfg.occ_grid_res;
+    if (o.res) {
+        float lo[3], hi[3];
+        for (int a = 0; a < 3; ++a) {
+            lo[a] = hpart[a];
+            hi[a] = hpart[3 * nb + a];
+            for (uint32_t p = 1; p < nb; ++p) {
+                lo[a] = std::min(lo[a], hpart[3 * p + a]);
+                hi[a] = std::max(hi[a], hpart[3 * nb + 3 * p + a]);
+            }
+        }
+        float ext = std::max(hi[0] - lo[0], std::max(hi[1] - lo[1], hi[2] - lo[2]));
+        float margin = 1e-3f * ext + 1e-6f;
+        for (int a = 0; a < 3; ++a) {
+            o.glo[a] = lo[a] - margin;
+            o.gmax[a] = hi[a] + margin;
+            o.gcell[a] = (o.gmax[a] - o.glo[a]) / (float)o.res;
+            o.ginv[a] = (float)o.res / (o.gmax[a] - o.glo[a]);
+        }
+        size_t ncell = (size_t)o.res * o.res * o.res;
+        uint32_t* cursor = nullptr;
+        RLC_TRY(dalloc(c, &c->occ_off, ncell + 1));
+        RLC_TRY(dalloc(c, &cursor, ncell));
+        RLC_HIP(c, launch_fill_u32(c->occ_off, 0u, ncell + 1, c->stream));
+        RLC_HIP(c, launch_fill_u32(cursor, 0u, ncell, c->stream));
+        RLC_HIP(c, launch_occ_count(c->box, K, o, c->occ_off, c->stream));
+        RLC_HIP(c, launch_exclusive_scan(c->occ_off, (uint32_t)(ncell + 1), c->stream));
+        uint32_t total = 0;
+        RLC_HIP(c, hipMemcpyAsync(&total, c->occ_off + ncell, sizeof(uint32_t), hipMemcpyDeviceToHost, c->stream));
+        RLC_HIP(c, hipStreamSynchronize(c->stream));
+        r = dalloc(c, &c->occ_ref, total);
+        if (r != RLC_OK) {
+            dfree(cursor);
+            return r;
+        }
+        o.off = c->occ_off;
+        o.ref = c->occ_ref;
+        RLC_HIP(c, launch_occ_fill(c->box, K, o, c->occ_off, cursor, c->occ_ref, c->stream));
+        RLC_HIP(c, hipStreamSynchronize(c->stream));
+        dfree(cursor);
+    }
+    c->K = K;
+    c->occ_set = true;
+    return RLC_OK;
+}
+
+int rlc_sample(rlc_ctx* c, const float* d_pos, const float* d_nrm, uint32_t P, uint32_t spp, uint32_t frame,
+               const rlc_samples* out) {
+    (void)d_nrm;
+    RLC_TRY(check_frame_args(c, d_pos, P, spp));
+    if (!out) return fail(c, RLC_EINVAL, "null sample records");
+    RLC_HIP(c, launch_sample(frame_params(c), d_pos, P, spp, frame, *out, c->stream));
+    return RLC_OK;
+}
+
+int rlc_shade(rlc_ctx* c, const float* d_pos, const float* d_nrm, uint32_t P, uint32_t spp,
+              const rlc_samples* in, float* d_radiance, float* d_contrib, float* d_reward) {
+    RLC_TRY(check_frame_args(c, d_pos, P, spp));
+    if (!in || !d_nrm || !d_radiance || !in->d_light || !in->d_inv_pdf || !in->d_y || !in->d_slot)
+        return fail(c, RLC_EINVAL, "missing shade input");
+    if (c->cfg.reward_mode == 1 && (!in->d_cell || !in->d_ready))
+        return fail(c, RLC_EINVAL, "cluster-size rewards need cell and ready records");
+    RLC_HIP(c, launch_shade(frame_params(c), d_pos, d_nrm, P, spp, *in, d_radiance, d_contrib, d_reward, c->stream));
+    return RLC_OK;
+}
+
+int rlc_learn(rlc_ctx* c, const rlc_samples* in, const float* d_reward, uint32_t n) {
+    RLC_TRY(need_tree(c));
+    if (n == 0) return RLC_OK;
+    if (!in || !in->d_cell || !in->d_slot || !d_reward) return fail(c, RLC_EINVAL, "missing learn input");
+    RLC_HIP(c, launch_learn(frame_params(c), *in, d_reward, n, c->stream));
+    return RLC_OK;
+}
+
+int rlc_adapt_cuts(rlc_ctx* c) {
+    RLC_TRY(need_tree(c));
+    RLC_HIP(c, launch_adapt(adapt_params(c), c->stream));
+    return RLC_OK;
+}
+
+int rlc_frame(rlc_ctx* c, const float* d_pos, const float* d_nrm, uint32_t P, uint32_t spp, uint32_t frame,
+              float* d_radiance) {
+    RLC_TRY(check_frame_args(c, d_pos, P, spp));
+    if (P && (!d_nrm || !d_radiance)) return fail(c, RLC_EINVAL, "null normal or radiance array");
+    hipEvent_t ev[3] = {nullptr, nullptr, nullptr};
+    if (c->timing) {
+        for (auto& e : ev) {
+            e = take_event(c);
+            if (!e) return fail(c, RLC_EHIP, "hipEventCreate failed");
+        }
+        RLC_HIP(c, hipEventRecord(ev[0], c->stream));
+    }
+    RLC_HIP(c, launch_frame(frame_params(c), d_pos, d_nrm, P, spp, frame, d_radiance, c->stream));
+    if (c->timing) RLC_HIP(c, hipEventRecord(ev[1], c->stream));
+    RLC_HIP(c, launch_adapt(adapt_params(c), c->stream));
+    if (c->timing) {
+        RLC_HIP(c, hipEventRecord(ev[2], c->stream));
+        for (auto& e : ev) c->pending.push_back(e);
+    }
+    return RLC_OK;
+}
+
+int rlc_visible(rlc_ctx* c, const float* d_x, const float* d_y, uint32_t n, uint8_t* d_vis) {
+    if (!c) return RLC_EINVAL;
+    if (n == 0) return RLC_OK;
+    if (!d_x || !d_y || !d_vis) return fail(c, RLC_EINVAL, "null array");
+    DevOcc o = c->occ;
+    o.K = c->occ_set ? c->K : 0u;
+    RLC_HIP(c, launch_visible(o, c->cfg.t_lo, d_x, d_y, n, d_vis, c->stream));
+    return RLC_OK;
+}
+
+int rlc_cell_keys(rlc_ctx* c, const float* d_pos, uint32_t n, uint64_t* d_keys) {
+    if (!c) return RLC_EINVAL;
+    if (n == 0) return RLC_OK;
+    if (!d_pos || !d_keys) return fail(c, RLC_EINVAL, "null array");
+    RLC_HIP(c, launch_cell_keys(frame_params(c), d_pos, n, d_keys, c->stream));
+    return RLC_OK;
+}
+
+int rlc_image_error(rlc_ctx* c, const float* d_img, const float* d_ref, uint32_t n, double* h_out) {
+    if (!c) return RLC_EINVAL;
+    if (!h_out || (n && (!d_img || !d_ref))) return fail(c, RLC_EINVAL, "null array");
+    if (n == 0) {
+        for (int i = 0; i < 5; ++i) h_out[i] = 0.0;
+        return RLC_OK;
+    }
+    uint32_t nb = std::min<uint32_t>(1024u, blocks_for(n));
+    RLC_HIP(c, launch_image_error(d_img, d_ref, n, c->d_partial, nb, c->stream));
+    std::vector<double> h(6 * (size_t)nb);
+    RLC_HIP(c, hipMemcpyAsync(h.data(), c->d_partial, sizeof(double) * h.size(), hipMemcpyDeviceToHost, c->stream));
+    RLC_HIP(c, hipStreamSynchronize(c->stream));
+    double s[6] = {0, 0, 0, 0, 0, 0};
+    for (uint32_t b = 0; b < nb; ++b) {
+        for (int f = 0; f < 5; ++f) s[f] += h[6 * b + f];
+        s[5] = std::max(s[5], h[6 * b + 5]);
+    }
+    double mean = s[0] / n;
+    h_out[0] = mean;
+    h_out[1] = std::max(0.0, s[1] / n - mean * mean);
+    h_out[2] = s[2] / n;
+    h_out[3] = s[4] > 0.0 ? s[3] / s[4] : 0.0;
+    h_out[4] = s[5];
+    return RLC_OK;
+}
+
+int rlc_sync(rlc_ctx* c) {
+    if (!c) return RLC_EINVAL;
+    RLC_HIP(c, hipStreamSynchronize(c->stream));
+    return read_device_errors(c);
+}
+
+int rlc_num_cells(rlc_ctx* c, uint32_t* h_n) {
+    if (!c || !h_n) return RLC_EINVAL;
+    RLC_HIP(c, hipMemcpyAsync(h_n, c->cells.n_live, sizeof(uint32_t), hipMemcpyDeviceToHost, c->stream));
+    RLC_HIP(c, hipStreamSynchronize(c->stream));
+    return RLC_OK;
+}
+
+int rlc_meff(rlc_ctx* c, uint32_t* h_meff) {
+    RLC_TRY(need_tree(c));
+    if (!h_meff) return RLC_EINVAL;
+    *h_meff = c->Meff;
+    return RLC_OK;
+}
+
+int rlc_dump_cells(rlc_ctx* c, uint32_t max_cells, uint64_t* h_keys, uint32_t* h_ready, uint32_t* h_node,
+                   uint32_t* h_end, float* h_Q, float* h_Qt, float* h_C, uint64_t* h_sum, uint32_t* h_cnt) {
+    RLC_TRY(need_tree(c));
+    RLC_TRY(rlc_sync(c));
+    uint32_t n = 0;
+    RLC_TRY(rlc_num_cells(c, &n));
+    if (n == 0) return RLC_OK;
+    const DevCells& d = c->cells;
+    std::vector<uint32_t> slots(n);
+    std::vector<unsigned long long> keys(d.capacity);
+    std::vector<uint32_t> ready(d.capacity);
+    RLC_HIP(c, hipMemcpy(slots.data(), d.live, sizeof(uint32_t) * n, hipMemcpyDeviceToHost));
+    RLC_HIP(c, hipMemcpy(keys.data(), d.keys, sizeof(unsigned long long) * d.capacity, hipMemcpyDeviceToHost));
+    RLC_HIP(c, hipMemcpy(ready.data(), d.ready, sizeof(uint32_t) * d.capacity, hipMemcpyDeviceToHost));
+    std::sort(slots.begin(), slots.end(), [&](uint32_t a, uint32_t b) { return keys[a] < keys[b]; });
+    uint32_t rows = std::min(n, max_cells);
+    if (rows == 0) return RLC_OK;
+    for (uint32_t i = 0; i < rows; ++i) {
+        if (h_keys) h_keys[i] = keys[slots[i]];
+        if (h_ready) h_ready[i] = ready[slots[i]];
+    }
+    const uint32_t Meff = c->Meff;
+    size_t cnt = (size_t)rows * Meff;
+    uint32_t* d_slots = nullptr;
+    uint32_t *dn = nullptr, *de = nullptr, *dc = nullptr;
+    float *dq = nullptr, *dqt = nullptr, *dC = nullptr;
+    unsigned long long* ds = nullptr;
+    int r = dalloc(c, &d_slots, rows);
+    if (r == RLC_OK && h_node) r = dalloc(c, &dn, cnt);
+    if (r == RLC_OK && h_end) r = dalloc(c, &de, cnt);
+    if (r == RLC_OK && h_Q) r = dalloc(c, &dq, cnt);
+    if (r == RLC_OK && h_Qt) r = dalloc(c, &dqt, cnt);
+    if (r == RLC_OK && h_C) r = dalloc(c, &dC, cnt);
+    if (r == RLC_OK && h_sum) r = dalloc(c, &ds, cnt);
+    if (r == RLC_OK && h_cnt) r = dalloc(c, &dc, cnt);
+    hipError_t e = hipSuccess;
+    if (r == RLC_OK) {
+        e = hipMemcpy(d_slots, slots.data(), sizeof(uint32_t) * rows, hipMemcpyHostToDevice);
+        if (e == hipSuccess) e = launch_gather_cells(d, Meff, d_slots, rows, dn, de, dq, dqt, dC, ds, dc, c->stream);
+        if (e == hipSuccess) e = hipStreamSynchronize(c->stream);
+        if (e == hipSuccess && h_node) e = hipMemcpy(h_node, dn, sizeof(uint32_t) * cnt, hipMemcpyDeviceToHost);
+        if (e == hipSuccess && h_end) e = hipMemcpy(h_end, de, sizeof(uint32_t) * cnt, hipMemcpyDeviceToHost);
+        if (e == hipSuccess && h_Q) e = hipMemcpy(h_Q, dq, sizeof(float) * cnt, hipMemcpyDeviceToHost);
+        if (e == hipSuccess && h_Qt) e = hipMemcpy(h_Qt, dqt, sizeof(float) * cnt, hipMemcpyDeviceToHost);
+        if (e == hipSuccess && h_C) e = hipMemcpy(h_C, dC, sizeof(float) * cnt, hipMemcpyDeviceToHost);
+        if (e == hipSuccess && h_sum) e = hipMemcpy(h_sum, ds, sizeof(uint64_t) * cnt, hipMemcpyDeviceToHost);
+        if (e == hipSuccess && h_cnt) e = hipMemcpy(h_cnt, dc, sizeof(uint32_t) * cnt, hipMemcpyDeviceToHost);
+    }
+    dfree(d_slots);
+    dfree(dn);
+    dfree(de);
+    dfree(dq);
+    dfree(dqt);
+    dfree(dC);
+    dfree(ds);
+    dfree(dc);
+    if (r != RLC_OK) return r;
+    if (e != hipSuccess) return fail(c, RLC_EHIP, "dump: %s", hipGetErrorString(e));
+    return RLC_OK;
+}
+
+int rlc_dump_tree(rlc_ctx* c, uint32_t* h_perm, uint32_t* h_left, uint32_t* h_right, uint32_t* h_parent,
+                  uint32_t* h_first, uint32_t* h_last, float* h_rec) {
+    RLC_TRY(need_tree(c));
+    RLC_HIP(c, hipStreamSynchronize(c->stream));
+    const uint32_t N = c->N, nn = 2 * N - 1;
+    if (h_perm) RLC_HIP(c, hipMemcpy(h_perm, c->perm, sizeof(uint32_t) * N, hipMemcpyDeviceToHost));
+    if (h_left && N > 1) RLC_HIP(c, hipMemcpy(h_left, c->left, sizeof(uint32_t) * (N - 1), hipMemcpyDeviceToHost));
+    if (h_right && N > 1) RLC_HIP(c, hipMemcpy(h_right, c->right, sizeof(uint32_t) * (N - 1), hipMemcpyDeviceToHost));
+    if (h_parent) RLC_HIP(c, hipMemcpy(h_parent, c->parent, sizeof(uint32_t) * nn, hipMemcpyDeviceToHost));
+    if (h_first) RLC_HIP(c, hipMemcpy(h_first, c->first, sizeof(uint32_t) * nn, hipMemcpyDeviceToHost));
+    if (h_last) RLC_HIP(c, hipMemcpy(h_last, c->last, sizeof(uint32_t) * nn, hipMemcpyDeviceToHost));
+    if (h_rec) RLC_HIP(c, hipMemcpy(h_rec, c->rec, sizeof(float4) * 4 * (size_t)N, hipMemcpyDeviceToHost));
+    return RLC_OK;
+}
+
+int rlc_get_template(rlc_ctx* c, uint32_t* h_node, uint32_t* h_end, uint32_t* h_meff) {
+    RLC_TRY(need_tree(c));
+    RLC_HIP(c, hipStreamSynchronize(c->stream));
+    if (h_node) RLC_HIP(c, hipMemcpy(h_node, c->tmpl_node, sizeof(uint32_t) * c->Meff, hipMemcpyDeviceToHost));
+    if (h_end) RLC_HIP(c, hipMemcpy(h_end, c->tmpl_end, sizeof(uint32_t) * c->Meff, hipMemcpyDeviceToHost));
+    if (h_meff) *h_meff = c->Meff;
+    return RLC_OK;
+}
+
+int rlc_set_timing(rlc_ctx* c, int enable) {
+    if (!c) return RLC_EINVAL;
+    c->timing = enable != 0;
+    return RLC_OK;
+}
+
+int rlc_get_timing(rlc_ctx* c, double* h_ms_fused, double* h_ms_adapt, uint32_t* h_frames) {
+    if (!c) return RLC_EINVAL;
+    double f = 0.0, a = 0.0;
+    uint32_t frames = (uint32_t)(c->pending.size() / 3);
+    for (uint32_t i = 0; i < frames; ++i) {
+        hipEvent_t* e = &c->pending[3 * i];
+        RLC_HIP(c, hipEventSynchronize(e[2]));
+        float t01 = 0.0f, t12 = 0.0f;
+        RLC_HIP(c, hipEventElapsedTime(&t01, e[0], e[1]));
+        RLC_HIP(c, hipEventElapsedTime(&t12, e[1], e[2]));
+        f += t01;
+        a += t12;
+    }
+    for (hipEvent_t e : c->pending) c->spare.push_back(e);
+    c->pending.clear();
+    if (h_ms_fused) *h_ms_fused = f;
+    if (h_ms_adapt) *h_ms_adapt = a;
+    if (h_frames) *h_frames = frames;
+    return RLC_OK;
+}
+
+}  // extern "C"

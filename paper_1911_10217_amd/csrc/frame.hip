@@ -1,0 +1,228 @@
+// Per-frame kernels of the hot path: sample (section 3: cluster from the
+// cell's cdf, light inside the cluster), shade (shadow ray, contribution,
+// estimate), learn (fixed-point statistics for Eq. 1), and the fused kernel
+// that runs all three for one sample per lane.
+#include "rlc_internal.h"
+
+namespace rlc {
+
+namespace {
+
+constexpr int kBlock = 256;
+
+// Sum over aligned groups of `spp` lanes (spp a power of two <= 64); every
+// lane of the group ends with the group's sum.
+__device__ __forceinline__ float group_sum(float v, uint32_t spp) {
+    for (uint32_t off = spp >> 1; off > 0; off >>= 1) v += __shfl_xor(v, (int)off, 64);
+    return v;
+}
+
+__device__ __forceinline__ bool pow2_le64(uint32_t spp) { return spp <= 64u && (spp & (spp - 1u)) == 0u; }
+
+__device__ __forceinline__ void scatter_stats(const FrameParams& fp, uint32_t cell, uint32_t s,
+                                              unsigned long long q) {
+    if (cell == RLC_NONE) return;
+    size_t idx = (size_t)cell * fp.cells.M + s;
+    atomicAdd(&fp.cells.sum[idx], q);
+    atomicAdd(&fp.cells.cnt[idx], 1u);
+}
+
+__global__ void __launch_bounds__(kBlock) k_sample(FrameParams fp, const float* __restrict__ pos, uint32_t P,
+                                                   uint32_t spp, uint32_t frame, rlc_samples out) {
+    uint32_t b = xcd_block(blockIdx.x, gridDim.x);
+    size_t i = (size_t)b * kBlock + threadIdx.x;
+    size_t n = (size_t)P * spp;
+    if (i >= n) return;
+    uint32_t p = (uint32_t)(i / spp), k = (uint32_t)(i % spp);
+    Sample sm;
+    draw_sample(fp, pos[3 * (size_t)p], pos[3 * (size_t)p + 1], pos[3 * (size_t)p + 2], p, k, frame, sm);
+    if (out.d_key) out.d_key[i] = sm.key;
+    if (out.d_cell) out.d_cell[i] = sm.cell;
+    if (out.d_ready) out.d_ready[i] = sm.ready;
+    if (out.d_slot) out.d_slot[i] = sm.s;
+    if (out.d_light) out.d_light[i] = sm.light;
+    if (out.d_inv_pdf) out.d_inv_pdf[i] = sm.inv_pdf;
+    if (out.d_y) {
+        out.d_y[3 * i] = sm.y[0];
+        out.d_y[3 * i + 1] = sm.y[1];
+        out.d_y[3 * i + 2] = sm.y[2];
+    }
+}
+
+// One lane per sample; the spp samples of a point share aligned lanes.
+__global__ void __launch_bounds__(kBlock) k_shade(FrameParams fp, const float* __restrict__ pos,
+                                                  const float* __restrict__ nrm, uint32_t P, uint32_t spp,
+                                                  rlc_samples in, float* __restrict__ radiance,
+                                                  float* __restrict__ contrib, float* __restrict__ reward) {
+    uint32_t b = xcd_block(blockIdx.x, gridDim.x);
+    size_t i = (size_t)b * kBlock + threadIdx.x;
+    size_t n = (size_t)P * spp;
+    bool valid = i < n;
+    float e[3] = {0.0f, 0.0f, 0.0f};
+    uint32_t p = 0, k = 0;
+    if (valid) {
+        p = (uint32_t)(i / spp);
+        k = (uint32_t)(i % spp);
+        float x[3] = {pos[3 * (size_t)p], pos[3 * (size_t)p + 1], pos[3 * (size_t)p + 2]};
+        float nn[3] = {nrm[3 * (size_t)p], nrm[3 * (size_t)p + 1], nrm[3 * (size_t)p + 2]};
+        float y[3] = {in.d_y[3 * i], in.d_y[3 * i + 1], in.d_y[3 * i + 2]};
+        uint32_t l = in.d_light[i];
+        float c[3];
+        contribution(fp, x, nn, l, y, c);
+        float ip = in.d_inv_pdf[i];
+        e[0] = c[0] * ip;
+        e[1] = c[1] * ip;
+        e[2] = c[2] * ip;
+        if (contrib) {
+            contrib[3 * i] = c[0];
+            contrib[3 * i + 1] = c[1];
+            contrib[3 * i + 2] = c[2];
+        }
+        // cluster size for the reward: from the table the sample used
+        uint32_t s = in.d_slot[i];
+        uint32_t size = 1u;
+        if (fp.reward_mode == 1u) {
+            uint32_t cell = in.d_cell[i];
+            const uint32_t* end = (cell != RLC_NONE && in.d_ready[i]) ? fp.cells.end + (size_t)cell * fp.cells.M
+                                                                       : fp.tmpl.end;
+            size = end[s] - (s ? end[s - 1u] : 0u);
+        }
+        float r = reward_of(fp, c, size);
+        if (!(r <= 3.402823466e38f)) atomicOr(fp.err, RLC_DERR_NONFINITE);
+        if (reward) reward[i] = r;
+    }
+    float inv_spp = 1.0f / (float)spp;
+    if (pow2_le64(spp)) {
+        e[0] = group_sum(e[0], spp);
+        e[1] = group_sum(e[1], spp);
+        e[2] = group_sum(e[2], spp);
+        if (valid && k == 0) {
+            radiance[3 * (size_t)p] = e[0] * inv_spp;
+            radiance[3 * (size_t)p + 1] = e[1] * inv_spp;
+            radiance[3 * (size_t)p + 2] = e[2] * inv_spp;
+        }
+    } else if (valid) {
+        atomicAdd(&radiance[3 * (size_t)p], e[0] * inv_spp);
+        atomicAdd(&radiance[3 * (size_t)p + 1], e[1] * inv_spp);
+        atomicAdd(&radiance[3 * (size_t)p + 2], e[2] * inv_spp);
+    }
+}
+
+__global__ void __launch_bounds__(kBlock) k_learn(FrameParams fp, rlc_samples in, const float* __restrict__ reward,
+                                                  uint32_t n) {
+    uint32_t b = xcd_block(blockIdx.x, gridDim.x);
+    size_t i = (size_t)b * kBlock + threadIdx.x;
+    if (i >= n) return;
+    scatter_stats(fp, in.d_cell[i], in.d_slot[i], reward_fixed(fp, reward[i]));
+}
+
+// Fused pass: one lane per sample (point p = i / spp, sample k = i % spp).
+__global__ void __launch_bounds__(kBlock) k_frame(FrameParams fp, const float* __restrict__ pos,
+                                                  const float* __restrict__ nrm, uint32_t P, uint32_t spp,
+                                                  uint32_t frame, float* __restrict__ radiance) {
+    uint32_t b = xcd_block(blockIdx.x, gridDim.x);
+    size_t i = (size_t)b * kBlock + threadIdx.x;
+    size_t n = (size_t)P * spp;
+    bool valid = i < n;
+    float e[3] = {0.0f, 0.0f, 0.0f};
+    uint32_t p = 0, k = 0;
+    if (valid) {
+        p = (uint32_t)(i / spp);
+        k = (uint32_t)(i % spp);
+        float x[3] = {pos[3 * (size_t)p], pos[3 * (size_t)p + 1], pos[3 * (size_t)p + 2]};
+        float nn[3] = {nrm[3 * (size_t)p], nrm[3 * (size_t)p + 1], nrm[3 * (size_t)p + 2]};
+        Sample sm;
+        draw_sample(fp, x[0], x[1], x[2], p, k, frame, sm);
+        float c[3];
+        contribution(fp, x, nn, sm.light, sm.y, c);
+        e[0] = c[0] * sm.inv_pdf;
+        e[1] = c[1] * sm.inv_pdf;
+        e[2] = c[2] * sm.inv_pdf;
+        float r = reward_of(fp, c, sm.size);
+        if (!(r <= 3.402823466e38f)) atomicOr(fp.err, RLC_DERR_NONFINITE);
+        scatter_stats(fp, sm.cell, sm.s, reward_fixed(fp, r));
+    }
+    float inv_spp = 1.0f / (float)spp;
+    if (pow2_le64(spp)) {
+        e[0] = group_sum(e[0], spp);
+        e[1] = group_sum(e[1], spp);
+        e[2] = group_sum(e[2], spp);
+        if (valid && k == 0) {
+            radiance[3 * (size_t)p] = e[0] * inv_spp;
+            radiance[3 * (size_t)p + 1] = e[1] * inv_spp;
+            radiance[3 * (size_t)p + 2] = e[2] * inv_spp;
+        }
+    } else if (valid) {
+        atomicAdd(&radiance[3 * (size_t)p], e[0] * inv_spp);
+        atomicAdd(&radiance[3 * (size_t)p + 1], e[1] * inv_spp);
+        atomicAdd(&radiance[3 * (size_t)p + 2], e[2] * inv_spp);
+    }
+}
+
+__global__ void k_zero_f32(float* a, size_t n) {
+    size_t i = (size_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (i < n) a[i] = 0.0f;
+}
+
+__global__ void __launch_bounds__(kBlock) k_cell_keys(FrameParams fp, const float* __restrict__ pos, uint32_t n,
+                                                      uint64_t* __restrict__ keys) {
+    size_t i = (size_t)blockIdx.x * kBlock + threadIdx.x;
+    if (i >= n) return;
+    uint32_t lin = cell_linear(fp, pos[3 * i], pos[3 * i + 1], pos[3 * i + 2]);
+    keys[i] = ((uint64_t)fp.scene_id << 32) | (uint64_t)lin;
+}
+
+inline uint32_t blocks_for(size_t n) { return (uint32_t)((n + kBlock - 1) / kBlock); }
+
+hipError_t zero_radiance_if_needed(float* radiance, uint32_t P, uint32_t spp, hipStream_t s) {
+    if (spp <= 64u && (spp & (spp - 1u)) == 0u) return hipSuccess;
+    size_t n = (size_t)P * 3;
+    hipLaunchKernelGGL(k_zero_f32, dim3(blocks_for(n)), dim3(kBlock), 0, s, radiance, n);
+    return hipGetLastError();
+}
+
+}  // namespace
+
+hipError_t launch_sample(const FrameParams& fp, const float* pos, uint32_t P, uint32_t spp, uint32_t frame,
+                         const rlc_samples& out, hipStream_t s) {
+    size_t n = (size_t)P * spp;
+    if (n == 0) return hipSuccess;
+    hipLaunchKernelGGL(k_sample, dim3(blocks_for(n)), dim3(kBlock), 0, s, fp, pos, P, spp, frame, out);
+    return hipGetLastError();
+}
+
+hipError_t launch_shade(const FrameParams& fp, const float* pos, const float* nrm, uint32_t P, uint32_t spp,
+                        const rlc_samples& in, float* radiance, float* contrib, float* reward, hipStream_t s) {
+    size_t n = (size_t)P * spp;
+    if (n == 0) return hipSuccess;
+    hipError_t e = zero_radiance_if_needed(radiance, P, spp, s);
+    if (e != hipSuccess) return e;
+    hipLaunchKernelGGL(k_shade, dim3(blocks_for(n)), dim3(kBlock), 0, s, fp, pos, nrm, P, spp, in, radiance,
+                       contrib, reward);
+    return hipGetLastError();
+}
+
+hipError_t launch_learn(const FrameParams& fp, const rlc_samples& in, const float* reward, uint32_t n,
+                        hipStream_t s) {
+    if (n == 0) return hipSuccess;
+    hipLaunchKernelGGL(k_learn, dim3(blocks_for(n)), dim3(kBlock), 0, s, fp, in, reward, n);
+    return hipGetLastError();
+}
+
+hipError_t launch_frame(const FrameParams& fp, const float* pos, const float* nrm, uint32_t P, uint32_t spp,
+                        uint32_t frame, float* radiance, hipStream_t s) {
+    size_t n = (size_t)P * spp;
+    if (n == 0) return hipSuccess;
+    hipError_t e = zero_radiance_if_needed(radiance, P, spp, s);
+    if (e != hipSuccess) return e;
+    hipLaunchKernelGGL(k_frame, dim3(blocks_for(n)), dim3(kBlock), 0, s, fp, pos, nrm, P, spp, frame, radiance);
+    return hipGetLastError();
+}
+
+hipError_t launch_cell_keys(const FrameParams& fp, const float* pos, uint32_t n, uint64_t* keys, hipStream_t s) {
+    if (n == 0) return hipSuccess;
+    hipLaunchKernelGGL(k_cell_keys, dim3(blocks_for(n)), dim3(kBlock), 0, s, fp, pos, n, keys);
+    return hipGetLastError();
+}
+
+}  // namespace rlc

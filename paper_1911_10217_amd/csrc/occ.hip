@@ -1,0 +1,132 @@
+// Occluders for the shadow rays: box packing, a uniform grid over the boxes
+// (counts, exclusive scan, fill), and a visibility-only kernel.
+#include "rlc_internal.h"
+
+namespace rlc {
+
+namespace {
+
+constexpr int kBlock = 256;
+
+__global__ void __launch_bounds__(kBlock) k_pack_boxes(const float* __restrict__ aabb, uint32_t K,
+                                                       float4* __restrict__ box, float* part_lo, float* part_hi,
+                                                       uint32_t* err) {
+    __shared__ float s_lo[3][kBlock];
+    __shared__ float s_hi[3][kBlock];
+    float lo[3] = {3.0e38f, 3.0e38f, 3.0e38f}, hi[3] = {-3.0e38f, -3.0e38f, -3.0e38f};
+    for (size_t i = (size_t)blockIdx.x * kBlock + threadIdx.x; i < K; i += (size_t)gridDim.x * kBlock) {
+        const float* a = aabb + 6 * i;
+        bool ok = true;
+        for (int k = 0; k < 6; ++k) ok &= fabsf(a[k]) <= 3.402823466e38f;
+        for (int k = 0; k < 3; ++k) ok &= a[k] <= a[3 + k];
+        if (!ok) atomicOr(err, RLC_DERR_INPUT);
+        box[2 * i] = make_float4(a[0], a[1], a[2], a[3]);
+        box[2 * i + 1] = make_float4(a[4], a[5], 0.0f, 0.0f);
+        for (int k = 0; k < 3; ++k) {
+            lo[k] = a[k] < lo[k] ? a[k] : lo[k];
+            hi[k] = a[3 + k] > hi[k] ? a[3 + k] : hi[k];
+        }
+    }
+    for (int a = 0; a < 3; ++a) {
+        s_lo[a][threadIdx.x] = lo[a];
+        s_hi[a][threadIdx.x] = hi[a];
+    }
+    __syncthreads();
+    for (int off = kBlock / 2; off > 0; off >>= 1) {
+        if ((int)threadIdx.x < off)
+            for (int a = 0; a < 3; ++a) {
+                float l2 = s_lo[a][threadIdx.x + off], h2 = s_hi[a][threadIdx.x + off];
+                if (l2 < s_lo[a][threadIdx.x]) s_lo[a][threadIdx.x] = l2;
+                if (h2 > s_hi[a][threadIdx.x]) s_hi[a][threadIdx.x] = h2;
+            }
+        __syncthreads();
+    }
+    if (threadIdx.x == 0)
+        for (int a = 0; a < 3; ++a) {
+            part_lo[3 * blockIdx.x + a] = s_lo[a][0];
+            part_hi[3 * blockIdx.x + a] = s_hi[a][0];
+        }
+}
+
+// Grid cells overlapped by box b grown by a margin of 1/1024 of a cell.
+__device__ __forceinline__ void box_cells(const DevOcc& occ, float4 b0, float4 b1, int lo[3], int hi[3]) {
+    const float bmin[3] = {b0.x, b0.y, b0.z};
+    const float bmax[3] = {b0.w, b1.x, b1.y};
+    const int res = (int)occ.res;
+    for (int a = 0; a < 3; ++a) {
+        float m = occ.gcell[a] * (1.0f / 1024.0f);
+        float f0 = floorf((bmin[a] - m - occ.glo[a]) * occ.ginv[a]);
+        float f1 = floorf((bmax[a] + m - occ.glo[a]) * occ.ginv[a]);
+        lo[a] = f0 < 0.0f ? 0 : (f0 >= (float)res ? res - 1 : (int)f0);
+        hi[a] = f1 < 0.0f ? 0 : (f1 >= (float)res ? res - 1 : (int)f1);
+    }
+}
+
+__global__ void __launch_bounds__(kBlock) k_occ_count(const float4* __restrict__ box, uint32_t K, DevOcc occ,
+                                                      uint32_t* __restrict__ counts) {
+    size_t i = (size_t)blockIdx.x * kBlock + threadIdx.x;
+    if (i >= K) return;
+    int lo[3], hi[3];
+    box_cells(occ, box[2 * i], box[2 * i + 1], lo, hi);
+    for (int z = lo[2]; z <= hi[2]; ++z)
+        for (int y = lo[1]; y <= hi[1]; ++y)
+            for (int x = lo[0]; x <= hi[0]; ++x)
+                atomicAdd(&counts[(uint32_t)x + occ.res * ((uint32_t)y + occ.res * (uint32_t)z)], 1u);
+}
+
+__global__ void __launch_bounds__(kBlock) k_occ_fill(const float4* __restrict__ box, uint32_t K, DevOcc occ,
+                                                     const uint32_t* __restrict__ off, uint32_t* __restrict__ cursor,
+                                                     uint32_t* __restrict__ ref) {
+    size_t i = (size_t)blockIdx.x * kBlock + threadIdx.x;
+    if (i >= K) return;
+    int lo[3], hi[3];
+    box_cells(occ, box[2 * i], box[2 * i + 1], lo, hi);
+    for (int z = lo[2]; z <= hi[2]; ++z)
+        for (int y = lo[1]; y <= hi[1]; ++y)
+            for (int x = lo[0]; x <= hi[0]; ++x) {
+                uint32_t c = (uint32_t)x + occ.res * ((uint32_t)y + occ.res * (uint32_t)z);
+                ref[off[c] + atomicAdd(&cursor[c], 1u)] = (uint32_t)i;
+            }
+}
+
+__global__ void __launch_bounds__(kBlock) k_visible(DevOcc occ, float t_lo, const float* __restrict__ x,
+                                                    const float* __restrict__ y, uint32_t n,
+                                                    uint8_t* __restrict__ vis) {
+    size_t i = (size_t)blockIdx.x * kBlock + threadIdx.x;
+    if (i >= n) return;
+    float o[3] = {x[3 * i], x[3 * i + 1], x[3 * i + 2]};
+    float d[3] = {y[3 * i] - o[0], y[3 * i + 1] - o[1], y[3 * i + 2] - o[2]};
+    vis[i] = segment_blocked(occ, o, d, t_lo) ? 0 : 1;
+}
+
+inline uint32_t blocks_for(size_t n) { return (uint32_t)((n + kBlock - 1) / kBlock); }
+
+}  // namespace
+
+hipError_t launch_pack_boxes(const float* aabb, uint32_t K, float4* box, float* part_lo, float* part_hi,
+                             uint32_t nblocks, uint32_t* err, hipStream_t s) {
+    hipLaunchKernelGGL(k_pack_boxes, dim3(nblocks), dim3(kBlock), 0, s, aabb, K, box, part_lo, part_hi, err);
+    return hipGetLastError();
+}
+
+hipError_t launch_occ_count(const float4* box, uint32_t K, DevOcc occ, uint32_t* counts, hipStream_t s) {
+    if (K == 0) return hipSuccess;
+    hipLaunchKernelGGL(k_occ_count, dim3(blocks_for(K)), dim3(kBlock), 0, s, box, K, occ, counts);
+    return hipGetLastError();
+}
+
+hipError_t launch_occ_fill(const float4* box, uint32_t K, DevOcc occ, const uint32_t* off, uint32_t* cursor,
+                           uint32_t* ref, hipStream_t s) {
+    if (K == 0) return hipSuccess;
+    hipLaunchKernelGGL(k_occ_fill, dim3(blocks_for(K)), dim3(kBlock), 0, s, box, K, occ, off, cursor, ref);
+    return hipGetLastError();
+}
+
+hipError_t launch_visible(DevOcc occ, float t_lo, const float* x, const float* y, uint32_t n, uint8_t* vis,
+                          hipStream_t s) {
+    if (n == 0) return hipSuccess;
+    hipLaunchKernelGGL(k_visible, dim3(blocks_for(n)), dim3(kBlock), 0, s, occ, t_lo, x, y, n, vis);
+    return hipGetLastError();
+}
+
+}  // namespace rlc

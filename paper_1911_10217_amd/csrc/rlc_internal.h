@@ -1,0 +1,471 @@
+// Internal declarations of librlc: device-side views of the library's
+// buffers, the per-sample device routines shared by the split and fused
+// kernels, and the host launchers of every kernel.
+#pragma once
+
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+#include "rlc.h"
+
+#define RLC_NONE 0xFFFFFFFFu
+#define RLC_EMPTY_KEY 0xFFFFFFFFFFFFFFFFull
+
+// device error word bits
+#define RLC_DERR_CAPACITY 1u
+#define RLC_DERR_NONFINITE 2u
+#define RLC_DERR_INPUT 4u
+
+namespace rlc {
+
+// Reference light tree in tree (Morton) order.  rec holds 64 bytes per light:
+// {v0.xyz v1.x} {v1.yz v2.xy} {v2.z Le.rgb} {area normal.xyz}.
+struct DevTree {
+    const float4* rec;
+    const uint32_t* left;
+    const uint32_t* right;
+    const uint32_t* parent;
+    const uint32_t* first;
+    const uint32_t* last;
+    uint32_t N;
+};
+
+// The initial cut: node ids, cluster ends, and the uniform Q~ / C a fresh
+// cell samples with.
+struct DevCut {
+    const uint32_t* node;
+    const uint32_t* end;
+    const float* Qt;
+    const float* C;
+    uint32_t Meff;
+};
+
+// Cell tables.  Row c of every per-slot array starts at c * M.
+struct DevCells {
+    unsigned long long* keys;   // RLC_EMPTY_KEY = free
+    uint32_t* ready;            // 1 once the cell's own table exists
+    uint32_t* node;
+    uint32_t* end;
+    float* Q;
+    float* Qt;
+    float* C;
+    unsigned long long* sum;    // fixed-point reward sums of the pass
+    uint32_t* cnt;              // sample counts of the pass
+    uint32_t* live;             // slots of all created cells
+    uint32_t* n_live;
+    uint32_t capacity;          // dense: cells of the grid; hashed: 2^k
+    uint32_t hashed;
+    uint32_t M;                 // row stride
+};
+
+// Occluders: box b is {min.xyz, max.x} {max.yz, 0, 0}.  With a grid,
+// off[res^3 + 1] / ref[] list the boxes overlapping each grid cell.
+struct DevOcc {
+    const float4* box;
+    const uint32_t* off;
+    const uint32_t* ref;
+    uint32_t K;
+    uint32_t res;               // 0: brute force over all boxes
+    float glo[3];
+    float gcell[3];             // grid cell size
+    float ginv[3];              // res / extent
+    float gmax[3];
+};
+
+struct FrameParams {
+    DevTree tree;
+    DevCut tmpl;
+    DevCells cells;
+    DevOcc occ;
+    float grid_lo[3];
+    float inv_cell[3];
+    uint32_t dims[3];
+    uint32_t scene_id;
+    uint32_t seed_lo, seed_hi;
+    float f_r;
+    float t_lo;
+    float reward_max;
+    float fx_scale;             // 2^fx_shift
+    uint32_t reward_mode;
+    uint32_t two_sided;
+    uint32_t* err;
+};
+
+struct AdaptParams {
+    DevTree tree;
+    DevCut tmpl;
+    DevCells cells;
+    float alpha;
+    float T;
+    float eps;
+    float fx_inv;               // 2^-fx_shift
+    uint32_t adapt;
+    uint32_t temporal;
+};
+
+// ---------------------------------------------------------------------------
+// Philox4x32-10 (Salmon et al., SC'11): ten rounds of two 32x32 multiplies
+// with a word permutation; the key advances by the Weyl constants between
+// rounds.
+// ---------------------------------------------------------------------------
+__device__ __forceinline__ void philox4x32_10(uint32_t& x0, uint32_t& x1, uint32_t& x2, uint32_t& x3,
+                                              uint32_t k0, uint32_t k1) {
+#pragma unroll
+    for (int r = 0; r < 10; ++r) {
+        uint32_t lo0 = 0xD2511F53u * x0;
+        uint32_t hi0 = __umulhi(0xD2511F53u, x0);
+        uint32_t lo1 = 0xCD9E8D57u * x2;
+        uint32_t hi1 = __umulhi(0xCD9E8D57u, x2);
+        uint32_t y0 = hi1 ^ x1 ^ k0;
+        uint32_t y2 = hi0 ^ x3 ^ k1;
+        x0 = y0;
+        x1 = lo1;
+        x2 = y2;
+        x3 = lo0;
+        k0 += 0x9E3779B9u;
+        k1 += 0xBB67AE85u;
+    }
+}
+
+__device__ __forceinline__ float unit24(uint32_t x) { return (float)(x >> 8) * (1.0f / 16777216.0f); }
+
+// floor-quantise one coordinate into [0, dims)
+__device__ __forceinline__ uint32_t axis_cell(float p, float lo, float inv, uint32_t dims) {
+    float f = floorf((p - lo) * inv);
+    if (!(f >= 0.0f)) return 0u;
+    if (f >= (float)dims) return dims - 1u;
+    return (uint32_t)f;
+}
+
+__device__ __forceinline__ uint32_t cell_linear(const FrameParams& fp, float x, float y, float z) {
+    uint32_t ix = axis_cell(x, fp.grid_lo[0], fp.inv_cell[0], fp.dims[0]);
+    uint32_t iy = axis_cell(y, fp.grid_lo[1], fp.inv_cell[1], fp.dims[1]);
+    uint32_t iz = axis_cell(z, fp.grid_lo[2], fp.inv_cell[2], fp.dims[2]);
+    return ix + fp.dims[0] * (iy + fp.dims[1] * iz);
+}
+
+__device__ __forceinline__ unsigned long long mix64(unsigned long long x) {
+    // SplitMix64 finaliser (Steele, Lea, Flood 2014)
+    x ^= x >> 30;
+    x *= 0xBF58476D1CE4E5B9ull;
+    x ^= x >> 27;
+    x *= 0x94D049BB133111EBull;
+    x ^= x >> 31;
+    return x;
+}
+
+// Find the table slot of a cell key, creating the cell if it is absent.
+// Creation only claims the slot and records it in the live list; the cell's
+// own table is filled at the end of the pass.
+__device__ __forceinline__ uint32_t find_or_create(const DevCells& c, unsigned long long key, uint32_t lin,
+                                                   uint32_t* err) {
+    if (!c.hashed) {
+        if (lin >= c.capacity) return RLC_NONE;
+        unsigned long long k = __atomic_load_n(&c.keys[lin], __ATOMIC_RELAXED);
+        if (k != key) {
+            unsigned long long old = atomicCAS(&c.keys[lin], RLC_EMPTY_KEY, key);
+            if (old == RLC_EMPTY_KEY) c.live[atomicAdd(c.n_live, 1u)] = lin;
+        }
+        return lin;
+    }
+    uint32_t mask = c.capacity - 1u;
+    uint32_t h = (uint32_t)mix64(key) & mask;
+    for (uint32_t probe = 0; probe < c.capacity; ++probe) {
+        unsigned long long k = __atomic_load_n(&c.keys[h], __ATOMIC_RELAXED);
+        if (k == key) return h;
+        if (k == RLC_EMPTY_KEY) {
+            unsigned long long old = atomicCAS(&c.keys[h], RLC_EMPTY_KEY, key);
+            if (old == RLC_EMPTY_KEY) {
+                c.live[atomicAdd(c.n_live, 1u)] = h;
+                return h;
+            }
+            if (old == key) return h;
+        }
+        h = (h + 1u) & mask;
+    }
+    atomicOr(err, RLC_DERR_CAPACITY);
+    return RLC_NONE;
+}
+
+// ---------------------------------------------------------------------------
+// Shadow rays
+// ---------------------------------------------------------------------------
+__device__ __forceinline__ bool box_blocks(const float4 b0, const float4 b1, const float o[3], const float d[3],
+                                           const float invd[3], float t_lo) {
+    const float bmin[3] = {b0.x, b0.y, b0.z};
+    const float bmax[3] = {b0.w, b1.x, b1.y};
+    float tn = t_lo;
+    float tf = 1.0f - t_lo;
+#pragma unroll
+    for (int a = 0; a < 3; ++a) {
+        if (d[a] == 0.0f) {
+            if (o[a] < bmin[a] || o[a] > bmax[a]) return false;
+            continue;
+        }
+        float t0 = (bmin[a] - o[a]) * invd[a];
+        float t1 = (bmax[a] - o[a]) * invd[a];
+        float tmin = t0 < t1 ? t0 : t1;
+        float tmax = t0 < t1 ? t1 : t0;
+        if (tmin > tn) tn = tmin;
+        if (tmax < tf) tf = tmax;
+    }
+    return tn < tf;
+}
+
+__device__ __forceinline__ bool blocked_brute(const DevOcc& occ, const float o[3], const float d[3],
+                                              const float invd[3], float t_lo) {
+    for (uint32_t b = 0; b < occ.K; ++b) {
+        if (box_blocks(occ.box[2 * b], occ.box[2 * b + 1], o, d, invd, t_lo)) return true;
+    }
+    return false;
+}
+
+// Grid walk (3-D DDA over the cells the segment crosses, in order).  Boxes
+// are listed in every grid cell that overlaps the box grown by a small
+// margin, so cells missed by rounding at cell corners are covered.
+__device__ __forceinline__ bool blocked_grid(const DevOcc& occ, const float o[3], const float d[3],
+                                             const float invd[3], float t_lo) {
+    float t0 = t_lo, t1 = 1.0f - t_lo;
+#pragma unroll
+    for (int a = 0; a < 3; ++a) {
+        if (d[a] == 0.0f) {
+            if (o[a] < occ.glo[a] || o[a] > occ.gmax[a]) return false;
+            continue;
+        }
+        float ta = (occ.glo[a] - o[a]) * invd[a];
+        float tb = (occ.gmax[a] - o[a]) * invd[a];
+        float lo = ta < tb ? ta : tb;
+        float hi = ta < tb ? tb : ta;
+        t0 = lo > t0 ? lo : t0;
+        t1 = hi < t1 ? hi : t1;
+    }
+    if (!(t0 <= t1)) return false;
+    const int res = (int)occ.res;
+    int c[3], step[3];
+#pragma unroll
+    for (int a = 0; a < 3; ++a) {
+        float p = o[a] + t0 * d[a];
+        float f = floorf((p - occ.glo[a]) * occ.ginv[a]);
+        int ci = f < 0.0f ? 0 : (f >= (float)res ? res - 1 : (int)f);
+        c[a] = ci;
+        step[a] = d[a] > 0.0f ? 1 : (d[a] < 0.0f ? -1 : 0);
+    }
+    const int max_steps = 3 * res + 3;
+    for (int it = 0; it < max_steps; ++it) {
+        uint32_t cell = (uint32_t)c[0] + occ.res * ((uint32_t)c[1] + occ.res * (uint32_t)c[2]);
+        uint32_t b0 = occ.off[cell], b1 = occ.off[cell + 1];
+        for (uint32_t j = b0; j < b1; ++j) {
+            uint32_t b = occ.ref[j];
+            if (box_blocks(occ.box[2 * b], occ.box[2 * b + 1], o, d, invd, t_lo)) return true;
+        }
+        // next cell boundary along each axis
+        float tnext = 3.0e38f;
+        int axis = -1;
+#pragma unroll
+        for (int a = 0; a < 3; ++a) {
+            if (step[a] == 0) continue;
+            float bound = occ.glo[a] + (float)(c[a] + (step[a] > 0 ? 1 : 0)) * occ.gcell[a];
+            float tb = (bound - o[a]) * invd[a];
+            if (tb < tnext) {
+                tnext = tb;
+                axis = a;
+            }
+        }
+        if (axis < 0 || tnext > t1) return false;
+        c[axis] += step[axis];
+        if (c[axis] < 0 || c[axis] >= res) return false;
+    }
+    return false;
+}
+
+__device__ __forceinline__ bool segment_blocked(const DevOcc& occ, const float o[3], const float d[3], float t_lo) {
+    if (occ.K == 0) return false;
+    float invd[3] = {1.0f / d[0], 1.0f / d[1], 1.0f / d[2]};
+    return occ.res ? blocked_grid(occ, o, d, invd, t_lo) : blocked_brute(occ, o, d, invd, t_lo);
+}
+
+// ---------------------------------------------------------------------------
+// One light sample (section 3): cluster from the cell's cdf, light inside
+// the cluster, point on the light.
+// ---------------------------------------------------------------------------
+struct Sample {
+    uint32_t cell;      // table slot or RLC_NONE
+    uint32_t ready;
+    uint32_t s;
+    uint32_t size;
+    uint32_t light;
+    float inv_pdf;
+    float y[3];
+    unsigned long long key;
+};
+
+__device__ __forceinline__ void draw_sample(const FrameParams& fp, float x, float y, float z, uint32_t pid,
+                                            uint32_t k, uint32_t frame, Sample& o) {
+    uint32_t lin = cell_linear(fp, x, y, z);
+    unsigned long long key = ((unsigned long long)fp.scene_id << 32) | (unsigned long long)lin;
+    uint32_t cell = find_or_create(fp.cells, key, lin, fp.err);
+    uint32_t rdy = (cell != RLC_NONE) ? fp.cells.ready[cell] : 0u;
+    const float* C;
+    const float* Qt;
+    const uint32_t* end;
+    if (rdy) {
+        size_t base = (size_t)cell * fp.cells.M;
+        C = fp.cells.C + base;
+        Qt = fp.cells.Qt + base;
+        end = fp.cells.end + base;
+    } else {
+        C = fp.tmpl.C;
+        Qt = fp.tmpl.Qt;
+        end = fp.tmpl.end;
+    }
+    const uint32_t Meff = fp.tmpl.Meff;
+    uint32_t w0 = pid, w1 = k, w2 = frame, w3 = fp.scene_id << 16;
+    philox4x32_10(w0, w1, w2, w3, fp.seed_lo, fp.seed_hi);
+    float u0 = unit24(w0);
+    unsigned long long draw40 = ((unsigned long long)(w0 & 0xFFu) << 32) | (unsigned long long)w1;
+    float u2 = unit24(w2);
+    float u3 = unit24(w3);
+
+    float total = C[Meff - 1u];
+    float t = u0 * total;
+    // smallest s with t < C[s] (C is non-decreasing)
+    uint32_t lo = 0, hi = Meff;
+    while (lo < hi) {
+        uint32_t mid = (lo + hi) >> 1;
+        if (t < C[mid])
+            hi = mid;
+        else
+            lo = mid + 1u;
+    }
+    uint32_t s = lo < Meff ? lo : Meff - 1u;
+    uint32_t begin = s ? end[s - 1u] : 0u;
+    uint32_t size = end[s] - begin;
+    float inv_pdf = ((float)size * total) / Qt[s];
+    uint32_t l = begin + (uint32_t)((draw40 * (unsigned long long)size) >> 40);
+
+    const float4 r0 = fp.tree.rec[4u * l + 0u];
+    const float4 r1 = fp.tree.rec[4u * l + 1u];
+    const float4 r2 = fp.tree.rec[4u * l + 2u];
+    float su = sqrtf(u2);
+    float b0 = 1.0f - su;
+    float b1 = u3 * su;
+    float b2 = (1.0f - b0) - b1;
+    o.y[0] = (b0 * r0.x + b1 * r0.w) + b2 * r1.z;
+    o.y[1] = (b0 * r0.y + b1 * r1.x) + b2 * r1.w;
+    o.y[2] = (b0 * r0.z + b1 * r1.y) + b2 * r2.x;
+    o.cell = cell;
+    o.ready = rdy;
+    o.s = s;
+    o.size = size;
+    o.light = l;
+    o.inv_pdf = inv_pdf;
+    o.key = key;
+}
+
+// Contribution c_l = Le f_r G A V of the sampled point y as seen from x.
+__device__ __forceinline__ void contribution(const FrameParams& fp, const float x[3], const float n[3],
+                                             uint32_t l, const float y[3], float c[3]) {
+    c[0] = c[1] = c[2] = 0.0f;
+    const float4 r2 = fp.tree.rec[4u * l + 2u];
+    const float4 r3 = fp.tree.rec[4u * l + 3u];
+    float d[3] = {y[0] - x[0], y[1] - x[1], y[2] - x[2]};
+    float dist2 = (d[0] * d[0] + d[1] * d[1]) + d[2] * d[2];
+    float area = r3.x;
+    if (!(dist2 > 0.0f && area > 0.0f)) return;
+    float dist = sqrtf(dist2);
+    float cos_x = ((n[0] * d[0] + n[1] * d[1]) + n[2] * d[2]) / dist;
+    float dl = (r3.y * d[0] + r3.z * d[1]) + r3.w * d[2];
+    float cos_l;
+    if (fp.two_sided)
+        cos_l = fabsf(dl) / dist;
+    else
+        cos_l = (dl < 0.0f ? -dl : 0.0f) / dist;
+    if (!(cos_x > 0.0f && cos_l > 0.0f)) return;
+    float G = (cos_x * cos_l) / dist2;
+    float kk = (fp.f_r * G) * area;
+    if (!(kk > 0.0f && (r2.y > 0.0f || r2.z > 0.0f || r2.w > 0.0f))) return;
+    if (segment_blocked(fp.occ, x, d, fp.t_lo)) return;
+    c[0] = r2.y * kk;
+    c[1] = r2.z * kk;
+    c[2] = r2.w * kk;
+}
+
+__device__ __forceinline__ float reward_of(const FrameParams& fp, const float c[3], uint32_t size) {
+    float r = (c[0] + c[1]) + c[2];
+    if (fp.reward_mode == 1u) r = r * (float)size;
+    return r;
+}
+
+__device__ __forceinline__ unsigned long long reward_fixed(const FrameParams& fp, float r) {
+    float rc = r < fp.reward_max ? r : fp.reward_max;
+    return (unsigned long long)rintf(rc * fp.fx_scale);
+}
+
+// Blocks are dealt to the 8 XCDs round-robin; give each XCD a contiguous
+// range of logical blocks so neighbouring points share one L2.
+__device__ __forceinline__ uint32_t xcd_block(uint32_t b, uint32_t nb) {
+    uint32_t q = nb >> 3, r = nb & 7u;
+    uint32_t x = b & 7u, j = b >> 3;
+    return x * q + (x < r ? x : r) + j;
+}
+
+}  // namespace rlc
+
+// ---------------------------------------------------------------------------
+// Host launchers (all enqueue on `s`; return hipError_t of the launch)
+// ---------------------------------------------------------------------------
+namespace rlc {
+// tree.hip
+hipError_t launch_tri_prep(const float* tri, uint32_t N, float* sums, float* part_lo, float* part_hi,
+                           uint32_t nblocks, uint32_t* err, hipStream_t s);
+hipError_t launch_bbox_final(const float* part_lo, const float* part_hi, uint32_t nparts, float* bbox,
+                             hipStream_t s);
+hipError_t launch_morton(const float* sums, const float* bbox, uint32_t N, uint32_t* keys, uint32_t* vals,
+                         hipStream_t s);
+hipError_t radix_sort_pairs(uint32_t* keys, uint32_t* vals, uint32_t* keys_tmp, uint32_t* vals_tmp,
+                            uint32_t* hist, uint32_t N, int bits, hipStream_t s);
+size_t radix_sort_hist_entries(uint32_t N);
+hipError_t launch_exclusive_scan(uint32_t* data, uint32_t n, hipStream_t s);
+hipError_t launch_gather_records(const float* tri, const float* emit, const uint32_t* perm, uint32_t N,
+                                 float4* rec, hipStream_t s);
+hipError_t launch_scatter_emission(const float* emit, const uint32_t* perm, uint32_t N, float4* rec,
+                                   hipStream_t s);
+hipError_t launch_radix_tree(const uint32_t* morton, const uint32_t* perm, uint32_t N, uint32_t* left,
+                             uint32_t* right, uint32_t* parent, uint32_t* first, uint32_t* last,
+                             hipStream_t s);
+hipError_t launch_initial_cut(DevTree tree, uint32_t M, uint32_t* node, uint32_t* end, float* Qt, float* C,
+                              hipStream_t s);
+hipError_t launch_check_finite(const float* a, uint32_t n, uint32_t* err, hipStream_t s);
+hipError_t launch_fill_u32(uint32_t* a, uint32_t v, size_t n, hipStream_t s);
+hipError_t launch_fill_u64(unsigned long long* a, unsigned long long v, size_t n, hipStream_t s);
+
+// occ.hip
+hipError_t launch_pack_boxes(const float* aabb, uint32_t K, float4* box, float* part_lo, float* part_hi,
+                             uint32_t nblocks, uint32_t* err, hipStream_t s);
+hipError_t launch_occ_count(const float4* box, uint32_t K, DevOcc occ, uint32_t* counts, hipStream_t s);
+hipError_t launch_occ_fill(const float4* box, uint32_t K, DevOcc occ, const uint32_t* off, uint32_t* cursor,
+                           uint32_t* ref, hipStream_t s);
+hipError_t launch_visible(DevOcc occ, float t_lo, const float* x, const float* y, uint32_t n, uint8_t* vis,
+                          hipStream_t s);
+
+// frame.hip
+hipError_t launch_sample(const FrameParams& fp, const float* pos, uint32_t P, uint32_t spp, uint32_t frame,
+                         const rlc_samples& out, hipStream_t s);
+hipError_t launch_shade(const FrameParams& fp, const float* pos, const float* nrm, uint32_t P, uint32_t spp,
+                        const rlc_samples& in, float* radiance, float* contrib, float* reward, hipStream_t s);
+hipError_t launch_learn(const FrameParams& fp, const rlc_samples& in, const float* reward, uint32_t n,
+                        hipStream_t s);
+hipError_t launch_frame(const FrameParams& fp, const float* pos, const float* nrm, uint32_t P, uint32_t spp,
+                        uint32_t frame, float* radiance, hipStream_t s);
+hipError_t launch_cell_keys(const FrameParams& fp, const float* pos, uint32_t n, uint64_t* keys, hipStream_t s);
+
+// adapt.hip
+hipError_t launch_adapt(const AdaptParams& ap, hipStream_t s);
+hipError_t launch_gather_cells(DevCells c, uint32_t Meff, const uint32_t* slots, uint32_t n, uint32_t* node,
+                               uint32_t* end, float* Q, float* Qt, float* C, unsigned long long* sum,
+                               uint32_t* cnt, hipStream_t s);
+
+// stats.hip
+hipError_t launch_image_error(const float* img, const float* ref, uint32_t n, double* partial,
+                              uint32_t nblocks, hipStream_t s);
+}  // namespace rlc

@@ -1,0 +1,367 @@
+"""Python binding of librlc (include/rlc.h): argument marshalling only.
+
+Every function keeps the C name and takes torch tensors on the GPU (their
+data_ptr() is passed as a device pointer) and the current torch stream.  All
+computation happens in librlc's HIP kernels; there is no fallback: if the
+library is not built, or no GPU is present, these calls raise.
+"""
+from __future__ import annotations
+
+import ctypes
+import os
+from typing import Optional
+
+import numpy as np
+
+HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(HERE, "librlc.so")
+
+RLC_OK = 0
+RLC_EINVAL = -1
+RLC_ENOMEM = -2
+RLC_EHIP = -3
+RLC_ECAPACITY = -4
+RLC_ESTATE = -5
+RLC_MMAX = 256
+
+_ERRNAMES = {RLC_EINVAL: "RLC_EINVAL", RLC_ENOMEM: "RLC_ENOMEM", RLC_EHIP: "RLC_EHIP",
+             RLC_ECAPACITY: "RLC_ECAPACITY", RLC_ESTATE: "RLC_ESTATE"}
+
+# every entry point declared in include/rlc.h
+EXPORTS = (
+    "rlc_create", "rlc_destroy", "rlc_build_light_tree", "rlc_set_emission", "rlc_set_occluders",
+    "rlc_sample", "rlc_shade", "rlc_learn", "rlc_adapt_cuts", "rlc_frame", "rlc_visible",
+    "rlc_cell_keys", "rlc_image_error", "rlc_sync", "rlc_last_error", "rlc_num_cells", "rlc_meff",
+    "rlc_dump_cells", "rlc_dump_tree", "rlc_get_template", "rlc_set_timing", "rlc_get_timing",
+)
+
+
+class RLCError(RuntimeError):
+    def __init__(self, code: int, msg: str):
+        super().__init__("%s (%d): %s" % (_ERRNAMES.get(code, "RLC_ERROR"), code, msg))
+        self.code = code
+
+
+class rlc_config(ctypes.Structure):
+    _fields_ = [
+        ("M", ctypes.c_uint32),
+        ("alpha", ctypes.c_float),
+        ("T", ctypes.c_float),
+        ("eps", ctypes.c_float),
+        ("fx_shift", ctypes.c_uint32),
+        ("reward_max", ctypes.c_float),
+        ("t_lo", ctypes.c_float),
+        ("reward_mode", ctypes.c_uint32),
+        ("two_sided", ctypes.c_uint32),
+        ("albedo", ctypes.c_float),
+        ("grid_lo", ctypes.c_float * 3),
+        ("grid_hi", ctypes.c_float * 3),
+        ("grid_dims", ctypes.c_uint32 * 3),
+        ("hashed", ctypes.c_uint32),
+        ("capacity", ctypes.c_uint32),
+        ("adapt", ctypes.c_uint32),
+        ("temporal", ctypes.c_uint32),
+        ("scene_id", ctypes.c_uint32),
+        ("occ_grid_res", ctypes.c_uint32),
+        ("reserved", ctypes.c_uint32),
+        ("seed", ctypes.c_uint64),
+    ]
+
+
+class rlc_samples(ctypes.Structure):
+    _fields_ = [(n, ctypes.c_void_p) for n in
+                ("d_key", "d_cell", "d_ready", "d_slot", "d_light", "d_inv_pdf", "d_y")]
+
+
+_vp = ctypes.c_void_p
+_u32 = ctypes.c_uint32
+_lib = None
+
+
+def lib():
+    """Load librlc.so (raises if it has not been built)."""
+    global _lib
+    if _lib is None:
+        if not os.path.exists(LIB_PATH):
+            raise ImportError("librlc.so is not built; run __graft_entry__.build() "
+                              "(or python -m paper_1911_10217_amd.build)")
+        L = ctypes.CDLL(LIB_PATH)
+        _declare(L)
+        _lib = L
+    return _lib
+
+
+def _declare(L):
+    i = ctypes.c_int
+    L.rlc_create.argtypes = [ctypes.POINTER(rlc_config), _vp, ctypes.POINTER(_vp)]
+    L.rlc_destroy.argtypes = [_vp]
+    L.rlc_build_light_tree.argtypes = [_vp, _vp, _vp, _u32]
+    L.rlc_set_emission.argtypes = [_vp, _vp, _u32]
+    L.rlc_set_occluders.argtypes = [_vp, _vp, _u32]
+    L.rlc_sample.argtypes = [_vp, _vp, _vp, _u32, _u32, _u32, ctypes.POINTER(rlc_samples)]
+    L.rlc_shade.argtypes = [_vp, _vp, _vp, _u32, _u32, ctypes.POINTER(rlc_samples), _vp, _vp, _vp]
+    L.rlc_learn.argtypes = [_vp, ctypes.POINTER(rlc_samples), _vp, _u32]
+    L.rlc_adapt_cuts.argtypes = [_vp]
+    L.rlc_frame.argtypes = [_vp, _vp, _vp, _u32, _u32, _u32, _vp]
+    L.rlc_visible.argtypes = [_vp, _vp, _vp, _u32, _vp]
+    L.rlc_cell_keys.argtypes = [_vp, _vp, _u32, _vp]
+    L.rlc_image_error.argtypes = [_vp, _vp, _vp, _u32, _vp]
+    L.rlc_sync.argtypes = [_vp]
+    L.rlc_last_error.argtypes = [_vp]
+    L.rlc_last_error.restype = ctypes.c_char_p
+    L.rlc_num_cells.argtypes = [_vp, _vp]
+    L.rlc_meff.argtypes = [_vp, _vp]
+    L.rlc_dump_cells.argtypes = [_vp, _u32] + [_vp] * 9
+    L.rlc_dump_tree.argtypes = [_vp] + [_vp] * 7
+    L.rlc_get_template.argtypes = [_vp, _vp, _vp, _vp]
+    L.rlc_set_timing.argtypes = [_vp, i]
+    L.rlc_get_timing.argtypes = [_vp, _vp, _vp, _vp]
+    for name in EXPORTS:
+        if name != "rlc_last_error":
+            getattr(L, name).restype = i
+
+
+def _ptr(t) -> Optional[int]:
+    if t is None:
+        return None
+    if isinstance(t, np.ndarray):
+        return t.ctypes.data
+    return t.data_ptr()
+
+
+def _dev(t, dtype, name):
+    import torch
+    if not isinstance(t, torch.Tensor) or t.device.type != "cuda":
+        raise TypeError("%s must be a CUDA/HIP torch tensor" % name)
+    if t.dtype != dtype:
+        raise TypeError("%s must be %s, got %s" % (name, dtype, t.dtype))
+    if not t.is_contiguous():
+        raise ValueError("%s must be contiguous" % name)
+    return t
+
+
+def _stream_handle():
+    import torch
+    return torch.cuda.current_stream().cuda_stream
+
+
+def make_config(params: dict) -> rlc_config:
+    c = rlc_config()
+    c.M = int(params["M"])
+    c.alpha = float(params["alpha"])
+    c.T = float(params["T"])
+    c.eps = float(params["eps"])
+    c.fx_shift = int(params["fx_shift"])
+    c.reward_max = float(params["reward_max"])
+    c.t_lo = float(params["t_lo"])
+    c.reward_mode = int(params["reward_mode"])
+    c.two_sided = int(params["two_sided"])
+    c.albedo = float(params["albedo"])
+    for a in range(3):
+        c.grid_lo[a] = float(params["grid_lo"][a])
+        c.grid_hi[a] = float(params["grid_hi"][a])
+        c.grid_dims[a] = int(params["grid_dims"][a])
+    c.hashed = int(params.get("hashed", 0))
+    c.capacity = int(params.get("capacity", 0))
+    c.adapt = int(params["adapt"])
+    c.temporal = int(params["temporal"])
+    c.scene_id = int(params["scene_id"])
+    c.occ_grid_res = int(params.get("occ_grid_res", 0))
+    c.seed = int(params["seed"])
+    return c
+
+
+class Context:
+    """An rlc_ctx bound to the torch stream current at creation."""
+
+    def __init__(self, params: dict, stream=None):
+        import torch
+        if not torch.cuda.is_available():
+            raise RuntimeError("librlc needs a GPU (torch.cuda.is_available() is False)")
+        L = lib()
+        self.params = dict(params)
+        self._cfg = make_config(params)
+        self._stream = stream if stream is not None else _stream_handle()
+        h = _vp()
+        rc = L.rlc_create(ctypes.byref(self._cfg), _vp(self._stream), ctypes.byref(h))
+        if rc != RLC_OK:
+            raise RLCError(rc, "rlc_create rejected the configuration")
+        self._h = h
+        self.N = 0
+
+    # -- helpers ---------------------------------------------------------------
+    def _check(self, rc: int, what: str):
+        if rc != RLC_OK:
+            msg = lib().rlc_last_error(self._h)
+            raise RLCError(rc, "%s: %s" % (what, msg.decode() if msg else ""))
+
+    def close(self):
+        h = getattr(self, "_h", None)
+        if h is not None and h.value:
+            lib().rlc_destroy(h)
+        self._h = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+    # -- the method's calls --------------------------------------------------------
+    def rlc_build_light_tree(self, tri, emit):
+        import torch
+        _dev(tri, torch.float32, "tri")
+        _dev(emit, torch.float32, "emit")
+        N = tri.numel() // 9
+        if tri.numel() != 9 * N or emit.numel() != 3 * N:
+            raise ValueError("tri must be N x 9 and emit N x 3")
+        self._check(lib().rlc_build_light_tree(self._h, _ptr(tri), _ptr(emit), N), "rlc_build_light_tree")
+        self.N = N
+
+    def rlc_set_emission(self, emit):
+        import torch
+        _dev(emit, torch.float32, "emit")
+        self._check(lib().rlc_set_emission(self._h, _ptr(emit), emit.numel() // 3), "rlc_set_emission")
+
+    def rlc_set_occluders(self, boxes):
+        import torch
+        K = 0 if boxes is None else boxes.numel() // 6
+        if K:
+            _dev(boxes, torch.float32, "boxes")
+        self._check(lib().rlc_set_occluders(self._h, _ptr(boxes) if K else None, K), "rlc_set_occluders")
+
+    def new_samples(self, n: int) -> dict:
+        import torch
+        dev = torch.device("cuda")
+        return dict(key=torch.empty(n, dtype=torch.int64, device=dev),
+                    cell=torch.empty(n, dtype=torch.int32, device=dev),
+                    ready=torch.empty(n, dtype=torch.int32, device=dev),
+                    slot=torch.empty(n, dtype=torch.int32, device=dev),
+                    light=torch.empty(n, dtype=torch.int32, device=dev),
+                    inv_pdf=torch.empty(n, dtype=torch.float32, device=dev),
+                    y=torch.empty((n, 3), dtype=torch.float32, device=dev))
+
+    @staticmethod
+    def _samples_struct(s: dict) -> rlc_samples:
+        return rlc_samples(*[_ptr(s.get(k)) for k in ("key", "cell", "ready", "slot", "light", "inv_pdf", "y")])
+
+    def rlc_sample(self, pos, nrm, spp: int, frame: int, out: Optional[dict] = None) -> dict:
+        import torch
+        _dev(pos, torch.float32, "pos")
+        P = pos.numel() // 3
+        out = out if out is not None else self.new_samples(P * spp)
+        st = self._samples_struct(out)
+        self._check(lib().rlc_sample(self._h, _ptr(pos), _ptr(nrm), P, spp, frame, ctypes.byref(st)), "rlc_sample")
+        return out
+
+    def rlc_shade(self, pos, nrm, spp: int, samples: dict, radiance=None, contrib: bool = True):
+        import torch
+        _dev(pos, torch.float32, "pos")
+        _dev(nrm, torch.float32, "nrm")
+        P = pos.numel() // 3
+        n = P * spp
+        radiance = radiance if radiance is not None else torch.empty((P, 3), dtype=torch.float32, device="cuda")
+        c = torch.empty((n, 3), dtype=torch.float32, device="cuda") if contrib else None
+        reward = torch.empty(n, dtype=torch.float32, device="cuda")
+        st = self._samples_struct(samples)
+        self._check(lib().rlc_shade(self._h, _ptr(pos), _ptr(nrm), P, spp, ctypes.byref(st), _ptr(radiance),
+                                    _ptr(c), _ptr(reward)), "rlc_shade")
+        return radiance, c, reward
+
+    def rlc_learn(self, samples: dict, reward):
+        st = self._samples_struct(samples)
+        self._check(lib().rlc_learn(self._h, ctypes.byref(st), _ptr(reward), reward.numel()), "rlc_learn")
+
+    def rlc_adapt_cuts(self):
+        self._check(lib().rlc_adapt_cuts(self._h), "rlc_adapt_cuts")
+
+    def rlc_frame(self, pos, nrm, spp: int, frame: int, radiance=None):
+        import torch
+        _dev(pos, torch.float32, "pos")
+        _dev(nrm, torch.float32, "nrm")
+        P = pos.numel() // 3
+        radiance = radiance if radiance is not None else torch.empty((P, 3), dtype=torch.float32, device="cuda")
+        _dev(radiance, torch.float32, "radiance")
+        self._check(lib().rlc_frame(self._h, _ptr(pos), _ptr(nrm), P, spp, frame, _ptr(radiance)), "rlc_frame")
+        return radiance
+
+    def rlc_visible(self, x, y):
+        import torch
+        _dev(x, torch.float32, "x")
+        _dev(y, torch.float32, "y")
+        n = x.numel() // 3
+        vis = torch.empty(n, dtype=torch.uint8, device="cuda")
+        self._check(lib().rlc_visible(self._h, _ptr(x), _ptr(y), n, _ptr(vis)), "rlc_visible")
+        return vis
+
+    def rlc_cell_keys(self, pos):
+        import torch
+        _dev(pos, torch.float32, "pos")
+        n = pos.numel() // 3
+        keys = torch.empty(n, dtype=torch.int64, device="cuda")
+        self._check(lib().rlc_cell_keys(self._h, _ptr(pos), n, _ptr(keys)), "rlc_cell_keys")
+        return keys
+
+    def rlc_image_error(self, img, ref) -> np.ndarray:
+        out = np.zeros(5, np.float64)
+        self._check(lib().rlc_image_error(self._h, _ptr(img), _ptr(ref), img.numel(), out.ctypes.data), "rlc_image_error")
+        return out
+
+    def rlc_sync(self):
+        self._check(lib().rlc_sync(self._h), "rlc_sync")
+
+    def rlc_num_cells(self) -> int:
+        n = np.zeros(1, np.uint32)
+        self._check(lib().rlc_num_cells(self._h, n.ctypes.data), "rlc_num_cells")
+        return int(n[0])
+
+    def rlc_meff(self) -> int:
+        n = np.zeros(1, np.uint32)
+        self._check(lib().rlc_meff(self._h, n.ctypes.data), "rlc_meff")
+        return int(n[0])
+
+    def rlc_dump_cells(self) -> dict:
+        n = self.rlc_num_cells()
+        m = self.rlc_meff()
+        d = dict(key=np.zeros(n, np.uint64), ready=np.zeros(n, np.uint32),
+                 node=np.zeros((n, m), np.uint32), end=np.zeros((n, m), np.uint32),
+                 Q=np.zeros((n, m), np.float32), Qt=np.zeros((n, m), np.float32),
+                 C=np.zeros((n, m), np.float32), sum=np.zeros((n, m), np.uint64),
+                 cnt=np.zeros((n, m), np.uint32))
+        if n:
+            self._check(lib().rlc_dump_cells(self._h, n, *[d[k].ctypes.data for k in
+                                                          ("key", "ready", "node", "end", "Q", "Qt", "C", "sum", "cnt")]),
+                        "rlc_dump_cells")
+        return d
+
+    def rlc_dump_tree(self) -> dict:
+        N = self.N
+        nn = 2 * N - 1
+        d = dict(perm=np.zeros(N, np.uint32), left=np.zeros(max(N - 1, 1), np.uint32),
+                 right=np.zeros(max(N - 1, 1), np.uint32), parent=np.zeros(nn, np.uint32),
+                 first=np.zeros(nn, np.uint32), last=np.zeros(nn, np.uint32),
+                 rec=np.zeros((N, 16), np.float32))
+        self._check(lib().rlc_dump_tree(self._h, *[d[k].ctypes.data for k in
+                                                   ("perm", "left", "right", "parent", "first", "last", "rec")]),
+                    "rlc_dump_tree")
+        d["left"] = d["left"][:N - 1]
+        d["right"] = d["right"][:N - 1]
+        return d
+
+    def rlc_get_template(self):
+        node = np.zeros(RLC_MMAX, np.uint32)
+        end = np.zeros(RLC_MMAX, np.uint32)
+        m = np.zeros(1, np.uint32)
+        self._check(lib().rlc_get_template(self._h, node.ctypes.data, end.ctypes.data, m.ctypes.data),
+                    "rlc_get_template")
+        return node[:m[0]].copy(), end[:m[0]].copy()
+
+    def rlc_set_timing(self, enable: bool):
+        self._check(lib().rlc_set_timing(self._h, 1 if enable else 0), "rlc_set_timing")
+
+    def rlc_get_timing(self):
+        f = np.zeros(1, np.float64)
+        a = np.zeros(1, np.float64)
+        n = np.zeros(1, np.uint32)
+        self._check(lib().rlc_get_timing(self._h, f.ctypes.data, a.ctypes.data, n.ctypes.data), "rlc_get_timing")
+        return float(f[0]), float(a[0]), int(n[0])
