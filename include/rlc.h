@@ -98,6 +98,10 @@ int rlc_destroy(rlc_ctx* ctx);
  * of min(M, N) nodes.  Resets every cell.  Synchronises (validates input). */
 int rlc_build_light_tree(rlc_ctx* ctx, const float* d_tri, const float* d_emit, uint32_t N);
 
+/* Forget every cell (keys, cuts, Q, statistics): the next pass starts from
+ * the initial cut everywhere, as after rlc_build_light_tree. */
+int rlc_reset_cells(rlc_ctx* ctx);
+
 /* Replace the emission of every light (d_emit: N x 3, input order); the tree
  * and the cuts are kept.  Used for animated lights. */
 int rlc_set_emission(rlc_ctx* ctx, const float* d_emit, uint32_t N);

@@ -410,6 +410,11 @@ int rlc_build_light_tree(rlc_ctx* c, const float* d_tri, const float* d_emit, ui
     return RLC_OK;
 }
 
+int rlc_reset_cells(rlc_ctx* c) {
+    if (!c) return RLC_EINVAL;
+    return reset_cells(c);
+}
+
 int rlc_set_emission(rlc_ctx* c, const float* d_emit, uint32_t N) {
     RLC_TRY(need_tree(c));
     if (!d_emit) return fail(c, RLC_EINVAL, "null emission array");

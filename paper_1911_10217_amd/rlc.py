@@ -29,7 +29,8 @@ _ERRNAMES = {RLC_EINVAL: "RLC_EINVAL", RLC_ENOMEM: "RLC_ENOMEM", RLC_EHIP: "RLC_
 
 # every entry point declared in include/rlc.h
 EXPORTS = (
-    "rlc_create", "rlc_destroy", "rlc_build_light_tree", "rlc_set_emission", "rlc_set_occluders",
+    "rlc_create", "rlc_destroy", "rlc_build_light_tree", "rlc_reset_cells", "rlc_set_emission",
+    "rlc_set_occluders",
     "rlc_sample", "rlc_shade", "rlc_learn", "rlc_adapt_cuts", "rlc_frame", "rlc_visible",
     "rlc_cell_keys", "rlc_image_error", "rlc_sync", "rlc_last_error", "rlc_num_cells", "rlc_meff",
     "rlc_dump_cells", "rlc_dump_tree", "rlc_get_template", "rlc_set_timing", "rlc_get_timing",
@@ -96,6 +97,7 @@ def _declare(L):
     L.rlc_create.argtypes = [ctypes.POINTER(rlc_config), _vp, ctypes.POINTER(_vp)]
     L.rlc_destroy.argtypes = [_vp]
     L.rlc_build_light_tree.argtypes = [_vp, _vp, _vp, _u32]
+    L.rlc_reset_cells.argtypes = [_vp]
     L.rlc_set_emission.argtypes = [_vp, _vp, _u32]
     L.rlc_set_occluders.argtypes = [_vp, _vp, _u32]
     L.rlc_sample.argtypes = [_vp, _vp, _vp, _u32, _u32, _u32, ctypes.POINTER(rlc_samples)]
@@ -217,6 +219,9 @@ class Context:
             raise ValueError("tri must be N x 9 and emit N x 3")
         self._check(lib().rlc_build_light_tree(self._h, _ptr(tri), _ptr(emit), N), "rlc_build_light_tree")
         self.N = N
+
+    def rlc_reset_cells(self):
+        self._check(lib().rlc_reset_cells(self._h), "rlc_reset_cells")
 
     def rlc_set_emission(self, emit):
         import torch

@@ -14,10 +14,14 @@ scenes stand in for them:
                  64 random boxes; an 8^3 dense grid, cut size 16, 16 spp,
                  8 static frames.
 * ``static``   - 65,536 triangles in 256 Gaussian clusters (sigma 0.02) under
-                 the ceiling of a unit room, 4,096 box occluders, and the
-                 1920x1080 primary hits of a pinhole camera in that room;
-                 64^3 hashed cells, cut size 64, 1 spp, 32 frames.  The room
-                 full of boxes plays the visibility-dominated interior.
+                 the ceiling of a unit room and 4,096 box occluders: 3,456
+                 cluttering the floor, 384 louvres just below the lights (the
+                 lights are seen only through the gaps between them) and 256
+                 in mid-air; the shading points are the 1920x1080 primary hits
+                 of a pinhole camera looking down across the room (about
+                 5,800 cells of the 64^3 hashed grid).  Cut size 64, 1 spp,
+                 32 frames.  It plays the paper's visibility-dominated
+                 interior lit through small openings.
 * ``dynamic``  - 16 walled compartments (4x4), each with its own cluster of
                  65,536 triangles under its ceiling (1,048,576 in total),
                  1,048,576 points on floors and walls, 16,384 wall bricks;
@@ -59,6 +63,7 @@ DEFAULT_PARAMS = dict(
     temporal=1,
     scene_id=0,
     seed=SEED_BASE + 1,
+    occ_grid_res=0,
     spp=1,
     frames=1,
 )
@@ -137,26 +142,32 @@ def make_tiny(n_lights=1024, n_points=4096, n_boxes=64, M=16, spp=16, frames=8,
 # --------------------------------------------------------------------------
 # Primary hits of a pinhole camera in a unit room with box occluders.
 # --------------------------------------------------------------------------
-def _primary_hits(boxes: np.ndarray, width: int, height: int, cam=(0.5, 0.45, 0.02),
-                  vfov_deg=60.0, room_lo=(0.0, 0.0, 0.0), room_hi=(1.0, 1.0, 1.0),
-                  extra_walls=None):
-    """Cast one ray through every pixel centre, camera looking down +z.
+def _primary_hits(boxes: np.ndarray, width: int, height: int, cam=(0.5, 0.45, 0.02), look=None,
+                  vfov_deg=60.0, room_lo=(0.0, 0.0, 0.0), room_hi=(1.0, 1.0, 1.0)):
+    """Cast one ray through every pixel centre of a pinhole camera at `cam`
+    looking at `look` (default: along +z), +y up.
 
     Returns float32 positions snapped onto the face that was hit and the
     axis-aligned face normal pointing back towards the camera.  Pixels are in
     row-major order, top row first.
     """
     o = np.asarray(cam, dtype=np.float64)
+    fwd = (np.asarray(look, np.float64) - o) if look is not None else np.array([0.0, 0.0, 1.0])
+    fwd /= np.linalg.norm(fwd)
+    right = np.cross(fwd, np.array([0.0, 1.0, 0.0]))
+    right /= np.linalg.norm(right)
+    up = np.cross(right, fwd)
     tan_h = math.tan(math.radians(vfov_deg) * 0.5)
     aspect = width / height
     px = (np.arange(width) + 0.5) / width * 2.0 - 1.0
     py = 1.0 - (np.arange(height) + 0.5) / height * 2.0
-    dx = np.broadcast_to(px[None, :] * tan_h * aspect, (height, width)).reshape(-1)
-    dy = np.broadcast_to(py[:, None] * tan_h, (height, width)).reshape(-1)
-    d = np.stack([dx, dy, np.ones_like(dx)], axis=1)
+    sx = np.broadcast_to(px[None, :] * tan_h * aspect, (height, width)).reshape(-1)
+    sy = np.broadcast_to(py[:, None] * tan_h, (height, width)).reshape(-1)
+    d = sx[:, None] * right[None, :] + sy[:, None] * up[None, :] + fwd[None, :]
     d /= np.linalg.norm(d, axis=1, keepdims=True)
     n_pix = d.shape[0]
-    inv = 1.0 / d
+    with np.errstate(divide="ignore"):
+        inv = 1.0 / d
 
     # room walls (inside faces); the camera is inside the room
     lo = np.asarray(room_lo, np.float64)
@@ -176,40 +187,46 @@ def _primary_hits(boxes: np.ndarray, width: int, height: int, cam=(0.5, 0.45, 0.
 
     # boxes: test each box against the pixels inside its screen-space bound
     bx = boxes.astype(np.float64)
-    if extra_walls is not None:
-        bx = np.concatenate([bx, extra_walls.astype(np.float64)], axis=0)
     corners = np.stack([np.stack([bx[:, 0 if (c & 1) == 0 else 3],
                                   bx[:, 1 if (c & 2) == 0 else 4],
                                   bx[:, 2 if (c & 4) == 0 else 5]], axis=1) for c in range(8)], axis=1)
     rel = corners - o[None, None, :]
-    zc = rel[:, :, 2]
-    front = np.all(zc > 1e-6, axis=1)
-    for b in np.nonzero(front)[0]:
-        sx = rel[b, :, 0] / zc[b] / (tan_h * aspect)
-        sy = rel[b, :, 1] / zc[b] / tan_h
-        c0 = int(max(0, math.floor((sx.min() + 1.0) * 0.5 * width) - 1))
-        c1 = int(min(width, math.ceil((sx.max() + 1.0) * 0.5 * width) + 1))
-        r0 = int(max(0, math.floor((1.0 - sy.max()) * 0.5 * height) - 1))
-        r1 = int(min(height, math.ceil((1.0 - sy.min()) * 0.5 * height) + 1))
-        if c0 >= c1 or r0 >= r1:
-            continue
-        idx = (np.arange(r0, r1)[:, None] * width + np.arange(c0, c1)[None, :]).reshape(-1)
+    zc = rel @ fwd
+    xc = rel @ right
+    yc = rel @ up
+    all_pix = np.arange(n_pix)
+    for b in range(bx.shape[0]):
+        if np.all(zc[b] <= 0):
+            continue  # behind the camera
+        if np.any(zc[b] <= 1e-6):
+            idx = all_pix
+        else:
+            qx = xc[b] / zc[b] / (tan_h * aspect)
+            qy = yc[b] / zc[b] / tan_h
+            c0 = int(max(0, math.floor((qx.min() + 1.0) * 0.5 * width) - 1))
+            c1 = int(min(width, math.ceil((qx.max() + 1.0) * 0.5 * width) + 1))
+            r0 = int(max(0, math.floor((1.0 - qy.max()) * 0.5 * height) - 1))
+            r1 = int(min(height, math.ceil((1.0 - qy.min()) * 0.5 * height) + 1))
+            if c0 >= c1 or r0 >= r1:
+                continue
+            idx = (np.arange(r0, r1)[:, None] * width + np.arange(c0, c1)[None, :]).reshape(-1)
         dd = d[idx]
         iv = inv[idx]
         tn = np.zeros(idx.size)
         tf = np.full(idx.size, np.inf)
         ax = np.zeros(idx.size, np.int64)
         pl = np.zeros(idx.size)
-        for a in range(3):
-            t0 = (bx[b, a] - o[a]) * iv[:, a]
-            t1 = (bx[b, 3 + a] - o[a]) * iv[:, a]
-            near = np.minimum(t0, t1)
-            enter_plane = np.where(dd[:, a] > 0, bx[b, a], bx[b, 3 + a])
-            upd = near > tn
-            tn = np.where(upd, near, tn)
-            ax = np.where(upd, a, ax)
-            pl = np.where(upd, enter_plane, pl)
-            tf = np.minimum(tf, np.maximum(t0, t1))
+        with np.errstate(invalid="ignore"):
+            for a in range(3):
+                t0 = (bx[b, a] - o[a]) * iv[:, a]
+                t1 = (bx[b, 3 + a] - o[a]) * iv[:, a]
+                near = np.minimum(t0, t1)
+                enter_plane = np.where(dd[:, a] > 0, bx[b, a], bx[b, 3 + a])
+                upd = near > tn
+                tn = np.where(upd, near, tn)
+                ax = np.where(upd, a, ax)
+                pl = np.where(upd, enter_plane, pl)
+                tf = np.minimum(tf, np.maximum(t0, t1))
         hit = (tn < tf) & (tn > 0) & (tn < t_best[idx])
         sel = idx[hit]
         t_best[sel] = tn[hit]
@@ -242,10 +259,17 @@ def make_static(width=1920, height=1080, n_clusters=256, per_cluster=256, n_boxe
     rng = np.random.default_rng(seed)
     tri, emit, _, _ = _clustered_lights(rng, n_clusters, per_cluster,
                                         [0.05, 0.90, 0.05], [0.95, 0.98, 0.95])
-    boxes = _random_boxes(rng, n_boxes, [0.0, 0.0, 0.1], [1.0, 0.85, 1.0])
-    pos, nrm = _primary_hits(boxes, width, height)
+    n_louvre = (n_boxes * 3) // 32
+    n_air = n_boxes // 16
+    n_floor = n_boxes - n_louvre - n_air
+    boxes = np.concatenate([
+        _random_boxes(rng, n_floor, [0.0, 0.0, 0.0], [1.0, 0.12, 1.0]),
+        _random_boxes(rng, n_louvre, [0.0, 0.78, 0.0], [1.0, 0.86, 1.0]),
+        _random_boxes(rng, n_air, [0.0, 0.15, 0.2], [1.0, 0.7, 1.0]),
+    ]).astype(np.float32)
+    pos, nrm = _primary_hits(boxes, width, height, cam=(0.1, 0.7, 0.05), look=(0.7, 0.1, 0.8))
     params = params_for(M=M, spp=spp, frames=frames, grid_dims=(64, 64, 64), hashed=1,
-                        capacity=capacity, seed=seed)
+                        capacity=capacity, seed=seed, occ_grid_res=64)
     params.update(overrides)
     return Scene("static", tri, emit, boxes, pos, nrm, params, image_size=(height, width))
 
