@@ -265,8 +265,8 @@ def main():
         "data": "synthetic",
         "config": {
             "workload": "static: 65,536 emissive triangles in 256 clusters, 2,073,600 primary hits "
-                        "(1920x1080), 4,096 box occluders in a 64^3 grid, 64^3 hashed cells, cut size 64, "
-                        "1 spp, passes from a fresh cell table",
+                        "(1920x1080, in 16x16 pixel tiles), 4,096 box occluders in a 64^3 grid, 64^3 hashed "
+                        "cells, cut size 64, 1 spp, passes from a fresh cell table",
             "samples_per_step": samples_per_step,
             "parallelism": "1 GPU",
         },

@@ -38,7 +38,7 @@ struct rlc_ctx {
     bool occ_set = false;
     uint32_t K = 0;
     float4* box = nullptr;
-    uint32_t* occ_off = nullptr;
+    uint32_t* occ_head = nullptr;
     uint32_t* occ_ref = nullptr;
     DevOcc occ{};
 
@@ -134,7 +134,7 @@ void free_tree(rlc_ctx* c) {
 
 void free_occ(rlc_ctx* c) {
     dfree(c->box);
-    dfree(c->occ_off);
+    dfree(c->occ_head);
     dfree(c->occ_ref);
     c->occ = DevOcc{};
     c->occ_set = false;
@@ -275,6 +275,7 @@ int rlc_create(const rlc_config* cfg, void* stream, rlc_ctx** out) {
         if (dense > (1u << 28)) return RLC_EINVAL;
         capacity = dense;
     }
+    if (capacity * (uint64_t)k.M >= 0xFFFFFFFFull) return RLC_EINVAL;  // (cell, cluster) bins index with 32 bits
     rlc_ctx* c = new (std::nothrow) rlc_ctx();
     if (!c) return RLC_ENOMEM;
     c->cfg = k;
@@ -458,35 +459,44 @@ int rlc_set_occluders(rlc_ctx* c, const float* d_aabb, uint32_t K) {
                 hi[a] = std::max(hi[a], hpart[3 * nb + 3 * p + a]);
             }
         }
-        float ext = std::max(hi[0] - lo[0], std::max(hi[1] - lo[1], hi[2] - lo[2]));
-        float margin = 1e-3f * ext + 1e-6f;
-        for (int a = 0; a < 3; ++a) {
-            o.glo[a] = lo[a] - margin;
-            o.gmax[a] = hi[a] + margin;
-            o.gcell[a] = (o.gmax[a] - o.glo[a]) / (float)o.res;
-            o.ginv[a] = (float)o.res / (o.gmax[a] - o.glo[a]);
-        }
-        size_t ncell = (size_t)o.res * o.res * o.res;
-        uint32_t* cursor = nullptr;
-        RLC_TRY(dalloc(c, &c->occ_off, ncell + 1));
-        RLC_TRY(dalloc(c, &cursor, ncell));
-        RLC_HIP(c, launch_fill_u32(c->occ_off, 0u, ncell + 1, c->stream));
-        RLC_HIP(c, launch_fill_u32(cursor, 0u, ncell, c->stream));
-        RLC_HIP(c, launch_occ_count(c->box, K, o, c->occ_off, c->stream));
-        RLC_HIP(c, launch_exclusive_scan(c->occ_off, (uint32_t)(ncell + 1), c->stream));
+        occ_grid_bounds(o, lo, hi, o.res);
+        const uint32_t ncell = o.res * o.res * o.res;
+        uint32_t *counts = nullptr, *start = nullptr, *cursor = nullptr;
+        r = dalloc(c, &counts, ncell);
+        if (r == RLC_OK) r = dalloc(c, &start, (size_t)ncell + 1);
+        if (r == RLC_OK) r = dalloc(c, &cursor, ncell);
+        if (r == RLC_OK) r = dalloc(c, &c->occ_head, ncell);
+        hipError_t e = hipSuccess;
+        auto step = [&](hipError_t x) {
+            if (e == hipSuccess) e = x;
+        };
         uint32_t total = 0;
-        RLC_HIP(c, hipMemcpyAsync(&total, c->occ_off + ncell, sizeof(uint32_t), hipMemcpyDeviceToHost, c->stream));
-        RLC_HIP(c, hipStreamSynchronize(c->stream));
-        r = dalloc(c, &c->occ_ref, total);
-        if (r != RLC_OK) {
-            dfree(cursor);
-            return r;
+        if (r == RLC_OK) {
+            step(launch_fill_u32(counts, 0u, ncell, c->stream));
+            step(launch_fill_u32(cursor, 0u, ncell, c->stream));
+            step(launch_occ_count(c->box, K, o, counts, c->stream));
+            step(launch_occ_sizes(counts, ncell, start, c->stream));
+            step(launch_exclusive_scan(start, ncell + 1, c->stream));
+            step(hipMemcpyAsync(&total, start + ncell, sizeof(uint32_t), hipMemcpyDeviceToHost, c->stream));
+            step(hipStreamSynchronize(c->stream));
         }
-        o.off = c->occ_off;
-        o.ref = c->occ_ref;
-        RLC_HIP(c, launch_occ_fill(c->box, K, o, c->occ_off, cursor, c->occ_ref, c->stream));
-        RLC_HIP(c, hipStreamSynchronize(c->stream));
+        if (r == RLC_OK && e == hipSuccess) {
+            if (total >= RLC_OCC_PAYLOAD || K > RLC_OCC_PAYLOAD)
+                r = fail(c, RLC_EINVAL, "too many occluder references for the grid (%u)", total);
+            else
+                r = dalloc(c, &c->occ_ref, total);
+        }
+        if (r == RLC_OK && e == hipSuccess) {
+            o.head = c->occ_head;
+            o.ref = c->occ_ref;
+            step(launch_occ_lists(c->box, K, o, counts, start, cursor, c->occ_head, c->occ_ref, c->stream));
+            step(hipStreamSynchronize(c->stream));
+        }
+        dfree(counts);
+        dfree(start);
         dfree(cursor);
+        if (r != RLC_OK) return r;
+        if (e != hipSuccess) return fail(c, RLC_EHIP, "occluder grid: %s", hipGetErrorString(e));
     }
     c->K = K;
     c->occ_set = true;

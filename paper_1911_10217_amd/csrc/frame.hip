@@ -19,12 +19,52 @@ __device__ __forceinline__ float group_sum(float v, uint32_t spp) {
 
 __device__ __forceinline__ bool pow2_le64(uint32_t spp) { return spp <= 64u && (spp & (spp - 1u)) == 0u; }
 
-__device__ __forceinline__ void scatter_stats(const FrameParams& fp, uint32_t cell, uint32_t s,
-                                              unsigned long long q) {
+// Per-block merge of the (cell, cluster) statistics before the global
+// atomics: the block's samples add their fixed-point reward and count into a
+// small LDS hash table keyed by bin = cell * M + cluster (integer sums, so
+// order-free), then each distinct bin is added to the cell table once.
+constexpr int kAggSlots = 2 * kBlock;
+constexpr uint32_t kNoBin = 0xFFFFFFFFu;
+
+struct AggTable {
+    uint32_t bin[kAggSlots];
+    unsigned long long sum[kAggSlots];
+    uint32_t cnt[kAggSlots];
+};
+
+__device__ __forceinline__ void agg_clear(AggTable& t) {
+    for (int j = threadIdx.x; j < kAggSlots; j += kBlock) {
+        t.bin[j] = kNoBin;
+        t.sum[j] = 0ull;
+        t.cnt[j] = 0u;
+    }
+}
+
+__device__ __forceinline__ void agg_add(AggTable& t, const FrameParams& fp, uint32_t cell, uint32_t s,
+                                        unsigned long long q) {
     if (cell == RLC_NONE) return;
-    size_t idx = (size_t)cell * fp.cells.M + s;
-    atomicAdd(&fp.cells.sum[idx], q);
-    atomicAdd(&fp.cells.cnt[idx], 1u);
+    const uint32_t bin = cell * fp.cells.M + s;
+    uint32_t h = (bin * 2654435761u) >> 23;  // 9-bit Fibonacci hash
+    for (int probe = 0; probe < kAggSlots; ++probe) {
+        const uint32_t old = atomicCAS(&t.bin[h], kNoBin, bin);
+        if (old == kNoBin || old == bin) {
+            atomicAdd(&t.sum[h], q);
+            atomicAdd(&t.cnt[h], 1u);
+            return;
+        }
+        h = (h + 1u) & (kAggSlots - 1);
+    }
+}
+
+__device__ __forceinline__ void agg_flush(const AggTable& t, const FrameParams& fp) {
+    for (int j = threadIdx.x; j < kAggSlots; j += kBlock) {
+        const uint32_t n = t.cnt[j];
+        if (n) {
+            const size_t idx = t.bin[j];
+            atomicAdd(&fp.cells.sum[idx], t.sum[j]);
+            atomicAdd(&fp.cells.cnt[idx], n);
+        }
+    }
 }
 
 __global__ void __launch_bounds__(kBlock) k_sample(FrameParams fp, const float* __restrict__ pos, uint32_t P,
@@ -110,16 +150,23 @@ __global__ void __launch_bounds__(kBlock) k_shade(FrameParams fp, const float* _
 
 __global__ void __launch_bounds__(kBlock) k_learn(FrameParams fp, rlc_samples in, const float* __restrict__ reward,
                                                   uint32_t n) {
+    __shared__ AggTable agg;
+    agg_clear(agg);
+    __syncthreads();
     uint32_t b = xcd_block(blockIdx.x, gridDim.x);
     size_t i = (size_t)b * kBlock + threadIdx.x;
-    if (i >= n) return;
-    scatter_stats(fp, in.d_cell[i], in.d_slot[i], reward_fixed(fp, reward[i]));
+    if (i < n) agg_add(agg, fp, in.d_cell[i], in.d_slot[i], reward_fixed(fp, reward[i]));
+    __syncthreads();
+    agg_flush(agg, fp);
 }
 
 // Fused pass: one lane per sample (point p = i / spp, sample k = i % spp).
 __global__ void __launch_bounds__(kBlock) k_frame(FrameParams fp, const float* __restrict__ pos,
                                                   const float* __restrict__ nrm, uint32_t P, uint32_t spp,
                                                   uint32_t frame, float* __restrict__ radiance) {
+    __shared__ AggTable agg;
+    agg_clear(agg);
+    __syncthreads();
     uint32_t b = xcd_block(blockIdx.x, gridDim.x);
     size_t i = (size_t)b * kBlock + threadIdx.x;
     size_t n = (size_t)P * spp;
@@ -140,8 +187,10 @@ __global__ void __launch_bounds__(kBlock) k_frame(FrameParams fp, const float* _
         e[2] = c[2] * sm.inv_pdf;
         float r = reward_of(fp, c, sm.size);
         if (!(r <= 3.402823466e38f)) atomicOr(fp.err, RLC_DERR_NONFINITE);
-        scatter_stats(fp, sm.cell, sm.s, reward_fixed(fp, r));
+        agg_add(agg, fp, sm.cell, sm.s, reward_fixed(fp, r));
     }
+    __syncthreads();
+    agg_flush(agg, fp);
     float inv_spp = 1.0f / (float)spp;
     if (pow2_le64(spp)) {
         e[0] = group_sum(e[0], spp);

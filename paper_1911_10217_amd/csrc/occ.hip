@@ -48,20 +48,6 @@ __global__ void __launch_bounds__(kBlock) k_pack_boxes(const float* __restrict__
         }
 }
 
-// Grid cells overlapped by box b grown by a margin of 1/1024 of a cell.
-__device__ __forceinline__ void box_cells(const DevOcc& occ, float4 b0, float4 b1, int lo[3], int hi[3]) {
-    const float bmin[3] = {b0.x, b0.y, b0.z};
-    const float bmax[3] = {b0.w, b1.x, b1.y};
-    const int res = (int)occ.res;
-    for (int a = 0; a < 3; ++a) {
-        float m = occ.gcell[a] * (1.0f / 1024.0f);
-        float f0 = floorf((bmin[a] - m - occ.glo[a]) * occ.ginv[a]);
-        float f1 = floorf((bmax[a] + m - occ.glo[a]) * occ.ginv[a]);
-        lo[a] = f0 < 0.0f ? 0 : (f0 >= (float)res ? res - 1 : (int)f0);
-        hi[a] = f1 < 0.0f ? 0 : (f1 >= (float)res ? res - 1 : (int)f1);
-    }
-}
-
 __global__ void __launch_bounds__(kBlock) k_occ_count(const float4* __restrict__ box, uint32_t K, DevOcc occ,
                                                       uint32_t* __restrict__ counts) {
     size_t i = (size_t)blockIdx.x * kBlock + threadIdx.x;
@@ -74,8 +60,33 @@ __global__ void __launch_bounds__(kBlock) k_occ_count(const float4* __restrict__
                 atomicAdd(&counts[(uint32_t)x + occ.res * ((uint32_t)y + occ.res * (uint32_t)z)], 1u);
 }
 
+// Space of cell c's list in ref: none for 0 or 1 box, count + indices otherwise.
+__global__ void __launch_bounds__(kBlock) k_occ_sizes(const uint32_t* __restrict__ counts, uint32_t ncell,
+                                                      uint32_t* __restrict__ sizes) {
+    size_t c = (size_t)blockIdx.x * kBlock + threadIdx.x;
+    if (c > ncell) return;
+    uint32_t n = c < ncell ? counts[c] : 0u;
+    sizes[c] = n >= 2u ? n + 1u : 0u;
+}
+
+__global__ void __launch_bounds__(kBlock) k_occ_heads(const uint32_t* __restrict__ counts,
+                                                      const uint32_t* __restrict__ start, uint32_t ncell,
+                                                      uint32_t* __restrict__ head, uint32_t* __restrict__ ref) {
+    size_t c = (size_t)blockIdx.x * kBlock + threadIdx.x;
+    if (c >= ncell) return;
+    uint32_t n = counts[c];
+    if (n >= 2u) {
+        head[c] = RLC_OCC_LIST | start[c];
+        ref[start[c]] = n;
+    } else {
+        head[c] = 0u;  // a single box writes its own header in k_occ_fill
+    }
+}
+
 __global__ void __launch_bounds__(kBlock) k_occ_fill(const float4* __restrict__ box, uint32_t K, DevOcc occ,
-                                                     const uint32_t* __restrict__ off, uint32_t* __restrict__ cursor,
+                                                     const uint32_t* __restrict__ counts,
+                                                     const uint32_t* __restrict__ start,
+                                                     uint32_t* __restrict__ cursor, uint32_t* __restrict__ head,
                                                      uint32_t* __restrict__ ref) {
     size_t i = (size_t)blockIdx.x * kBlock + threadIdx.x;
     if (i >= K) return;
@@ -85,7 +96,10 @@ __global__ void __launch_bounds__(kBlock) k_occ_fill(const float4* __restrict__ 
         for (int y = lo[1]; y <= hi[1]; ++y)
             for (int x = lo[0]; x <= hi[0]; ++x) {
                 uint32_t c = (uint32_t)x + occ.res * ((uint32_t)y + occ.res * (uint32_t)z);
-                ref[off[c] + atomicAdd(&cursor[c], 1u)] = (uint32_t)i;
+                if (counts[c] == 1u)
+                    head[c] = RLC_OCC_ONE | (uint32_t)i;
+                else
+                    ref[start[c] + 1u + atomicAdd(&cursor[c], 1u)] = (uint32_t)i;
             }
 }
 
@@ -115,10 +129,18 @@ hipError_t launch_occ_count(const float4* box, uint32_t K, DevOcc occ, uint32_t*
     return hipGetLastError();
 }
 
-hipError_t launch_occ_fill(const float4* box, uint32_t K, DevOcc occ, const uint32_t* off, uint32_t* cursor,
-                           uint32_t* ref, hipStream_t s) {
+hipError_t launch_occ_lists(const float4* box, uint32_t K, DevOcc occ, const uint32_t* counts, uint32_t* start,
+                            uint32_t* cursor, uint32_t* head, uint32_t* ref, hipStream_t s) {
     if (K == 0) return hipSuccess;
-    hipLaunchKernelGGL(k_occ_fill, dim3(blocks_for(K)), dim3(kBlock), 0, s, box, K, occ, off, cursor, ref);
+    const uint32_t ncell = occ.res * occ.res * occ.res;
+    hipLaunchKernelGGL(k_occ_heads, dim3(blocks_for(ncell)), dim3(kBlock), 0, s, counts, start, ncell, head, ref);
+    hipLaunchKernelGGL(k_occ_fill, dim3(blocks_for(K)), dim3(kBlock), 0, s, box, K, occ, counts, start, cursor, head,
+                       ref);
+    return hipGetLastError();
+}
+
+hipError_t launch_occ_sizes(const uint32_t* counts, uint32_t ncell, uint32_t* sizes, hipStream_t s) {
+    hipLaunchKernelGGL(k_occ_sizes, dim3(blocks_for((size_t)ncell + 1)), dim3(kBlock), 0, s, counts, ncell, sizes);
     return hipGetLastError();
 }
 

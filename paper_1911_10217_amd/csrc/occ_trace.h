@@ -1,0 +1,247 @@
+// Shadow-ray visibility against axis-aligned boxes: the slab test and the
+// uniform-grid walk.  Compiled for the device (frame and occluder kernels)
+// and for the host (the CPU check of the grid walk), so everything here is
+// __host__ __device__ and free of device intrinsics.
+//
+// The answer of a shadow ray is defined box by box: the segment x + t d,
+// t in (t_lo, 1 - t_lo), is blocked by a box when the slab intervals
+// intersect with tn < tf strictly, an axis with d = 0 either excluding the
+// box (origin outside the slab) or not constraining it.  The grid only
+// decides which boxes a ray tests; it never changes that answer.
+#pragma once
+
+#include <hip/hip_runtime.h>
+#include <math.h>
+#include <stdint.h>
+
+namespace rlc {
+
+// Box b of the occluder set is stored as two float4: {min.xyz, max.x} and
+// {max.yz, 0, 0}.  Grid cell c has a 32-bit header head[c]: 0 when no box
+// overlaps it; RLC_OCC_ONE | b when box b is the only one; RLC_OCC_LIST | s
+// when several do, their count at ref[s] and their indices at ref[s + 1..].
+#define RLC_OCC_ONE 0x40000000u
+#define RLC_OCC_LIST 0x80000000u
+#define RLC_OCC_PAYLOAD 0x3FFFFFFFu
+
+struct DevOcc {
+    const float4* box;
+    const uint32_t* head;       // res^3 cell headers
+    const uint32_t* ref;        // box lists of cells holding two or more boxes
+    uint32_t K;
+    uint32_t res;               // 0: test every box
+    float glo[3];               // grid box, slightly larger than the boxes' union
+    float gcell[3];             // grid cell size
+    float ginv[3];              // res / extent
+    float gmax[3];
+};
+
+// Grid box and cell size for boxes whose union spans [lo, hi]: the union
+// grown by 1/1000 of its largest extent, cut into res^3 cells.
+__host__ __device__ inline void occ_grid_bounds(DevOcc& o, const float lo[3], const float hi[3], uint32_t res) {
+    float ext = fmaxf(hi[0] - lo[0], fmaxf(hi[1] - lo[1], hi[2] - lo[2]));
+    float margin = 1e-3f * ext + 1e-6f;
+    o.res = res;
+    for (int a = 0; a < 3; ++a) {
+        o.glo[a] = lo[a] - margin;
+        o.gmax[a] = hi[a] + margin;
+        o.gcell[a] = (o.gmax[a] - o.glo[a]) / (float)res;
+        o.ginv[a] = (float)res / (o.gmax[a] - o.glo[a]);
+    }
+}
+
+// Box test as defined (any direction, including d_a = 0 and subnormal d_a).
+__host__ __device__ inline bool box_blocks_def(const float4 b0, const float4 b1, const float o[3],
+                                               const float d[3], const float invd[3], float t_lo) {
+    const float bmin[3] = {b0.x, b0.y, b0.z};
+    const float bmax[3] = {b0.w, b1.x, b1.y};
+    float tn = t_lo;
+    float tf = 1.0f - t_lo;
+    for (int a = 0; a < 3; ++a) {
+        if (d[a] == 0.0f) {
+            if (o[a] < bmin[a] || o[a] > bmax[a]) return false;
+            continue;
+        }
+        float t0 = (bmin[a] - o[a]) * invd[a];
+        float t1 = (bmax[a] - o[a]) * invd[a];
+        float tmin = t0 < t1 ? t0 : t1;
+        float tmax = t0 < t1 ? t1 : t0;
+        if (tmin > tn) tn = tmin;
+        if (tmax < tf) tf = tmax;
+    }
+    return tn < tf;
+}
+
+// The same test, branch-free, for rays whose three direction components are
+// normal numbers: then 1/d is finite and non-zero, no interval bound is NaN,
+// and min/max give the interval ends the definition picks (up to the sign
+// of a zero, which no comparison sees).
+__host__ __device__ inline bool box_blocks_fast(const float4 b0, const float4 b1, const float o[3],
+                                                const float invd[3], float tn0, float tf0) {
+    float t0x = (b0.x - o[0]) * invd[0], t1x = (b0.w - o[0]) * invd[0];
+    float t0y = (b0.y - o[1]) * invd[1], t1y = (b1.x - o[1]) * invd[1];
+    float t0z = (b0.z - o[2]) * invd[2], t1z = (b1.y - o[2]) * invd[2];
+    float tn = fmaxf(fmaxf(tn0, fminf(t0x, t1x)), fmaxf(fminf(t0y, t1y), fminf(t0z, t1z)));
+    float tf = fminf(fminf(tf0, fmaxf(t0x, t1x)), fminf(fmaxf(t0y, t1y), fmaxf(t0z, t1z)));
+    return tn < tf;
+}
+
+__host__ __device__ inline bool normal_dir(const float d[3]) {
+    const float tiny = 1.17549435e-38f;  // smallest normal float
+    return fabsf(d[0]) >= tiny && fabsf(d[1]) >= tiny && fabsf(d[2]) >= tiny;
+}
+
+template <bool FAST>
+__host__ __device__ inline bool test_box(const DevOcc& occ, uint32_t b, const float o[3], const float d[3],
+                                         const float invd[3], float t_lo) {
+    const float4 b0 = occ.box[2 * b], b1 = occ.box[2 * b + 1];
+    if (FAST) return box_blocks_fast(b0, b1, o, invd, t_lo, 1.0f - t_lo);
+    return box_blocks_def(b0, b1, o, d, invd, t_lo);
+}
+
+// Grid cells overlapped by a box grown by 1/256 of a cell on every side, so
+// that a walk whose cell boundaries are off by rounding still lists it.
+__host__ __device__ inline void box_cells(const DevOcc& occ, float4 b0, float4 b1, int lo[3], int hi[3]) {
+    const float bmin[3] = {b0.x, b0.y, b0.z};
+    const float bmax[3] = {b0.w, b1.x, b1.y};
+    const int res = (int)occ.res;
+    for (int a = 0; a < 3; ++a) {
+        float m = occ.gcell[a] * (1.0f / 256.0f);
+        float f0 = floorf((bmin[a] - m - occ.glo[a]) * occ.ginv[a]);
+        float f1 = floorf((bmax[a] + m - occ.glo[a]) * occ.ginv[a]);
+        lo[a] = f0 < 0.0f ? 0 : (f0 >= (float)res ? res - 1 : (int)f0);
+        hi[a] = f1 < 0.0f ? 0 : (f1 >= (float)res ? res - 1 : (int)f1);
+    }
+}
+
+template <bool FAST>
+__host__ __device__ inline bool blocked_brute(const DevOcc& occ, const float o[3], const float d[3],
+                                              const float invd[3], float t_lo) {
+    for (uint32_t b = 0; b < occ.K; ++b)
+        if (test_box<FAST>(occ, b, o, d, invd, t_lo)) return true;
+    return false;
+}
+
+// Test the boxes listed in one grid cell (header h).  Two mailbox slots
+// skip a box that was just tested in a previous cell.
+template <bool FAST>
+__host__ __device__ inline bool cell_blocks(const DevOcc& occ, uint32_t h, uint32_t& last0, uint32_t& last1,
+                                            const float o[3], const float d[3], const float invd[3], float t_lo) {
+    if (h & RLC_OCC_ONE) {
+        const uint32_t b = h & RLC_OCC_PAYLOAD;
+        if (b == last0 || b == last1) return false;
+        last1 = last0;
+        last0 = b;
+        return test_box<FAST>(occ, b, o, d, invd, t_lo);
+    }
+    if (h & RLC_OCC_LIST) {
+        const uint32_t s0 = h & RLC_OCC_PAYLOAD;
+        const uint32_t n = occ.ref[s0];
+        for (uint32_t j = 1; j <= n; ++j) {
+            const uint32_t b = occ.ref[s0 + j];
+            if (b == last0 || b == last1) continue;
+            last1 = last0;
+            last0 = b;
+            if (test_box<FAST>(occ, b, o, d, invd, t_lo)) return true;
+        }
+    }
+    return false;
+}
+
+// Walk the grid cells the segment crosses, in order (3-D DDA,
+// Amanatides-Woo).  The parameter of the next boundary along each axis grows
+// by the cell size over |d| per step; boxes are listed in cells grown by
+// 1/256 of a cell, which covers the accumulated rounding of that sum (at
+// most 3 res steps of half an ulp of t).  Each axis counts the cells left
+// before the walk leaves the grid.
+template <bool FAST>
+__host__ __device__ inline bool blocked_grid(const DevOcc& occ, const float o[3], const float d[3],
+                                             const float invd[3], float t_lo) {
+    float t0 = t_lo, t1 = 1.0f - t_lo;
+    for (int a = 0; a < 3; ++a) {
+        if (d[a] == 0.0f) {
+            if (o[a] < occ.glo[a] || o[a] > occ.gmax[a]) return false;
+            continue;
+        }
+        float ta = (occ.glo[a] - o[a]) * invd[a];
+        float tb = (occ.gmax[a] - o[a]) * invd[a];
+        float lo = ta < tb ? ta : tb;
+        float hi = ta < tb ? tb : ta;
+        t0 = lo > t0 ? lo : t0;
+        t1 = hi < t1 ? hi : t1;
+    }
+    if (!(t0 <= t1)) return false;
+    const int res = (int)occ.res;
+    float tx, ty, tz, dtx, dty, dtz;
+    int rx, ry, rz, sx, sy, sz;
+    int lin = 0;
+    {
+        int c[3];
+        float tn[3], dt[3];
+        int rem[3], st[3];
+        for (int a = 0; a < 3; ++a) {
+            float p = o[a] + t0 * d[a];
+            float f = floorf((p - occ.glo[a]) * occ.ginv[a]);
+            c[a] = f < 0.0f ? 0 : (f >= (float)res ? res - 1 : (int)f);
+            if (d[a] == 0.0f) {
+                tn[a] = 3.0e38f;
+                dt[a] = 0.0f;
+                rem[a] = 0;
+                st[a] = 0;
+            } else {
+                const bool up = d[a] > 0.0f;
+                const float bound = occ.glo[a] + (float)(c[a] + (up ? 1 : 0)) * occ.gcell[a];
+                tn[a] = (bound - o[a]) * invd[a];
+                dt[a] = occ.gcell[a] * fabsf(invd[a]);
+                rem[a] = up ? res - 1 - c[a] : c[a];
+                st[a] = up ? 1 : -1;
+            }
+        }
+        lin = c[0] + res * (c[1] + res * c[2]);
+        tx = tn[0];
+        ty = tn[1];
+        tz = tn[2];
+        dtx = dt[0];
+        dty = dt[1];
+        dtz = dt[2];
+        rx = rem[0];
+        ry = rem[1];
+        rz = rem[2];
+        sx = st[0];
+        sy = st[1] * res;
+        sz = st[2] * res * res;
+    }
+    uint32_t last0 = 0xFFFFFFFFu, last1 = 0xFFFFFFFFu;
+    const int max_steps = 3 * res + 3;
+    for (int it = 0; it < max_steps; ++it) {
+        if (cell_blocks<FAST>(occ, occ.head[lin], last0, last1, o, d, invd, t_lo)) return true;
+        const bool ax = tx <= ty && tx <= tz;
+        const bool ay = !ax && ty <= tz;
+        const float tm = ax ? tx : (ay ? ty : tz);
+        const int rm = ax ? rx : (ay ? ry : rz);
+        if (tm > t1 || rm == 0) return false;
+        lin += ax ? sx : (ay ? sy : sz);
+        if (ax) {
+            tx += dtx;
+            --rx;
+        } else if (ay) {
+            ty += dty;
+            --ry;
+        } else {
+            tz += dtz;
+            --rz;
+        }
+    }
+    return false;
+}
+
+// Is the segment o -> o + d blocked over t in (t_lo, 1 - t_lo)?
+__host__ __device__ inline bool segment_blocked(const DevOcc& occ, const float o[3], const float d[3], float t_lo) {
+    if (occ.K == 0) return false;
+    const float invd[3] = {1.0f / d[0], 1.0f / d[1], 1.0f / d[2]};
+    if (normal_dir(d))
+        return occ.res ? blocked_grid<true>(occ, o, d, invd, t_lo) : blocked_brute<true>(occ, o, d, invd, t_lo);
+    return occ.res ? blocked_grid<false>(occ, o, d, invd, t_lo) : blocked_brute<false>(occ, o, d, invd, t_lo);
+}
+
+}  // namespace rlc

@@ -7,6 +7,7 @@
 #include <stdint.h>
 
 #include "rlc.h"
+#include "occ_trace.h"
 
 #define RLC_NONE 0xFFFFFFFFu
 #define RLC_EMPTY_KEY 0xFFFFFFFFFFFFFFFFull
@@ -56,20 +57,6 @@ struct DevCells {
     uint32_t capacity;          // dense: cells of the grid; hashed: 2^k
     uint32_t hashed;
     uint32_t M;                 // row stride
-};
-
-// Occluders: box b is {min.xyz, max.x} {max.yz, 0, 0}.  With a grid,
-// off[res^3 + 1] / ref[] list the boxes overlapping each grid cell.
-struct DevOcc {
-    const float4* box;
-    const uint32_t* off;
-    const uint32_t* ref;
-    uint32_t K;
-    uint32_t res;               // 0: brute force over all boxes
-    float glo[3];
-    float gcell[3];             // grid cell size
-    float ginv[3];              // res / extent
-    float gmax[3];
 };
 
 struct FrameParams {
@@ -156,12 +143,15 @@ __device__ __forceinline__ unsigned long long mix64(unsigned long long x) {
 
 // Find the table slot of a cell key, creating the cell if it is absent.
 // Creation only claims the slot and records it in the live list; the cell's
-// own table is filled at the end of the pass.
+// own table is filled at the end of the pass.  A slot's key changes once,
+// from empty to its key, by compare-and-swap, so the probe reads it with a
+// plain (cached) load: a stale "empty" only sends the lane to the CAS, whose
+// returned value is current.
 __device__ __forceinline__ uint32_t find_or_create(const DevCells& c, unsigned long long key, uint32_t lin,
                                                    uint32_t* err) {
     if (!c.hashed) {
         if (lin >= c.capacity) return RLC_NONE;
-        unsigned long long k = __atomic_load_n(&c.keys[lin], __ATOMIC_RELAXED);
+        unsigned long long k = c.keys[lin];
         if (k != key) {
             unsigned long long old = atomicCAS(&c.keys[lin], RLC_EMPTY_KEY, key);
             if (old == RLC_EMPTY_KEY) c.live[atomicAdd(c.n_live, 1u)] = lin;
@@ -171,7 +161,7 @@ __device__ __forceinline__ uint32_t find_or_create(const DevCells& c, unsigned l
     uint32_t mask = c.capacity - 1u;
     uint32_t h = (uint32_t)mix64(key) & mask;
     for (uint32_t probe = 0; probe < c.capacity; ++probe) {
-        unsigned long long k = __atomic_load_n(&c.keys[h], __ATOMIC_RELAXED);
+        unsigned long long k = c.keys[h];
         if (k == key) return h;
         if (k == RLC_EMPTY_KEY) {
             unsigned long long old = atomicCAS(&c.keys[h], RLC_EMPTY_KEY, key);
@@ -185,103 +175,6 @@ __device__ __forceinline__ uint32_t find_or_create(const DevCells& c, unsigned l
     }
     atomicOr(err, RLC_DERR_CAPACITY);
     return RLC_NONE;
-}
-
-// ---------------------------------------------------------------------------
-// Shadow rays
-// ---------------------------------------------------------------------------
-__device__ __forceinline__ bool box_blocks(const float4 b0, const float4 b1, const float o[3], const float d[3],
-                                           const float invd[3], float t_lo) {
-    const float bmin[3] = {b0.x, b0.y, b0.z};
-    const float bmax[3] = {b0.w, b1.x, b1.y};
-    float tn = t_lo;
-    float tf = 1.0f - t_lo;
-#pragma unroll
-    for (int a = 0; a < 3; ++a) {
-        if (d[a] == 0.0f) {
-            if (o[a] < bmin[a] || o[a] > bmax[a]) return false;
-            continue;
-        }
-        float t0 = (bmin[a] - o[a]) * invd[a];
-        float t1 = (bmax[a] - o[a]) * invd[a];
-        float tmin = t0 < t1 ? t0 : t1;
-        float tmax = t0 < t1 ? t1 : t0;
-        if (tmin > tn) tn = tmin;
-        if (tmax < tf) tf = tmax;
-    }
-    return tn < tf;
-}
-
-__device__ __forceinline__ bool blocked_brute(const DevOcc& occ, const float o[3], const float d[3],
-                                              const float invd[3], float t_lo) {
-    for (uint32_t b = 0; b < occ.K; ++b) {
-        if (box_blocks(occ.box[2 * b], occ.box[2 * b + 1], o, d, invd, t_lo)) return true;
-    }
-    return false;
-}
-
-// Grid walk (3-D DDA over the cells the segment crosses, in order).  Boxes
-// are listed in every grid cell that overlaps the box grown by a small
-// margin, so cells missed by rounding at cell corners are covered.
-__device__ __forceinline__ bool blocked_grid(const DevOcc& occ, const float o[3], const float d[3],
-                                             const float invd[3], float t_lo) {
-    float t0 = t_lo, t1 = 1.0f - t_lo;
-#pragma unroll
-    for (int a = 0; a < 3; ++a) {
-        if (d[a] == 0.0f) {
-            if (o[a] < occ.glo[a] || o[a] > occ.gmax[a]) return false;
-            continue;
-        }
-        float ta = (occ.glo[a] - o[a]) * invd[a];
-        float tb = (occ.gmax[a] - o[a]) * invd[a];
-        float lo = ta < tb ? ta : tb;
-        float hi = ta < tb ? tb : ta;
-        t0 = lo > t0 ? lo : t0;
-        t1 = hi < t1 ? hi : t1;
-    }
-    if (!(t0 <= t1)) return false;
-    const int res = (int)occ.res;
-    int c[3], step[3];
-#pragma unroll
-    for (int a = 0; a < 3; ++a) {
-        float p = o[a] + t0 * d[a];
-        float f = floorf((p - occ.glo[a]) * occ.ginv[a]);
-        int ci = f < 0.0f ? 0 : (f >= (float)res ? res - 1 : (int)f);
-        c[a] = ci;
-        step[a] = d[a] > 0.0f ? 1 : (d[a] < 0.0f ? -1 : 0);
-    }
-    const int max_steps = 3 * res + 3;
-    for (int it = 0; it < max_steps; ++it) {
-        uint32_t cell = (uint32_t)c[0] + occ.res * ((uint32_t)c[1] + occ.res * (uint32_t)c[2]);
-        uint32_t b0 = occ.off[cell], b1 = occ.off[cell + 1];
-        for (uint32_t j = b0; j < b1; ++j) {
-            uint32_t b = occ.ref[j];
-            if (box_blocks(occ.box[2 * b], occ.box[2 * b + 1], o, d, invd, t_lo)) return true;
-        }
-        // next cell boundary along each axis
-        float tnext = 3.0e38f;
-        int axis = -1;
-#pragma unroll
-        for (int a = 0; a < 3; ++a) {
-            if (step[a] == 0) continue;
-            float bound = occ.glo[a] + (float)(c[a] + (step[a] > 0 ? 1 : 0)) * occ.gcell[a];
-            float tb = (bound - o[a]) * invd[a];
-            if (tb < tnext) {
-                tnext = tb;
-                axis = a;
-            }
-        }
-        if (axis < 0 || tnext > t1) return false;
-        c[axis] += step[axis];
-        if (c[axis] < 0 || c[axis] >= res) return false;
-    }
-    return false;
-}
-
-__device__ __forceinline__ bool segment_blocked(const DevOcc& occ, const float o[3], const float d[3], float t_lo) {
-    if (occ.K == 0) return false;
-    float invd[3] = {1.0f / d[0], 1.0f / d[1], 1.0f / d[2]};
-    return occ.res ? blocked_grid(occ, o, d, invd, t_lo) : blocked_brute(occ, o, d, invd, t_lo);
 }
 
 // ---------------------------------------------------------------------------
@@ -443,8 +336,9 @@ hipError_t launch_fill_u64(unsigned long long* a, unsigned long long v, size_t n
 hipError_t launch_pack_boxes(const float* aabb, uint32_t K, float4* box, float* part_lo, float* part_hi,
                              uint32_t nblocks, uint32_t* err, hipStream_t s);
 hipError_t launch_occ_count(const float4* box, uint32_t K, DevOcc occ, uint32_t* counts, hipStream_t s);
-hipError_t launch_occ_fill(const float4* box, uint32_t K, DevOcc occ, const uint32_t* off, uint32_t* cursor,
-                           uint32_t* ref, hipStream_t s);
+hipError_t launch_occ_sizes(const uint32_t* counts, uint32_t ncell, uint32_t* sizes, hipStream_t s);
+hipError_t launch_occ_lists(const float4* box, uint32_t K, DevOcc occ, const uint32_t* counts, uint32_t* start,
+                            uint32_t* cursor, uint32_t* head, uint32_t* ref, hipStream_t s);
 hipError_t launch_visible(DevOcc occ, float t_lo, const float* x, const float* y, uint32_t n, uint8_t* vis,
                           hipStream_t s);
 

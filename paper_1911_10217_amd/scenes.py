@@ -19,7 +19,8 @@ scenes stand in for them:
                  lights are seen only through the gaps between them) and 256
                  in mid-air; the shading points are the 1920x1080 primary hits
                  of a pinhole camera looking down across the room (about
-                 5,800 cells of the 64^3 hashed grid).  Cut size 64, 1 spp,
+                 5,800 cells of the 64^3 hashed grid), listed in 16x16 pixel
+                 tiles of 8x8 sub-tiles as a tiled renderer emits them.  Cut size 64, 1 spp,
                  32 frames.  It plays the paper's visibility-dominated
                  interior lit through small openings.
 * ``dynamic``  - 16 walled compartments (4x4), each with its own cluster of
@@ -80,6 +81,14 @@ class Scene:
     params: dict
     emission_at: Optional[Callable[[int], np.ndarray]] = None  # frame -> (N, 3)
     image_size: Optional[tuple] = None
+    pixel: Optional[np.ndarray] = None   # image position (row * width + col) of each point
+
+    def to_image(self, values: np.ndarray) -> np.ndarray:
+        """Per-point values (P, ...) laid out as the (height, width, ...) image."""
+        h, w = self.image_size
+        out = np.zeros((h * w,) + values.shape[1:], values.dtype)
+        out[self.pixel] = values
+        return out.reshape((h, w) + values.shape[1:])
 
     @property
     def N(self) -> int:
@@ -241,6 +250,15 @@ def _primary_hits(boxes: np.ndarray, width: int, height: int, cam=(0.5, 0.45, 0.
     return _f32(p), _f32(nrm)
 
 
+def tiled_pixel_order(width: int, height: int, tile: int = 16, sub: int = 8) -> np.ndarray:
+    """Row-major pixel indices reordered into tile x tile blocks made of
+    sub x sub blocks (the order a tiled renderer emits its primary hits in);
+    partial tiles at the right and bottom edges keep the same nesting."""
+    y, x = np.divmod(np.arange(width * height), width)
+    order = np.lexsort((x % sub, y % sub, (x % tile) // sub, (y % tile) // sub, x // tile, y // tile))
+    return order
+
+
 def _clustered_lights(rng, n_clusters, per_cluster, centre_lo, centre_hi, sigma=0.02, half=0.005):
     centres = rng.uniform(centre_lo, centre_hi, size=(n_clusters, 3))
     cen = centres[:, None, :] + sigma * rng.standard_normal((n_clusters, per_cluster, 3))
@@ -268,10 +286,12 @@ def make_static(width=1920, height=1080, n_clusters=256, per_cluster=256, n_boxe
         _random_boxes(rng, n_air, [0.0, 0.15, 0.2], [1.0, 0.7, 1.0]),
     ]).astype(np.float32)
     pos, nrm = _primary_hits(boxes, width, height, cam=(0.1, 0.7, 0.05), look=(0.7, 0.1, 0.8))
+    order = tiled_pixel_order(width, height)
     params = params_for(M=M, spp=spp, frames=frames, grid_dims=(64, 64, 64), hashed=1,
                         capacity=capacity, seed=seed, occ_grid_res=64)
     params.update(overrides)
-    return Scene("static", tri, emit, boxes, pos, nrm, params, image_size=(height, width))
+    return Scene("static", tri, emit, boxes, np.ascontiguousarray(pos[order]), np.ascontiguousarray(nrm[order]),
+                 params, image_size=(height, width), pixel=order.astype(np.int64))
 
 
 # --------------------------------------------------------------------------
