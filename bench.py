@@ -116,6 +116,8 @@ def main():
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=32)
     ap.add_argument("--warmup", type=int, default=3)
+    ap.add_argument("--workload", default="static", choices=("static", "dynamic"),
+                    help="static: the headline workload; dynamic: animated lights in walled compartments")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--cpu-stride", type=int, default=10, help="CPU baseline runs every n-th point")
     ap.add_argument("--copy-calib-mib", type=int, default=0,
@@ -145,8 +147,8 @@ def main():
     dev = torch.device("cuda:0")
     torch.cuda.set_device(dev)
 
-    print("[bench] generating the static workload", file=sys.stderr, flush=True)
-    s = scenes.make_static()
+    print("[bench] generating the %s workload" % args.workload, file=sys.stderr, flush=True)
+    s = scenes.make_static() if args.workload == "static" else scenes.make_dynamic()
     p = dict(s.params, occ_grid_res=64)
     spp = int(p["spp"])
     P = s.P
@@ -168,9 +170,20 @@ def main():
         torch.cuda.synchronize()
         del a, b
 
+    # animated lights: every pass's emission is resident on the device and
+    # set by rlc_set_emission inside the timed pass
+    emissions = None
+    if s.emission_at is not None:
+        emissions = [t(s.emission_at(f)) for f in range(max(args.steps, args.warmup) + 1)]
+
+    def one_pass(f):
+        if emissions is not None:
+            ctx.rlc_set_emission(emissions[f])
+        ctx.rlc_frame(pos, nrm, spp, f, radiance)
+
     print("[bench] warm-up: %d passes" % args.warmup, file=sys.stderr, flush=True)
     for f in range(args.warmup):
-        ctx.rlc_frame(pos, nrm, spp, f, radiance)
+        one_pass(f)
     ctx.rlc_sync()
 
     # ---- timed: passes 0..K-1 from a fresh cell table ----
@@ -180,7 +193,7 @@ def main():
     stop = torch.cuda.Event(enable_timing=True)
     start.record()
     for f in range(args.steps):
-        ctx.rlc_frame(pos, nrm, spp, f, radiance)
+        one_pass(f)
     stop.record()
     torch.cuda.synchronize()
     ctx.rlc_sync()
@@ -193,7 +206,7 @@ def main():
     ctx.rlc_reset_cells()
     ctx.rlc_set_timing(True)
     for f in range(args.steps):
-        ctx.rlc_frame(pos, nrm, spp, f, radiance)
+        one_pass(f)
     fused_ms, adapt_ms, nframes = ctx.rlc_get_timing()
     ctx.rlc_set_timing(False)
     fused_avg_ms = fused_ms / max(nframes, 1)
@@ -242,6 +255,8 @@ def main():
         print("[bench] CPU oracle: %d points x %d passes" % (sel.size, args.steps), file=sys.stderr, flush=True)
         t0 = time.perf_counter()
         for f in range(args.steps):
+            if s.emission_at is not None:
+                orc.set_emission(s.emission_at(f))
             orc.frame(s.pos[sel], s.nrm[sel], spp, f, pid=sel)
             orc.adapt()
         dt = time.perf_counter() - t0
@@ -250,6 +265,15 @@ def main():
                "sample": "every %dth point (%d of %d) for the same %d passes, single-threaded C oracle, %.1f s"
                          % (args.cpu_stride, sel.size, P, args.steps, dt)}
 
+    if args.workload == "static":
+        workload = ("static: 65,536 emissive triangles in 256 clusters, 2,073,600 primary hits "
+                    "(1920x1080, in 16x16 pixel tiles), 4,096 box occluders in a 64^3 grid, 64^3 hashed "
+                    "cells, cut size 64, 1 spp, passes from a fresh cell table")
+    else:
+        workload = ("dynamic: 1,048,576 emissive triangles in 16 walled compartments, emission "
+                    "Le (1 + sin(2 pi f t + phi)) per compartment set every pass, 1,048,576 points, "
+                    "16,384 wall bricks in a 64^3 grid, 64^3 hashed cells, cut size 64, 1 spp, "
+                    "temporal adaptation, passes from a fresh cell table")
     line = {
         "metric": METRIC,
         "value": round(value, 1),
@@ -264,9 +288,7 @@ def main():
         "dtype": "f32",
         "data": "synthetic",
         "config": {
-            "workload": "static: 65,536 emissive triangles in 256 clusters, 2,073,600 primary hits "
-                        "(1920x1080, in 16x16 pixel tiles), 4,096 box occluders in a 64^3 grid, 64^3 hashed "
-                        "cells, cut size 64, 1 spp, passes from a fresh cell table",
+            "workload": workload,
             "samples_per_step": samples_per_step,
             "parallelism": "1 GPU",
         },

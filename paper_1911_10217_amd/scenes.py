@@ -297,7 +297,7 @@ def make_static(width=1920, height=1080, n_clusters=256, per_cluster=256, n_boxe
 # --------------------------------------------------------------------------
 # dynamic: walled compartments, each with its own animated light
 # --------------------------------------------------------------------------
-def make_dynamic(n_points=1 << 20, per_cluster=65536, grid=4, bricks_per_axis=None, M=64, spp=1,
+def make_dynamic(n_points=1 << 20, per_cluster=65536, grid=4, n_bricks=16384, M=64, spp=1,
                  frames=60, seed=SEED_BASE + 3, capacity=1 << 19, **overrides) -> Scene:
     rng = np.random.default_rng(seed)
     n_comp = grid * grid
@@ -305,7 +305,8 @@ def make_dynamic(n_points=1 << 20, per_cluster=65536, grid=4, bricks_per_axis=No
     # lights: one cluster per compartment, centred under its ceiling
     cx = (np.arange(grid) + 0.5) * cw
     centres = np.array([[cx[i], 0.93, cx[j]] for j in range(grid) for i in range(grid)], np.float64)
-    cen = centres[:, None, :] + np.array([0.15 * cw, 0.01, 0.15 * cw]) * rng.standard_normal((n_comp, per_cluster, 3))
+    spread = np.array([0.15 * cw, 0.01, 0.15 * cw])
+    cen = centres[:, None, :] + spread * rng.standard_normal((n_comp, per_cluster, 3))
     verts = cen[:, :, None, :] + rng.uniform(-0.002, 0.002, size=(n_comp, per_cluster, 3, 3))
     tri = _f32(verts.reshape(n_comp * per_cluster, 9))
     base = rng.random((n_comp, 3))
@@ -313,63 +314,64 @@ def make_dynamic(n_points=1 << 20, per_cluster=65536, grid=4, bricks_per_axis=No
     phase = rng.uniform(0.0, 2.0 * np.pi, size=n_comp)
 
     def emission_at(frame: int) -> np.ndarray:
+        # Le (1 + sin(2 pi f t + phi)) per compartment, t = frame index
         s = 1.0 + np.sin(2.0 * np.pi * freq * float(frame) + phase)
         return _f32(np.repeat(base * s[:, None], per_cluster, axis=0))
 
     emit = emission_at(0)
-    # walls: 16,384 bricks along the interior partition planes (x = k/grid and
-    # z = k/grid for k = 1..grid-1), floor to ceiling
-    n_planes = 2 * (grid - 1)
-    total_bricks = 16384
-    per_plane = total_bricks // n_planes
-    rows = int(round(math.sqrt(per_plane)))
-    cols = per_plane // rows
-    bricks = []
+    # walls: bricks tiling the interior partition planes x = k/grid and
+    # z = k/grid (k = 1..grid-1), floor to ceiling, 0.02 thick
     th = 0.01
-    for axis in (0, 2):
-        for k in range(1, grid):
-            w = k * cw
-            for r in range(rows):
-                y0, y1 = r / rows, (r + 1) / rows
-                for cidx in range(cols):
-                    u0, u1 = cidx / cols, (cidx + 1) / cols
-                    if axis == 0:
-                        bricks.append([w - th, y0, u0, w + th, y1, u1])
-                    else:
-                        bricks.append([u0, y0, w - th, u1, y1, w + th])
-    while len(bricks) < total_bricks:  # pad with tiny boxes hugging the floor
+    n_planes = 2 * (grid - 1)
+    bricks = []
+    if n_planes:
+        per_plane = n_bricks // n_planes
+        rows = max(1, int(round(math.sqrt(per_plane))))
+        cols = max(1, per_plane // rows)
+        for axis in (0, 2):
+            for k in range(1, grid):
+                w = k * cw
+                for r in range(rows):
+                    y0, y1 = r / rows, (r + 1) / rows
+                    for c in range(cols):
+                        u0, u1 = c / cols, (c + 1) / cols
+                        if axis == 0:
+                            bricks.append([w - th, y0, u0, w + th, y1, u1])
+                        else:
+                            bricks.append([u0, y0, w - th, u1, y1, w + th])
+    while len(bricks) < n_bricks:  # pad with small boxes under the floor
         bricks.append([0.0, -0.02, 0.0, 0.001, -0.01, 0.001])
-    boxes = _f32(np.array(bricks[:total_bricks]))
-    # points: floors (half) and the four walls of each compartment (half)
-    n_floor = n_points // 2
+    boxes = _f32(np.array(bricks[:n_bricks]).reshape(-1, 6))
+    # points: half on compartment floors, half on compartment walls
     comp = rng.integers(0, n_comp, size=n_points)
     ci = comp % grid
     cj = comp // grid
-    pos = np.zeros((n_points, 3))
-    nrm = np.zeros((n_points, 3))
+    lo_x = ci * cw + th
+    lo_z = cj * cw + th
+    span = cw - 2 * th
     u = rng.random(n_points)
     v = rng.random(n_points)
-    inner_lo_x = ci * cw + (th if True else 0.0)
-    inner_lo_z = cj * cw + th
-    span = cw - 2 * th
-    pos[:n_floor, 0] = inner_lo_x[:n_floor] + u[:n_floor] * span
-    pos[:n_floor, 1] = 0.0
-    pos[:n_floor, 2] = inner_lo_z[:n_floor] + v[:n_floor] * span
-    nrm[:n_floor, 1] = 1.0
     side = rng.integers(0, 4, size=n_points)
-    wall = slice(n_floor, n_points)
-    s = side[wall]
-    h = v[wall] * 0.9
-    t = inner_lo_x[wall] * 0 + u[wall] * span
-    px = np.where(s == 0, inner_lo_x[wall], np.where(s == 1, inner_lo_x[wall] + span, inner_lo_x[wall] + t))
-    pz = np.where(s == 2, inner_lo_z[wall], np.where(s == 3, inner_lo_z[wall] + span, inner_lo_z[wall] + t))
-    pos[wall, 0] = px
-    pos[wall, 1] = h
-    pos[wall, 2] = pz
-    nrm[wall, 0] = np.where(s == 0, 1.0, np.where(s == 1, -1.0, 0.0))
-    nrm[wall, 2] = np.where(s == 2, 1.0, np.where(s == 3, -1.0, 0.0))
+    floor = np.arange(n_points) < n_points // 2
+    pos = np.zeros((n_points, 3))
+    nrm = np.zeros((n_points, 3))
+    # floor points
+    pos[:, 0] = lo_x + u * span
+    pos[:, 2] = lo_z + v * span
+    nrm[:, 1] = 1.0
+    # wall points: side 0/1 = -x/+x wall, 2/3 = -z/+z wall
+    wall = ~floor
+    h = v * 0.9
+    px = np.where(side == 0, lo_x, np.where(side == 1, lo_x + span, lo_x + u * span))
+    pz = np.where(side == 2, lo_z, np.where(side == 3, lo_z + span, lo_z + u * span))
+    pos[wall, 0] = px[wall]
+    pos[wall, 1] = h[wall]
+    pos[wall, 2] = pz[wall]
+    nrm[wall] = 0.0
+    nrm[wall, 0] = np.where(side[wall] == 0, 1.0, np.where(side[wall] == 1, -1.0, 0.0))
+    nrm[wall, 2] = np.where(side[wall] == 2, 1.0, np.where(side[wall] == 3, -1.0, 0.0))
     params = params_for(M=M, spp=spp, frames=frames, grid_dims=(64, 64, 64), hashed=1,
-                        capacity=capacity, seed=seed)
+                        capacity=capacity, seed=seed, occ_grid_res=64)
     params.update(overrides)
     return Scene("dynamic", tri, emit, boxes, _f32(pos), _f32(nrm), params, emission_at=emission_at)
 

@@ -358,3 +358,52 @@ def test_image_error_fp64(torch):
     want = [A.mean(), A.var(), ((A - B) ** 2).mean(), (((A - B) / np.where(nz, B, 1)) ** 2)[nz].mean(),
             np.abs(A - B).max()]
     np.testing.assert_allclose(out, want, rtol=1e-9)
+
+
+# --------------------------------------------------------------------------
+# animated emission (walled compartments): the lights change every frame,
+# the cuts keep learning across frames
+# --------------------------------------------------------------------------
+def test_dynamic_emission_parity_small(torch):
+    s = scenes.make_dynamic(n_points=4096, per_cluster=256, grid=2, n_bricks=1024, frames=8, M=16)
+    p = s.params
+    ctx, orc = _make(torch, s)
+    pos, nrm = _t(torch, s.pos), _t(torch, s.nrm)
+    for f in range(p["frames"]):
+        e = s.emission_at(f)
+        ctx.rlc_set_emission(_t(torch, e))
+        orc.set_emission(e)
+        rad = ctx.rlc_frame(pos, nrm, 1, f).cpu().numpy()
+        ref, _ = orc.frame(s.pos, s.nrm, 1, f)
+        orc.adapt()
+        ok, err = _rad_close(rad, ref)
+        assert ok, (f, err)
+        _assert_cells_equal(ctx.rlc_dump_cells(), orc.cells())
+    g = ctx.rlc_dump_tree()
+    assert np.array_equal(g["rec"][:, 9:12], orc.tree()["rec"][:, 9:12])
+
+
+def test_dynamic_full_size_sampled_cells(torch):
+    s = scenes.make_dynamic()
+    p = s.params
+    frames = 5
+    ctx, orc = _make(torch, s)
+    g, o = ctx.rlc_dump_tree(), orc.tree()
+    for k in ("perm", "left", "right", "parent", "first", "last", "rec"):
+        assert np.array_equal(g[k], o[k]), k
+    pos, nrm = _t(torch, s.pos), _t(torch, s.nrm)
+    keys = orc.cell_keys(s.pos)
+    uniq = np.unique(keys)
+    pick = np.random.default_rng(5).choice(uniq, 10, replace=False)
+    sel = np.nonzero(np.isin(keys, pick))[0].astype(np.uint32)
+    for f in range(frames):
+        e = s.emission_at(f)
+        ctx.rlc_set_emission(_t(torch, e))
+        orc.set_emission(e)
+        rad = ctx.rlc_frame(pos, nrm, 1, f).cpu().numpy()[sel]
+        ref, _ = orc.frame(s.pos[sel], s.nrm[sel], 1, f, pid=sel)
+        orc.adapt()
+        ok, err = _rad_close(rad, ref)
+        assert ok, (f, err)
+    ctx.rlc_sync()
+    _assert_cells_equal(ctx.rlc_dump_cells(), orc.cells(), keys=pick)
