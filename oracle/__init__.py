@@ -20,10 +20,12 @@ import numpy as np
 
 _HERE = os.path.dirname(os.path.abspath(__file__))
 _SRC = os.path.join(_HERE, "rlc_oracle.c")
+_SRC_MLP = os.path.join(_HERE, "rlc_oracle_mlp.c")
 _SO = os.path.join(_HERE, "liboracle.so")
 _lib = None
 
 MMAX = 256
+MIX_M = 64
 
 
 def build(force: bool = True) -> str:
@@ -32,7 +34,7 @@ def build(force: bool = True) -> str:
         tmp = _SO + ".tmp%d" % os.getpid()
         subprocess.check_call(["gcc", "-O2", "-std=c11", "-Wall", "-ffp-contract=off",
                                "-fno-fast-math", "-fexcess-precision=standard", "-fPIC",
-                               "-shared", "-o", tmp, _SRC, "-lm"])
+                               "-shared", "-o", tmp, _SRC, _SRC_MLP, "-lm"])
         os.replace(tmp, _SO)
     return _SO
 
@@ -40,7 +42,8 @@ def build(force: bool = True) -> str:
 def lib():
     global _lib
     if _lib is None:
-        if not os.path.exists(_SO) or os.path.getmtime(_SO) < os.path.getmtime(_SRC):
+        if not os.path.exists(_SO) or os.path.getmtime(_SO) < max(os.path.getmtime(_SRC),
+                                                                    os.path.getmtime(_SRC_MLP)):
             build()
         _lib = ctypes.CDLL(_SO)
         _declare(_lib)
@@ -71,7 +74,8 @@ class OrcConfig(ctypes.Structure):
 
 class OrcRecords(ctypes.Structure):
     _fields_ = [(n, ctypes.c_void_p) for n in
-                ("key", "ready", "slot", "light", "inv_pdf", "y", "contrib", "reward")]
+                ("key", "ready", "slot", "light", "inv_pdf", "y", "contrib", "reward", "fnode",
+                 "weight", "comp")]
 
 
 _vp = ctypes.c_void_p
@@ -102,6 +106,19 @@ def _declare(L):
     L.orc_load_cell.argtypes = [_vp, _u32, _vp, _vp]
     L.orc_truth_unoccluded.argtypes = [_vp, _vp, _vp, _u32, _vp]
     L.orc_truth_mc.argtypes = [_vp, _vp, _vp, _vp, _u32, _u32, _u32, _vp]
+    L.orc_fixed_cut.restype = _u32
+    L.orc_fixed_cut.argtypes = [_vp, _vp, _vp]
+    L.orc_set_mixture.argtypes = [_vp, _vp, _u32, ctypes.c_float]
+    L.orc_mlp_nparam.restype = _u32
+    L.orc_bf16_round.argtypes = [_vp, _u32, _vp]
+    L.orc_mlp_encode.argtypes = [_vp, _vp, _u32, _vp, _vp, _vp]
+    L.orc_mlp_forward.argtypes = [_vp, _vp, _u32, ctypes.c_int, _vp, _vp]
+    L.orc_mlp_loss_grad.argtypes = [_vp, _vp, _vp, _vp, _u32, ctypes.c_int, _vp, _vp]
+    _d = ctypes.c_double
+    L.orc_mlp_adam.argtypes = [_vp, _vp, _vp, _vp, _u32, _u32, _d, _d, _d, _d]
+    L.orc_mlp_shuffle.argtypes = [_u32, _u32, _u32, ctypes.c_uint64, _vp]
+    L.orc_mlp_train.argtypes = [_vp, _vp, _vp, _vp, _vp, _u32, _vp, _vp, _vp, _u32, _u32, _u32, _d, _d, _d,
+                                _d, _u32, ctypes.c_uint64, ctypes.c_int, _vp]
 
 
 def _p(a):
@@ -187,6 +204,24 @@ class Oracle:
         m = lib().orc_get_template(self._h, _p(node), _p(end))
         return node[:m].copy(), end[:m].copy()
 
+    def fixed_cut(self):
+        """The fixed breadth-first cut (up to 64 nodes) of the learned proposal."""
+        node = np.zeros(MIX_M, np.uint32)
+        end = np.zeros(MIX_M, np.uint32)
+        m = lib().orc_fixed_cut(self._h, _p(node), _p(end))
+        return node[:m].copy(), end[:m].copy()
+
+    def set_mixture(self, cdf=None, w: float = 0.5):
+        """Turn the 50/50 (w) mixture with a learned per-point cdf on (rows of 64
+        inclusive running sums, indexed by point id), or off with None."""
+        if cdf is None:
+            lib().orc_set_mixture(self._h, None, 0, 0.0)
+            self._mix = None
+            return
+        self._mix = _c(cdf, np.float32).reshape(-1, MIX_M)
+        if lib().orc_set_mixture(self._h, _p(self._mix), self._mix.shape[0], float(w)) != 0:
+            raise ValueError("bad mixture")
+
     @property
     def Meff(self) -> int:
         return int(lib().orc_meff(self._h))
@@ -225,9 +260,12 @@ class Oracle:
             rec = dict(key=np.zeros(n, np.uint64), ready=np.zeros(n, np.uint32),
                        slot=np.zeros(n, np.uint32), light=np.zeros(n, np.uint32),
                        inv_pdf=np.zeros(n, np.float32), y=np.zeros((n, 3), np.float32),
-                       contrib=np.zeros((n, 3), np.float32), reward=np.zeros(n, np.float32))
+                       contrib=np.zeros((n, 3), np.float32), reward=np.zeros(n, np.float32),
+                       fnode=np.zeros(n, np.uint32), weight=np.zeros(n, np.float32),
+                       comp=np.zeros(n, np.uint32))
             recs = OrcRecords(*[_p(rec[k]) for k in ("key", "ready", "slot", "light", "inv_pdf",
-                                                     "y", "contrib", "reward")])
+                                                     "y", "contrib", "reward", "fnode", "weight",
+                                                     "comp")])
         lib().orc_frame(self._h, _p(pos), _p(nrm), _p(pid_a), P, int(spp), int(frame), _p(rad),
                         ctypes.byref(recs) if recs is not None else None)
         return rad, rec
@@ -310,3 +348,92 @@ def cdf(Q, eps: float):
     C = np.zeros_like(Q)
     lib().orc_cdf(_p(Q), Q.size, float(eps), _p(Qt), _p(C))
     return Qt, C
+
+
+# -- learned proposal (rlc_oracle_mlp.c) ---------------------------------------
+MLP_IN, MLP_H, MLP_OUT = 144, 64, 64
+
+
+def mlp_nparam() -> int:
+    return int(lib().orc_mlp_nparam())
+
+
+def bf16_round(a) -> np.ndarray:
+    a = _c(a, np.float64)
+    out = np.zeros_like(a)
+    lib().orc_bf16_round(_p(a), a.size, _p(out))
+    return out
+
+
+def mlp_encode(pos, nrm, lo, hi) -> np.ndarray:
+    pos = _c(pos, np.float32).reshape(-1, 3)
+    nrm = _c(nrm, np.float32).reshape(-1, 3)
+    lo = _c(lo, np.float32).reshape(3)
+    hi = _c(hi, np.float32).reshape(3)
+    out = np.zeros((pos.shape[0], MLP_IN), np.float64)
+    lib().orc_mlp_encode(_p(pos), _p(nrm), pos.shape[0], _p(lo), _p(hi), _p(out))
+    return out
+
+
+def mlp_forward(params, x, bf16: bool = False):
+    """(logits, probabilities), each (n, 64)."""
+    params = _c(params, np.float64)
+    x = _c(x, np.float64).reshape(-1, MLP_IN)
+    n = x.shape[0]
+    z = np.zeros((n, MLP_OUT))
+    q = np.zeros((n, MLP_OUT))
+    lib().orc_mlp_forward(_p(params), _p(x), n, int(bf16), _p(z), _p(q))
+    return z, q
+
+
+def mlp_loss_grad(params, x, node, w, bf16: bool = False):
+    params = _c(params, np.float64)
+    x = _c(x, np.float64).reshape(-1, MLP_IN)
+    node = _c(node, np.uint32)
+    w = _c(w, np.float64)
+    loss = np.zeros(1)
+    g = np.zeros(mlp_nparam())
+    if lib().orc_mlp_loss_grad(_p(params), _p(x), _p(node), _p(w), x.shape[0], int(bf16), _p(loss),
+                               _p(g)) != 0:
+        raise ValueError("bad tuple")
+    return float(loss[0]), g
+
+
+def mlp_adam(params, m, v, grad, step: int, lr=1e-3, beta1=0.9, beta2=0.999, eps=1e-8):
+    """One Adam step in place on float64 arrays."""
+    lib().orc_mlp_adam(_p(params), _p(m), _p(v), _p(_c(grad, np.float64)), params.size, int(step), lr, beta1,
+                       beta2, eps)
+
+
+def mlp_shuffle(n: int, epoch: int, scene_id: int, seed: int) -> np.ndarray:
+    out = np.zeros(n, np.uint32)
+    lib().orc_mlp_shuffle(n, epoch, scene_id, seed, _p(out))
+    return out
+
+
+def mlp_train(params, m, v, step: int, xall, pid, node, w, epochs: int, batch: int, lr=1e-3, beta1=0.9,
+              beta2=0.999, eps=1e-8, scene_id: int = 0, seed: int = 0, bf16: bool = False):
+    """Minibatch Adam training in place; returns (new step count, last batch loss)."""
+    xall = _c(xall, np.float64).reshape(-1, MLP_IN)
+    pid = _c(pid, np.uint32)
+    node = _c(node, np.uint32)
+    w = _c(w, np.float64)
+    st = np.array([step], np.uint32)
+    loss = np.zeros(1)
+    rc = lib().orc_mlp_train(_p(params), _p(m), _p(v), _p(st), _p(xall), xall.shape[0], _p(pid), _p(node), _p(w),
+                             pid.size, epochs, batch, lr, beta1, beta2, eps, scene_id, seed, int(bf16), _p(loss))
+    if rc != 0:
+        raise ValueError("bad training input")
+    return int(st[0]), float(loss[0])
+
+
+def mlp_cdf(probs) -> np.ndarray:
+    """Inclusive running sums in FP32, left to right, of FP32-rounded
+    probabilities: the per-point table the mixture draws from."""
+    q = np.asarray(probs, np.float64).astype(np.float32)
+    out = np.zeros_like(q)
+    acc = np.zeros(q.shape[0], np.float32)
+    for k in range(q.shape[1]):
+        acc = (acc + q[:, k]).astype(np.float32)
+        out[:, k] = acc
+    return out

@@ -33,6 +33,7 @@
 #define ORC_ENOMEM (-2)
 #define ORC_MMAX 256u
 #define ORC_NONE 0xFFFFFFFFu
+#define ORC_MIX_M 64u
 
 /* ------------------------------------------------------------------------ */
 /* Configuration (mirrors the method's parameters: M, alpha, T of section 3) */
@@ -126,6 +127,13 @@ typedef struct orc_ctx {
     uint32_t tmpl_end[ORC_MMAX];
     float tmpl_Qt[ORC_MMAX];
     float tmpl_C[ORC_MMAX];
+    /* fixed cut of the learned proposal, and the proposal's per-point cdf */
+    uint32_t fix_M;
+    uint32_t fix_node[ORC_MIX_M];
+    uint32_t fix_end[ORC_MIX_M];
+    float* mix_cdf;        /* rows of ORC_MIX_M floats, indexed by point id; NULL: off */
+    uint32_t mix_rows;
+    float mix_w;           /* probability of drawing from the cell's cut */
     /* grid of cells, indexed by the cell key's linear part */
     uint32_t ncell_slots;
     cell** cells;
@@ -275,9 +283,13 @@ static int build_tree(orc_ctx* c, const float* tri, const float* emit)
 /* the cut is "a monotonically increasing list of indices marking the end  */
 /* of each cluster" (section 3).                                            */
 /* ------------------------------------------------------------------------ */
-static void initial_cut(orc_ctx* c)
+/* Breadth-first cut of at most M nodes: starting from the root, the       */
+/* leftmost internal node of the list is replaced by its two children until */
+/* M nodes are live or only leaves remain; the result in left-to-right      */
+/* (first light) order.  Returns the number of nodes.                       */
+static uint32_t breadth_first_cut(const orc_ctx* c, uint32_t Mreq, uint32_t* node, uint32_t* end)
 {
-    uint32_t M = c->cfg.M < c->N ? c->cfg.M : c->N;
+    uint32_t M = Mreq < c->N ? Mreq : c->N;
     uint32_t list[2 * ORC_MMAX];
     int removed[2 * ORC_MMAX];
     uint32_t len = 0, live = 0;
@@ -297,25 +309,34 @@ static void initial_cut(orc_ctx* c)
     }
     uint32_t n = 0;
     for (uint32_t i = 0; i < len; ++i)
-        if (!removed[i]) c->tmpl_node[n++] = list[i];
+        if (!removed[i]) node[n++] = list[i];
     /* insertion sort by first light */
     for (uint32_t i = 1; i < n; ++i) {
-        uint32_t v = c->tmpl_node[i];
+        uint32_t v = node[i];
         uint32_t j = i;
-        while (j > 0 && c->first[c->tmpl_node[j - 1]] > c->first[v]) {
-            c->tmpl_node[j] = c->tmpl_node[j - 1];
+        while (j > 0 && c->first[node[j - 1]] > c->first[v]) {
+            node[j] = node[j - 1];
             --j;
         }
-        c->tmpl_node[j] = v;
+        node[j] = v;
     }
+    for (uint32_t s = 0; s < n; ++s) end[s] = c->last[node[s]] + 1u;
+    return n;
+}
+
+/* The initial cut every new cell starts from (section 3). */
+static void initial_cut(orc_ctx* c)
+{
+    uint32_t n = breadth_first_cut(c, c->cfg.M, c->tmpl_node, c->tmpl_end);
     c->Meff = n;
-    for (uint32_t s = 0; s < n; ++s) c->tmpl_end[s] = c->last[c->tmpl_node[s]] + 1u;
     /* a fresh cell has Q = 0 everywhere, so its Q~ and C follow from the
      * end-of-pass rule with S = 0: every cluster equally likely. */
     for (uint32_t s = 0; s < n; ++s) {
         c->tmpl_Qt[s] = 1.0f;
         c->tmpl_C[s] = (s == 0) ? 1.0f : c->tmpl_C[s - 1] + 1.0f;
     }
+    /* the fixed cut the learned proposal distributes over */
+    c->fix_M = breadth_first_cut(c, ORC_MIX_M, c->fix_node, c->fix_end);
 }
 
 /* ------------------------------------------------------------------------ */
@@ -374,6 +395,7 @@ void orc_destroy(orc_ctx* c)
     free(c->last);
     free(c->rec);
     free(c->boxes);
+    free(c->mix_cdf);
     free(c);
 }
 
@@ -404,6 +426,34 @@ uint32_t orc_get_template(const orc_ctx* c, uint32_t* node, uint32_t* end)
     if (node) memcpy(node, c->tmpl_node, sizeof(uint32_t) * c->Meff);
     if (end) memcpy(end, c->tmpl_end, sizeof(uint32_t) * c->Meff);
     return c->Meff;
+}
+
+/* The fixed breadth-first cut of up to 64 nodes that the learned proposal
+ * puts its distribution over. */
+uint32_t orc_fixed_cut(const orc_ctx* c, uint32_t* node, uint32_t* end)
+{
+    if (node) memcpy(node, c->fix_node, sizeof(uint32_t) * c->fix_M);
+    if (end) memcpy(end, c->fix_end, sizeof(uint32_t) * c->fix_M);
+    return c->fix_M;
+}
+
+/* Mixture proposal: cdf holds, per point id, the inclusive running sums of
+ * the learned probabilities of the fixed cut's nodes (rows of 64 floats, the
+ * first fix_M used).  A light is drawn from the cell's cut with probability
+ * w and from the learned proposal otherwise.  cdf = NULL switches it off. */
+int orc_set_mixture(orc_ctx* c, const float* cdf, uint32_t rows, float w)
+{
+    free(c->mix_cdf);
+    c->mix_cdf = NULL;
+    c->mix_rows = 0;
+    if (!cdf) return ORC_OK;
+    if (!(w >= 0.0f && w <= 1.0f) || rows == 0) return ORC_EINVAL;
+    c->mix_cdf = (float*)malloc(sizeof(float) * ORC_MIX_M * (size_t)rows);
+    if (!c->mix_cdf) return ORC_ENOMEM;
+    memcpy(c->mix_cdf, cdf, sizeof(float) * ORC_MIX_M * (size_t)rows);
+    c->mix_rows = rows;
+    c->mix_w = w;
+    return ORC_OK;
 }
 
 /* ------------------------------------------------------------------------ */
@@ -495,6 +545,9 @@ typedef struct orc_records {
     float* y;           /* point on the light, 3 per sample */
     float* contrib;     /* c_l, RGB, 3 per sample */
     float* reward;      /* scalar reward fed to Eq. 1 */
+    uint32_t* fnode;    /* index of the fixed-cut node holding the light */
+    float* weight;      /* training weight (c_l summed over RGB) / p(l) */
+    uint32_t* comp;     /* 1 if the learned proposal drew the light */
 } orc_records;
 
 static cell* get_or_create_cell(orc_ctx* c, uint32_t lin)
@@ -529,19 +582,75 @@ static void one_sample(orc_ctx* c, const float* x, const float* nx, uint32_t pid
     float u2 = unit_float(w[2]);
     float u3 = unit_float(w[3]);
 
-    /* cluster: smallest s with t < C[s] */
-    float t = u0 * C[Meff - 1];
-    uint32_t s = Meff - 1;
-    for (uint32_t i = 0; i < Meff; ++i)
-        if (t < C[i]) {
-            s = i;
-            break;
-        }
-    uint32_t begin = (s == 0) ? 0u : end[s - 1];
-    uint32_t size = end[s] - begin;
-    float inv_pdf = ((float)size * C[Meff - 1]) / Qt[s];
-    /* light inside the cluster, uniformly (reading of "randomly") */
-    uint32_t l = begin + (uint32_t)((draw40 * (uint64_t)size) >> 40);
+    /* component of the mixture: counter tag 1 (only with the proposal on) */
+    const float* q = NULL;
+    int use_mlp = 0;
+    if (c->mix_cdf && pid < c->mix_rows) {
+        uint32_t ctr1[4] = {pid, k, frame, (uint32_t)(cfg->scene_id << 16) | 1u};
+        uint32_t w1[4];
+        philox4x32_10(ctr1, key, w1);
+        q = c->mix_cdf + (size_t)pid * ORC_MIX_M;
+        use_mlp = !(unit_float(w1[0]) < c->mix_w);
+    }
+    uint32_t Mf = c->fix_M;
+    uint32_t s, begin, size, l, kf = ORC_NONE, fbegin = 0, fsize = 0;
+    if (!use_mlp) {
+        /* cluster: smallest s with t < C[s] */
+        float t = u0 * C[Meff - 1];
+        s = Meff - 1;
+        for (uint32_t i = 0; i < Meff; ++i)
+            if (t < C[i]) {
+                s = i;
+                break;
+            }
+        begin = (s == 0) ? 0u : end[s - 1];
+        size = end[s] - begin;
+        /* light inside the cluster, uniformly (reading of "randomly") */
+        l = begin + (uint32_t)((draw40 * (uint64_t)size) >> 40);
+    } else {
+        /* node of the fixed cut from the learned cdf, then a light inside it
+         * uniformly; the same random words as the tabular draw */
+        float t = u0 * q[Mf - 1];
+        kf = Mf - 1;
+        for (uint32_t i = 0; i < Mf; ++i)
+            if (t < q[i]) {
+                kf = i;
+                break;
+            }
+        fbegin = (kf == 0) ? 0u : c->fix_end[kf - 1];
+        fsize = c->fix_end[kf] - fbegin;
+        l = fbegin + (uint32_t)((draw40 * (uint64_t)fsize) >> 40);
+        /* the cell's cluster that holds l */
+        s = Meff - 1;
+        for (uint32_t i = 0; i < Meff; ++i)
+            if (l < end[i]) {
+                s = i;
+                break;
+            }
+        begin = (s == 0) ? 0u : end[s - 1];
+        size = end[s] - begin;
+    }
+    if (kf == ORC_NONE && (q || (out && (out->fnode || out->weight)))) {
+        kf = Mf - 1;
+        for (uint32_t i = 0; i < Mf; ++i)
+            if (l < c->fix_end[i]) {
+                kf = i;
+                break;
+            }
+        fbegin = (kf == 0) ? 0u : c->fix_end[kf - 1];
+        fsize = c->fix_end[kf] - fbegin;
+    }
+    float inv_pdf;
+    if (q) {
+        /* p(l) = w p_cut(l) + (1 - w) p_learned(l), each uniform inside its
+         * cluster / node */
+        float pt = Qt[s] / ((float)size * C[Meff - 1]);
+        float qk = q[kf] - (kf ? q[kf - 1] : 0.0f);
+        float pm = qk / ((float)fsize * q[Mf - 1]);
+        inv_pdf = 1.0f / (c->mix_w * pt + (1.0f - c->mix_w) * pm);
+    } else {
+        inv_pdf = ((float)size * C[Meff - 1]) / Qt[s];
+    }
 
     /* uniform point on the triangle */
     const float* r = c->rec + 16u * l;
@@ -585,9 +694,11 @@ static void one_sample(orc_ctx* c, const float* x, const float* nx, uint32_t pid
     float rew = (cl[0] + cl[1]) + cl[2];
     if (cfg->reward_mode == 1) rew = rew * (float)size;
     float rc = rew < cfg->reward_max ? rew : cfg->reward_max;
-    uint64_t q = (uint64_t)rintf(rc * ldexpf(1.0f, (int)cfg->fx_shift));
-    if (ce) {
-        ce->sum[s] += q;
+    uint64_t qfx = (uint64_t)rintf(rc * ldexpf(1.0f, (int)cfg->fx_shift));
+    /* reading: only draws from the cell's own cut feed Eq. 1 (inside a
+     * cluster they are uniform, as the update assumes) */
+    if (ce && !use_mlp) {
+        ce->sum[s] += qfx;
         ce->cnt[s] += 1u;
     }
     if (out) {
@@ -601,6 +712,9 @@ static void one_sample(orc_ctx* c, const float* x, const float* nx, uint32_t pid
         if (out->contrib)
             for (int a = 0; a < 3; ++a) out->contrib[3 * ri + a] = cl[a];
         if (out->reward) out->reward[ri] = rew;
+        if (out->fnode) out->fnode[ri] = kf;
+        if (out->weight) out->weight[ri] = ((cl[0] + cl[1]) + cl[2]) * inv_pdf;
+        if (out->comp) out->comp[ri] = (uint32_t)use_mlp;
     }
 }
 
