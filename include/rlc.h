@@ -152,6 +152,45 @@ int rlc_cell_keys(rlc_ctx* ctx, const float* d_pos, uint32_t n, uint64_t* d_keys
  * (over entries with ref != 0), max abs error; n = number of floats. */
 int rlc_image_error(rlc_ctx* ctx, const float* d_img, const float* d_ref, uint32_t n, double* h_out);
 
+/* ---- batched passes over several scenes ----
+ * One persistent kernel renders a pass of every scene of the batch (work
+ * items of `tile` samples drawn across all scenes), then one kernel adapts
+ * every scene's cells; both are captured once in a hipGraph and replayed
+ * each pass.  Results are identical to rlc_frame on each scene.  All scenes'
+ * contexts must use the batch's stream; the pointers are fixed at creation
+ * (static points); emission may still change between passes.  Rebuild the
+ * batch after rebuilding a scene's tree or occluders. */
+typedef struct rlc_batch rlc_batch;
+
+typedef struct rlc_batch_scene {
+    rlc_ctx* ctx;          /* scene with its tree (and occluders) set */
+    const float* d_pos;    /* P x 3 */
+    const float* d_nrm;    /* P x 3 */
+    float* d_radiance;     /* P x 3, the pass's mean estimate per point */
+    uint32_t P;
+    uint32_t spp;          /* a power of two, at most 64 */
+} rlc_batch_scene;
+
+typedef struct rlc_schedule {
+    uint32_t tile;          /* samples per work item, a multiple of 256 */
+    uint32_t blocks_per_cu; /* persistent blocks launched per compute unit */
+    uint32_t dynamic;       /* 1: blocks take items from a counter; 0: contiguous ranges */
+    uint32_t cell_sorted;   /* 1: points visited in cell order (wave-per-cell locality) */
+} rlc_schedule;
+
+int rlc_batch_create(const rlc_batch_scene* scenes, uint32_t n, void* stream, rlc_batch** out);
+int rlc_batch_destroy(rlc_batch* b);
+int rlc_batch_set_schedule(rlc_batch* b, const rlc_schedule* sched);
+int rlc_batch_get_schedule(rlc_batch* b, rlc_schedule* sched);
+/* Time every candidate schedule over `passes` passes (HIP events), keep the
+ * fastest, then reset every scene's cells.  h_ms (may be NULL) receives the
+ * mean pass time of each candidate, in the order of h_cands (may be NULL);
+ * both hold up to *h_ncand entries on entry and the count on return. */
+int rlc_batch_autotune(rlc_batch* b, uint32_t passes, rlc_schedule* h_best, rlc_schedule* h_cands, double* h_ms,
+                       uint32_t* h_ncand);
+/* One pass of every scene (graph launch). */
+int rlc_batch_frame(rlc_batch* b, uint32_t frame);
+
 /* ---- inspection, checkpoint and parity interface (synchronise) ---- */
 int rlc_sync(rlc_ctx* ctx);
 const char* rlc_last_error(const rlc_ctx* ctx);

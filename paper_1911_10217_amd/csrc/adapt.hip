@@ -37,161 +37,126 @@ __device__ __forceinline__ unsigned long long wave_min_u64(unsigned long long v)
     return v;
 }
 
-// One block = one wavefront; it walks the list of created cells.
-__global__ void __launch_bounds__(kWave) k_adapt(AdaptParams ap) {
-    __shared__ uint32_t s_node[RLC_MMAX];
-    __shared__ float s_Q[RLC_MMAX];
-    __shared__ uint32_t s_nnode[RLC_MMAX];
-    __shared__ float s_nQ[RLC_MMAX];
-    __shared__ float s_Qt[RLC_MMAX];
-    __shared__ float s_C[RLC_MMAX];
+struct AdaptLds {
+    uint32_t node[RLC_MMAX];
+    float Q[RLC_MMAX];
+    uint32_t nnode[RLC_MMAX];
+    float nQ[RLC_MMAX];
+    float Qt[RLC_MMAX];
+    float C[RLC_MMAX];
+};
 
+// End of pass for table slot c, by one wavefront (= the block).
+__device__ void adapt_cell(const AdaptParams& ap, uint32_t c, AdaptLds& L) {
     const DevCells& cells = ap.cells;
     const uint32_t lane = threadIdx.x;
     const uint32_t Meff = ap.tmpl.Meff;
     const uint32_t M = cells.M;
-    const uint32_t n_live = *cells.n_live;
     const uint32_t per = (Meff + kWave - 1) / kWave;
+    const size_t base = (size_t)c * M;
+    uint32_t cnt[kMaxPerLane];
+    bool any = false;
+#pragma unroll
+    for (int j = 0; j < kMaxPerLane; ++j) {
+        uint32_t s = lane + kWave * j;
+        cnt[j] = (j < (int)per && s < Meff) ? cells.cnt[base + s] : 0u;
+        any |= cnt[j] != 0u;
+    }
+    if (!__any(any)) return;  // no samples this pass: the cell is left as it is
 
-    for (uint32_t li = blockIdx.x; li < n_live; li += gridDim.x) {
-        const uint32_t c = cells.live[li];
-        const size_t base = (size_t)c * M;
-        uint32_t cnt[kMaxPerLane];
-        bool any = false;
+    const bool fresh = cells.ready[c] == 0u || ap.temporal == 0u;
+    // load the cut and Q (a fresh cell starts from the initial cut, Q = 0)
 #pragma unroll
-        for (int j = 0; j < kMaxPerLane; ++j) {
-            uint32_t s = lane + kWave * j;
-            cnt[j] = (j < (int)per && s < Meff) ? cells.cnt[base + s] : 0u;
-            any |= cnt[j] != 0u;
-        }
-        if (!__any(any)) continue;  // no samples this pass: the cell is left as it is
-
-        const bool fresh = cells.ready[c] == 0u || ap.temporal == 0u;
-        // load the cut and Q (a fresh cell starts from the initial cut, Q = 0)
-#pragma unroll
-        for (int j = 0; j < kMaxPerLane; ++j) {
-            uint32_t s = lane + kWave * j;
-            if (j < (int)per && s < Meff) {
-                uint32_t nd;
-                float q;
-                if (fresh) {
-                    nd = ap.tmpl.node[s];
-                    q = 0.0f;
-                } else {
-                    nd = cells.node[base + s];
-                    q = cells.Q[base + s];
-                }
-                if (ap.temporal && cnt[j]) {
-                    // Eq. 1 applied to the n samples of the pass at once
-                    float a_n = pow_uint(1.0f - ap.alpha, cnt[j]);
-                    float m = ((float)cells.sum[base + s] * ap.fx_inv) / (float)cnt[j];
-                    float t1 = a_n * q;
-                    float t2 = (1.0f - a_n) * m;
-                    q = t1 + t2;
-                }
-                s_node[s] = nd;
-                s_Q[s] = q;
-            }
-        }
-        __syncthreads();
-
-        // ---- split-collapse (one step) ----
-        bool changed = false;
-        uint32_t smax = RLC_NONE, smin = RLC_NONE;
-        float qpmin = 0.0f;
-        if (ap.temporal && ap.adapt && Meff >= 2u) {
-            // l_max: largest Q among splittable cut nodes, ties -> smallest slot
-            unsigned long long best = 0ull;
-#pragma unroll
-            for (int j = 0; j < kMaxPerLane; ++j) {
-                uint32_t s = lane + kWave * j;
-                if (j < (int)per && s < Meff) {
-                    uint32_t nd = s_node[s];
-                    if (ap.tree.last[nd] > ap.tree.first[nd]) {
-                        unsigned long long key = ((unsigned long long)__float_as_uint(s_Q[s]) << 32) |
-                                                 (unsigned long long)(0xFFFFFFFFu - s);
-                        best = key > best ? key : best;
-                    }
-                }
-            }
-            best = wave_max_u64(best);
-            if (best != 0ull) smax = 0xFFFFFFFFu - (uint32_t)(best & 0xFFFFFFFFull);
-            // p_min: sibling pairs (s, s+1) not holding l_max, smallest Q sum
-            unsigned long long worst = ~0ull;
-#pragma unroll
-            for (int j = 0; j < kMaxPerLane; ++j) {
-                uint32_t s = lane + kWave * j;
-                if (j < (int)per && s + 1u < Meff && s != smax && s + 1u != smax) {
-                    uint32_t n0 = s_node[s], n1 = s_node[s + 1u];
-                    uint32_t p = ap.tree.parent[n0];
-                    if (p != RLC_NONE && ap.tree.left[p] == n0 && ap.tree.right[p] == n1) {
-                        float qp = s_Q[s] + s_Q[s + 1u];
-                        unsigned long long key = ((unsigned long long)__float_as_uint(qp) << 32) | s;
-                        worst = key < worst ? key : worst;
-                    }
-                }
-            }
-            worst = wave_min_u64(worst);
-            if (smax != RLC_NONE && worst != ~0ull) {
-                smin = (uint32_t)(worst & 0xFFFFFFFFull);
-                qpmin = __uint_as_float((uint32_t)(worst >> 32));
-                changed = s_Q[smax] > ap.T * qpmin;
-            }
-        }
-        if (changed) {
-            // new slot of old slot s: s + [s > smax] - [s > smin + 1]
-#pragma unroll
-            for (int j = 0; j < kMaxPerLane; ++j) {
-                uint32_t s = lane + kWave * j;
-                if (j < (int)per && s < Meff && s != smin + 1u) {
-                    uint32_t nd = s_node[s];
-                    float q = s_Q[s];
-                    uint32_t dst = s + (s > smax ? 1u : 0u) - (s > smin + 1u ? 1u : 0u);
-                    if (s == smin) {
-                        s_nnode[dst] = ap.tree.parent[nd];
-                        s_nQ[dst] = qpmin;
-                    } else if (s == smax) {
-                        float h = 0.5f * q;
-                        s_nnode[dst] = ap.tree.left[nd];
-                        s_nQ[dst] = h;
-                        s_nnode[dst + 1u] = ap.tree.right[nd];
-                        s_nQ[dst + 1u] = h;
-                    } else {
-                        s_nnode[dst] = nd;
-                        s_nQ[dst] = q;
-                    }
-                }
-            }
-            __syncthreads();
-#pragma unroll
-            for (int j = 0; j < kMaxPerLane; ++j) {
-                uint32_t s = lane + kWave * j;
-                if (j < (int)per && s < Meff) {
-                    s_node[s] = s_nnode[s];
-                    s_Q[s] = s_nQ[s];
-                }
-            }
-            __syncthreads();
-        }
-
-        // ---- Q~ and Eq. 2: sums taken left to right ----
-        if (lane == 0) {
-            float S = 0.0f;
-            for (uint32_t s = 0; s < Meff; ++s) S = S + s_Q[s];
-            float acc = 0.0f;
-            if (S == 0.0f) {
-                for (uint32_t s = 0; s < Meff; ++s) {
-                    s_Qt[s] = 1.0f;
-                    acc = s ? acc + 1.0f : 1.0f;
-                    s_C[s] = acc;
-                }
+    for (int j = 0; j < kMaxPerLane; ++j) {
+        uint32_t s = lane + kWave * j;
+        if (j < (int)per && s < Meff) {
+            uint32_t nd;
+            float q;
+            if (fresh) {
+                nd = ap.tmpl.node[s];
+                q = 0.0f;
             } else {
-                float fl = (ap.eps * S) / (float)Meff;
-                for (uint32_t s = 0; s < Meff; ++s) {
-                    float qt = s_Q[s] + fl;
-                    s_Qt[s] = qt;
-                    acc = s ? acc + qt : qt;
-                    s_C[s] = acc;
+                nd = cells.node[base + s];
+                q = cells.Q[base + s];
+            }
+            if (ap.temporal && cnt[j]) {
+                // Eq. 1 applied to the n samples of the pass at once
+                float a_n = pow_uint(1.0f - ap.alpha, cnt[j]);
+                float m = ((float)cells.sum[base + s] * ap.fx_inv) / (float)cnt[j];
+                float t1 = a_n * q;
+                float t2 = (1.0f - a_n) * m;
+                q = t1 + t2;
+            }
+            L.node[s] = nd;
+            L.Q[s] = q;
+        }
+    }
+    __syncthreads();
+
+    // ---- split-collapse (one step) ----
+    bool changed = false;
+    uint32_t smax = RLC_NONE, smin = RLC_NONE;
+    float qpmin = 0.0f;
+    if (ap.temporal && ap.adapt && Meff >= 2u) {
+        // l_max: largest Q among splittable cut nodes, ties -> smallest slot
+        unsigned long long best = 0ull;
+#pragma unroll
+        for (int j = 0; j < kMaxPerLane; ++j) {
+            uint32_t s = lane + kWave * j;
+            if (j < (int)per && s < Meff) {
+                uint32_t nd = L.node[s];
+                if (ap.tree.last[nd] > ap.tree.first[nd]) {
+                    unsigned long long key = ((unsigned long long)__float_as_uint(L.Q[s]) << 32) |
+                                             (unsigned long long)(0xFFFFFFFFu - s);
+                    best = key > best ? key : best;
+                }
+            }
+        }
+        best = wave_max_u64(best);
+        if (best != 0ull) smax = 0xFFFFFFFFu - (uint32_t)(best & 0xFFFFFFFFull);
+        // p_min: sibling pairs (s, s+1) not holding l_max, smallest Q sum
+        unsigned long long worst = ~0ull;
+#pragma unroll
+        for (int j = 0; j < kMaxPerLane; ++j) {
+            uint32_t s = lane + kWave * j;
+            if (j < (int)per && s + 1u < Meff && s != smax && s + 1u != smax) {
+                uint32_t n0 = L.node[s], n1 = L.node[s + 1u];
+                uint32_t p = ap.tree.parent[n0];
+                if (p != RLC_NONE && ap.tree.left[p] == n0 && ap.tree.right[p] == n1) {
+                    float qp = L.Q[s] + L.Q[s + 1u];
+                    unsigned long long key = ((unsigned long long)__float_as_uint(qp) << 32) | s;
+                    worst = key < worst ? key : worst;
+                }
+            }
+        }
+        worst = wave_min_u64(worst);
+        if (smax != RLC_NONE && worst != ~0ull) {
+            smin = (uint32_t)(worst & 0xFFFFFFFFull);
+            qpmin = __uint_as_float((uint32_t)(worst >> 32));
+            changed = L.Q[smax] > ap.T * qpmin;
+        }
+    }
+    if (changed) {
+        // new slot of old slot s: s + [s > smax] - [s > smin + 1]
+#pragma unroll
+        for (int j = 0; j < kMaxPerLane; ++j) {
+            uint32_t s = lane + kWave * j;
+            if (j < (int)per && s < Meff && s != smin + 1u) {
+                uint32_t nd = L.node[s];
+                float q = L.Q[s];
+                uint32_t dst = s + (s > smax ? 1u : 0u) - (s > smin + 1u ? 1u : 0u);
+                if (s == smin) {
+                    L.nnode[dst] = ap.tree.parent[nd];
+                    L.nQ[dst] = qpmin;
+                } else if (s == smax) {
+                    float h = 0.5f * q;
+                    L.nnode[dst] = ap.tree.left[nd];
+                    L.nQ[dst] = h;
+                    L.nnode[dst + 1u] = ap.tree.right[nd];
+                    L.nQ[dst + 1u] = h;
+                } else {
+                    L.nnode[dst] = nd;
+                    L.nQ[dst] = q;
                 }
             }
         }
@@ -200,18 +165,67 @@ __global__ void __launch_bounds__(kWave) k_adapt(AdaptParams ap) {
         for (int j = 0; j < kMaxPerLane; ++j) {
             uint32_t s = lane + kWave * j;
             if (j < (int)per && s < Meff) {
-                uint32_t nd = s_node[s];
-                cells.node[base + s] = nd;
-                cells.end[base + s] = ap.tree.last[nd] + 1u;
-                cells.Q[base + s] = s_Q[s];
-                cells.Qt[base + s] = s_Qt[s];
-                cells.C[base + s] = s_C[s];
-                cells.sum[base + s] = 0ull;
-                cells.cnt[base + s] = 0u;
+                L.node[s] = L.nnode[s];
+                L.Q[s] = L.nQ[s];
             }
         }
-        if (lane == 0) cells.ready[c] = 1u;
         __syncthreads();
+    }
+
+    // ---- Q~ and Eq. 2: sums taken left to right ----
+    if (lane == 0) {
+        float S = 0.0f;
+        for (uint32_t s = 0; s < Meff; ++s) S = S + L.Q[s];
+        float acc = 0.0f;
+        if (S == 0.0f) {
+            for (uint32_t s = 0; s < Meff; ++s) {
+                L.Qt[s] = 1.0f;
+                acc = s ? acc + 1.0f : 1.0f;
+                L.C[s] = acc;
+            }
+        } else {
+            float fl = (ap.eps * S) / (float)Meff;
+            for (uint32_t s = 0; s < Meff; ++s) {
+                float qt = L.Q[s] + fl;
+                L.Qt[s] = qt;
+                acc = s ? acc + qt : qt;
+                L.C[s] = acc;
+            }
+        }
+    }
+    __syncthreads();
+#pragma unroll
+    for (int j = 0; j < kMaxPerLane; ++j) {
+        uint32_t s = lane + kWave * j;
+        if (j < (int)per && s < Meff) {
+            uint32_t nd = L.node[s];
+            cells.node[base + s] = nd;
+            cells.end[base + s] = ap.tree.last[nd] + 1u;
+            cells.Q[base + s] = L.Q[s];
+            cells.Qt[base + s] = L.Qt[s];
+            cells.C[base + s] = L.C[s];
+            cells.sum[base + s] = 0ull;
+            cells.cnt[base + s] = 0u;
+        }
+    }
+    if (lane == 0) cells.ready[c] = 1u;
+    __syncthreads();
+}
+
+// One block = one wavefront; it walks the list of created cells.
+__global__ void __launch_bounds__(kWave) k_adapt(AdaptParams ap) {
+    __shared__ AdaptLds L;
+    const uint32_t n_live = *ap.cells.n_live;
+    for (uint32_t li = blockIdx.x; li < n_live; li += gridDim.x) adapt_cell(ap, ap.cells.live[li], L);
+}
+
+// The same over every scene of a batch.
+__global__ void __launch_bounds__(kWave) k_batch_adapt(const AdaptParams* __restrict__ aps, uint32_t n_scenes) {
+    __shared__ AdaptLds L;
+    for (uint32_t sc = 0; sc < n_scenes; ++sc) {
+        const AdaptParams ap = aps[sc];
+        const uint32_t n_live = *ap.cells.n_live;
+        for (uint32_t li = blockIdx.x; li < n_live; li += gridDim.x) adapt_cell(ap, ap.cells.live[li], L);
     }
 }
 
@@ -232,6 +246,11 @@ __global__ void k_gather_cells(DevCells c, uint32_t Meff, const uint32_t* __rest
 }
 
 }  // namespace
+
+hipError_t launch_batch_adapt(const AdaptParams* aps, uint32_t n_scenes, hipStream_t s) {
+    hipLaunchKernelGGL(k_batch_adapt, dim3(8192), dim3(kWave), 0, s, aps, n_scenes);
+    return hipGetLastError();
+}
 
 hipError_t launch_adapt(const AdaptParams& ap, hipStream_t s) {
     // enough waves to cover the chip several times over; each walks the

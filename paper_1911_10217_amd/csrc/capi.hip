@@ -735,4 +735,263 @@ int rlc_get_timing(rlc_ctx* c, double* h_ms_fused, double* h_ms_adapt, uint32_t*
     return RLC_OK;
 }
 
+// ---------------------------------------------------------------------------
+// batched passes
+// ---------------------------------------------------------------------------
+}  // extern "C"
+
+struct rlc_batch {
+    std::vector<rlc_batch_scene> scenes;
+    hipStream_t stream = nullptr;
+    rlc_schedule sched{512, 8, 1, 0};
+    uint32_t n_cu = 256;
+    uint32_t total_items = 0;
+    BatchScene* d_scenes = nullptr;
+    AdaptParams* d_adapt = nullptr;
+    uint32_t* d_counter = nullptr;
+    uint32_t* d_frame = nullptr;
+    std::vector<uint32_t*> perms;  // cell-order visiting permutation per scene
+    hipGraph_t graph = nullptr;
+    hipGraphExec_t exec = nullptr;
+    uint32_t next_frame = 0;
+    bool frame_known = false;
+};
+
+namespace {
+
+void batch_drop_graph(rlc_batch* b) {
+    if (b->exec) (void)hipGraphExecDestroy(b->exec);
+    if (b->graph) (void)hipGraphDestroy(b->graph);
+    b->exec = nullptr;
+    b->graph = nullptr;
+}
+
+// Visiting order of a scene's points sorted by cell (stable: ties keep
+// input order), built once with the library's radix sort.
+int batch_make_perm(rlc_ctx* c, const rlc_batch_scene& sc, uint32_t** out) {
+    *out = nullptr;
+    uint32_t *lin = nullptr, *idx = nullptr, *kt = nullptr, *vt = nullptr, *hist = nullptr;
+    int r = dalloc(c, &lin, sc.P);
+    if (r == RLC_OK) r = dalloc(c, &idx, sc.P);
+    if (r == RLC_OK) r = dalloc(c, &kt, sc.P);
+    if (r == RLC_OK) r = dalloc(c, &vt, sc.P);
+    if (r == RLC_OK) r = dalloc(c, &hist, radix_sort_hist_entries(sc.P));
+    hipError_t e = hipSuccess;
+    if (r == RLC_OK) {
+        uint64_t cells = (uint64_t)c->cfg.grid_dims[0] * c->cfg.grid_dims[1] * c->cfg.grid_dims[2];
+        int bits = 1;
+        while (bits < 32 && (1ull << bits) < cells) ++bits;
+        e = launch_cell_lin(frame_params(c), sc.d_pos, sc.P, lin, idx, c->stream);
+        if (e == hipSuccess) e = radix_sort_pairs(lin, idx, kt, vt, hist, sc.P, bits, c->stream);
+        if (e == hipSuccess) e = hipStreamSynchronize(c->stream);
+    }
+    dfree(lin);
+    dfree(kt);
+    dfree(vt);
+    dfree(hist);
+    if (r != RLC_OK || e != hipSuccess) {
+        dfree(idx);
+        return r != RLC_OK ? r : fail(c, RLC_EHIP, "cell order: %s", hipGetErrorString(e));
+    }
+    *out = idx;
+    return RLC_OK;
+}
+
+int batch_upload(rlc_batch* b) {
+    rlc_ctx* c0 = b->scenes[0].ctx;
+    const uint32_t tile = b->sched.tile;
+    std::vector<BatchScene> hs(b->scenes.size());
+    std::vector<AdaptParams> ha(b->scenes.size());
+    uint32_t item = 0;
+    for (size_t i = 0; i < b->scenes.size(); ++i) {
+        const rlc_batch_scene& sc = b->scenes[i];
+        BatchScene& d = hs[i];
+        d.fp = frame_params(sc.ctx);
+        d.pos = sc.d_pos;
+        d.nrm = sc.d_nrm;
+        d.perm = b->sched.cell_sorted ? b->perms[i] : nullptr;
+        d.radiance = sc.d_radiance;
+        d.P = sc.P;
+        d.spp = sc.spp;
+        uint64_t n = (uint64_t)sc.P * sc.spp;
+        d.items = (uint32_t)((n + tile - 1) / tile);
+        d.item_begin = item;
+        item += d.items;
+        ha[i] = adapt_params(sc.ctx);
+    }
+    b->total_items = item;
+    RLC_HIP(c0, hipMemcpy(b->d_scenes, hs.data(), sizeof(BatchScene) * hs.size(), hipMemcpyHostToDevice));
+    RLC_HIP(c0, hipMemcpy(b->d_adapt, ha.data(), sizeof(AdaptParams) * ha.size(), hipMemcpyHostToDevice));
+    return RLC_OK;
+}
+
+// Capture one pass (reset the work counter, the persistent frame kernel, the
+// adapt kernel over every scene, advance the device frame index).
+int batch_capture(rlc_batch* b) {
+    rlc_ctx* c0 = b->scenes[0].ctx;
+    batch_drop_graph(b);
+    RLC_TRY(batch_upload(b));
+    const uint32_t grid = b->sched.blocks_per_cu * b->n_cu;
+    const uint32_t rounds = b->sched.tile / 256u;
+    RLC_HIP(c0, hipStreamBeginCapture(b->stream, hipStreamCaptureModeThreadLocal));
+    hipError_t e = launch_batch_begin(b->d_counter, b->stream);
+    if (e == hipSuccess)
+        e = launch_batch_frame(b->d_scenes, (uint32_t)b->scenes.size(), b->total_items, rounds, b->sched.dynamic,
+                               grid, b->d_counter, b->d_frame, b->stream);
+    if (e == hipSuccess) e = launch_batch_adapt(b->d_adapt, (uint32_t)b->scenes.size(), b->stream);
+    if (e == hipSuccess) e = launch_batch_end(b->d_frame, b->stream);
+    hipGraph_t g = nullptr;
+    hipError_t e2 = hipStreamEndCapture(b->stream, &g);
+    if (e != hipSuccess || e2 != hipSuccess) {
+        if (g) (void)hipGraphDestroy(g);
+        return fail(c0, RLC_EHIP, "batch graph capture: %s", hipGetErrorString(e != hipSuccess ? e : e2));
+    }
+    b->graph = g;
+    RLC_HIP(c0, hipGraphInstantiate(&b->exec, b->graph, nullptr, nullptr, 0));
+    return RLC_OK;
+}
+
+bool valid_schedule(const rlc_schedule& s) {
+    return s.tile >= 256 && s.tile % 256 == 0 && s.tile <= 65536 && s.blocks_per_cu >= 1 && s.blocks_per_cu <= 64 &&
+           s.dynamic <= 1 && s.cell_sorted <= 1;
+}
+
+}  // namespace
+
+extern "C" {
+
+int rlc_batch_create(const rlc_batch_scene* scenes, uint32_t n, void* stream, rlc_batch** out) {
+    if (!out) return RLC_EINVAL;
+    *out = nullptr;
+    if (!scenes || n == 0) return RLC_EINVAL;
+    if (!stream) return fail(scenes[0].ctx, RLC_EINVAL, "a batch needs a non-default stream (graph capture)");
+    for (uint32_t i = 0; i < n; ++i) {
+        const rlc_batch_scene& sc = scenes[i];
+        if (!sc.ctx) return RLC_EINVAL;
+        if (!sc.ctx->tree_built) return fail(sc.ctx, RLC_ESTATE, "batch scene %u: the light tree has not been built", i);
+        if (sc.ctx->stream != (hipStream_t)stream)
+            return fail(sc.ctx, RLC_EINVAL, "batch scene %u: its context uses another stream", i);
+        if (sc.P && (!sc.d_pos || !sc.d_nrm || !sc.d_radiance))
+            return fail(sc.ctx, RLC_EINVAL, "batch scene %u: null array", i);
+        if (sc.spp == 0 || sc.spp > 64 || (sc.spp & (sc.spp - 1)))
+            return fail(sc.ctx, RLC_EINVAL, "batch scene %u: spp must be a power of two <= 64", i);
+        if ((uint64_t)sc.P * sc.spp > 0xFFFFFFFFull) return fail(sc.ctx, RLC_EINVAL, "batch scene %u too large", i);
+        for (uint32_t j = 0; j < i; ++j)
+            if (scenes[j].ctx == sc.ctx) return fail(sc.ctx, RLC_EINVAL, "a context appears twice in the batch");
+    }
+    rlc_batch* b = new (std::nothrow) rlc_batch();
+    if (!b) return RLC_ENOMEM;
+    b->scenes.assign(scenes, scenes + n);
+    b->stream = (hipStream_t)stream;
+    rlc_ctx* c0 = scenes[0].ctx;
+    int dev = 0;
+    hipDeviceProp_t prop;
+    if (hipGetDevice(&dev) == hipSuccess && hipGetDeviceProperties(&prop, dev) == hipSuccess && prop.multiProcessorCount > 0)
+        b->n_cu = (uint32_t)prop.multiProcessorCount;
+    int r = dalloc(c0, &b->d_scenes, n);
+    if (r == RLC_OK) r = dalloc(c0, &b->d_adapt, n);
+    if (r == RLC_OK) r = dalloc(c0, &b->d_counter, 1);
+    if (r == RLC_OK) r = dalloc(c0, &b->d_frame, 1);
+    b->perms.assign(n, nullptr);
+    for (uint32_t i = 0; r == RLC_OK && i < n; ++i)
+        if (scenes[i].P) r = batch_make_perm(scenes[i].ctx, scenes[i], &b->perms[i]);
+    if (r == RLC_OK) {
+        hipError_t e = launch_set_u32(b->d_frame, 0u, b->stream);
+        if (e != hipSuccess) r = fail(c0, RLC_EHIP, "batch: %s", hipGetErrorString(e));
+    }
+    if (r == RLC_OK) r = batch_capture(b);
+    if (r != RLC_OK) {
+        rlc_batch_destroy(b);
+        return r;
+    }
+    *out = b;
+    return RLC_OK;
+}
+
+int rlc_batch_destroy(rlc_batch* b) {
+    if (!b) return RLC_OK;
+    (void)hipStreamSynchronize(b->stream);
+    batch_drop_graph(b);
+    dfree(b->d_scenes);
+    dfree(b->d_adapt);
+    dfree(b->d_counter);
+    dfree(b->d_frame);
+    for (auto& p : b->perms) dfree(p);
+    delete b;
+    return RLC_OK;
+}
+
+int rlc_batch_set_schedule(rlc_batch* b, const rlc_schedule* sched) {
+    if (!b || !sched) return RLC_EINVAL;
+    if (!valid_schedule(*sched)) return fail(b->scenes[0].ctx, RLC_EINVAL, "invalid schedule");
+    RLC_HIP(b->scenes[0].ctx, hipStreamSynchronize(b->stream));
+    b->sched = *sched;
+    return batch_capture(b);
+}
+
+int rlc_batch_get_schedule(rlc_batch* b, rlc_schedule* sched) {
+    if (!b || !sched) return RLC_EINVAL;
+    *sched = b->sched;
+    return RLC_OK;
+}
+
+int rlc_batch_frame(rlc_batch* b, uint32_t frame) {
+    if (!b) return RLC_EINVAL;
+    rlc_ctx* c0 = b->scenes[0].ctx;
+    if (!b->frame_known || frame != b->next_frame) RLC_HIP(c0, launch_set_u32(b->d_frame, frame, b->stream));
+    RLC_HIP(c0, hipGraphLaunch(b->exec, b->stream));
+    b->next_frame = frame + 1;
+    b->frame_known = true;
+    return RLC_OK;
+}
+
+int rlc_batch_autotune(rlc_batch* b, uint32_t passes, rlc_schedule* h_best, rlc_schedule* h_cands, double* h_ms,
+                       uint32_t* h_ncand) {
+    if (!b || passes == 0) return RLC_EINVAL;
+    rlc_ctx* c0 = b->scenes[0].ctx;
+    std::vector<rlc_schedule> cands;
+    for (uint32_t tile : {256u, 512u, 1024u, 2048u})
+        for (uint32_t bpc : {4u, 8u, 16u})
+            for (uint32_t dyn : {0u, 1u})
+                for (uint32_t srt : {0u, 1u}) cands.push_back(rlc_schedule{tile, bpc, dyn, srt});
+    hipEvent_t e0 = nullptr, e1 = nullptr;
+    RLC_HIP(c0, hipEventCreate(&e0));
+    RLC_HIP(c0, hipEventCreate(&e1));
+    std::vector<double> ms(cands.size(), 0.0);
+    size_t best = 0;
+    int r = RLC_OK;
+    for (size_t i = 0; i < cands.size() && r == RLC_OK; ++i) {
+        for (auto& sc : b->scenes) r = r == RLC_OK ? reset_cells(sc.ctx) : r;
+        if (r == RLC_OK) r = rlc_batch_set_schedule(b, &cands[i]);
+        if (r == RLC_OK) r = rlc_batch_frame(b, 0);  // warm-up pass
+        if (r != RLC_OK) break;
+        hipError_t e = hipEventRecord(e0, b->stream);
+        for (uint32_t f = 1; e == hipSuccess && f <= passes; ++f)
+            e = rlc_batch_frame(b, f) == RLC_OK ? hipSuccess : hipErrorUnknown;
+        if (e == hipSuccess) e = hipEventRecord(e1, b->stream);
+        if (e == hipSuccess) e = hipEventSynchronize(e1);
+        float t = 0.0f;
+        if (e == hipSuccess) e = hipEventElapsedTime(&t, e0, e1);
+        if (e != hipSuccess) r = fail(c0, RLC_EHIP, "autotune timing: %s", hipGetErrorString(e));
+        ms[i] = (double)t / passes;
+        if (ms[i] < ms[best]) best = i;
+    }
+    (void)hipEventDestroy(e0);
+    (void)hipEventDestroy(e1);
+    if (r != RLC_OK) return r;
+    for (auto& sc : b->scenes) RLC_TRY(reset_cells(sc.ctx));
+    RLC_TRY(rlc_batch_set_schedule(b, &cands[best]));
+    b->frame_known = false;
+    if (h_best) *h_best = cands[best];
+    if (h_ncand) {
+        uint32_t cap = *h_ncand;
+        for (uint32_t i = 0; i < cands.size() && i < cap; ++i) {
+            if (h_cands) h_cands[i] = cands[i];
+            if (h_ms) h_ms[i] = ms[i];
+        }
+        *h_ncand = (uint32_t)cands.size();
+    }
+    return RLC_OK;
+}
+
 }  // extern "C"

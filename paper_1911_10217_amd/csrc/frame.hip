@@ -56,13 +56,18 @@ __device__ __forceinline__ void agg_add(AggTable& t, const FrameParams& fp, uint
     }
 }
 
-__device__ __forceinline__ void agg_flush(const AggTable& t, const FrameParams& fp) {
+// Each thread flushes and clears its own slots, so no barrier is needed
+// between the two; the caller syncs before the table is used again.
+__device__ __forceinline__ void agg_flush(AggTable& t, const FrameParams& fp) {
     for (int j = threadIdx.x; j < kAggSlots; j += kBlock) {
         const uint32_t n = t.cnt[j];
         if (n) {
             const size_t idx = t.bin[j];
             atomicAdd(&fp.cells.sum[idx], t.sum[j]);
             atomicAdd(&fp.cells.cnt[idx], n);
+            t.bin[j] = kNoBin;
+            t.sum[j] = 0ull;
+            t.cnt[j] = 0u;
         }
     }
 }
@@ -160,22 +165,24 @@ __global__ void __launch_bounds__(kBlock) k_learn(FrameParams fp, rlc_samples in
     agg_flush(agg, fp);
 }
 
-// Fused pass: one lane per sample (point p = i / spp, sample k = i % spp).
-__global__ void __launch_bounds__(kBlock) k_frame(FrameParams fp, const float* __restrict__ pos,
-                                                  const float* __restrict__ nrm, uint32_t P, uint32_t spp,
-                                                  uint32_t frame, float* __restrict__ radiance) {
-    __shared__ AggTable agg;
-    agg_clear(agg);
-    __syncthreads();
-    uint32_t b = xcd_block(blockIdx.x, gridDim.x);
-    size_t i = (size_t)b * kBlock + threadIdx.x;
-    size_t n = (size_t)P * spp;
-    bool valid = i < n;
+// One block's samples i0 + threadIdx.x of a pass: sample, shade and learn
+// (section 3).  Sample i belongs to point q = i / spp, sample k = i % spp;
+// with a point order `perm` the point is perm[q] (its random numbers and
+// radiance are those of that point, so any order gives the same results).
+// The aggregation table must be clear on entry and is clear on exit; the
+// block is synchronised on exit.
+__device__ void frame_block(const FrameParams& fp, const float* __restrict__ pos, const float* __restrict__ nrm,
+                            const uint32_t* __restrict__ perm, uint32_t P, uint32_t spp, uint32_t frame,
+                            float* __restrict__ radiance, size_t i0, AggTable& agg) {
+    const size_t i = i0 + threadIdx.x;
+    const size_t n = (size_t)P * spp;
+    const bool valid = i < n;
     float e[3] = {0.0f, 0.0f, 0.0f};
     uint32_t p = 0, k = 0;
     if (valid) {
-        p = (uint32_t)(i / spp);
+        const uint32_t q = (uint32_t)(i / spp);
         k = (uint32_t)(i % spp);
+        p = perm ? perm[q] : q;
         float x[3] = {pos[3 * (size_t)p], pos[3 * (size_t)p + 1], pos[3 * (size_t)p + 2]};
         float nn[3] = {nrm[3 * (size_t)p], nrm[3 * (size_t)p + 1], nrm[3 * (size_t)p + 2]};
         Sample sm;
@@ -206,6 +213,66 @@ __global__ void __launch_bounds__(kBlock) k_frame(FrameParams fp, const float* _
         atomicAdd(&radiance[3 * (size_t)p + 1], e[1] * inv_spp);
         atomicAdd(&radiance[3 * (size_t)p + 2], e[2] * inv_spp);
     }
+    __syncthreads();
+}
+
+// Fused pass: one lane per sample.
+__global__ void __launch_bounds__(kBlock) k_frame(FrameParams fp, const float* __restrict__ pos,
+                                                  const float* __restrict__ nrm, uint32_t P, uint32_t spp,
+                                                  uint32_t frame, float* __restrict__ radiance) {
+    __shared__ AggTable agg;
+    agg_clear(agg);
+    __syncthreads();
+    const uint32_t b = xcd_block(blockIdx.x, gridDim.x);
+    frame_block(fp, pos, nrm, nullptr, P, spp, frame, radiance, (size_t)b * kBlock, agg);
+}
+
+// Batched pass over several scenes: persistent blocks take work items of
+// `rounds` x 256 samples, either from a counter (dynamic) or as contiguous
+// ranges assigned per XCD (static).  Item -> scene by the scenes' first items.
+__global__ void __launch_bounds__(kBlock) k_batch_frame(const BatchScene* __restrict__ scenes, uint32_t n_scenes,
+                                                        uint32_t total_items, uint32_t rounds, uint32_t dynamic,
+                                                        uint32_t* __restrict__ counter,
+                                                        const uint32_t* __restrict__ frame_ptr) {
+    __shared__ AggTable agg;
+    __shared__ uint32_t s_item;
+    agg_clear(agg);
+    const uint32_t frame = *frame_ptr;
+    const uint32_t lb = xcd_block(blockIdx.x, gridDim.x);
+    const uint32_t per_block = (total_items + gridDim.x - 1) / gridDim.x;
+    uint32_t next = lb * per_block;
+    const uint32_t stop = min(total_items, next + per_block);
+    __syncthreads();
+    for (;;) {
+        uint32_t item;
+        if (dynamic) {
+            if (threadIdx.x == 0) s_item = atomicAdd(counter, 1u);
+            __syncthreads();
+            item = __builtin_amdgcn_readfirstlane(s_item);
+            if (item >= total_items) break;
+        } else {
+            if (next >= stop) break;
+            item = next++;
+        }
+        uint32_t sc = 0;
+        while (sc + 1u < n_scenes && scenes[sc + 1u].item_begin <= item) ++sc;
+        const BatchScene& S = scenes[sc];
+        const size_t first = (size_t)(item - S.item_begin) * rounds * kBlock;
+        for (uint32_t r = 0; r < rounds; ++r)
+            frame_block(S.fp, S.pos, S.nrm, S.perm, S.P, S.spp, frame, S.radiance, first + (size_t)r * kBlock, agg);
+    }
+}
+
+__global__ void k_batch_begin(uint32_t* counter) { *counter = 0u; }
+__global__ void k_batch_end(uint32_t* frame) { *frame += 1u; }
+__global__ void k_set_u32(uint32_t* p, uint32_t v) { *p = v; }
+
+__global__ void __launch_bounds__(kBlock) k_cell_lin(FrameParams fp, const float* __restrict__ pos, uint32_t n,
+                                                     uint32_t* __restrict__ lin, uint32_t* __restrict__ idx) {
+    size_t i = (size_t)blockIdx.x * kBlock + threadIdx.x;
+    if (i >= n) return;
+    lin[i] = cell_linear(fp, pos[3 * i], pos[3 * i + 1], pos[3 * i + 2]);
+    idx[i] = (uint32_t)i;
 }
 
 __global__ void k_zero_f32(float* a, size_t n) {
@@ -271,6 +338,37 @@ hipError_t launch_frame(const FrameParams& fp, const float* pos, const float* nr
 hipError_t launch_cell_keys(const FrameParams& fp, const float* pos, uint32_t n, uint64_t* keys, hipStream_t s) {
     if (n == 0) return hipSuccess;
     hipLaunchKernelGGL(k_cell_keys, dim3(blocks_for(n)), dim3(kBlock), 0, s, fp, pos, n, keys);
+    return hipGetLastError();
+}
+
+hipError_t launch_cell_lin(const FrameParams& fp, const float* pos, uint32_t n, uint32_t* lin, uint32_t* idx,
+                           hipStream_t s) {
+    if (n == 0) return hipSuccess;
+    hipLaunchKernelGGL(k_cell_lin, dim3(blocks_for(n)), dim3(kBlock), 0, s, fp, pos, n, lin, idx);
+    return hipGetLastError();
+}
+
+hipError_t launch_batch_begin(uint32_t* counter, hipStream_t s) {
+    hipLaunchKernelGGL(k_batch_begin, dim3(1), dim3(1), 0, s, counter);
+    return hipGetLastError();
+}
+
+hipError_t launch_batch_end(uint32_t* frame, hipStream_t s) {
+    hipLaunchKernelGGL(k_batch_end, dim3(1), dim3(1), 0, s, frame);
+    return hipGetLastError();
+}
+
+hipError_t launch_set_u32(uint32_t* p, uint32_t v, hipStream_t s) {
+    hipLaunchKernelGGL(k_set_u32, dim3(1), dim3(1), 0, s, p, v);
+    return hipGetLastError();
+}
+
+hipError_t launch_batch_frame(const BatchScene* scenes, uint32_t n_scenes, uint32_t total_items, uint32_t rounds,
+                              uint32_t dynamic, uint32_t grid, uint32_t* counter, const uint32_t* frame,
+                              hipStream_t s) {
+    if (total_items == 0) return hipSuccess;
+    hipLaunchKernelGGL(k_batch_frame, dim3(grid), dim3(kBlock), 0, s, scenes, n_scenes, total_items, rounds, dynamic,
+                       counter, frame);
     return hipGetLastError();
 }
 

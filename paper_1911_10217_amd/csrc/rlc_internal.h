@@ -78,6 +78,20 @@ struct FrameParams {
     uint32_t* err;
 };
 
+// One scene of a batched pass: its parameters, inputs and output, and the
+// first work item that belongs to it.
+struct BatchScene {
+    FrameParams fp;
+    const float* pos;
+    const float* nrm;
+    const uint32_t* perm;       // point visiting order, or null for input order
+    float* radiance;
+    uint32_t P;
+    uint32_t spp;
+    uint32_t item_begin;
+    uint32_t items;
+};
+
 struct AdaptParams {
     DevTree tree;
     DevCut tmpl;
@@ -352,9 +366,18 @@ hipError_t launch_learn(const FrameParams& fp, const rlc_samples& in, const floa
 hipError_t launch_frame(const FrameParams& fp, const float* pos, const float* nrm, uint32_t P, uint32_t spp,
                         uint32_t frame, float* radiance, hipStream_t s);
 hipError_t launch_cell_keys(const FrameParams& fp, const float* pos, uint32_t n, uint64_t* keys, hipStream_t s);
+hipError_t launch_cell_lin(const FrameParams& fp, const float* pos, uint32_t n, uint32_t* lin, uint32_t* idx,
+                           hipStream_t s);
+hipError_t launch_batch_begin(uint32_t* counter, hipStream_t s);
+hipError_t launch_batch_end(uint32_t* frame, hipStream_t s);
+hipError_t launch_set_u32(uint32_t* p, uint32_t v, hipStream_t s);
+hipError_t launch_batch_frame(const BatchScene* scenes, uint32_t n_scenes, uint32_t total_items, uint32_t rounds,
+                              uint32_t dynamic, uint32_t grid, uint32_t* counter, const uint32_t* frame,
+                              hipStream_t s);
 
 // adapt.hip
 hipError_t launch_adapt(const AdaptParams& ap, hipStream_t s);
+hipError_t launch_batch_adapt(const AdaptParams* aps, uint32_t n_scenes, hipStream_t s);
 hipError_t launch_gather_cells(DevCells c, uint32_t Meff, const uint32_t* slots, uint32_t n, uint32_t* node,
                                uint32_t* end, float* Q, float* Qt, float* C, unsigned long long* sum,
                                uint32_t* cnt, hipStream_t s);

@@ -34,6 +34,8 @@ EXPORTS = (
     "rlc_sample", "rlc_shade", "rlc_learn", "rlc_adapt_cuts", "rlc_frame", "rlc_visible",
     "rlc_cell_keys", "rlc_image_error", "rlc_sync", "rlc_last_error", "rlc_num_cells", "rlc_meff",
     "rlc_dump_cells", "rlc_dump_tree", "rlc_get_template", "rlc_set_timing", "rlc_get_timing",
+    "rlc_batch_create", "rlc_batch_destroy", "rlc_batch_set_schedule", "rlc_batch_get_schedule",
+    "rlc_batch_autotune", "rlc_batch_frame",
 )
 
 
@@ -72,6 +74,19 @@ class rlc_config(ctypes.Structure):
 class rlc_samples(ctypes.Structure):
     _fields_ = [(n, ctypes.c_void_p) for n in
                 ("d_key", "d_cell", "d_ready", "d_slot", "d_light", "d_inv_pdf", "d_y")]
+
+
+class rlc_batch_scene(ctypes.Structure):
+    _fields_ = [("ctx", ctypes.c_void_p), ("d_pos", ctypes.c_void_p), ("d_nrm", ctypes.c_void_p),
+                ("d_radiance", ctypes.c_void_p), ("P", ctypes.c_uint32), ("spp", ctypes.c_uint32)]
+
+
+class rlc_schedule(ctypes.Structure):
+    _fields_ = [("tile", ctypes.c_uint32), ("blocks_per_cu", ctypes.c_uint32), ("dynamic", ctypes.c_uint32),
+                ("cell_sorted", ctypes.c_uint32)]
+
+    def as_dict(self):
+        return {k: int(getattr(self, k)) for k, _ in self._fields_}
 
 
 _vp = ctypes.c_void_p
@@ -116,6 +131,13 @@ def _declare(L):
     L.rlc_dump_cells.argtypes = [_vp, _u32] + [_vp] * 9
     L.rlc_dump_tree.argtypes = [_vp] + [_vp] * 7
     L.rlc_get_template.argtypes = [_vp, _vp, _vp, _vp]
+    L.rlc_batch_create.argtypes = [ctypes.POINTER(rlc_batch_scene), _u32, _vp, ctypes.POINTER(_vp)]
+    L.rlc_batch_destroy.argtypes = [_vp]
+    L.rlc_batch_set_schedule.argtypes = [_vp, ctypes.POINTER(rlc_schedule)]
+    L.rlc_batch_get_schedule.argtypes = [_vp, ctypes.POINTER(rlc_schedule)]
+    L.rlc_batch_autotune.argtypes = [_vp, _u32, ctypes.POINTER(rlc_schedule), ctypes.POINTER(rlc_schedule),
+                                     _vp, _vp]
+    L.rlc_batch_frame.argtypes = [_vp, _u32]
     L.rlc_set_timing.argtypes = [_vp, i]
     L.rlc_get_timing.argtypes = [_vp, _vp, _vp, _vp]
     for name in EXPORTS:
@@ -370,3 +392,74 @@ class Context:
         n = np.zeros(1, np.uint32)
         self._check(lib().rlc_get_timing(self._h, f.ctypes.data, a.ctypes.data, n.ctypes.data), "rlc_get_timing")
         return float(f[0]), float(a[0]), int(n[0])
+
+
+class Batch:
+    """rlc_batch: one pass of several scenes per graph launch.
+
+    scenes: list of (Context, pos, nrm, spp); radiance tensors are allocated
+    here and returned by rlc_batch_frame.  All contexts must have been created
+    on `stream` (a torch.cuda.Stream, not the default stream)."""
+
+    def __init__(self, scenes, stream):
+        import torch
+        L = lib()
+        self._keep = []
+        self.radiance = []
+        arr = (rlc_batch_scene * len(scenes))()
+        for i, (ctx, pos, nrm, spp) in enumerate(scenes):
+            _dev(pos, torch.float32, "pos")
+            _dev(nrm, torch.float32, "nrm")
+            P = pos.numel() // 3
+            rad = torch.zeros((P, 3), dtype=torch.float32, device=pos.device)
+            self.radiance.append(rad)
+            self._keep += [ctx, pos, nrm, rad]
+            arr[i] = rlc_batch_scene(ctx._h.value, _ptr(pos), _ptr(nrm), _ptr(rad), P, int(spp))
+        self._ctx0 = scenes[0][0]
+        h = _vp()
+        rc = L.rlc_batch_create(arr, len(scenes), _vp(stream.cuda_stream), ctypes.byref(h))
+        if rc != RLC_OK:
+            msg = L.rlc_last_error(self._ctx0._h)
+            raise RLCError(rc, "rlc_batch_create: %s" % (msg.decode() if msg else ""))
+        self._h = h
+
+    def _check(self, rc, what):
+        if rc != RLC_OK:
+            msg = lib().rlc_last_error(self._ctx0._h)
+            raise RLCError(rc, "%s: %s" % (what, msg.decode() if msg else ""))
+
+    def close(self):
+        h = getattr(self, "_h", None)
+        if h is not None and h.value:
+            lib().rlc_batch_destroy(h)
+        self._h = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+    def rlc_batch_frame(self, frame: int):
+        self._check(lib().rlc_batch_frame(self._h, int(frame)), "rlc_batch_frame")
+        return self.radiance
+
+    def rlc_batch_set_schedule(self, tile=512, blocks_per_cu=8, dynamic=1, cell_sorted=0):
+        sc = rlc_schedule(tile, blocks_per_cu, dynamic, cell_sorted)
+        self._check(lib().rlc_batch_set_schedule(self._h, ctypes.byref(sc)), "rlc_batch_set_schedule")
+
+    def rlc_batch_get_schedule(self) -> dict:
+        sc = rlc_schedule()
+        self._check(lib().rlc_batch_get_schedule(self._h, ctypes.byref(sc)), "rlc_batch_get_schedule")
+        return sc.as_dict()
+
+    def rlc_batch_autotune(self, passes: int = 2):
+        best = rlc_schedule()
+        cap = 64
+        cands = (rlc_schedule * cap)()
+        ms = np.zeros(cap, np.float64)
+        n = np.array([cap], np.uint32)
+        self._check(lib().rlc_batch_autotune(self._h, int(passes), ctypes.byref(best), cands, ms.ctypes.data,
+                                             n.ctypes.data), "rlc_batch_autotune")
+        k = int(n[0])
+        return best.as_dict(), [(cands[i].as_dict(), float(ms[i])) for i in range(min(k, cap))]
