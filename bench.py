@@ -110,16 +110,214 @@ def write_traffic(fetch_csv, write_csv, copy_mib):
         json.dump(out, f, indent=1)
     print(json.dumps(out))
 
+MLP_FLOP_PER_TUPLE = 2 * (144 * 64 + 3 * 64 * 64) + 2 * 3 * 64 * 64 + 2 * (144 * 64 + 3 * 64 * 64)
+PEAK_BF16_TFLOPS = 2500.0
+LEARNED_TRUTH = os.path.join(ROOT, "tests", "golden", "learned_truth.txt")
+
+
+def run_learned(args, np, torch, rlc, scenes, dev):
+    """The learned proposal against the plain method at equal GPU time.
+
+    Workload: the tiny scene (1,024 emissive triangles, 4,096 points, 64 box
+    occluders, 8^3 cells, cut size 16, 16 spp per pass).  Plain: passes of
+    the method from a fresh cell table.  Learned: 8 passes of the method that
+    log (point, fixed-cut node, weight) for every sample, training of the MLP
+    (epochs x minibatch Adam over the 524,288 logged tuples), one forward pass
+    for the per-point cdf, then passes that draw from the 50/50 mixture.  A
+    GPU-time budget is the plain method's time for n passes; each form's
+    image is the mean of the passes that fit in it.  MSE against the FP64
+    oracle truth at every 16th point (a stored table written by the oracle).
+    All times are HIP events on the library's stream, training included."""
+    s = scenes.make_tiny()
+    p = dict(s.params)
+    spp = int(p["spp"])
+    P = s.P
+    log_passes = 8
+    budgets = [int(x) for x in args.budgets.split(",")]
+    nmax = max(budgets)
+    truth = np.loadtxt(LEARNED_TRUTH)
+    ref_pid = truth[:, 0].astype(np.int64)
+    ref = truth[:, 1:]
+
+    t = lambda a: torch.from_numpy(np.ascontiguousarray(a)).to(dev)
+    pos, nrm = t(s.pos), t(s.nrm)
+    ctx = rlc.Context(p)
+    ctx.rlc_build_light_tree(t(s.tri), t(s.emit))
+    ctx.rlc_set_occluders(t(s.boxes))
+    rad = torch.empty((nmax, P, 3), dtype=torch.float32, device=dev)
+    n_log = log_passes * P * spp
+    lp = torch.empty(n_log, dtype=torch.int32, device=dev)
+    ln = torch.empty(n_log, dtype=torch.int32, device=dev)
+    lw = torch.empty(n_log, dtype=torch.float32, device=dev)
+
+    def events(n):
+        return [torch.cuda.Event(enable_timing=True) for _ in range(n)]
+
+    # points inside the emitter band (y >= 0.9) can lie arbitrarily close to
+    # a triangle: their estimates are heavy-tailed, so the MSE is also given
+    # over the points below the band
+    below = s.pos[ref_pid, 1] < 0.9
+
+    def mse_curve(frames):
+        img = rad[:frames, ref_pid].double().cpu().numpy()
+        mean = np.cumsum(img, axis=0) / np.arange(1, frames + 1)[:, None, None]
+        err = (mean - ref[None]) ** 2
+        return err.mean(axis=(1, 2)), err[:, below].mean(axis=(1, 2))
+
+    # warm-up of every kernel involved, then a fresh state
+    print("[bench] learned: warm-up", file=sys.stderr, flush=True)
+    for f in range(2):
+        ctx.rlc_frame(pos, nrm, spp, f, rad[f])
+    ctx.rlc_mlp_init(p["seed"])
+    ctx.rlc_set_sample_log(lp[:P * spp], ln[:P * spp], lw[:P * spp])
+    ctx.rlc_frame(pos, nrm, spp, 0, rad[0])
+    ctx.rlc_set_sample_log()
+    ctx.rlc_mlp_train(pos, nrm, lp[:P * spp], ln[:P * spp], lw[:P * spp], 1, args.mlp_batch, args.mlp_lr)
+    cdf, _ = ctx.rlc_mlp_forward(pos, nrm)
+    ctx.rlc_set_mixture(cdf, 0.5)
+    ctx.rlc_frame(pos, nrm, spp, 1, rad[1])
+    ctx.rlc_set_mixture()
+    torch.cuda.synchronize()
+
+    # ---- plain: nmax passes, an event after each ----
+    ctx.rlc_reset_cells()
+    ev = events(nmax + 1)
+    torch.cuda.synchronize()
+    ev[0].record()
+    for f in range(nmax):
+        ctx.rlc_frame(pos, nrm, spp, f, rad[f])
+        ev[f + 1].record()
+    torch.cuda.synchronize()
+    plain_t = np.array([ev[0].elapsed_time(e) for e in ev[1:]])
+    plain_mse, plain_mse_b = mse_curve(nmax)
+
+    # ---- learned: log, train, forward, mixture passes ----
+    ctx.rlc_reset_cells()
+    ctx.rlc_mlp_init(p["seed"])
+    k_mix = nmax
+    ev = events(log_passes + 1)
+    ev_train, ev_fwd = events(2)
+    ev_mix = events(k_mix)
+    torch.cuda.synchronize()
+    ev[0].record()
+    for f in range(log_passes):
+        sl = slice(f * P * spp, (f + 1) * P * spp)
+        ctx.rlc_set_sample_log(lp[sl], ln[sl], lw[sl])
+        ctx.rlc_frame(pos, nrm, spp, f, rad[f])
+        ev[f + 1].record()
+    ctx.rlc_set_sample_log()
+    ctx.rlc_set_timing(True)
+    loss = ctx.rlc_mlp_train(pos, nrm, lp, ln, lw, args.mlp_epochs, args.mlp_batch, args.mlp_lr)
+    ev_train.record()
+    ctx.rlc_set_timing(False)
+    cdf, _ = ctx.rlc_mlp_forward(pos, nrm)
+    ctx.rlc_set_mixture(cdf, 0.5)
+    ev_fwd.record()
+    for j in range(k_mix - log_passes):
+        ctx.rlc_frame(pos, nrm, spp, log_passes + j, rad[log_passes + j])
+        ev_mix[j].record()
+    torch.cuda.synchronize()
+    ctx.rlc_set_mixture()
+    fb_ms, upd_ms, steps = ctx.rlc_get_mlp_timing()
+    t_log = ev[0].elapsed_time(ev[log_passes])
+    t_train = ev[log_passes].elapsed_time(ev_train)
+    t_fwd = ev_train.elapsed_time(ev_fwd)
+    mix_t = np.array([ev[0].elapsed_time(ev[f + 1]) for f in range(log_passes)] +
+                     [ev[0].elapsed_time(e) for e in ev_mix[:k_mix - log_passes]])
+    learned_mse, learned_mse_b = mse_curve(k_mix)
+
+    rows = []
+    for n in budgets:
+        budget = float(plain_t[n - 1])
+        fit = int(np.searchsorted(mix_t, budget, side="right"))
+        # the logged passes always count; mixture passes only after training
+        m = learned_mse[fit - 1] if fit >= 1 else float("nan")
+        mb = learned_mse_b[fit - 1] if fit >= 1 else float("nan")
+        rows.append({"budget_passes_plain": n, "budget_ms": round(budget, 4),
+                     "plain_mse": float(plain_mse[n - 1]),
+                     "learned_passes": fit, "learned_mse": float(m),
+                     "ratio_learned_to_plain": round(float(m / plain_mse[n - 1]), 4) if fit >= 1 else None,
+                     "plain_mse_below_band": float(plain_mse_b[n - 1]), "learned_mse_below_band": float(mb),
+                     "ratio_below_band": round(float(mb / plain_mse_b[n - 1]), 4) if fit >= 1 else None})
+    equal_samples = {"passes": nmax, "plain_mse": float(plain_mse[nmax - 1]),
+                     "learned_mse": float(learned_mse[nmax - 1]),
+                     "ratio_learned_to_plain": round(float(learned_mse[nmax - 1] / plain_mse[nmax - 1]), 4),
+                     "plain_mse_below_band": float(plain_mse_b[nmax - 1]),
+                     "learned_mse_below_band": float(learned_mse_b[nmax - 1]),
+                     "ratio_below_band": round(float(learned_mse_b[nmax - 1] / plain_mse_b[nmax - 1]), 4)}
+
+    mix_ms = ev_fwd.elapsed_time(ev_mix[k_mix - log_passes - 1]) if k_mix > log_passes else 0.0
+    n_mix = k_mix - log_passes
+    value = P * spp * n_mix / (mix_ms * 1e-3) if mix_ms > 0 else 0.0
+    fb_avg = fb_ms / max(steps, 1)
+    flop = MLP_FLOP_PER_TUPLE * min(args.mlp_batch, n_log)
+    achieved = flop / (fb_avg * 1e-3) / 1e12 if fb_avg > 0 else 0.0
+    line = {
+        "metric": METRIC,
+        "value": round(value, 1),
+        "unit": "samples/s",
+        "n_gpus": 1,
+        "steps": n_mix,
+        "warmup": 2,
+        "ms_per_step": round(mix_ms / max(n_mix, 1), 4),
+        "higher_is_better": True,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": "f32+bf16",
+        "data": "synthetic",
+        "config": {
+            "workload": ("learned: tiny scene (1,024 emissive triangles, 4,096 points, 64 box occluders, "
+                         "8^3 cells, cut size 16, 16 spp); 8 logged passes, MLP 144-64-64-64-64 trained "
+                         "%d epochs (batch %d, lr %g), then 50/50 mixture passes"
+                         % (args.mlp_epochs, args.mlp_batch, args.mlp_lr)),
+            "samples_per_step": P * spp,
+            "parallelism": "1 GPU",
+        },
+        "mse": {
+            "reference": "FP64 oracle truth (12x12 strata per light, exact shadows) at every 16th point",
+            "points": int(ref_pid.size), "points_below_band": int(below.sum()),
+            "equal_gpu_time": rows,
+            "equal_samples": equal_samples,
+            "plain_ms_per_pass": round(float(plain_t[-1] / nmax), 4),
+            "learned_ms": {"log_passes": round(t_log, 4), "train": round(t_train, 4),
+                           "forward": round(t_fwd, 4), "mixture_per_pass": round(mix_ms / max(n_mix, 1), 4)},
+            "train_steps": steps,
+            "train_last_loss": loss,
+        },
+        "roofline": {
+            "bound": "mfma",
+            "achieved": round(achieved, 3),
+            "peak": PEAK_BF16_TFLOPS,
+            "unit": "TFLOP/s",
+            "frac": round(achieved / PEAK_BF16_TFLOPS, 6),
+            "traffic": None,
+            "kernel": "k_mlp_fwd_bwd (forward + backward of one minibatch, BF16 MFMA)",
+            "alg_flop_per_launch": flop,
+            "kernel_ms": round(fb_avg, 4),
+            "adam_ms": round(upd_ms / max(steps, 1), 4),
+        },
+        "cpu_baseline": None,
+    }
+    print(json.dumps(line), flush=True)
+    ctx.close()
+
+
 
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=32)
     ap.add_argument("--warmup", type=int, default=3)
-    ap.add_argument("--workload", default="static", choices=("static", "dynamic"),
-                    help="static: the headline workload; dynamic: animated lights in walled compartments")
+    ap.add_argument("--workload", default="static", choices=("static", "dynamic", "learned"),
+                    help="static: the headline workload; dynamic: animated lights in walled compartments; "
+                         "learned: the tiny scene, plain method against the MLP mixture at equal GPU time")
+    ap.add_argument("--mlp-epochs", type=int, default=1)
+    ap.add_argument("--mlp-batch", type=int, default=16384)
+    ap.add_argument("--mlp-lr", type=float, default=1e-2)
+    ap.add_argument("--budgets", default="32,128,512,2048",
+                    help="learned: GPU-time budgets, as the plain method's time for this many passes")
     ap.add_argument("--no-cpu-baseline", action="store_true")
-    ap.add_argument("--cpu-stride", type=int, default=10, help="CPU baseline runs every n-th point")
+    ap.add_argument("--cpu-stride", type=int, default=20, help="CPU baseline runs every n-th point")
     ap.add_argument("--copy-calib-mib", type=int, default=0,
                     help="also run a plain device copy of this many MiB (counter calibration)")
     ap.add_argument("--write-traffic", nargs=2, metavar=("FETCH_CSV", "WRITE_CSV"),
@@ -146,6 +344,9 @@ def main():
         sys.exit(1)
     dev = torch.device("cuda:0")
     torch.cuda.set_device(dev)
+    if args.workload == "learned":
+        run_learned(args, np, torch, rlc, scenes, dev)
+        return
 
     print("[bench] generating the %s workload" % args.workload, file=sys.stderr, flush=True)
     s = scenes.make_static() if args.workload == "static" else scenes.make_dynamic()

@@ -85,6 +85,8 @@ typedef struct rlc_samples {
     uint32_t* d_light;     /* light index in tree order */
     float* d_inv_pdf;      /* 1 / p(light) */
     float* d_y;            /* point on the light, 3 floats per sample */
+    uint32_t* d_comp;      /* 1 if the learned proposal drew the light (mixture on);
+                              rlc_learn skips those samples */
 } rlc_samples;
 
 /* Create a context whose work goes to `stream` (hipStream_t).  Allocates
@@ -191,6 +193,73 @@ int rlc_batch_autotune(rlc_batch* b, uint32_t passes, rlc_schedule* h_best, rlc_
 /* One pass of every scene (graph launch). */
 int rlc_batch_frame(rlc_batch* b, uint32_t frame);
 
+/* ---- learned proposal (an extension beyond the paper's method) ----
+ * A small network maps a point's position and normal to a distribution over
+ * the nodes of a fixed breadth-first cut of up to 64 nodes of the light tree
+ * (the first min(64, N) nodes that the initial-cut rule of section 3 gives
+ * for M = 64).  Inputs: the position normalised to the cell-grid box and
+ * the normal, each coordinate v encoded as sin / cos of 2^k pi v for
+ * k = 0..11 (144 values, value 24 c + 2 k + {0: sin, 1: cos}); three hidden
+ * layers of 64 ReLU units; 64 logits; softmax.  Parameters, FP32, flat:
+ * W1 [64][144], b1 [64], W2 [64][64], b2, W3 [64][64], b3, W4 [64][64], b4
+ * (row = output unit): RLC_MLP_PARAMS floats.  The network computes with
+ * BF16 weights, inputs and activations and FP32 sums (matrix cores).
+ *
+ * Sampling with the mixture on (rlc_set_mixture): each sample draws from the
+ * cell's cut with probability w and from the network's distribution
+ * otherwise (a node, then a light in it uniformly), choosing by Philox at
+ * counter (point, sample, frame, scene_id << 16 | 1); its density is
+ * p(l) = w p_cut(l) + (1 - w) q(node(l)) / size(node(l)), so the estimate
+ * stays unbiased for any network.  Only draws from the cut feed Eq. 1.
+ *
+ * Training: minibatch Adam (beta1 0.9, beta2 0.999, eps 1e-8) on the
+ * weighted cross-entropy -sum_i w_i log q(x_i)[node_i] / sum_i w_i over
+ * logged tuples (point, fixed-cut node, w = (c_l summed over RGB) / p(l)).
+ * Epoch e visits the tuples in ascending order of the first Philox word at
+ * counter (i, e, 0, scene_id << 16 | 2) (ties by i), in batches of `batch`;
+ * each batch is one Adam step. */
+#define RLC_MLP_PARAMS 21760u
+#define RLC_MLP_NODES 64u
+
+/* The fixed cut (node ids, cluster ends in tree order; up to 64). Synchronises. */
+int rlc_mlp_fixed_cut(rlc_ctx* ctx, uint32_t* h_node, uint32_t* h_end, uint32_t* h_m);
+/* Weights uniform in +-sqrt(6 / fan_in) from Philox at counter
+ * (parameter index, 0, 0, scene_id << 16 | 3) under key `seed`; biases 0.
+ * Resets Adam. */
+int rlc_mlp_init(rlc_ctx* ctx, uint64_t seed);
+/* Copy RLC_MLP_PARAMS floats in (resets Adam; synchronises, rejects
+ * non-finite values) or out. */
+int rlc_mlp_set_params(rlc_ctx* ctx, const float* d_params);
+int rlc_mlp_get_params(rlc_ctx* ctx, float* d_params);
+/* Forward pass for P points: d_cdf (P x 64, may be NULL) the inclusive
+ * running sums of the 64 probabilities, left to right in FP32 (the table
+ * the mixture draws from); d_logits (P x 64, may be NULL). */
+int rlc_mlp_forward(rlc_ctx* ctx, const float* d_pos, const float* d_nrm, uint32_t P, float* d_cdf,
+                    float* d_logits);
+/* Gradient of the loss over the n tuples (d_pid[i] < P indexes d_pos/d_nrm,
+ * d_node[i] < 64, d_w[i] >= 0) into d_grad (RLC_MLP_PARAMS floats); the
+ * weights are unchanged.  h_loss (may be NULL) receives the loss.
+ * Synchronises; bad tuples give RLC_EINVAL. */
+int rlc_mlp_grad(rlc_ctx* ctx, const float* d_pos, const float* d_nrm, uint32_t P, const uint32_t* d_pid,
+                 const uint32_t* d_node, const float* d_w, uint32_t n, float* d_grad, float* h_loss);
+/* `epochs` epochs of minibatch Adam at learning rate lr over the n tuples;
+ * h_loss (may be NULL) receives the last batch's loss.  Synchronises. */
+int rlc_mlp_train(rlc_ctx* ctx, const float* d_pos, const float* d_nrm, uint32_t P, const uint32_t* d_pid,
+                  const uint32_t* d_node, const float* d_w, uint32_t n, uint32_t epochs, uint32_t batch,
+                  float lr, float* h_loss);
+/* Mixture for the following rlc_frame / rlc_sample calls: d_cdf holds
+ * `rows` rows of 64 running sums (row = point index of the pass; e.g. from
+ * rlc_mlp_forward), non-decreasing with a positive last used entry; w is
+ * the probability of drawing from the cell's cut.  d_cdf = NULL turns the
+ * mixture off.  The array must stay valid while the mixture is on.
+ * Batched passes ignore it. */
+int rlc_set_mixture(rlc_ctx* ctx, const float* d_cdf, uint32_t rows, float w);
+/* Training records of the following rlc_frame calls: for sample k of point
+ * p, entry p * spp + k receives the point index, the fixed-cut node of the
+ * drawn light and w = (c_l summed over RGB) / p(l).  `capacity` entries;
+ * all NULL turns logging off.  Batched passes ignore it. */
+int rlc_set_sample_log(rlc_ctx* ctx, uint32_t* d_pid, uint32_t* d_node, float* d_w, uint64_t capacity);
+
 /* ---- inspection, checkpoint and parity interface (synchronise) ---- */
 int rlc_sync(rlc_ctx* ctx);
 const char* rlc_last_error(const rlc_ctx* ctx);
@@ -214,6 +283,9 @@ int rlc_get_template(rlc_ctx* ctx, uint32_t* h_node, uint32_t* h_end, uint32_t* 
  * number of frames since the last call. */
 int rlc_set_timing(rlc_ctx* ctx, int enable);
 int rlc_get_timing(rlc_ctx* ctx, double* h_ms_fused, double* h_ms_adapt, uint32_t* h_frames);
+/* The same for rlc_mlp_train: summed milliseconds of the forward+backward
+ * kernels and of the Adam updates, and the number of steps. */
+int rlc_get_mlp_timing(rlc_ctx* ctx, double* h_ms_fwd_bwd, double* h_ms_update, uint32_t* h_steps);
 
 #ifdef __cplusplus
 }

@@ -52,9 +52,43 @@ struct rlc_ctx {
     float f_r = 0.0f;
     float fx_scale = 1.0f, fx_inv = 1.0f;
 
+    // learned proposal: fixed breadth-first cut of up to 64 nodes, FP32
+    // master weights with Adam moments, BF16 operand fragments, scratch
+    uint32_t fix_M = 0;
+    uint32_t* fix_node = nullptr;
+    uint32_t* fix_end = nullptr;
+    float* fix_Qt = nullptr;
+    float* fix_C = nullptr;
+    bool mlp_ready = false;
+    float* mlp_master = nullptr;
+    float* mlp_m = nullptr;
+    float* mlp_v = nullptr;
+    uint16_t* mlp_frag = nullptr;
+    uint32_t mlp_step = 0;
+    float* mlp_partial = nullptr;
+    uint32_t mlp_partial_blocks = 0;
+    float* mlp_part_w = nullptr;
+    float* mlp_part_loss = nullptr;
+    float* mlp_loss = nullptr;
+    uint32_t* mlp_keys = nullptr;
+    uint32_t* mlp_vals = nullptr;
+    uint32_t* mlp_ktmp = nullptr;
+    uint32_t* mlp_vtmp = nullptr;
+    uint32_t* mlp_hist = nullptr;
+    uint32_t mlp_order_cap = 0;
+    // mixture with the learned proposal, and per-sample training records
+    const float* mix_cdf = nullptr;
+    uint32_t mix_rows = 0;
+    float mix_w = 0.5f;
+    uint32_t* log_pid = nullptr;
+    uint32_t* log_node = nullptr;
+    float* log_w = nullptr;
+    uint64_t log_cap = 0;
+
     // per-kernel timing
     bool timing = false;
     std::vector<hipEvent_t> pending;   // 3 per timed frame
+    std::vector<hipEvent_t> mlp_pending;  // 3 per timed training step
     std::vector<hipEvent_t> spare;
 };
 
@@ -129,7 +163,33 @@ void free_tree(rlc_ctx* c) {
     dfree(c->tmpl_end);
     dfree(c->tmpl_Qt);
     dfree(c->tmpl_C);
+    dfree(c->fix_node);
+    dfree(c->fix_end);
+    dfree(c->fix_Qt);
+    dfree(c->fix_C);
+    c->fix_M = 0;
+    c->mix_cdf = nullptr;
+    c->mix_rows = 0;
     c->tree_built = false;
+}
+
+void free_mlp(rlc_ctx* c) {
+    dfree(c->mlp_master);
+    dfree(c->mlp_m);
+    dfree(c->mlp_v);
+    dfree(c->mlp_frag);
+    dfree(c->mlp_partial);
+    dfree(c->mlp_part_w);
+    dfree(c->mlp_part_loss);
+    dfree(c->mlp_loss);
+    dfree(c->mlp_keys);
+    dfree(c->mlp_vals);
+    dfree(c->mlp_ktmp);
+    dfree(c->mlp_vtmp);
+    dfree(c->mlp_hist);
+    c->mlp_partial_blocks = 0;
+    c->mlp_order_cap = 0;
+    c->mlp_ready = false;
 }
 
 void free_occ(rlc_ctx* c) {
@@ -185,6 +245,13 @@ FrameParams frame_params(const rlc_ctx* c) {
     fp.reward_mode = c->cfg.reward_mode;
     fp.two_sided = c->cfg.two_sided;
     fp.err = c->d_err;
+    fp.mix_cdf = c->mix_cdf;
+    fp.fix_end = c->fix_end;
+    fp.fix_M = c->fix_M;
+    fp.mix_w = c->mix_w;
+    fp.log_pid = c->log_pid;
+    fp.log_node = c->log_node;
+    fp.log_w = c->log_w;
     return fp;
 }
 
@@ -214,6 +281,11 @@ int check_frame_args(rlc_ctx* c, const void* pos, uint32_t P, uint32_t spp) {
     if (!pos) return fail(c, RLC_EINVAL, "null point array");
     if (spp == 0) return fail(c, RLC_EINVAL, "spp must be >= 1");
     if ((uint64_t)P * spp > 0xFFFFFFFFull) return fail(c, RLC_EINVAL, "P * spp exceeds 2^32 - 1");
+    if (c->mix_cdf && P > c->mix_rows)
+        return fail(c, RLC_EINVAL, "the mixture cdf has %u rows, the pass has %u points", c->mix_rows, P);
+    if (c->log_node && (uint64_t)P * spp > c->log_cap)
+        return fail(c, RLC_EINVAL, "sample log holds %llu records, the pass has %llu",
+                    (unsigned long long)c->log_cap, (unsigned long long)P * spp);
     return RLC_OK;
 }
 
@@ -241,6 +313,86 @@ int read_device_errors(rlc_ctx* c) {
         if (err & RLC_DERR_INPUT) return fail(c, RLC_EINVAL, "non-finite or inverted input");
         if (err & RLC_DERR_NONFINITE) return fail(c, RLC_EINVAL, "non-finite contribution");
     }
+    return RLC_OK;
+}
+
+}  // namespace
+
+// ---------------------------------------------------------------------------
+// Learned proposal
+// ---------------------------------------------------------------------------
+namespace {
+
+constexpr float kAdamBeta1 = 0.9f, kAdamBeta2 = 0.999f, kAdamEps = 1e-8f;
+
+MlpEncode mlp_encode_params(const rlc_ctx* c) {
+    MlpEncode e;
+    for (int a = 0; a < 3; ++a) {
+        e.lo[a] = c->cfg.grid_lo[a];
+        e.ext[a] = c->cfg.grid_hi[a] - c->cfg.grid_lo[a];
+    }
+    return e;
+}
+
+int mlp_alloc(rlc_ctx* c) {
+    if (c->mlp_master) return RLC_OK;
+    RLC_TRY(dalloc(c, &c->mlp_master, kMlpParams));
+    RLC_TRY(dalloc(c, &c->mlp_m, kMlpParams));
+    RLC_TRY(dalloc(c, &c->mlp_v, kMlpParams));
+    RLC_TRY(dalloc(c, &c->mlp_frag, 8 * (size_t)kMlpFragVecs));
+    RLC_TRY(dalloc(c, &c->mlp_loss, 1));
+    // the padding of the first layer's operands (inputs 144..159) stays zero
+    RLC_HIP(c, hipMemsetAsync(c->mlp_frag, 0, sizeof(uint16_t) * 8 * (size_t)kMlpFragVecs, c->stream));
+    return RLC_OK;
+}
+
+// New weights in master: zero Adam's state, refresh the BF16 operands.
+int mlp_reset_optimizer(rlc_ctx* c) {
+    RLC_HIP(c, hipMemsetAsync(c->mlp_m, 0, sizeof(float) * kMlpParams, c->stream));
+    RLC_HIP(c, hipMemsetAsync(c->mlp_v, 0, sizeof(float) * kMlpParams, c->stream));
+    RLC_HIP(c, launch_mlp_refresh(c->mlp_master, c->mlp_frag, c->stream));
+    c->mlp_step = 0;
+    c->mlp_ready = true;
+    return RLC_OK;
+}
+
+int mlp_partials(rlc_ctx* c, uint32_t nblocks) {
+    if (nblocks <= c->mlp_partial_blocks) return RLC_OK;
+    dfree(c->mlp_partial);
+    dfree(c->mlp_part_w);
+    dfree(c->mlp_part_loss);
+    c->mlp_partial_blocks = 0;
+    RLC_TRY(dalloc(c, &c->mlp_partial, (size_t)nblocks * kMlpParams));
+    RLC_TRY(dalloc(c, &c->mlp_part_w, nblocks));
+    RLC_TRY(dalloc(c, &c->mlp_part_loss, nblocks));
+    c->mlp_partial_blocks = nblocks;
+    return RLC_OK;
+}
+
+int mlp_order_buffers(rlc_ctx* c, uint32_t n) {
+    if (n <= c->mlp_order_cap) return RLC_OK;
+    dfree(c->mlp_keys);
+    dfree(c->mlp_vals);
+    dfree(c->mlp_ktmp);
+    dfree(c->mlp_vtmp);
+    dfree(c->mlp_hist);
+    c->mlp_order_cap = 0;
+    RLC_TRY(dalloc(c, &c->mlp_keys, n));
+    RLC_TRY(dalloc(c, &c->mlp_vals, n));
+    RLC_TRY(dalloc(c, &c->mlp_ktmp, n));
+    RLC_TRY(dalloc(c, &c->mlp_vtmp, n));
+    RLC_TRY(dalloc(c, &c->mlp_hist, radix_sort_hist_entries(n)));
+    c->mlp_order_cap = n;
+    return RLC_OK;
+}
+
+int check_tuples(rlc_ctx* c, const float* pos, const float* nrm, uint32_t P, const uint32_t* pid,
+                 const uint32_t* node, const float* w, uint32_t n) {
+    RLC_TRY(need_tree(c));
+    if (!c->mlp_ready) return fail(c, RLC_ESTATE, "the network has no weights (rlc_mlp_init / set_params)");
+    if (n == 0) return RLC_OK;
+    if (P == 0 || !pos || !nrm) return fail(c, RLC_EINVAL, "tuples need the points they refer to");
+    if (!pid || !node || !w) return fail(c, RLC_EINVAL, "null tuple array");
     return RLC_OK;
 }
 
@@ -322,6 +474,7 @@ int rlc_destroy(rlc_ctx* c) {
     if (c->stream || true) (void)hipStreamSynchronize(c->stream);
     free_tree(c);
     free_occ(c);
+    free_mlp(c);
     DevCells& d = c->cells;
     dfree(d.keys);
     dfree(d.ready);
@@ -337,6 +490,7 @@ int rlc_destroy(rlc_ctx* c) {
     dfree(c->d_err);
     dfree(c->d_partial);
     for (hipEvent_t e : c->pending) (void)hipEventDestroy(e);
+    for (hipEvent_t e : c->mlp_pending) (void)hipEventDestroy(e);
     for (hipEvent_t e : c->spare) (void)hipEventDestroy(e);
     delete c;
     return RLC_OK;
@@ -363,6 +517,10 @@ int rlc_build_light_tree(rlc_ctx* c, const float* d_tri, const float* d_emit, ui
     RLC_TRY(dalloc(c, &c->tmpl_end, M));
     RLC_TRY(dalloc(c, &c->tmpl_Qt, M));
     RLC_TRY(dalloc(c, &c->tmpl_C, M));
+    RLC_TRY(dalloc(c, &c->fix_node, RLC_MIX_M));
+    RLC_TRY(dalloc(c, &c->fix_end, RLC_MIX_M));
+    RLC_TRY(dalloc(c, &c->fix_Qt, RLC_MIX_M));
+    RLC_TRY(dalloc(c, &c->fix_C, RLC_MIX_M));
     // temporaries
     float* sums = nullptr;
     float* part = nullptr;
@@ -394,6 +552,8 @@ int rlc_build_light_tree(rlc_ctx* c, const float* d_tri, const float* d_emit, ui
         c->N = N;
         c->Meff = std::min(M, N);
         step(launch_initial_cut(dev_tree(c), M, c->tmpl_node, c->tmpl_end, c->tmpl_Qt, c->tmpl_C, c->stream));
+        c->fix_M = std::min(RLC_MIX_M, N);
+        step(launch_initial_cut(dev_tree(c), RLC_MIX_M, c->fix_node, c->fix_end, c->fix_Qt, c->fix_C, c->stream));
         step(hipStreamSynchronize(c->stream));
     }
     dfree(sums);
@@ -527,6 +687,8 @@ int rlc_learn(rlc_ctx* c, const rlc_samples* in, const float* d_reward, uint32_t
     RLC_TRY(need_tree(c));
     if (n == 0) return RLC_OK;
     if (!in || !in->d_cell || !in->d_slot || !d_reward) return fail(c, RLC_EINVAL, "missing learn input");
+    if (c->mix_cdf && !in->d_comp)
+        return fail(c, RLC_EINVAL, "with the mixture on, learning needs the component records");
     RLC_HIP(c, launch_learn(frame_params(c), *in, d_reward, n, c->stream));
     return RLC_OK;
 }
@@ -708,6 +870,168 @@ int rlc_get_template(rlc_ctx* c, uint32_t* h_node, uint32_t* h_end, uint32_t* h_
     return RLC_OK;
 }
 
+int rlc_mlp_fixed_cut(rlc_ctx* c, uint32_t* h_node, uint32_t* h_end, uint32_t* h_m) {
+    RLC_TRY(need_tree(c));
+    RLC_HIP(c, hipStreamSynchronize(c->stream));
+    if (h_node) RLC_HIP(c, hipMemcpy(h_node, c->fix_node, sizeof(uint32_t) * c->fix_M, hipMemcpyDeviceToHost));
+    if (h_end) RLC_HIP(c, hipMemcpy(h_end, c->fix_end, sizeof(uint32_t) * c->fix_M, hipMemcpyDeviceToHost));
+    if (h_m) *h_m = c->fix_M;
+    return RLC_OK;
+}
+
+int rlc_mlp_init(rlc_ctx* c, uint64_t seed) {
+    if (!c) return RLC_EINVAL;
+    RLC_TRY(mlp_alloc(c));
+    RLC_HIP(c, launch_mlp_init(c->mlp_master, c->cfg.scene_id, (uint32_t)(seed & 0xFFFFFFFFull),
+                               (uint32_t)(seed >> 32), c->stream));
+    return mlp_reset_optimizer(c);
+}
+
+int rlc_mlp_set_params(rlc_ctx* c, const float* d_params) {
+    if (!c) return RLC_EINVAL;
+    if (!d_params) return fail(c, RLC_EINVAL, "null parameter array");
+    RLC_TRY(mlp_alloc(c));
+    RLC_HIP(c, hipMemcpyAsync(c->mlp_master, d_params, sizeof(float) * kMlpParams, hipMemcpyDeviceToDevice,
+                              c->stream));
+    RLC_HIP(c, launch_fill_u32(c->d_err, 0u, 1, c->stream));
+    RLC_HIP(c, launch_check_finite(c->mlp_master, kMlpParams, c->d_err, c->stream));
+    RLC_TRY(read_device_errors(c));
+    return mlp_reset_optimizer(c);
+}
+
+int rlc_mlp_get_params(rlc_ctx* c, float* d_params) {
+    if (!c) return RLC_EINVAL;
+    if (!c->mlp_ready) return fail(c, RLC_ESTATE, "the network has no weights");
+    if (!d_params) return fail(c, RLC_EINVAL, "null parameter array");
+    RLC_HIP(c, hipMemcpyAsync(d_params, c->mlp_master, sizeof(float) * kMlpParams, hipMemcpyDeviceToDevice,
+                              c->stream));
+    return RLC_OK;
+}
+
+int rlc_mlp_forward(rlc_ctx* c, const float* d_pos, const float* d_nrm, uint32_t P, float* d_cdf,
+                    float* d_logits) {
+    if (!c) return RLC_EINVAL;
+    if (!c->mlp_ready) return fail(c, RLC_ESTATE, "the network has no weights");
+    if (P == 0) return RLC_OK;
+    if (!d_pos || !d_nrm) return fail(c, RLC_EINVAL, "null point array");
+    if (!d_cdf && !d_logits) return fail(c, RLC_EINVAL, "no output");
+    RLC_HIP(c, launch_mlp_forward(c->mlp_frag, c->mlp_master, mlp_encode_params(c), d_pos, d_nrm, P, d_cdf, d_logits,
+                                  c->stream));
+    return RLC_OK;
+}
+
+int rlc_mlp_grad(rlc_ctx* c, const float* d_pos, const float* d_nrm, uint32_t P, const uint32_t* d_pid,
+                 const uint32_t* d_node, const float* d_w, uint32_t n, float* d_grad, float* h_loss) {
+    if (!c) return RLC_EINVAL;
+    RLC_TRY(check_tuples(c, d_pos, d_nrm, P, d_pid, d_node, d_w, n));
+    if (!d_grad) return fail(c, RLC_EINVAL, "null gradient array");
+    const uint32_t nb = std::max<uint32_t>(1u, (n + kMlpTuplesPerBlock - 1u) / kMlpTuplesPerBlock);
+    RLC_TRY(mlp_partials(c, nb));
+    RLC_HIP(c, launch_fill_u32(c->d_err, 0u, 1, c->stream));
+    if (n == 0) {
+        RLC_HIP(c, hipMemsetAsync(c->mlp_part_w, 0, sizeof(float), c->stream));
+        RLC_HIP(c, hipMemsetAsync(c->mlp_part_loss, 0, sizeof(float), c->stream));
+        RLC_HIP(c, hipMemsetAsync(c->mlp_partial, 0, sizeof(float) * kMlpParams, c->stream));
+    }
+    RLC_HIP(c, launch_mlp_fwd_bwd(c->mlp_frag, c->mlp_master, mlp_encode_params(c), d_pos, d_nrm, P, nullptr, d_pid,
+                                  d_node, d_w, n, c->mlp_partial, c->mlp_part_w, c->mlp_part_loss, c->d_err,
+                                  c->stream));
+    RLC_HIP(c, launch_mlp_reduce(c->mlp_partial, c->mlp_part_w, c->mlp_part_loss, nb, 0u, d_grad, nullptr, nullptr,
+                                 nullptr, nullptr, 0.0f, 0.0f, 0.0f, 0.0f, 1.0f, 1.0f, c->mlp_loss, c->stream));
+    float loss = 0.0f;
+    RLC_HIP(c, hipMemcpyAsync(&loss, c->mlp_loss, sizeof(float), hipMemcpyDeviceToHost, c->stream));
+    RLC_TRY(read_device_errors(c));
+    if (h_loss) *h_loss = loss;
+    return RLC_OK;
+}
+
+int rlc_mlp_train(rlc_ctx* c, const float* d_pos, const float* d_nrm, uint32_t P, const uint32_t* d_pid,
+                  const uint32_t* d_node, const float* d_w, uint32_t n, uint32_t epochs, uint32_t batch, float lr,
+                  float* h_loss) {
+    if (!c) return RLC_EINVAL;
+    RLC_TRY(check_tuples(c, d_pos, d_nrm, P, d_pid, d_node, d_w, n));
+    if (batch == 0 || batch > (1u << 24)) return fail(c, RLC_EINVAL, "batch must be in 1..2^24");
+    if (!(lr > 0.0f) || !std::isfinite(lr)) return fail(c, RLC_EINVAL, "learning rate must be positive");
+    if (n == 0 || epochs == 0) return RLC_OK;
+    const uint32_t bmax = std::min(batch, n);
+    const uint32_t nb = (bmax + kMlpTuplesPerBlock - 1u) / kMlpTuplesPerBlock;
+    RLC_TRY(mlp_partials(c, nb));
+    RLC_TRY(mlp_order_buffers(c, n));
+    RLC_HIP(c, launch_fill_u32(c->d_err, 0u, 1, c->stream));
+    const MlpEncode enc = mlp_encode_params(c);
+    const uint32_t seed_lo = (uint32_t)(c->cfg.seed & 0xFFFFFFFFull), seed_hi = (uint32_t)(c->cfg.seed >> 32);
+    for (uint32_t e = 0; e < epochs; ++e) {
+        RLC_HIP(c, launch_mlp_shuffle_keys(n, e, c->cfg.scene_id, seed_lo, seed_hi, c->mlp_keys, c->mlp_vals,
+                                           c->stream));
+        RLC_HIP(c, radix_sort_pairs(c->mlp_keys, c->mlp_vals, c->mlp_ktmp, c->mlp_vtmp, c->mlp_hist, n, 32,
+                                    c->stream));
+        for (uint32_t b0 = 0; b0 < n; b0 += batch) {
+            const uint32_t nbat = std::min(batch, n - b0);
+            const uint32_t blocks = (nbat + kMlpTuplesPerBlock - 1u) / kMlpTuplesPerBlock;
+            hipEvent_t ev[3] = {nullptr, nullptr, nullptr};
+            if (c->timing) {
+                for (auto& x : ev) {
+                    x = take_event(c);
+                    if (!x) return fail(c, RLC_EHIP, "hipEventCreate failed");
+                }
+                RLC_HIP(c, hipEventRecord(ev[0], c->stream));
+            }
+            RLC_HIP(c, launch_mlp_fwd_bwd(c->mlp_frag, c->mlp_master, enc, d_pos, d_nrm, P, c->mlp_vals + b0, d_pid,
+                                          d_node, d_w, nbat, c->mlp_partial, c->mlp_part_w, c->mlp_part_loss,
+                                          c->d_err, c->stream));
+            if (c->timing) RLC_HIP(c, hipEventRecord(ev[1], c->stream));
+            c->mlp_step += 1u;
+            const double t = (double)c->mlp_step;
+            const float c1 = (float)(1.0 - std::pow((double)kAdamBeta1, t));
+            const float c2 = (float)(1.0 - std::pow((double)kAdamBeta2, t));
+            RLC_HIP(c, launch_mlp_reduce(c->mlp_partial, c->mlp_part_w, c->mlp_part_loss, blocks, 1u, nullptr,
+                                         c->mlp_master, c->mlp_m, c->mlp_v, c->mlp_frag, lr, kAdamBeta1,
+                                         kAdamBeta2, kAdamEps, c1, c2, c->mlp_loss, c->stream));
+            if (c->timing) {
+                RLC_HIP(c, hipEventRecord(ev[2], c->stream));
+                for (auto& x : ev) c->mlp_pending.push_back(x);
+            }
+        }
+    }
+    float loss = 0.0f;
+    RLC_HIP(c, hipMemcpyAsync(&loss, c->mlp_loss, sizeof(float), hipMemcpyDeviceToHost, c->stream));
+    RLC_TRY(read_device_errors(c));
+    if (h_loss) *h_loss = loss;
+    return RLC_OK;
+}
+
+int rlc_set_mixture(rlc_ctx* c, const float* d_cdf, uint32_t rows, float w) {
+    RLC_TRY(need_tree(c));
+    if (!d_cdf) {
+        c->mix_cdf = nullptr;
+        c->mix_rows = 0;
+        return RLC_OK;
+    }
+    if (rows == 0) return fail(c, RLC_EINVAL, "the mixture cdf has no rows");
+    if (!(w >= 0.0f && w <= 1.0f)) return fail(c, RLC_EINVAL, "mixture weight must be in [0, 1]");
+    c->mix_cdf = d_cdf;
+    c->mix_rows = rows;
+    c->mix_w = w;
+    return RLC_OK;
+}
+
+int rlc_set_sample_log(rlc_ctx* c, uint32_t* d_pid, uint32_t* d_node, float* d_w, uint64_t capacity) {
+    if (!c) return RLC_EINVAL;
+    if (!d_pid && !d_node && !d_w) {
+        c->log_pid = nullptr;
+        c->log_node = nullptr;
+        c->log_w = nullptr;
+        c->log_cap = 0;
+        return RLC_OK;
+    }
+    if (!d_pid || !d_node || !d_w) return fail(c, RLC_EINVAL, "the sample log needs all three arrays");
+    c->log_pid = d_pid;
+    c->log_node = d_node;
+    c->log_w = d_w;
+    c->log_cap = capacity;
+    return RLC_OK;
+}
+
 int rlc_set_timing(rlc_ctx* c, int enable) {
     if (!c) return RLC_EINVAL;
     c->timing = enable != 0;
@@ -735,11 +1059,32 @@ int rlc_get_timing(rlc_ctx* c, double* h_ms_fused, double* h_ms_adapt, uint32_t*
     return RLC_OK;
 }
 
+int rlc_get_mlp_timing(rlc_ctx* c, double* h_ms_fwd_bwd, double* h_ms_update, uint32_t* h_steps) {
+    if (!c) return RLC_EINVAL;
+    double f = 0.0, u = 0.0;
+    uint32_t steps = (uint32_t)(c->mlp_pending.size() / 3);
+    for (uint32_t i = 0; i < steps; ++i) {
+        hipEvent_t* e = &c->mlp_pending[3 * i];
+        RLC_HIP(c, hipEventSynchronize(e[2]));
+        float t01 = 0.0f, t12 = 0.0f;
+        RLC_HIP(c, hipEventElapsedTime(&t01, e[0], e[1]));
+        RLC_HIP(c, hipEventElapsedTime(&t12, e[1], e[2]));
+        f += t01;
+        u += t12;
+    }
+    for (hipEvent_t e : c->mlp_pending) c->spare.push_back(e);
+    c->mlp_pending.clear();
+    if (h_ms_fwd_bwd) *h_ms_fwd_bwd = f;
+    if (h_ms_update) *h_ms_update = u;
+    if (h_steps) *h_steps = steps;
+    return RLC_OK;
+}
+
+}  // extern "C"
+
 // ---------------------------------------------------------------------------
 // batched passes
 // ---------------------------------------------------------------------------
-}  // extern "C"
-
 struct rlc_batch {
     std::vector<rlc_batch_scene> scenes;
     hipStream_t stream = nullptr;
@@ -807,6 +1152,11 @@ int batch_upload(rlc_batch* b) {
         const rlc_batch_scene& sc = b->scenes[i];
         BatchScene& d = hs[i];
         d.fp = frame_params(sc.ctx);
+        // batched passes draw from the cells' cuts alone and keep no log
+        d.fp.mix_cdf = nullptr;
+        d.fp.log_pid = nullptr;
+        d.fp.log_node = nullptr;
+        d.fp.log_w = nullptr;
         d.pos = sc.d_pos;
         d.nrm = sc.d_nrm;
         d.perm = b->sched.cell_sorted ? b->perms[i] : nullptr;

@@ -87,6 +87,7 @@ __global__ void __launch_bounds__(kBlock) k_sample(FrameParams fp, const float* 
     if (out.d_slot) out.d_slot[i] = sm.s;
     if (out.d_light) out.d_light[i] = sm.light;
     if (out.d_inv_pdf) out.d_inv_pdf[i] = sm.inv_pdf;
+    if (out.d_comp) out.d_comp[i] = sm.comp;
     if (out.d_y) {
         out.d_y[3 * i] = sm.y[0];
         out.d_y[3 * i + 1] = sm.y[1];
@@ -160,7 +161,9 @@ __global__ void __launch_bounds__(kBlock) k_learn(FrameParams fp, rlc_samples in
     __syncthreads();
     uint32_t b = xcd_block(blockIdx.x, gridDim.x);
     size_t i = (size_t)b * kBlock + threadIdx.x;
-    if (i < n) agg_add(agg, fp, in.d_cell[i], in.d_slot[i], reward_fixed(fp, reward[i]));
+    // draws of the learned proposal do not feed Eq. 1
+    if (i < n && !(in.d_comp && in.d_comp[i]))
+        agg_add(agg, fp, in.d_cell[i], in.d_slot[i], reward_fixed(fp, reward[i]));
     __syncthreads();
     agg_flush(agg, fp);
 }
@@ -194,7 +197,15 @@ __device__ void frame_block(const FrameParams& fp, const float* __restrict__ pos
         e[2] = c[2] * sm.inv_pdf;
         float r = reward_of(fp, c, sm.size);
         if (!(r <= 3.402823466e38f)) atomicOr(fp.err, RLC_DERR_NONFINITE);
-        agg_add(agg, fp, sm.cell, sm.s, reward_fixed(fp, r));
+        // only draws from the cell's own cut are uniform inside a cluster,
+        // as Eq. 1's statistics assume
+        if (!sm.comp) agg_add(agg, fp, sm.cell, sm.s, reward_fixed(fp, r));
+        if (fp.log_node) {
+            const size_t li = (size_t)p * spp + k;
+            fp.log_pid[li] = p;
+            fp.log_node[li] = sm.fnode;
+            fp.log_w[li] = ((c[0] + c[1]) + c[2]) * sm.inv_pdf;
+        }
     }
     __syncthreads();
     agg_flush(agg, fp);

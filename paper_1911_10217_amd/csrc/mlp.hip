@@ -1,0 +1,630 @@
+// The learned proposal: a 144 -> 64 -> 64 -> 64 -> 64 MLP (ReLU hidden
+// layers, softmax output) from a point's position and normal to a
+// distribution over the nodes of a fixed 64-node breadth-first cut.  It is
+// mixed with the cell's cut distribution when sampling, so the estimator
+// stays unbiased, and trained on the (point, node, contribution / density)
+// records the frames log, by minimising the weighted cross-entropy
+// -sum_i w_i log q_i[k_i] / sum_i w_i (the one-sample form of the KL
+// divergence from the contribution-proportional target) with Adam.
+//
+// Arithmetic: BF16 operands on the matrix cores with FP32 accumulation
+// (v_mfma_f32_16x16x32_bf16), FP32 biases, softmax and optimizer.
+//
+// MFMA operand layout (one wave, lane l = 16 g + i):
+//   A (16 x 32): lane holds A[i][8 g + e], e = 0..7
+//   B (32 x 16): lane holds B[8 g + e][i]
+//   D (16 x 16): lane holds D[4 g + r][i], r = 0..3
+// A layer computes its output transposed, H^T = W X^T: A is a 16-row tile
+// of W, B the inputs of 16 points, D the tile's 16 units for those points.
+// The D registers of two neighbouring tiles are exactly the 8 values one
+// lane contributes to the next layer's B operand if the next layer's
+// weights are stored with their input units in the matching order
+// (hidden_pos below), so activations never leave registers.
+#include "rlc_internal.h"
+
+namespace rlc {
+
+namespace {
+
+typedef __bf16 bf16x8 __attribute__((ext_vector_type(8)));
+typedef unsigned short u16x8 __attribute__((ext_vector_type(8)));
+typedef float f32x4 __attribute__((ext_vector_type(4)));
+
+constexpr int kBlock = 256;
+constexpr uint32_t kIn = 144, kH = 64;
+constexpr uint32_t kNP = kMlpParams;
+// flat parameter layout: W1 [64][144], b1, W2 [64][64], b2, W3, b3, W4, b4
+constexpr uint32_t oW1 = 0, ob1 = oW1 + kH * kIn, oW2 = ob1 + kH, ob2 = oW2 + kH * kH, oW3 = ob2 + kH,
+                   ob3 = oW3 + kH * kH, oW4 = ob3 + kH, ob4 = oW4 + kH * kH;
+static_assert(ob4 + kH == kNP, "parameter count");
+// fragment regions, in 16-byte vectors: forward operands of layers 1-4 (A =
+// W tile), then transposed operands of layers 2-4 (A = W^T tile) used to
+// back-propagate; [tile][k-block][lane]
+constexpr uint32_t fF1 = 0, fF2 = 1280, fF3 = 1792, fF4 = 2304, fT2 = 2816, fT3 = 3328, fT4 = 3840;
+static_assert(fT4 + 512 == kMlpFragVecs, "fragment count");
+constexpr uint32_t kFwdVecs = fT2;
+constexpr uint32_t kLds = 72;  // LDS row stride (BF16) of the gradient staging tiles
+
+__device__ __forceinline__ uint16_t bf16_bits(float f) {
+    uint32_t u = __float_as_uint(f);
+    u += 0x7FFFu + ((u >> 16) & 1u);  // round to nearest even
+    return (uint16_t)(u >> 16);
+}
+
+__device__ __forceinline__ float bf16_val(uint16_t b) { return __uint_as_float((uint32_t)b << 16); }
+
+__device__ __forceinline__ bf16x8 pack8(const float* v) {
+    u16x8 b;
+#pragma unroll
+    for (int e = 0; e < 8; ++e) b[e] = bf16_bits(v[e]);
+    return __builtin_bit_cast(bf16x8, b);
+}
+
+__device__ __forceinline__ uint16_t elem(bf16x8 v, int e) { return __builtin_bit_cast(u16x8, v)[e]; }
+
+__device__ __forceinline__ f32x4 mfma(bf16x8 a, bf16x8 b, f32x4 c) {
+    return __builtin_amdgcn_mfma_f32_16x16x32_bf16(a, b, c, 0, 0, 0);
+}
+
+// Slot of hidden unit j in the B operand built from accumulator registers:
+// k-block kb, lane group g, element e, with j = 32 kb + 16 (e / 4) + 4 g + e % 4.
+__device__ __forceinline__ void hidden_pos(uint32_t j, uint32_t& kb, uint32_t& g, uint32_t& e) {
+    kb = j >> 5;
+    const uint32_t r = j & 31u;
+    g = (r & 15u) >> 2;
+    e = 4u * (r >> 4) + (r & 3u);
+}
+
+// Fragment element of weight W_L[o][j] in the forward operands, and (layers
+// 2-4) in the transposed ones.
+__device__ __forceinline__ uint32_t frag_fwd(uint32_t layer, uint32_t o, uint32_t j) {
+    const uint32_t t = o >> 4, i = o & 15u;
+    if (layer == 1u) {
+        const uint32_t kb = j >> 5, g = (j & 31u) >> 3, e = j & 7u;
+        return ((fF1 + (t * 5u + kb) * 64u + 16u * g + i) << 3) + e;
+    }
+    uint32_t kb, g, e;
+    hidden_pos(j, kb, g, e);
+    const uint32_t base = layer == 2u ? fF2 : (layer == 3u ? fF3 : fF4);
+    return ((base + (t * 2u + kb) * 64u + 16u * g + i) << 3) + e;
+}
+
+__device__ __forceinline__ uint32_t frag_tr(uint32_t layer, uint32_t o, uint32_t j) {
+    const uint32_t t = j >> 4, i = j & 15u;
+    uint32_t kb, g, e;
+    hidden_pos(o, kb, g, e);
+    const uint32_t base = layer == 2u ? fT2 : (layer == 3u ? fT3 : fT4);
+    return ((base + (t * 2u + kb) * 64u + 16u * g + i) << 3) + e;
+}
+
+// Parameter p -> (layer, o, j) for weights; false for a bias.
+__device__ __forceinline__ bool weight_of(uint32_t p, uint32_t& layer, uint32_t& o, uint32_t& j) {
+    if (p < ob1) {
+        layer = 1u;
+        o = p / kIn;
+        j = p % kIn;
+        return true;
+    }
+    const uint32_t offs[3] = {oW2, oW3, oW4};
+#pragma unroll
+    for (uint32_t L = 0; L < 3; ++L)
+        if (p >= offs[L] && p < offs[L] + kH * kH) {
+            layer = L + 2u;
+            o = (p - offs[L]) >> 6;
+            j = (p - offs[L]) & 63u;
+            return true;
+        }
+    return false;
+}
+
+__device__ __forceinline__ void write_frag(uint16_t* frag, uint32_t p, float val) {
+    uint32_t layer, o, j;
+    if (!weight_of(p, layer, o, j)) return;
+    const uint16_t b = bf16_bits(val);
+    frag[frag_fwd(layer, o, j)] = b;
+    if (layer > 1u) frag[frag_tr(layer, o, j)] = b;
+}
+
+// The inputs a lane supplies to layer 1 for its point: for k-block kb the 8
+// encoded values 32 kb + 8 g .. + 7 (value 24 c + 2 k + {0, 1} is sin / cos
+// of 2^k pi v_c); indices from 144 on are zero padding.
+__device__ __forceinline__ void encode_b(const float v[6], uint32_t g, bf16x8 xb[5]) {
+#pragma unroll
+    for (uint32_t kb = 0; kb < 5u; ++kb) {
+        const uint32_t base = 32u * kb + 8u * g;
+        float val[8];
+        if (base < kIn) {
+            const uint32_t c = base / 24u, m = (base % 24u) >> 3;
+#pragma unroll
+            for (uint32_t e2 = 0; e2 < 4u; ++e2) {
+                const float ph = ldexpf(v[c], (int)(4u * m + e2));
+                val[2 * e2] = sinpif(ph);
+                val[2 * e2 + 1] = cospif(ph);
+            }
+        } else {
+#pragma unroll
+            for (int e = 0; e < 8; ++e) val[e] = 0.0f;
+        }
+        xb[kb] = pack8(val);
+    }
+}
+
+__device__ __forceinline__ void point_inputs(const MlpEncode& enc, const float* pos, const float* nrm, uint32_t p,
+                                             float v[6]) {
+#pragma unroll
+    for (int a = 0; a < 3; ++a) {
+        const float num = pos[3 * (size_t)p + a] - enc.lo[a];
+        v[a] = num / enc.ext[a];
+        v[3 + a] = nrm[3 * (size_t)p + a];
+    }
+}
+
+// One dense layer for 16 points: out[t] = W tile t . B + bias (FP32).
+template <int KB>
+__device__ __forceinline__ void dense(const bf16x8* __restrict__ frag, const bf16x8 (&b)[KB],
+                                      const float* __restrict__ bias, uint32_t lane, f32x4 (&out)[4]) {
+    const uint32_t g = lane >> 4;
+#pragma unroll
+    for (uint32_t t = 0; t < 4u; ++t) {
+        f32x4 acc = {0.0f, 0.0f, 0.0f, 0.0f};
+#pragma unroll
+        for (int kb = 0; kb < KB; ++kb) acc = mfma(frag[(t * KB + kb) * 64u + lane], b[kb], acc);
+#pragma unroll
+        for (uint32_t r = 0; r < 4u; ++r) out[t][r] = acc[r] + bias[16u * t + 4u * g + r];
+    }
+}
+
+// ReLU of two tiles' registers into the next layer's B operand (BF16).
+__device__ __forceinline__ void relu_to_b(const f32x4 (&h)[4], bf16x8 (&b)[2]) {
+#pragma unroll
+    for (int kb = 0; kb < 2; ++kb) {
+        float val[8];
+#pragma unroll
+        for (int r = 0; r < 4; ++r) {
+            val[r] = h[2 * kb][r] > 0.0f ? h[2 * kb][r] : 0.0f;
+            val[4 + r] = h[2 * kb + 1][r] > 0.0f ? h[2 * kb + 1][r] : 0.0f;
+        }
+        b[kb] = pack8(val);
+    }
+}
+
+struct Fwd {
+    bf16x8 x[5];
+    f32x4 h1[4], h2[4], h3[4], z[4];
+    bf16x8 a1[2], a2[2], a3[2];
+};
+
+__device__ __forceinline__ void forward16(const bf16x8* __restrict__ frag, const float* __restrict__ master,
+                                          const float v[6], uint32_t lane, Fwd& f) {
+    encode_b(v, lane >> 4, f.x);
+    dense<5>(frag + fF1, f.x, master + ob1, lane, f.h1);
+    relu_to_b(f.h1, f.a1);
+    dense<2>(frag + fF2, f.a1, master + ob2, lane, f.h2);
+    relu_to_b(f.h2, f.a2);
+    dense<2>(frag + fF3, f.a2, master + ob3, lane, f.h3);
+    relu_to_b(f.h3, f.a3);
+    dense<2>(frag + fF4, f.a3, master + ob4, lane, f.z);
+}
+
+// Softmax over a point's 64 logits, which sit in the 4 lanes i, i+16, i+32,
+// i+48 (16 each).  Returns the probabilities in place of the logits and the
+// log of the normaliser relative to the max.
+__device__ __forceinline__ void softmax16(f32x4 (&z)[4], float& zmax, float& log_s) {
+    float m = z[0][0];
+#pragma unroll
+    for (int t = 0; t < 4; ++t)
+#pragma unroll
+        for (int r = 0; r < 4; ++r) m = fmaxf(m, z[t][r]);
+    m = fmaxf(m, __shfl_xor(m, 16, 64));
+    m = fmaxf(m, __shfl_xor(m, 32, 64));
+    float s = 0.0f;
+#pragma unroll
+    for (int t = 0; t < 4; ++t)
+#pragma unroll
+        for (int r = 0; r < 4; ++r) {
+            z[t][r] = expf(z[t][r] - m);
+            s += z[t][r];
+        }
+    s += __shfl_xor(s, 16, 64);
+    s += __shfl_xor(s, 32, 64);
+#pragma unroll
+    for (int t = 0; t < 4; ++t)
+#pragma unroll
+        for (int r = 0; r < 4; ++r) z[t][r] = z[t][r] / s;
+    zmax = m;
+    log_s = logf(s);
+}
+
+// ---------------------------------------------------------------------------
+// Inference: per point, the inclusive running sums of the 64 probabilities
+// (and optionally the logits).  Blocks stage the forward operands in LDS and
+// walk groups of 16 points, one group per wave per round.
+// ---------------------------------------------------------------------------
+__global__ void __launch_bounds__(kBlock) k_mlp_forward(const bf16x8* __restrict__ frag,
+                                                        const float* __restrict__ master, MlpEncode enc,
+                                                        const float* __restrict__ pos,
+                                                        const float* __restrict__ nrm, uint32_t P,
+                                                        float* __restrict__ cdf, float* __restrict__ logits) {
+    __shared__ bf16x8 s_frag[kFwdVecs];
+    __shared__ float s_q[4][16][65];
+    for (uint32_t j = threadIdx.x; j < kFwdVecs; j += kBlock) s_frag[j] = frag[j];
+    __syncthreads();
+    const uint32_t lane = threadIdx.x & 63u, wave = threadIdx.x >> 6, i16 = lane & 15u, g = lane >> 4;
+    const uint32_t ngroups = (P + 15u) >> 4;
+    for (uint32_t base = blockIdx.x * 4u; base < ngroups; base += gridDim.x * 4u) {
+        const uint32_t grp = base + wave;
+        const uint32_t p = grp * 16u + i16;
+        const bool valid = grp < ngroups && p < P;
+        float v[6];
+        point_inputs(enc, pos, nrm, valid ? p : 0u, v);
+        Fwd f;
+        forward16(s_frag, master, v, lane, f);
+        if (valid && logits) {
+#pragma unroll
+            for (uint32_t t = 0; t < 4u; ++t)
+                *reinterpret_cast<float4*>(logits + (size_t)p * 64u + 16u * t + 4u * g) =
+                    make_float4(f.z[t][0], f.z[t][1], f.z[t][2], f.z[t][3]);
+        }
+        float zmax, log_s;
+        softmax16(f.z, zmax, log_s);
+#pragma unroll
+        for (uint32_t t = 0; t < 4u; ++t)
+#pragma unroll
+            for (uint32_t r = 0; r < 4u; ++r) s_q[wave][i16][16u * t + 4u * g + r] = f.z[t][r];
+        __syncthreads();
+        if (valid && g == 0u && cdf) {
+            float acc = 0.0f;
+            float* row = cdf + (size_t)p * 64u;
+            for (uint32_t k = 0; k < 64u; k += 4u) {
+                float4 o;
+                acc = acc + s_q[wave][i16][k];
+                o.x = acc;
+                acc = acc + s_q[wave][i16][k + 1u];
+                o.y = acc;
+                acc = acc + s_q[wave][i16][k + 2u];
+                o.z = acc;
+                acc = acc + s_q[wave][i16][k + 3u];
+                o.w = acc;
+                *reinterpret_cast<float4*>(row + k) = o;
+            }
+        }
+        __syncthreads();
+    }
+}
+
+// ---------------------------------------------------------------------------
+// Training: forward and backward of 64 tuples per block (16 per wave), and
+// the block's share of the weight gradient, sum over its tuples of
+// G_L A_{L-1}^T, staged through LDS one layer at a time.  Writes one row of
+// partial sums (all parameters), and the block's sum of weights and of
+// weighted losses; the reduction over blocks is done in a fixed order by
+// k_mlp_reduce.
+// ---------------------------------------------------------------------------
+__device__ __forceinline__ void stage_hidden(uint16_t* __restrict__ s, const bf16x8 (&b)[2], uint32_t g,
+                                             uint32_t col) {
+#pragma unroll
+    for (uint32_t kb = 0; kb < 2u; ++kb)
+#pragma unroll
+        for (uint32_t e = 0; e < 8u; ++e) {
+            const uint32_t j = 32u * kb + 16u * (e >> 2) + 4u * g + (e & 3u);
+            s[j * kLds + col] = elem(b[kb], (int)e);
+        }
+}
+
+// gW tile (to, tj) over the block's 64 tuples, added to the partial row.
+__device__ __forceinline__ void wgrad_tile(const uint16_t* __restrict__ sG, const uint16_t* __restrict__ sA,
+                                           uint32_t to, uint32_t tj, uint32_t nin, uint32_t lane,
+                                           float* __restrict__ prow) {
+    const uint32_t i16 = lane & 15u, g = lane >> 4;
+    f32x4 acc = {0.0f, 0.0f, 0.0f, 0.0f};
+#pragma unroll
+    for (uint32_t kb = 0; kb < 2u; ++kb) {
+        const bf16x8 a = *reinterpret_cast<const bf16x8*>(sG + (16u * to + i16) * kLds + 32u * kb + 8u * g);
+        const bf16x8 b = *reinterpret_cast<const bf16x8*>(sA + (16u * tj + i16) * kLds + 32u * kb + 8u * g);
+        acc = mfma(a, b, acc);
+    }
+#pragma unroll
+    for (uint32_t r = 0; r < 4u; ++r) prow[(16u * to + 4u * g + r) * nin + 16u * tj + i16] = acc[r];
+}
+
+__global__ void __launch_bounds__(kBlock) k_mlp_fwd_bwd(const bf16x8* __restrict__ frag,
+                                                        const float* __restrict__ master, MlpEncode enc,
+                                                        const float* __restrict__ pos,
+                                                        const float* __restrict__ nrm, uint32_t P,
+                                                        const uint32_t* __restrict__ order,
+                                                        const uint32_t* __restrict__ pid,
+                                                        const uint32_t* __restrict__ node,
+                                                        const float* __restrict__ w, uint32_t n,
+                                                        float* __restrict__ partial, float* __restrict__ part_w,
+                                                        float* __restrict__ part_loss, uint32_t* __restrict__ err) {
+    __shared__ __attribute__((aligned(16))) uint16_t sG[kH * kLds];
+    __shared__ __attribute__((aligned(16))) uint16_t sA[kIn * kLds];
+    __shared__ float s_w[64], s_l[64];
+    const uint32_t lane = threadIdx.x & 63u, wave = threadIdx.x >> 6, i16 = lane & 15u, g = lane >> 4;
+    const uint32_t col = wave * 16u + i16;
+    const uint32_t tb = blockIdx.x * kMlpTuplesPerBlock + col;
+    uint32_t pt = 0, nd = 0;
+    float wt = 0.0f;
+    if (tb < n) {
+        const uint32_t t = order ? order[tb] : tb;
+        pt = pid[t];
+        nd = node[t];
+        wt = w[t];
+        if (pt >= P || nd >= 64u || !(wt >= 0.0f && wt <= 3.402823466e38f)) {
+            if (g == 0u) atomicOr(err, RLC_DERR_INPUT);
+            pt = 0;
+            nd = 0;
+            wt = 0.0f;
+        }
+    }
+    float v[6];
+    point_inputs(enc, pos, nrm, pt, v);
+    Fwd f;
+    forward16(frag, master, v, lane, f);
+    float zmax, log_s;
+    f32x4 zl[4];
+#pragma unroll
+    for (int t = 0; t < 4; ++t) zl[t] = f.z[t];
+    softmax16(f.z, zmax, log_s);
+    // loss term -w log q[node], from the lane holding the target's logit
+    {
+        const uint32_t tn = nd >> 4, gn = (nd & 15u) >> 2, rn = nd & 3u;
+        if (g == gn) {
+            float zn = 0.0f;
+#pragma unroll
+            for (uint32_t t = 0; t < 4u; ++t)
+#pragma unroll
+                for (uint32_t r = 0; r < 4u; ++r)
+                    if (t == tn && r == rn) zn = zl[t][r];
+            s_l[col] = -(wt * ((zn - zmax) - log_s));
+            s_w[col] = wt;
+        }
+    }
+    // output gradient w (q - e_node), then back through layers 4, 3, 2
+    bf16x8 gB4[2], gB3[2], gB2[2], gB1[2];
+    {
+        f32x4 g4[4];
+#pragma unroll
+        for (uint32_t t = 0; t < 4u; ++t)
+#pragma unroll
+            for (uint32_t r = 0; r < 4u; ++r) {
+                const uint32_t u = 16u * t + 4u * g + r;
+                g4[t][r] = wt * (f.z[t][r] - (u == nd ? 1.0f : 0.0f));
+            }
+#pragma unroll
+        for (int kb = 0; kb < 2; ++kb) {
+            float val[8];
+#pragma unroll
+            for (int r = 0; r < 4; ++r) {
+                val[r] = g4[2 * kb][r];
+                val[4 + r] = g4[2 * kb + 1][r];
+            }
+            gB4[kb] = pack8(val);
+        }
+    }
+    auto back = [&](const bf16x8* __restrict__ fr, const bf16x8 (&gin)[2], const f32x4 (&hpre)[4],
+                    bf16x8 (&gout)[2]) {
+        f32x4 d[4];
+#pragma unroll
+        for (uint32_t t = 0; t < 4u; ++t) {
+            f32x4 acc = {0.0f, 0.0f, 0.0f, 0.0f};
+#pragma unroll
+            for (uint32_t kb = 0; kb < 2u; ++kb) acc = mfma(fr[(t * 2u + kb) * 64u + lane], gin[kb], acc);
+#pragma unroll
+            for (uint32_t r = 0; r < 4u; ++r) d[t][r] = hpre[t][r] > 0.0f ? acc[r] : 0.0f;
+        }
+#pragma unroll
+        for (int kb = 0; kb < 2; ++kb) {
+            float val[8];
+#pragma unroll
+            for (int r = 0; r < 4; ++r) {
+                val[r] = d[2 * kb][r];
+                val[4 + r] = d[2 * kb + 1][r];
+            }
+            gout[kb] = pack8(val);
+        }
+    };
+    back(frag + fT4, gB4, f.h3, gB3);
+    back(frag + fT3, gB3, f.h2, gB2);
+    back(frag + fT2, gB2, f.h1, gB1);
+
+    float* prow = partial + (size_t)blockIdx.x * kNP;
+    // layers 4, 3, 2: G_L (64 rows) against the previous activations (64 rows)
+    const bf16x8* gs[3] = {gB4, gB3, gB2};
+    const bf16x8* as[3] = {f.a3, f.a2, f.a1};
+    const uint32_t ow[3] = {oW4, oW3, oW2}, ob[3] = {ob4, ob3, ob2};
+#pragma unroll
+    for (int L = 0; L < 3; ++L) {
+        const bf16x8(&gg)[2] = *reinterpret_cast<const bf16x8(*)[2]>(gs[L]);
+        const bf16x8(&aa)[2] = *reinterpret_cast<const bf16x8(*)[2]>(as[L]);
+        stage_hidden(sG, gg, g, col);
+        stage_hidden(sA, aa, g, col);
+        __syncthreads();
+#pragma unroll
+        for (uint32_t k = 0; k < 4u; ++k) {
+            const uint32_t tile = wave * 4u + k;
+            wgrad_tile(sG, sA, tile >> 2, tile & 3u, kH, lane, prow + ow[L]);
+        }
+        if (threadIdx.x < kH) {
+            float s = 0.0f;
+            for (uint32_t c = 0; c < 64u; ++c) s += bf16_val(sG[threadIdx.x * kLds + c]);
+            prow[ob[L] + threadIdx.x] = s;
+        }
+        __syncthreads();
+    }
+    // layer 1: G_1 against the encoded inputs (144 rows)
+    stage_hidden(sG, gB1, g, col);
+#pragma unroll
+    for (uint32_t kb = 0; kb < 5u; ++kb)
+#pragma unroll
+        for (uint32_t e = 0; e < 8u; ++e) {
+            const uint32_t j = 32u * kb + 8u * g + e;
+            if (j < kIn) sA[j * kLds + col] = elem(f.x[kb], (int)e);
+        }
+    __syncthreads();
+    for (uint32_t k = 0; k < 9u; ++k) {
+        const uint32_t tile = wave * 9u + k;  // 36 tiles: 4 output x 9 input
+        wgrad_tile(sG, sA, tile / 9u, tile % 9u, kIn, lane, prow + oW1);
+    }
+    if (threadIdx.x < kH) {
+        float s = 0.0f;
+        for (uint32_t c = 0; c < 64u; ++c) s += bf16_val(sG[threadIdx.x * kLds + c]);
+        prow[ob1 + threadIdx.x] = s;
+    }
+    if (threadIdx.x == 0) {
+        float sw = 0.0f, sl = 0.0f;
+        for (uint32_t c = 0; c < 64u; ++c) {
+            sw += s_w[c];
+            sl += s_l[c];
+        }
+        part_w[blockIdx.x] = sw;
+        part_loss[blockIdx.x] = sl;
+    }
+}
+
+// Sum of the blocks' partial rows, divided by the batch's sum of weights;
+// then either stored (mode 0) or applied by Adam (mode 1, with the bias
+// corrections c1 = 1 - beta1^t, c2 = 1 - beta2^t) with the BF16 operands
+// refreshed from the new FP32 weights.  A block covers 32 parameters with 8
+// row groups: group r sums rows r, r + 8, ... in order, and the 8 group sums
+// are added in group order, so the result does not depend on scheduling.
+constexpr uint32_t kRedCols = 32, kRedGroups = kBlock / kRedCols;
+
+__global__ void __launch_bounds__(kBlock) k_mlp_reduce(const float* __restrict__ partial,
+                                                       const float* __restrict__ part_w,
+                                                       const float* __restrict__ part_loss, uint32_t nblocks,
+                                                       uint32_t mode, float* __restrict__ out,
+                                                       float* __restrict__ master, float* __restrict__ m,
+                                                       float* __restrict__ v, uint16_t* __restrict__ frag, float lr,
+                                                       float beta1, float beta2, float eps, float c1, float c2,
+                                                       float* __restrict__ loss) {
+    __shared__ float s_part[kRedGroups][kRedCols];
+    __shared__ float s_inv;
+    const uint32_t col = threadIdx.x % kRedCols, grp = threadIdx.x / kRedCols;
+    const uint32_t p = blockIdx.x * kRedCols + col;
+    float acc = 0.0f;
+    if (p < kNP)
+        for (uint32_t b = grp; b < nblocks; b += kRedGroups) acc += partial[(size_t)b * kNP + p];
+    s_part[grp][col] = acc;
+    if (threadIdx.x == 0) {
+        float sw = 0.0f;
+        for (uint32_t b = 0; b < nblocks; ++b) sw += part_w[b];
+        const float inv = sw > 0.0f ? 1.0f / sw : 0.0f;
+        s_inv = inv;
+        if (blockIdx.x == 0 && loss) {
+            float sl = 0.0f;
+            for (uint32_t b = 0; b < nblocks; ++b) sl += part_loss[b];
+            *loss = sl * inv;
+        }
+    }
+    __syncthreads();
+    if (grp != 0 || p >= kNP) return;
+    float gsum = 0.0f;
+    for (uint32_t r = 0; r < kRedGroups; ++r) gsum += s_part[r][col];
+    const float gr = gsum * s_inv;
+    if (mode == 0u) {
+        out[p] = gr;
+        return;
+    }
+    const float mm = beta1 * m[p] + (1.0f - beta1) * gr;
+    const float vv = beta2 * v[p] + (1.0f - beta2) * (gr * gr);
+    m[p] = mm;
+    v[p] = vv;
+    const float mh = mm / c1, vh = vv / c2;
+    const float np = master[p] - lr * mh / (sqrtf(vh) + eps);
+    master[p] = np;
+    write_frag(frag, p, np);
+}
+
+__global__ void __launch_bounds__(kBlock) k_mlp_refresh(const float* __restrict__ master,
+                                                        uint16_t* __restrict__ frag) {
+    const uint32_t p = blockIdx.x * kBlock + threadIdx.x;
+    if (p < kNP) write_frag(frag, p, master[p]);
+}
+
+// Training order of an epoch: key of tuple i = first word of Philox at
+// counter (i, epoch, 0, scene << 16 | 2); sorted (stably) by key.
+__global__ void __launch_bounds__(kBlock) k_mlp_shuffle_keys(uint32_t n, uint32_t epoch, uint32_t scene_id,
+                                                             uint32_t seed_lo, uint32_t seed_hi,
+                                                             uint32_t* __restrict__ keys,
+                                                             uint32_t* __restrict__ vals) {
+    const uint32_t i = blockIdx.x * kBlock + threadIdx.x;
+    if (i >= n) return;
+    uint32_t x0 = i, x1 = epoch, x2 = 0u, x3 = (scene_id << 16) | 2u;
+    philox4x32_10(x0, x1, x2, x3, seed_lo, seed_hi);
+    keys[i] = x0;
+    vals[i] = i;
+}
+
+// Initial weights: uniform in +-sqrt(6 / fan_in) (He et al. 2015, uniform
+// form) from Philox at counter (p, 0, 0, scene << 16 | 3); biases zero.
+__global__ void __launch_bounds__(kBlock) k_mlp_init(float* __restrict__ master, uint32_t scene_id,
+                                                     uint32_t seed_lo, uint32_t seed_hi) {
+    const uint32_t p = blockIdx.x * kBlock + threadIdx.x;
+    if (p >= kNP) return;
+    uint32_t layer, o, j;
+    if (!weight_of(p, layer, o, j)) {
+        master[p] = 0.0f;
+        return;
+    }
+    uint32_t x0 = p, x1 = 0u, x2 = 0u, x3 = (scene_id << 16) | 3u;
+    philox4x32_10(x0, x1, x2, x3, seed_lo, seed_hi);
+    const float a = sqrtf(6.0f / (layer == 1u ? (float)kIn : (float)kH));
+    master[p] = (2.0f * unit24(x0) - 1.0f) * a;
+}
+
+inline uint32_t blocks_for(size_t n) { return (uint32_t)((n + kBlock - 1) / kBlock); }
+
+}  // namespace
+
+hipError_t launch_mlp_refresh(const float* master, uint16_t* frag, hipStream_t s) {
+    hipLaunchKernelGGL(k_mlp_refresh, dim3(blocks_for(kNP)), dim3(kBlock), 0, s, master, frag);
+    return hipGetLastError();
+}
+
+hipError_t launch_mlp_forward(const uint16_t* frag, const float* master, MlpEncode enc, const float* pos,
+                              const float* nrm, uint32_t P, float* cdf, float* logits, hipStream_t s) {
+    if (P == 0) return hipSuccess;
+    const uint32_t groups = (P + 15u) / 16u;
+    uint32_t grid = (groups + 3u) / 4u;
+    if (grid > 2048u) grid = 2048u;
+    hipLaunchKernelGGL(k_mlp_forward, dim3(grid), dim3(kBlock), 0, s, reinterpret_cast<const bf16x8*>(frag),
+                       master, enc, pos, nrm, P, cdf, logits);
+    return hipGetLastError();
+}
+
+hipError_t launch_mlp_fwd_bwd(const uint16_t* frag, const float* master, MlpEncode enc, const float* pos,
+                              const float* nrm, uint32_t P, const uint32_t* order, const uint32_t* pid,
+                              const uint32_t* node, const float* w, uint32_t n, float* partial, float* part_w,
+                              float* part_loss, uint32_t* err, hipStream_t s) {
+    if (n == 0) return hipSuccess;
+    const uint32_t grid = (n + kMlpTuplesPerBlock - 1u) / kMlpTuplesPerBlock;
+    hipLaunchKernelGGL(k_mlp_fwd_bwd, dim3(grid), dim3(kBlock), 0, s, reinterpret_cast<const bf16x8*>(frag),
+                       master, enc, pos, nrm, P, order, pid, node, w, n, partial, part_w, part_loss, err);
+    return hipGetLastError();
+}
+
+hipError_t launch_mlp_reduce(const float* partial, const float* part_w, const float* part_loss, uint32_t nblocks,
+                             uint32_t mode, float* out, float* master, float* m, float* v, uint16_t* frag,
+                             float lr, float beta1, float beta2, float eps, float c1, float c2, float* loss,
+                             hipStream_t s) {
+    hipLaunchKernelGGL(k_mlp_reduce, dim3((kNP + kRedCols - 1) / kRedCols), dim3(kBlock), 0, s, partial, part_w,
+                       part_loss,
+                       nblocks, mode, out, master, m, v, frag, lr, beta1, beta2, eps, c1, c2, loss);
+    return hipGetLastError();
+}
+
+hipError_t launch_mlp_shuffle_keys(uint32_t n, uint32_t epoch, uint32_t scene_id, uint32_t seed_lo,
+                                   uint32_t seed_hi, uint32_t* keys, uint32_t* vals, hipStream_t s) {
+    if (n == 0) return hipSuccess;
+    hipLaunchKernelGGL(k_mlp_shuffle_keys, dim3(blocks_for(n)), dim3(kBlock), 0, s, n, epoch, scene_id, seed_lo,
+                       seed_hi, keys, vals);
+    return hipGetLastError();
+}
+
+hipError_t launch_mlp_init(float* master, uint32_t scene_id, uint32_t seed_lo, uint32_t seed_hi, hipStream_t s) {
+    hipLaunchKernelGGL(k_mlp_init, dim3(blocks_for(kNP)), dim3(kBlock), 0, s, master, scene_id, seed_lo, seed_hi);
+    return hipGetLastError();
+}
+
+}  // namespace rlc

@@ -16,6 +16,7 @@
 #define RLC_DERR_CAPACITY 1u
 #define RLC_DERR_NONFINITE 2u
 #define RLC_DERR_INPUT 4u
+#define RLC_MIX_M 64u           // nodes of the learned proposal's fixed cut (row stride of its cdf)
 
 namespace rlc {
 
@@ -76,6 +77,16 @@ struct FrameParams {
     uint32_t reward_mode;
     uint32_t two_sided;
     uint32_t* err;
+    // learned proposal: per-point inclusive running sums of the fixed cut's
+    // probabilities (rows of RLC_MIX_M), or null for draws from the cut alone
+    const float* mix_cdf;
+    const uint32_t* fix_end;    // cluster ends of the fixed cut
+    uint32_t fix_M;
+    float mix_w;                // probability of drawing from the cell's cut
+    // optional per-sample training records, index point * spp + sample
+    uint32_t* log_pid;
+    uint32_t* log_node;
+    float* log_w;
 };
 
 // One scene of a batched pass: its parameters, inputs and output, and the
@@ -198,6 +209,8 @@ __device__ __forceinline__ uint32_t find_or_create(const DevCells& c, unsigned l
 struct Sample {
     uint32_t cell;      // table slot or RLC_NONE
     uint32_t ready;
+    uint32_t comp;      // 1: drawn by the learned proposal
+    uint32_t fnode;     // fixed-cut node holding the light (RLC_NONE if not needed)
     uint32_t s;
     uint32_t size;
     uint32_t light;
@@ -233,22 +246,84 @@ __device__ __forceinline__ void draw_sample(const FrameParams& fp, float x, floa
     float u2 = unit24(w2);
     float u3 = unit24(w3);
 
-    float total = C[Meff - 1u];
-    float t = u0 * total;
-    // smallest s with t < C[s] (C is non-decreasing)
-    uint32_t lo = 0, hi = Meff;
-    while (lo < hi) {
-        uint32_t mid = (lo + hi) >> 1;
-        if (t < C[mid])
-            hi = mid;
-        else
-            lo = mid + 1u;
+    // mixture component: counter tag 1, only with the learned proposal on
+    const float* q = nullptr;
+    bool use_mlp = false;
+    if (fp.mix_cdf) {
+        uint32_t c0 = pid, c1 = k, c2 = frame, c3 = (fp.scene_id << 16) | 1u;
+        philox4x32_10(c0, c1, c2, c3, fp.seed_lo, fp.seed_hi);
+        q = fp.mix_cdf + (size_t)pid * RLC_MIX_M;
+        use_mlp = !(unit24(c0) < fp.mix_w);
     }
-    uint32_t s = lo < Meff ? lo : Meff - 1u;
-    uint32_t begin = s ? end[s - 1u] : 0u;
-    uint32_t size = end[s] - begin;
-    float inv_pdf = ((float)size * total) / Qt[s];
-    uint32_t l = begin + (uint32_t)((draw40 * (unsigned long long)size) >> 40);
+    const float total = C[Meff - 1u];
+    const uint32_t Mf = fp.fix_M;
+    uint32_t s, l, kf = RLC_NONE, fsize = 0;
+    if (!use_mlp) {
+        // smallest s with t < C[s] (C is non-decreasing)
+        float t = u0 * total;
+        uint32_t lo = 0, hi = Meff;
+        while (lo < hi) {
+            uint32_t mid = (lo + hi) >> 1;
+            if (t < C[mid])
+                hi = mid;
+            else
+                lo = mid + 1u;
+        }
+        s = lo < Meff ? lo : Meff - 1u;
+        uint32_t b = s ? end[s - 1u] : 0u;
+        l = b + (uint32_t)((draw40 * (unsigned long long)(end[s] - b)) >> 40);
+    } else {
+        // node of the fixed cut from the learned cdf, a light inside it, and
+        // the cell's cluster that holds that light
+        float t = u0 * q[Mf - 1u];
+        uint32_t lo = 0, hi = Mf;
+        while (lo < hi) {
+            uint32_t mid = (lo + hi) >> 1;
+            if (t < q[mid])
+                hi = mid;
+            else
+                lo = mid + 1u;
+        }
+        kf = lo < Mf ? lo : Mf - 1u;
+        uint32_t fb = kf ? fp.fix_end[kf - 1u] : 0u;
+        fsize = fp.fix_end[kf] - fb;
+        l = fb + (uint32_t)((draw40 * (unsigned long long)fsize) >> 40);
+        lo = 0;
+        hi = Meff - 1u;
+        while (lo < hi) {
+            uint32_t mid = (lo + hi) >> 1;
+            if (l < end[mid])
+                hi = mid;
+            else
+                lo = mid + 1u;
+        }
+        s = lo;
+    }
+    if (kf == RLC_NONE && (q || fp.log_node)) {
+        uint32_t lo = 0, hi = Mf - 1u;
+        while (lo < hi) {
+            uint32_t mid = (lo + hi) >> 1;
+            if (l < fp.fix_end[mid])
+                hi = mid;
+            else
+                lo = mid + 1u;
+        }
+        kf = lo;
+        fsize = fp.fix_end[kf] - (kf ? fp.fix_end[kf - 1u] : 0u);
+    }
+    const uint32_t begin = s ? end[s - 1u] : 0u;
+    const uint32_t size = end[s] - begin;
+    float inv_pdf;
+    if (q) {
+        // p(l) = w p_cut(l) + (1 - w) p_learned(l), each uniform inside its
+        // cluster or node
+        float pt = Qt[s] / ((float)size * total);
+        float qk = q[kf] - (kf ? q[kf - 1u] : 0.0f);
+        float pm = qk / ((float)fsize * q[Mf - 1u]);
+        inv_pdf = 1.0f / (fp.mix_w * pt + (1.0f - fp.mix_w) * pm);
+    } else {
+        inv_pdf = ((float)size * total) / Qt[s];
+    }
 
     const float4 r0 = fp.tree.rec[4u * l + 0u];
     const float4 r1 = fp.tree.rec[4u * l + 1u];
@@ -262,6 +337,8 @@ __device__ __forceinline__ void draw_sample(const FrameParams& fp, float x, floa
     o.y[2] = (b0 * r0.z + b1 * r1.y) + b2 * r2.x;
     o.cell = cell;
     o.ready = rdy;
+    o.comp = use_mlp ? 1u : 0u;
+    o.fnode = kf;
     o.s = s;
     o.size = size;
     o.light = l;
@@ -381,6 +458,31 @@ hipError_t launch_batch_adapt(const AdaptParams* aps, uint32_t n_scenes, hipStre
 hipError_t launch_gather_cells(DevCells c, uint32_t Meff, const uint32_t* slots, uint32_t n, uint32_t* node,
                                uint32_t* end, float* Q, float* Qt, float* C, unsigned long long* sum,
                                uint32_t* cnt, hipStream_t s);
+
+// mlp.hip: the learned proposal (144 -> 64 -> 64 -> 64 -> 64, BF16 MFMA)
+constexpr uint32_t kMlpParams = 64u * 144u + 64u + 3u * (64u * 64u + 64u);
+constexpr uint32_t kMlpFragVecs = 4352u;   // 16-byte BF16 operand fragments
+constexpr uint32_t kMlpTuplesPerBlock = 64u;
+struct MlpEncode {
+    float lo[3];
+    float ext[3];
+};
+hipError_t launch_mlp_refresh(const float* master, uint16_t* frag, hipStream_t s);
+hipError_t launch_mlp_forward(const uint16_t* frag, const float* master, MlpEncode enc, const float* pos,
+                              const float* nrm, uint32_t P, float* cdf, float* logits, hipStream_t s);
+hipError_t launch_mlp_fwd_bwd(const uint16_t* frag, const float* master, MlpEncode enc, const float* pos,
+                              const float* nrm, uint32_t P, const uint32_t* order, const uint32_t* pid,
+                              const uint32_t* node, const float* w, uint32_t n, float* partial, float* part_w,
+                              float* part_loss, uint32_t* err, hipStream_t s);
+// mode 0: write the batch gradient to `out`; mode 1: Adam step on master
+// (m, v), then refresh the BF16 fragments
+hipError_t launch_mlp_reduce(const float* partial, const float* part_w, const float* part_loss, uint32_t nblocks,
+                             uint32_t mode, float* out, float* master, float* m, float* v, uint16_t* frag,
+                             float lr, float beta1, float beta2, float eps, float c1, float c2, float* loss,
+                             hipStream_t s);
+hipError_t launch_mlp_shuffle_keys(uint32_t n, uint32_t epoch, uint32_t scene_id, uint32_t seed_lo,
+                                   uint32_t seed_hi, uint32_t* keys, uint32_t* vals, hipStream_t s);
+hipError_t launch_mlp_init(float* master, uint32_t scene_id, uint32_t seed_lo, uint32_t seed_hi, hipStream_t s);
 
 // stats.hip
 hipError_t launch_image_error(const float* img, const float* ref, uint32_t n, double* partial,

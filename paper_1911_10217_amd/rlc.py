@@ -36,7 +36,11 @@ EXPORTS = (
     "rlc_dump_cells", "rlc_dump_tree", "rlc_get_template", "rlc_set_timing", "rlc_get_timing",
     "rlc_batch_create", "rlc_batch_destroy", "rlc_batch_set_schedule", "rlc_batch_get_schedule",
     "rlc_batch_autotune", "rlc_batch_frame",
+    "rlc_mlp_fixed_cut", "rlc_mlp_init", "rlc_mlp_set_params", "rlc_mlp_get_params", "rlc_mlp_forward",
+    "rlc_mlp_grad", "rlc_mlp_train", "rlc_set_mixture", "rlc_set_sample_log", "rlc_get_mlp_timing",
 )
+RLC_MLP_PARAMS = 21760
+RLC_MLP_NODES = 64
 
 
 class RLCError(RuntimeError):
@@ -73,7 +77,7 @@ class rlc_config(ctypes.Structure):
 
 class rlc_samples(ctypes.Structure):
     _fields_ = [(n, ctypes.c_void_p) for n in
-                ("d_key", "d_cell", "d_ready", "d_slot", "d_light", "d_inv_pdf", "d_y")]
+                ("d_key", "d_cell", "d_ready", "d_slot", "d_light", "d_inv_pdf", "d_y", "d_comp")]
 
 
 class rlc_batch_scene(ctypes.Structure):
@@ -140,6 +144,17 @@ def _declare(L):
     L.rlc_batch_frame.argtypes = [_vp, _u32]
     L.rlc_set_timing.argtypes = [_vp, i]
     L.rlc_get_timing.argtypes = [_vp, _vp, _vp, _vp]
+    f = ctypes.c_float
+    L.rlc_mlp_fixed_cut.argtypes = [_vp, _vp, _vp, _vp]
+    L.rlc_mlp_init.argtypes = [_vp, ctypes.c_uint64]
+    L.rlc_mlp_set_params.argtypes = [_vp, _vp]
+    L.rlc_mlp_get_params.argtypes = [_vp, _vp]
+    L.rlc_mlp_forward.argtypes = [_vp, _vp, _vp, _u32, _vp, _vp]
+    L.rlc_mlp_grad.argtypes = [_vp, _vp, _vp, _u32, _vp, _vp, _vp, _u32, _vp, _vp]
+    L.rlc_mlp_train.argtypes = [_vp, _vp, _vp, _u32, _vp, _vp, _vp, _u32, _u32, _u32, f, _vp]
+    L.rlc_set_mixture.argtypes = [_vp, _vp, _u32, f]
+    L.rlc_set_sample_log.argtypes = [_vp, _vp, _vp, _vp, ctypes.c_uint64]
+    L.rlc_get_mlp_timing.argtypes = [_vp, _vp, _vp, _vp]
     for name in EXPORTS:
         if name != "rlc_last_error":
             getattr(L, name).restype = i
@@ -266,11 +281,13 @@ class Context:
                     slot=torch.empty(n, dtype=torch.int32, device=dev),
                     light=torch.empty(n, dtype=torch.int32, device=dev),
                     inv_pdf=torch.empty(n, dtype=torch.float32, device=dev),
-                    y=torch.empty((n, 3), dtype=torch.float32, device=dev))
+                    y=torch.empty((n, 3), dtype=torch.float32, device=dev),
+                    comp=torch.empty(n, dtype=torch.int32, device=dev))
 
     @staticmethod
     def _samples_struct(s: dict) -> rlc_samples:
-        return rlc_samples(*[_ptr(s.get(k)) for k in ("key", "cell", "ready", "slot", "light", "inv_pdf", "y")])
+        return rlc_samples(*[_ptr(s.get(k)) for k in ("key", "cell", "ready", "slot", "light", "inv_pdf", "y",
+                                                      "comp")])
 
     def rlc_sample(self, pos, nrm, spp: int, frame: int, out: Optional[dict] = None) -> dict:
         import torch
@@ -392,6 +409,99 @@ class Context:
         n = np.zeros(1, np.uint32)
         self._check(lib().rlc_get_timing(self._h, f.ctypes.data, a.ctypes.data, n.ctypes.data), "rlc_get_timing")
         return float(f[0]), float(a[0]), int(n[0])
+
+    def rlc_get_mlp_timing(self):
+        f = np.zeros(1, np.float64)
+        u = np.zeros(1, np.float64)
+        n = np.zeros(1, np.uint32)
+        self._check(lib().rlc_get_mlp_timing(self._h, f.ctypes.data, u.ctypes.data, n.ctypes.data),
+                    "rlc_get_mlp_timing")
+        return float(f[0]), float(u[0]), int(n[0])
+
+    # -- learned proposal ------------------------------------------------------------
+    def rlc_mlp_fixed_cut(self):
+        node = np.zeros(RLC_MLP_NODES, np.uint32)
+        end = np.zeros(RLC_MLP_NODES, np.uint32)
+        m = np.zeros(1, np.uint32)
+        self._check(lib().rlc_mlp_fixed_cut(self._h, node.ctypes.data, end.ctypes.data, m.ctypes.data),
+                    "rlc_mlp_fixed_cut")
+        return node[:m[0]].copy(), end[:m[0]].copy()
+
+    def rlc_mlp_init(self, seed: int):
+        self._check(lib().rlc_mlp_init(self._h, int(seed)), "rlc_mlp_init")
+
+    def rlc_mlp_set_params(self, params):
+        import torch
+        _dev(params, torch.float32, "params")
+        if params.numel() != RLC_MLP_PARAMS:
+            raise ValueError("params must hold %d floats" % RLC_MLP_PARAMS)
+        self._check(lib().rlc_mlp_set_params(self._h, _ptr(params)), "rlc_mlp_set_params")
+
+    def rlc_mlp_get_params(self):
+        import torch
+        out = torch.empty(RLC_MLP_PARAMS, dtype=torch.float32, device="cuda")
+        self._check(lib().rlc_mlp_get_params(self._h, _ptr(out)), "rlc_mlp_get_params")
+        return out
+
+    def rlc_mlp_forward(self, pos, nrm, cdf: bool = True, logits: bool = False):
+        import torch
+        _dev(pos, torch.float32, "pos")
+        _dev(nrm, torch.float32, "nrm")
+        P = pos.numel() // 3
+        c = torch.empty((P, RLC_MLP_NODES), dtype=torch.float32, device="cuda") if cdf else None
+        z = torch.empty((P, RLC_MLP_NODES), dtype=torch.float32, device="cuda") if logits else None
+        self._check(lib().rlc_mlp_forward(self._h, _ptr(pos), _ptr(nrm), P, _ptr(c), _ptr(z)), "rlc_mlp_forward")
+        return c, z
+
+    @staticmethod
+    def _tuples(pid, node, w):
+        import torch
+        _dev(pid, torch.int32, "pid")
+        _dev(node, torch.int32, "node")
+        _dev(w, torch.float32, "w")
+        n = pid.numel()
+        if node.numel() != n or w.numel() != n:
+            raise ValueError("pid, node and w must have the same length")
+        return n
+
+    def rlc_mlp_grad(self, pos, nrm, pid, node, w):
+        import torch
+        n = self._tuples(pid, node, w)
+        g = torch.empty(RLC_MLP_PARAMS, dtype=torch.float32, device="cuda")
+        loss = np.zeros(1, np.float32)
+        self._check(lib().rlc_mlp_grad(self._h, _ptr(pos), _ptr(nrm), pos.numel() // 3, _ptr(pid), _ptr(node),
+                                       _ptr(w), n, _ptr(g), loss.ctypes.data), "rlc_mlp_grad")
+        return float(loss[0]), g
+
+    def rlc_mlp_train(self, pos, nrm, pid, node, w, epochs: int, batch: int, lr: float) -> float:
+        n = self._tuples(pid, node, w)
+        loss = np.zeros(1, np.float32)
+        self._check(lib().rlc_mlp_train(self._h, _ptr(pos), _ptr(nrm), pos.numel() // 3, _ptr(pid), _ptr(node),
+                                        _ptr(w), n, int(epochs), int(batch), float(lr), loss.ctypes.data),
+                    "rlc_mlp_train")
+        return float(loss[0])
+
+    def rlc_set_mixture(self, cdf=None, w: float = 0.5):
+        import torch
+        if cdf is None:
+            self._mix_keep = None
+            self._check(lib().rlc_set_mixture(self._h, None, 0, 0.0), "rlc_set_mixture")
+            return
+        _dev(cdf, torch.float32, "cdf")
+        rows = cdf.numel() // RLC_MLP_NODES
+        self._mix_keep = cdf
+        self._check(lib().rlc_set_mixture(self._h, _ptr(cdf), rows, float(w)), "rlc_set_mixture")
+
+    def rlc_set_sample_log(self, pid=None, node=None, w=None):
+        import torch
+        if pid is None:
+            self._log_keep = None
+            self._check(lib().rlc_set_sample_log(self._h, None, None, None, 0), "rlc_set_sample_log")
+            return
+        n = self._tuples(pid, node, w)
+        self._log_keep = (pid, node, w)
+        self._check(lib().rlc_set_sample_log(self._h, _ptr(pid), _ptr(node), _ptr(w), n), "rlc_set_sample_log")
+
 
 
 class Batch:
