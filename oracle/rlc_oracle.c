@@ -847,6 +847,12 @@ static void rebuild_cdf(const float* Q, uint32_t Meff, float eps, float* Qt, flo
         for (uint32_t s = 0; s < Meff; ++s) Qt[s] = 1.0f;
     } else {
         float floor_term = (eps * S) / (float)Meff;
+        /* reading: with eps > 0 every cluster keeps a positive probability.
+         * Q decays geometrically under Eq. 1 when a cell's rewards stay 0,
+         * and once S is tiny the floor underflows to 0; it is then held at
+         * the smallest normal float, which tends to the S = 0 rule (all
+         * clusters equally likely) as S -> 0. */
+        if (eps > 0.0f && floor_term < 1.17549435e-38f) floor_term = 1.17549435e-38f;
         for (uint32_t s = 0; s < Meff; ++s) Qt[s] = Q[s] + floor_term;
     }
     C[0] = Qt[0];

@@ -185,6 +185,10 @@ __device__ void adapt_cell(const AdaptParams& ap, uint32_t c, AdaptLds& L) {
             }
         } else {
             float fl = (ap.eps * S) / (float)Meff;
+            // with eps > 0 the floor never underflows to 0 (Q decays towards
+            // subnormals in cells whose rewards stay 0): at least the
+            // smallest normal float, so every cluster keeps p > 0
+            if (ap.eps > 0.0f && fl < 1.17549435e-38f) fl = 1.17549435e-38f;
             for (uint32_t s = 0; s < Meff; ++s) {
                 float qt = L.Q[s] + fl;
                 L.Qt[s] = qt;

@@ -383,6 +383,32 @@ def test_dynamic_emission_parity_small(torch):
     assert np.array_equal(g["rec"][:, 9:12], orc.tree()["rec"][:, 9:12])
 
 
+def test_cells_with_vanishing_rewards(torch):
+    """Emission switched off after a few passes: Q decays under Eq. 1 through
+    the subnormal range to 0.  Cells stay bit-exact with the oracle, every
+    cluster keeps p > 0 and no estimate becomes NaN."""
+    s = scenes.make_tiny(n_lights=64, n_points=4, spp=16, M=4, n_boxes=0)
+    ctx, orc = _make(torch, s)
+    pos, nrm = _t(torch, s.pos), _t(torch, s.nrm)
+    dark = np.zeros_like(s.emit)
+    saw_subnormal = False
+    for f in range(300):
+        if f == 4:
+            ctx.rlc_set_emission(_t(torch, dark))
+            orc.set_emission(dark)
+        rad = ctx.rlc_frame(pos, nrm, 16, f).cpu().numpy()
+        ref, _ = orc.frame(s.pos, s.nrm, 16, f)
+        orc.adapt()
+        assert np.isfinite(rad).all(), f
+        c = orc.cells()
+        qmax = c["Q"].max(axis=1)
+        saw_subnormal |= bool(((qmax > 0) & (qmax < np.float32(1.17549435e-38))).any())
+        if f % 25 == 0 or f > 150:
+            _assert_cells_equal(ctx.rlc_dump_cells(), c)
+            assert (c["Qt"] > 0).all()
+    assert saw_subnormal
+
+
 def test_dynamic_full_size_sampled_cells(torch):
     s = scenes.make_dynamic()
     p = s.params

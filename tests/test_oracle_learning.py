@@ -84,6 +84,32 @@ def test_cdf_floor_and_normalisation(orc):
     assert abs(p.sum() - 1.0) < 1e-5
 
 
+def test_cdf_floor_survives_subnormal_q(orc):
+    """A cell whose rewards stay 0 sees Q decay geometrically under Eq. 1
+    until the sums are subnormal; the floor must not underflow to 0, or a
+    cluster gets probability 0 while the clamp at the end of the search can
+    still pick it (1/p = inf)."""
+    tiny = np.float32(1e-44)  # subnormal
+    for Q in ([tiny, 0, 0, 0], [0, 0, 0, tiny], [np.float32(3e-38), 0, 0, 0]):
+        Q = np.array(Q, np.float32)
+        Qt, C = orc.cdf(Q, 0.05)
+        assert np.all(Qt > 0) and np.all(np.diff(C) > 0)
+        p = Qt.astype(np.float64) / float(C[-1])
+        assert p[Q > 0].min() >= p.max() - 1e-12
+        if Q.max() < 1e-40:
+            # p tends to the S = 0 rule: nearly uniform
+            assert np.abs(p - 0.25).max() < 0.01
+    # decay to subnormal sums through Eq. 1 itself, then the cdf stays proper
+    q = np.full(16, 1e-30, np.float32)
+    q = orc.ema(q, np.zeros(16, np.uint64), np.full(16, 200, np.uint32), 0.1, FX)
+    assert 0 < q.max() < np.float32(1.17549435e-38)
+    Qt, C = orc.cdf(q, 0.05)
+    assert np.all(Qt > 0) and np.all(np.isfinite(16.0 * C[-1] / Qt))
+    # eps = 0 keeps Eq. 2 literal
+    Qt0, _ = orc.cdf(np.array([tiny, 0, 0, 0], np.float32), 0.0)
+    assert Qt0[1] == 0.0
+
+
 # --------------------------------------------------------------------------
 # split-collapse (section 3 and Fig. 1)
 # --------------------------------------------------------------------------
