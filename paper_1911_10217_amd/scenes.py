@@ -376,6 +376,36 @@ def make_dynamic(n_points=1 << 20, per_cluster=65536, grid=4, n_bricks=16384, M=
     return Scene("dynamic", tri, emit, boxes, _f32(pos), _f32(nrm), params, emission_at=emission_at)
 
 
+# --------------------------------------------------------------------------
+# batched: uneven static-style scenes rendered together
+# --------------------------------------------------------------------------
+def _log_uniform(rng, lo, hi):
+    return float(math.exp(rng.uniform(math.log(lo), math.log(hi))))
+
+
+def make_batch(n_scenes=16, seed=SEED_BASE + 4, capacity=1 << 16, frames=16, **overrides):
+    """n_scenes scenes in the style of the static workload with log-uniform
+    sizes: emitters in [4,096, 1,048,576] (256 clusters), shading points in
+    [65,536, 2,097,152] (primary hits of a 16:9 camera), box occluders in
+    [64, 16,384]; cut sizes 16, 32, 64 in turn; scene i has scene id i."""
+    rng = np.random.default_rng(seed)
+    out = []
+    for i in range(n_scenes):
+        N = int(round(_log_uniform(rng, 4096, 1 << 20)))
+        P = int(round(_log_uniform(rng, 65536, 1 << 21)))
+        K = int(round(_log_uniform(rng, 64, 16384)))
+        M = (16, 32, 64)[i % 3]
+        width = max(16, int(round(math.sqrt(P * 16.0 / 9.0))))
+        height = max(9, int(round(P / width)))
+        per_cluster = max(1, int(round(N / 256)))
+        s = make_static(width=width, height=height, n_clusters=256, per_cluster=per_cluster, n_boxes=K, M=M,
+                        spp=1, frames=frames, seed=int(rng.integers(1 << 40)), capacity=capacity, scene_id=i,
+                        **overrides)
+        s.name = "batch%d" % i
+        out.append(s)
+    return out
+
+
 WORKLOADS = {"tiny": make_tiny, "static": make_static, "dynamic": make_dynamic}
 
 
