@@ -10,56 +10,60 @@ namespace {
 
 constexpr int kBlock = 256;
 
-// Sum over aligned groups of `spp` lanes (spp a power of two <= 64); every
-// lane of the group ends with the group's sum.
-__device__ __forceinline__ float group_sum(float v, uint32_t spp) {
-    for (uint32_t off = spp >> 1; off > 0; off >>= 1) v += __shfl_xor(v, (int)off, 64);
-    return v;
-}
-
 __device__ __forceinline__ bool pow2_le64(uint32_t spp) { return spp <= 64u && (spp & (spp - 1u)) == 0u; }
 
 // Per-block merge of the (cell, cluster) statistics before the global
 // atomics: the block's samples add their fixed-point reward and count into a
 // small LDS hash table keyed by bin = cell * M + cluster (integer sums, so
-// order-free), then each distinct bin is added to the cell table once.
-constexpr int kAggSlots = 2 * kBlock;
+// order-free), then each distinct bin is added to the cell table once.  A
+// sample whose bin finds no slot within kAggProbes probes goes straight to
+// the cell table.
 constexpr uint32_t kNoBin = 0xFFFFFFFFu;
+constexpr int kAggProbes = 32;
 
-struct AggTable {
-    uint32_t bin[kAggSlots];
-    unsigned long long sum[kAggSlots];
-    uint32_t cnt[kAggSlots];
+template <int SLOTS>
+struct AggTableT {
+    static_assert((SLOTS & (SLOTS - 1)) == 0, "power of two");
+    uint32_t bin[SLOTS];
+    unsigned long long sum[SLOTS];
+    uint32_t cnt[SLOTS];
 };
+using AggTable = AggTableT<2 * kBlock>;
 
-__device__ __forceinline__ void agg_clear(AggTable& t) {
-    for (int j = threadIdx.x; j < kAggSlots; j += kBlock) {
+template <int SLOTS>
+__device__ __forceinline__ void agg_clear(AggTableT<SLOTS>& t) {
+    for (int j = threadIdx.x; j < SLOTS; j += kBlock) {
         t.bin[j] = kNoBin;
         t.sum[j] = 0ull;
         t.cnt[j] = 0u;
     }
 }
 
-__device__ __forceinline__ void agg_add(AggTable& t, const FrameParams& fp, uint32_t cell, uint32_t s,
+template <int SLOTS>
+__device__ __forceinline__ void agg_add(AggTableT<SLOTS>& t, const FrameParams& fp, uint32_t cell, uint32_t s,
                                         unsigned long long q) {
     if (cell == RLC_NONE) return;
     const uint32_t bin = cell * fp.cells.M + s;
-    uint32_t h = (bin * 2654435761u) >> 23;  // 9-bit Fibonacci hash
-    for (int probe = 0; probe < kAggSlots; ++probe) {
+    constexpr int kBits = __builtin_ctz(SLOTS);
+    uint32_t h = (bin * 2654435761u) >> (32 - kBits);  // Fibonacci hash
+    for (int probe = 0; probe < kAggProbes; ++probe) {
         const uint32_t old = atomicCAS(&t.bin[h], kNoBin, bin);
         if (old == kNoBin || old == bin) {
             atomicAdd(&t.sum[h], q);
             atomicAdd(&t.cnt[h], 1u);
             return;
         }
-        h = (h + 1u) & (kAggSlots - 1);
+        h = (h + 1u) & (SLOTS - 1);
     }
+    atomicAdd(&fp.cells.sum[bin], q);
+    atomicAdd(&fp.cells.cnt[bin], 1u);
 }
 
 // Each thread flushes and clears its own slots, so no barrier is needed
 // between the two; the caller syncs before the table is used again.
-__device__ __forceinline__ void agg_flush(AggTable& t, const FrameParams& fp) {
-    for (int j = threadIdx.x; j < kAggSlots; j += kBlock) {
+template <int SLOTS>
+__device__ __forceinline__ void agg_flush(AggTableT<SLOTS>& t, const FrameParams& fp) {
+    for (int j = threadIdx.x; j < SLOTS; j += kBlock) {
         const uint32_t n = t.cnt[j];
         if (n) {
             const size_t idx = t.bin[j];
@@ -69,6 +73,29 @@ __device__ __forceinline__ void agg_flush(AggTable& t, const FrameParams& fp) {
             t.sum[j] = 0ull;
             t.cnt[j] = 0u;
         }
+    }
+}
+
+// A point's spp estimates summed one after another in sample order (the
+// order of the definition), through LDS: the block's 256 samples hold whole
+// points when spp is a power of two up to 64.
+__device__ __forceinline__ void point_sums(float (*s_e)[3], const float e[3], uint32_t spp, bool valid, uint32_t k,
+                                           uint32_t p, float* __restrict__ radiance) {
+    const float inv_spp = 1.0f / (float)spp;
+    s_e[threadIdx.x][0] = e[0];
+    s_e[threadIdx.x][1] = e[1];
+    s_e[threadIdx.x][2] = e[2];
+    __syncthreads();
+    if (valid && k == 0) {
+        float acc[3] = {e[0], e[1], e[2]};
+        for (uint32_t j = 1; j < spp; ++j) {
+            acc[0] = acc[0] + s_e[threadIdx.x + j][0];
+            acc[1] = acc[1] + s_e[threadIdx.x + j][1];
+            acc[2] = acc[2] + s_e[threadIdx.x + j][2];
+        }
+        radiance[3 * (size_t)p] = acc[0] * inv_spp;
+        radiance[3 * (size_t)p + 1] = acc[1] * inv_spp;
+        radiance[3 * (size_t)p + 2] = acc[2] * inv_spp;
     }
 }
 
@@ -137,17 +164,11 @@ __global__ void __launch_bounds__(kBlock) k_shade(FrameParams fp, const float* _
         if (!(r <= 3.402823466e38f)) atomicOr(fp.err, RLC_DERR_NONFINITE);
         if (reward) reward[i] = r;
     }
-    float inv_spp = 1.0f / (float)spp;
     if (pow2_le64(spp)) {
-        e[0] = group_sum(e[0], spp);
-        e[1] = group_sum(e[1], spp);
-        e[2] = group_sum(e[2], spp);
-        if (valid && k == 0) {
-            radiance[3 * (size_t)p] = e[0] * inv_spp;
-            radiance[3 * (size_t)p + 1] = e[1] * inv_spp;
-            radiance[3 * (size_t)p + 2] = e[2] * inv_spp;
-        }
+        __shared__ float s_e[kBlock][3];
+        point_sums(s_e, e, spp, valid, k, p, radiance);
     } else if (valid) {
+        const float inv_spp = 1.0f / (float)spp;
         atomicAdd(&radiance[3 * (size_t)p], e[0] * inv_spp);
         atomicAdd(&radiance[3 * (size_t)p + 1], e[1] * inv_spp);
         atomicAdd(&radiance[3 * (size_t)p + 2], e[2] * inv_spp);
@@ -176,7 +197,7 @@ __global__ void __launch_bounds__(kBlock) k_learn(FrameParams fp, rlc_samples in
 // block is synchronised on exit.
 __device__ void frame_block(const FrameParams& fp, const float* __restrict__ pos, const float* __restrict__ nrm,
                             const uint32_t* __restrict__ perm, uint32_t P, uint32_t spp, uint32_t frame,
-                            float* __restrict__ radiance, size_t i0, AggTable& agg) {
+                            float* __restrict__ radiance, size_t i0, AggTable& agg, float (*s_e)[3]) {
     const size_t i = i0 + threadIdx.x;
     const size_t n = (size_t)P * spp;
     const bool valid = i < n;
@@ -209,17 +230,10 @@ __device__ void frame_block(const FrameParams& fp, const float* __restrict__ pos
     }
     __syncthreads();
     agg_flush(agg, fp);
-    float inv_spp = 1.0f / (float)spp;
     if (pow2_le64(spp)) {
-        e[0] = group_sum(e[0], spp);
-        e[1] = group_sum(e[1], spp);
-        e[2] = group_sum(e[2], spp);
-        if (valid && k == 0) {
-            radiance[3 * (size_t)p] = e[0] * inv_spp;
-            radiance[3 * (size_t)p + 1] = e[1] * inv_spp;
-            radiance[3 * (size_t)p + 2] = e[2] * inv_spp;
-        }
+        point_sums(s_e, e, spp, valid, k, p, radiance);
     } else if (valid) {
+        const float inv_spp = 1.0f / (float)spp;
         atomicAdd(&radiance[3 * (size_t)p], e[0] * inv_spp);
         atomicAdd(&radiance[3 * (size_t)p + 1], e[1] * inv_spp);
         atomicAdd(&radiance[3 * (size_t)p + 2], e[2] * inv_spp);
@@ -232,10 +246,11 @@ __global__ void __launch_bounds__(kBlock) k_frame(FrameParams fp, const float* _
                                                   const float* __restrict__ nrm, uint32_t P, uint32_t spp,
                                                   uint32_t frame, float* __restrict__ radiance) {
     __shared__ AggTable agg;
+    __shared__ float s_e[kBlock][3];
     agg_clear(agg);
     __syncthreads();
     const uint32_t b = xcd_block(blockIdx.x, gridDim.x);
-    frame_block(fp, pos, nrm, nullptr, P, spp, frame, radiance, (size_t)b * kBlock, agg);
+    frame_block(fp, pos, nrm, nullptr, P, spp, frame, radiance, (size_t)b * kBlock, agg, s_e);
 }
 
 // Batched pass over several scenes: persistent blocks take work items of
@@ -246,6 +261,7 @@ __global__ void __launch_bounds__(kBlock) k_batch_frame(const BatchScene* __rest
                                                         uint32_t* __restrict__ counter,
                                                         const uint32_t* __restrict__ frame_ptr) {
     __shared__ AggTable agg;
+    __shared__ float s_e[kBlock][3];
     __shared__ uint32_t s_item;
     agg_clear(agg);
     const uint32_t frame = *frame_ptr;
@@ -270,7 +286,8 @@ __global__ void __launch_bounds__(kBlock) k_batch_frame(const BatchScene* __rest
         const BatchScene& S = scenes[sc];
         const size_t first = (size_t)(item - S.item_begin) * rounds * kBlock;
         for (uint32_t r = 0; r < rounds; ++r)
-            frame_block(S.fp, S.pos, S.nrm, S.perm, S.P, S.spp, frame, S.radiance, first + (size_t)r * kBlock, agg);
+            frame_block(S.fp, S.pos, S.nrm, S.perm, S.P, S.spp, frame, S.radiance, first + (size_t)r * kBlock, agg,
+                        s_e);
     }
 }
 

@@ -16,6 +16,10 @@
 
 namespace rlc {
 
+// Everything here is inlined into its callers: the small arrays it passes
+// around must stay in registers.
+#define RLC_WALK_INLINE __host__ __device__ __attribute__((always_inline)) inline
+
 // Box b of the occluder set is stored as two float4: {min.xyz, max.x} and
 // {max.yz, 0, 0}.  Grid cell c has a 32-bit header head[c]: 0 when no box
 // overlaps it; RLC_OCC_ONE | b when box b is the only one; RLC_OCC_LIST | s
@@ -38,7 +42,7 @@ struct DevOcc {
 
 // Grid box and cell size for boxes whose union spans [lo, hi]: the union
 // grown by 1/1000 of its largest extent, cut into res^3 cells.
-__host__ __device__ inline void occ_grid_bounds(DevOcc& o, const float lo[3], const float hi[3], uint32_t res) {
+RLC_WALK_INLINE void occ_grid_bounds(DevOcc& o, const float lo[3], const float hi[3], uint32_t res) {
     float ext = fmaxf(hi[0] - lo[0], fmaxf(hi[1] - lo[1], hi[2] - lo[2]));
     float margin = 1e-3f * ext + 1e-6f;
     o.res = res;
@@ -51,7 +55,7 @@ __host__ __device__ inline void occ_grid_bounds(DevOcc& o, const float lo[3], co
 }
 
 // Box test as defined (any direction, including d_a = 0 and subnormal d_a).
-__host__ __device__ inline bool box_blocks_def(const float4 b0, const float4 b1, const float o[3],
+RLC_WALK_INLINE bool box_blocks_def(const float4 b0, const float4 b1, const float o[3],
                                                const float d[3], const float invd[3], float t_lo) {
     const float bmin[3] = {b0.x, b0.y, b0.z};
     const float bmax[3] = {b0.w, b1.x, b1.y};
@@ -76,7 +80,7 @@ __host__ __device__ inline bool box_blocks_def(const float4 b0, const float4 b1,
 // normal numbers: then 1/d is finite and non-zero, no interval bound is NaN,
 // and min/max give the interval ends the definition picks (up to the sign
 // of a zero, which no comparison sees).
-__host__ __device__ inline bool box_blocks_fast(const float4 b0, const float4 b1, const float o[3],
+RLC_WALK_INLINE bool box_blocks_fast(const float4 b0, const float4 b1, const float o[3],
                                                 const float invd[3], float tn0, float tf0) {
     float t0x = (b0.x - o[0]) * invd[0], t1x = (b0.w - o[0]) * invd[0];
     float t0y = (b0.y - o[1]) * invd[1], t1y = (b1.x - o[1]) * invd[1];
@@ -86,13 +90,13 @@ __host__ __device__ inline bool box_blocks_fast(const float4 b0, const float4 b1
     return tn < tf;
 }
 
-__host__ __device__ inline bool normal_dir(const float d[3]) {
+RLC_WALK_INLINE bool normal_dir(const float d[3]) {
     const float tiny = 1.17549435e-38f;  // smallest normal float
     return fabsf(d[0]) >= tiny && fabsf(d[1]) >= tiny && fabsf(d[2]) >= tiny;
 }
 
 template <bool FAST>
-__host__ __device__ inline bool test_box(const DevOcc& occ, uint32_t b, const float o[3], const float d[3],
+RLC_WALK_INLINE bool test_box(const DevOcc& occ, uint32_t b, const float o[3], const float d[3],
                                          const float invd[3], float t_lo) {
     const float4 b0 = occ.box[2 * b], b1 = occ.box[2 * b + 1];
     if (FAST) return box_blocks_fast(b0, b1, o, invd, t_lo, 1.0f - t_lo);
@@ -101,7 +105,7 @@ __host__ __device__ inline bool test_box(const DevOcc& occ, uint32_t b, const fl
 
 // Grid cells overlapped by a box grown by 1/256 of a cell on every side, so
 // that a walk whose cell boundaries are off by rounding still lists it.
-__host__ __device__ inline void box_cells(const DevOcc& occ, float4 b0, float4 b1, int lo[3], int hi[3]) {
+RLC_WALK_INLINE void box_cells(const DevOcc& occ, float4 b0, float4 b1, int lo[3], int hi[3]) {
     const float bmin[3] = {b0.x, b0.y, b0.z};
     const float bmax[3] = {b0.w, b1.x, b1.y};
     const int res = (int)occ.res;
@@ -115,7 +119,7 @@ __host__ __device__ inline void box_cells(const DevOcc& occ, float4 b0, float4 b
 }
 
 template <bool FAST>
-__host__ __device__ inline bool blocked_brute(const DevOcc& occ, const float o[3], const float d[3],
+RLC_WALK_INLINE bool blocked_brute(const DevOcc& occ, const float o[3], const float d[3],
                                               const float invd[3], float t_lo) {
     for (uint32_t b = 0; b < occ.K; ++b)
         if (test_box<FAST>(occ, b, o, d, invd, t_lo)) return true;
@@ -125,7 +129,7 @@ __host__ __device__ inline bool blocked_brute(const DevOcc& occ, const float o[3
 // Test the boxes listed in one grid cell (header h).  Two mailbox slots
 // skip a box that was just tested in a previous cell.
 template <bool FAST>
-__host__ __device__ inline bool cell_blocks(const DevOcc& occ, uint32_t h, uint32_t& last0, uint32_t& last1,
+RLC_WALK_INLINE bool cell_blocks(const DevOcc& occ, uint32_t h, uint32_t& last0, uint32_t& last1,
                                             const float o[3], const float d[3], const float invd[3], float t_lo) {
     if (h & RLC_OCC_ONE) {
         const uint32_t b = h & RLC_OCC_PAYLOAD;
@@ -154,9 +158,21 @@ __host__ __device__ inline bool cell_blocks(const DevOcc& occ, uint32_t h, uint3
 // 1/256 of a cell, which covers the accumulated rounding of that sum (at
 // most 3 res steps of half an ulp of t).  Each axis counts the cells left
 // before the walk leaves the grid.
-template <bool FAST>
-__host__ __device__ inline bool blocked_grid(const DevOcc& occ, const float o[3], const float d[3],
-                                             const float invd[3], float t_lo) {
+//
+// The walk state lives in a struct: walk_begin sets it up, each walk_step
+// tests one cell's boxes and moves to the next cell.
+struct WalkState {
+    float t1;
+    float tx, ty, tz, dtx, dty, dtz;
+    int rx, ry, rz, sx, sy, sz;
+    int lin;
+    int it;
+    uint32_t last0, last1;
+};
+
+// false: the segment misses the grid (nothing to test).
+RLC_WALK_INLINE bool walk_begin(const DevOcc& occ, const float o[3], const float d[3],
+                                           const float invd[3], float t_lo, WalkState& w) {
     float t0 = t_lo, t1 = 1.0f - t_lo;
     for (int a = 0; a < 3; ++a) {
         if (d[a] == 0.0f) {
@@ -172,71 +188,87 @@ __host__ __device__ inline bool blocked_grid(const DevOcc& occ, const float o[3]
     }
     if (!(t0 <= t1)) return false;
     const int res = (int)occ.res;
-    float tx, ty, tz, dtx, dty, dtz;
-    int rx, ry, rz, sx, sy, sz;
-    int lin = 0;
-    {
-        int c[3];
-        float tn[3], dt[3];
-        int rem[3], st[3];
-        for (int a = 0; a < 3; ++a) {
-            float p = o[a] + t0 * d[a];
-            float f = floorf((p - occ.glo[a]) * occ.ginv[a]);
-            c[a] = f < 0.0f ? 0 : (f >= (float)res ? res - 1 : (int)f);
-            if (d[a] == 0.0f) {
-                tn[a] = 3.0e38f;
-                dt[a] = 0.0f;
-                rem[a] = 0;
-                st[a] = 0;
-            } else {
-                const bool up = d[a] > 0.0f;
-                const float bound = occ.glo[a] + (float)(c[a] + (up ? 1 : 0)) * occ.gcell[a];
-                tn[a] = (bound - o[a]) * invd[a];
-                dt[a] = occ.gcell[a] * fabsf(invd[a]);
-                rem[a] = up ? res - 1 - c[a] : c[a];
-                st[a] = up ? 1 : -1;
-            }
-        }
-        lin = c[0] + res * (c[1] + res * c[2]);
-        tx = tn[0];
-        ty = tn[1];
-        tz = tn[2];
-        dtx = dt[0];
-        dty = dt[1];
-        dtz = dt[2];
-        rx = rem[0];
-        ry = rem[1];
-        rz = rem[2];
-        sx = st[0];
-        sy = st[1] * res;
-        sz = st[2] * res * res;
-    }
-    uint32_t last0 = 0xFFFFFFFFu, last1 = 0xFFFFFFFFu;
-    const int max_steps = 3 * res + 3;
-    for (int it = 0; it < max_steps; ++it) {
-        if (cell_blocks<FAST>(occ, occ.head[lin], last0, last1, o, d, invd, t_lo)) return true;
-        const bool ax = tx <= ty && tx <= tz;
-        const bool ay = !ax && ty <= tz;
-        const float tm = ax ? tx : (ay ? ty : tz);
-        const int rm = ax ? rx : (ay ? ry : rz);
-        if (tm > t1 || rm == 0) return false;
-        lin += ax ? sx : (ay ? sy : sz);
-        if (ax) {
-            tx += dtx;
-            --rx;
-        } else if (ay) {
-            ty += dty;
-            --ry;
+    int c[3];
+    float tn[3], dt[3];
+    int rem[3], st[3];
+    for (int a = 0; a < 3; ++a) {
+        float p = o[a] + t0 * d[a];
+        float f = floorf((p - occ.glo[a]) * occ.ginv[a]);
+        c[a] = f < 0.0f ? 0 : (f >= (float)res ? res - 1 : (int)f);
+        if (d[a] == 0.0f) {
+            tn[a] = 3.0e38f;
+            dt[a] = 0.0f;
+            rem[a] = 0;
+            st[a] = 0;
         } else {
-            tz += dtz;
-            --rz;
+            const bool up = d[a] > 0.0f;
+            const float bound = occ.glo[a] + (float)(c[a] + (up ? 1 : 0)) * occ.gcell[a];
+            tn[a] = (bound - o[a]) * invd[a];
+            dt[a] = occ.gcell[a] * fabsf(invd[a]);
+            rem[a] = up ? res - 1 - c[a] : c[a];
+            st[a] = up ? 1 : -1;
         }
     }
-    return false;
+    w.t1 = t1;
+    w.lin = c[0] + res * (c[1] + res * c[2]);
+    w.tx = tn[0];
+    w.ty = tn[1];
+    w.tz = tn[2];
+    w.dtx = dt[0];
+    w.dty = dt[1];
+    w.dtz = dt[2];
+    w.rx = rem[0];
+    w.ry = rem[1];
+    w.rz = rem[2];
+    w.sx = st[0];
+    w.sy = st[1] * res;
+    w.sz = st[2] * res * res;
+    w.it = 0;
+    w.last0 = 0xFFFFFFFFu;
+    w.last1 = 0xFFFFFFFFu;
+    return true;
+}
+
+// Test the current cell, then move to the next one.  Returns 1 when a box
+// blocks the segment, 2 when the walk has ended unblocked, 0 otherwise.
+template <bool FAST>
+RLC_WALK_INLINE int walk_step(const DevOcc& occ, WalkState& w, const float o[3], const float d[3],
+                                         const float invd[3], float t_lo) {
+    if (cell_blocks<FAST>(occ, occ.head[w.lin], w.last0, w.last1, o, d, invd, t_lo)) return 1;
+    // the axis with the nearest boundary moves on (ties: x, then y).  Written
+    // with value selects and integer masks, not selects between fields, so
+    // the state stays in registers.
+    const float tx = w.tx, ty = w.ty, tz = w.tz;
+    const bool ax = tx <= ty && tx <= tz;
+    const bool ay = !ax && ty <= tz;
+    const bool az = !ax && !ay;
+    const int ix = ax ? 1 : 0, iy = ay ? 1 : 0, iz = az ? 1 : 0;
+    const float tm = fminf(tx, fminf(ty, tz));
+    const int rm = ix * w.rx + iy * w.ry + iz * w.rz;
+    if (tm > w.t1 || rm == 0 || ++w.it >= 3 * (int)occ.res + 3) return 2;
+    w.lin += ix * w.sx + iy * w.sy + iz * w.sz;
+    w.tx = ax ? tx + w.dtx : tx;
+    w.ty = ay ? ty + w.dty : ty;
+    w.tz = az ? tz + w.dtz : tz;
+    w.rx -= ix;
+    w.ry -= iy;
+    w.rz -= iz;
+    return 0;
+}
+
+template <bool FAST>
+RLC_WALK_INLINE bool blocked_grid(const DevOcc& occ, const float o[3], const float d[3],
+                                             const float invd[3], float t_lo) {
+    WalkState w;
+    if (!walk_begin(occ, o, d, invd, t_lo, w)) return false;
+    for (;;) {
+        const int r = walk_step<FAST>(occ, w, o, d, invd, t_lo);
+        if (r) return r == 1;
+    }
 }
 
 // Is the segment o -> o + d blocked over t in (t_lo, 1 - t_lo)?
-__host__ __device__ inline bool segment_blocked(const DevOcc& occ, const float o[3], const float d[3], float t_lo) {
+RLC_WALK_INLINE bool segment_blocked(const DevOcc& occ, const float o[3], const float d[3], float t_lo) {
     if (occ.K == 0) return false;
     const float invd[3] = {1.0f / d[0], 1.0f / d[1], 1.0f / d[2]};
     if (normal_dir(d))

@@ -346,16 +346,20 @@ __device__ __forceinline__ void draw_sample(const FrameParams& fp, float x, floa
     o.key = key;
 }
 
-// Contribution c_l = Le f_r G A V of the sampled point y as seen from x.
-__device__ __forceinline__ void contribution(const FrameParams& fp, const float x[3], const float n[3],
-                                             uint32_t l, const float y[3], float c[3]) {
-    c[0] = c[1] = c[2] = 0.0f;
+// The unshadowed contribution Le f_r G A of the sampled point y as seen from
+// x, and the segment d = y - x.  Returns false (cu = 0) when the sample
+// cannot contribute whatever the visibility.
+__device__ __forceinline__ bool contribution_unshadowed(const FrameParams& fp, const float x[3], const float n[3],
+                                                       uint32_t l, const float y[3], float cu[3], float d[3]) {
+    cu[0] = cu[1] = cu[2] = 0.0f;
     const float4 r2 = fp.tree.rec[4u * l + 2u];
     const float4 r3 = fp.tree.rec[4u * l + 3u];
-    float d[3] = {y[0] - x[0], y[1] - x[1], y[2] - x[2]};
+    d[0] = y[0] - x[0];
+    d[1] = y[1] - x[1];
+    d[2] = y[2] - x[2];
     float dist2 = (d[0] * d[0] + d[1] * d[1]) + d[2] * d[2];
     float area = r3.x;
-    if (!(dist2 > 0.0f && area > 0.0f)) return;
+    if (!(dist2 > 0.0f && area > 0.0f)) return false;
     float dist = sqrtf(dist2);
     float cos_x = ((n[0] * d[0] + n[1] * d[1]) + n[2] * d[2]) / dist;
     float dl = (r3.y * d[0] + r3.z * d[1]) + r3.w * d[2];
@@ -364,14 +368,22 @@ __device__ __forceinline__ void contribution(const FrameParams& fp, const float 
         cos_l = fabsf(dl) / dist;
     else
         cos_l = (dl < 0.0f ? -dl : 0.0f) / dist;
-    if (!(cos_x > 0.0f && cos_l > 0.0f)) return;
+    if (!(cos_x > 0.0f && cos_l > 0.0f)) return false;
     float G = (cos_x * cos_l) / dist2;
     float kk = (fp.f_r * G) * area;
-    if (!(kk > 0.0f && (r2.y > 0.0f || r2.z > 0.0f || r2.w > 0.0f))) return;
-    if (segment_blocked(fp.occ, x, d, fp.t_lo)) return;
-    c[0] = r2.y * kk;
-    c[1] = r2.z * kk;
-    c[2] = r2.w * kk;
+    if (!(kk > 0.0f && (r2.y > 0.0f || r2.z > 0.0f || r2.w > 0.0f))) return false;
+    cu[0] = r2.y * kk;
+    cu[1] = r2.z * kk;
+    cu[2] = r2.w * kk;
+    return true;
+}
+
+// Contribution c_l = Le f_r G A V of the sampled point y as seen from x.
+__device__ __forceinline__ void contribution(const FrameParams& fp, const float x[3], const float n[3],
+                                             uint32_t l, const float y[3], float c[3]) {
+    float d[3];
+    if (contribution_unshadowed(fp, x, n, l, y, c, d) && segment_blocked(fp.occ, x, d, fp.t_lo))
+        c[0] = c[1] = c[2] = 0.0f;
 }
 
 __device__ __forceinline__ float reward_of(const FrameParams& fp, const float c[3], uint32_t size) {

@@ -38,7 +38,13 @@ def _make(torch, s, params=None, with_boxes=True):
     return ctx, orc
 
 
-def _rad_close(gpu, ref):
+def _rad_close(gpu, ref, spp=1):
+    """Radiance within RAD_RTOL relative error; when spp is a power of two up
+    to 64 the kernels sum a point's estimates in sample order, as the
+    definition does, and the FP32 results are identical bit for bit."""
+    if spp <= 64 and (spp & (spp - 1)) == 0 and not np.array_equal(gpu, ref):
+        diff = np.abs(gpu.astype(np.float64) - ref)
+        return False, "not bit-identical: %d values differ, max abs %g" % (int((gpu != ref).sum()), diff.max())
     err = np.abs(gpu.astype(np.float64) - ref) / np.maximum(np.abs(ref.astype(np.float64)), 1e-30)
     ok = (err <= RAD_RTOL) | (np.abs(gpu - ref) <= 1e-30)
     return bool(ok.all()), float(np.max(np.where(ok, 0.0, err))) if not ok.all() else 0.0
@@ -187,7 +193,7 @@ def test_split_steps_parity(torch, reward_mode):
         shade = ctx.rlc_shade(pos, nrm, p["spp"], smp)
         ref_rad, rec = orc.frame(s.pos, s.nrm, p["spp"], f, records=True)
         _records_equal(smp, shade, rec)
-        ok, err = _rad_close(shade[0].cpu().numpy(), ref_rad)
+        ok, err = _rad_close(shade[0].cpu().numpy(), ref_rad, p["spp"])
         assert ok, err
         ctx.rlc_learn(smp, shade[2])
         # statistics before the end of the pass
@@ -225,7 +231,7 @@ def test_fused_frames_parity_tiny(torch, variant):
         rad = ctx.rlc_frame(pos, nrm, p["spp"], f).cpu().numpy()
         ref, _ = orc.frame(s.pos, s.nrm, p["spp"], f)
         orc.adapt()
-        ok, err = _rad_close(rad, ref)
+        ok, err = _rad_close(rad, ref, p["spp"])
         assert ok, (f, err)
         _assert_cells_equal(ctx.rlc_dump_cells(), orc.cells())
     ctx.rlc_sync()
@@ -243,7 +249,7 @@ def test_ragged_and_empty(torch):
         rad = ctx.rlc_frame(pos, nrm, 2, f).cpu().numpy()
         ref, _ = orc.frame(s.pos, s.nrm, 2, f)
         orc.adapt()
-        assert _rad_close(rad, ref)[0]
+        assert _rad_close(rad, ref, 2)[0]
     _assert_cells_equal(ctx.rlc_dump_cells(), orc.cells())
 
 
