@@ -39,11 +39,19 @@ __device__ __forceinline__ unsigned long long wave_min_u64(unsigned long long v)
 
 struct AdaptLds {
     uint32_t node[RLC_MMAX];
+    uint32_t end[RLC_MMAX];     // one past the cluster's last light
+    uint32_t par[RLC_MMAX];     // the cluster node's parent
     float Q[RLC_MMAX];
     uint32_t nnode[RLC_MMAX];
-    float nQ[RLC_MMAX];
-    float Qt[RLC_MMAX];
-    float C[RLC_MMAX];
+    // the new cut's ends and Q during split-collapse, then Q~ and C
+    union {
+        uint32_t nend[RLC_MMAX];
+        float Qt[RLC_MMAX];
+    };
+    union {
+        float nQ[RLC_MMAX];
+        float C[RLC_MMAX];
+    };
 };
 
 // End of pass for table slot c, by one wavefront (= the block).
@@ -70,15 +78,20 @@ __device__ void adapt_cell(const AdaptParams& ap, uint32_t c, AdaptLds& L) {
     for (int j = 0; j < kMaxPerLane; ++j) {
         uint32_t s = lane + kWave * j;
         if (j < (int)per && s < Meff) {
-            uint32_t nd;
+            uint32_t nd, en;
             float q;
             if (fresh) {
                 nd = ap.tmpl.node[s];
+                en = ap.tmpl.end[s];
                 q = 0.0f;
             } else {
                 nd = cells.node[base + s];
+                en = cells.end[base + s];
                 q = cells.Q[base + s];
             }
+            // the one tree lookup the step needs for every cluster: its parent
+            L.par[s] = ap.tree.parent[nd];
+            L.end[s] = en;
             if (ap.temporal && cnt[j]) {
                 // Eq. 1 applied to the n samples of the pass at once
                 float a_n = pow_uint(1.0f - ap.alpha, cnt[j]);
@@ -104,8 +117,8 @@ __device__ void adapt_cell(const AdaptParams& ap, uint32_t c, AdaptLds& L) {
         for (int j = 0; j < kMaxPerLane; ++j) {
             uint32_t s = lane + kWave * j;
             if (j < (int)per && s < Meff) {
-                uint32_t nd = L.node[s];
-                if (ap.tree.last[nd] > ap.tree.first[nd]) {
+                // a cluster of two or more lights is an internal node
+                if (L.end[s] - (s ? L.end[s - 1u] : 0u) > 1u) {
                     unsigned long long key = ((unsigned long long)__float_as_uint(L.Q[s]) << 32) |
                                              (unsigned long long)(0xFFFFFFFFu - s);
                     best = key > best ? key : best;
@@ -120,9 +133,9 @@ __device__ void adapt_cell(const AdaptParams& ap, uint32_t c, AdaptLds& L) {
         for (int j = 0; j < kMaxPerLane; ++j) {
             uint32_t s = lane + kWave * j;
             if (j < (int)per && s + 1u < Meff && s != smax && s + 1u != smax) {
-                uint32_t n0 = L.node[s], n1 = L.node[s + 1u];
-                uint32_t p = ap.tree.parent[n0];
-                if (p != RLC_NONE && ap.tree.left[p] == n0 && ap.tree.right[p] == n1) {
+                // neighbouring cut nodes with one parent are its two children
+                const uint32_t p = L.par[s];
+                if (p != RLC_NONE && p == L.par[s + 1u]) {
                     float qp = L.Q[s] + L.Q[s + 1u];
                     unsigned long long key = ((unsigned long long)__float_as_uint(qp) << 32) | s;
                     worst = key < worst ? key : worst;
@@ -146,16 +159,22 @@ __device__ void adapt_cell(const AdaptParams& ap, uint32_t c, AdaptLds& L) {
                 float q = L.Q[s];
                 uint32_t dst = s + (s > smax ? 1u : 0u) - (s > smin + 1u ? 1u : 0u);
                 if (s == smin) {
-                    L.nnode[dst] = ap.tree.parent[nd];
+                    // the parent covers both children: it ends where the right one does
+                    L.nnode[dst] = L.par[s];
+                    L.nend[dst] = L.end[s + 1u];
                     L.nQ[dst] = qpmin;
                 } else if (s == smax) {
                     float h = 0.5f * q;
-                    L.nnode[dst] = ap.tree.left[nd];
+                    const uint32_t lc = ap.tree.left[nd];
+                    L.nnode[dst] = lc;
+                    L.nend[dst] = ap.tree.last[lc] + 1u;
                     L.nQ[dst] = h;
                     L.nnode[dst + 1u] = ap.tree.right[nd];
+                    L.nend[dst + 1u] = L.end[s];
                     L.nQ[dst + 1u] = h;
                 } else {
                     L.nnode[dst] = nd;
+                    L.nend[dst] = L.end[s];
                     L.nQ[dst] = q;
                 }
             }
@@ -166,6 +185,7 @@ __device__ void adapt_cell(const AdaptParams& ap, uint32_t c, AdaptLds& L) {
             uint32_t s = lane + kWave * j;
             if (j < (int)per && s < Meff) {
                 L.node[s] = L.nnode[s];
+                L.end[s] = L.nend[s];
                 L.Q[s] = L.nQ[s];
             }
         }
@@ -202,9 +222,8 @@ __device__ void adapt_cell(const AdaptParams& ap, uint32_t c, AdaptLds& L) {
     for (int j = 0; j < kMaxPerLane; ++j) {
         uint32_t s = lane + kWave * j;
         if (j < (int)per && s < Meff) {
-            uint32_t nd = L.node[s];
-            cells.node[base + s] = nd;
-            cells.end[base + s] = ap.tree.last[nd] + 1u;
+            cells.node[base + s] = L.node[s];
+            cells.end[base + s] = L.end[s];
             cells.Q[base + s] = L.Q[s];
             cells.Qt[base + s] = L.Qt[s];
             cells.C[base + s] = L.C[s];
