@@ -149,6 +149,7 @@ def run_learned(args, np, torch, rlc, scenes, dev):
     lp = torch.empty(n_log, dtype=torch.int32, device=dev)
     ln = torch.empty(n_log, dtype=torch.int32, device=dev)
     lw = torch.empty(n_log, dtype=torch.float32, device=dev)
+    cdf = torch.empty((P, 64), dtype=torch.float32, device=dev)
 
     def events(n):
         return [torch.cuda.Event(enable_timing=True) for _ in range(n)]
@@ -173,7 +174,7 @@ def run_learned(args, np, torch, rlc, scenes, dev):
     ctx.rlc_frame(pos, nrm, spp, 0, rad[0])
     ctx.rlc_set_sample_log()
     ctx.rlc_mlp_train(pos, nrm, lp[:P * spp], ln[:P * spp], lw[:P * spp], 1, args.mlp_batch, args.mlp_lr)
-    cdf, _ = ctx.rlc_mlp_forward(pos, nrm)
+    ctx.rlc_mlp_forward(pos, nrm, cdf=cdf)
     ctx.rlc_set_mixture(cdf, 0.5)
     ctx.rlc_frame(pos, nrm, spp, 1, rad[1])
     ctx.rlc_set_mixture()
@@ -206,11 +207,9 @@ def run_learned(args, np, torch, rlc, scenes, dev):
         ctx.rlc_frame(pos, nrm, spp, f, rad[f])
         ev[f + 1].record()
     ctx.rlc_set_sample_log()
-    ctx.rlc_set_timing(True)
-    loss = ctx.rlc_mlp_train(pos, nrm, lp, ln, lw, args.mlp_epochs, args.mlp_batch, args.mlp_lr)
+    ctx.rlc_mlp_train(pos, nrm, lp, ln, lw, args.mlp_epochs, args.mlp_batch, args.mlp_lr, sync=False)
     ev_train.record()
-    ctx.rlc_set_timing(False)
-    cdf, _ = ctx.rlc_mlp_forward(pos, nrm)
+    ctx.rlc_mlp_forward(pos, nrm, cdf=cdf)
     ctx.rlc_set_mixture(cdf, 0.5)
     ev_fwd.record()
     for j in range(k_mix - log_passes):
@@ -218,13 +217,20 @@ def run_learned(args, np, torch, rlc, scenes, dev):
         ev_mix[j].record()
     torch.cuda.synchronize()
     ctx.rlc_set_mixture()
+    ctx.rlc_sync()
+    learned_mse, learned_mse_b = mse_curve(k_mix)
+    # per-kernel durations of the training steps, in a separate run with HIP
+    # events around each launch (the same training from the same weights)
+    ctx.rlc_mlp_init(p["seed"])
+    ctx.rlc_set_timing(True)
+    loss = ctx.rlc_mlp_train(pos, nrm, lp, ln, lw, args.mlp_epochs, args.mlp_batch, args.mlp_lr)
+    ctx.rlc_set_timing(False)
     fb_ms, upd_ms, steps = ctx.rlc_get_mlp_timing()
     t_log = ev[0].elapsed_time(ev[log_passes])
     t_train = ev[log_passes].elapsed_time(ev_train)
     t_fwd = ev_train.elapsed_time(ev_fwd)
     mix_t = np.array([ev[0].elapsed_time(ev[f + 1]) for f in range(log_passes)] +
                      [ev[0].elapsed_time(e) for e in ev_mix[:k_mix - log_passes]])
-    learned_mse, learned_mse_b = mse_curve(k_mix)
 
     rows = []
     for n in budgets:

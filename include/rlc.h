@@ -242,8 +242,10 @@ int rlc_mlp_forward(rlc_ctx* ctx, const float* d_pos, const float* d_nrm, uint32
  * Synchronises; bad tuples give RLC_EINVAL. */
 int rlc_mlp_grad(rlc_ctx* ctx, const float* d_pos, const float* d_nrm, uint32_t P, const uint32_t* d_pid,
                  const uint32_t* d_node, const float* d_w, uint32_t n, float* d_grad, float* h_loss);
-/* `epochs` epochs of minibatch Adam at learning rate lr over the n tuples;
- * h_loss (may be NULL) receives the last batch's loss.  Synchronises. */
+/* `epochs` epochs of minibatch Adam at learning rate lr over the n tuples.
+ * With h_loss non-NULL the call synchronises, reports bad tuples and
+ * returns the last batch's loss; with h_loss NULL it only enqueues, and bad
+ * tuples are reported by the next synchronising call. */
 int rlc_mlp_train(rlc_ctx* ctx, const float* d_pos, const float* d_nrm, uint32_t P, const uint32_t* d_pid,
                   const uint32_t* d_node, const float* d_w, uint32_t n, uint32_t epochs, uint32_t batch,
                   float lr, float* h_loss);

@@ -993,10 +993,11 @@ int rlc_mlp_train(rlc_ctx* c, const float* d_pos, const float* d_nrm, uint32_t P
             }
         }
     }
+    if (!h_loss) return RLC_OK;  // asynchronous: bad tuples are reported by the next synchronising call
     float loss = 0.0f;
     RLC_HIP(c, hipMemcpyAsync(&loss, c->mlp_loss, sizeof(float), hipMemcpyDeviceToHost, c->stream));
     RLC_TRY(read_device_errors(c));
-    if (h_loss) *h_loss = loss;
+    *h_loss = loss;
     return RLC_OK;
 }
 

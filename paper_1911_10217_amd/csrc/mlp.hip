@@ -503,8 +503,19 @@ __global__ void __launch_bounds__(kBlock) k_mlp_reduce(const float* __restrict__
     const uint32_t col = threadIdx.x % kRedCols, grp = threadIdx.x / kRedCols;
     const uint32_t p = blockIdx.x * kRedCols + col;
     float acc = 0.0f;
-    if (p < kNP)
-        for (uint32_t b = grp; b < nblocks; b += kRedGroups) acc += partial[(size_t)b * kNP + p];
+    if (p < kNP) {
+        // rows grp, grp + 8, ... added in that order; the loads of a run of 8
+        // rows are issued before their additions
+        uint32_t b = grp;
+        for (; b + 7u * kRedGroups < nblocks; b += 8u * kRedGroups) {
+            float v[8];
+#pragma unroll
+            for (uint32_t j = 0; j < 8u; ++j) v[j] = partial[(size_t)(b + j * kRedGroups) * kNP + p];
+#pragma unroll
+            for (uint32_t j = 0; j < 8u; ++j) acc += v[j];
+        }
+        for (; b < nblocks; b += kRedGroups) acc += partial[(size_t)b * kNP + p];
+    }
     s_part[grp][col] = acc;
     if (threadIdx.x == 0) {
         float sw = 0.0f;

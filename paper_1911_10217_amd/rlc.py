@@ -443,13 +443,25 @@ class Context:
         self._check(lib().rlc_mlp_get_params(self._h, _ptr(out)), "rlc_mlp_get_params")
         return out
 
-    def rlc_mlp_forward(self, pos, nrm, cdf: bool = True, logits: bool = False):
+    def rlc_mlp_forward(self, pos, nrm, cdf=True, logits=False):
+        """cdf / logits: True to allocate the output, a (P, 64) float32 tensor
+        to write into, or False/None for none."""
         import torch
         _dev(pos, torch.float32, "pos")
         _dev(nrm, torch.float32, "nrm")
         P = pos.numel() // 3
-        c = torch.empty((P, RLC_MLP_NODES), dtype=torch.float32, device="cuda") if cdf else None
-        z = torch.empty((P, RLC_MLP_NODES), dtype=torch.float32, device="cuda") if logits else None
+
+        def out(spec, name):
+            if spec is True:
+                return torch.empty((P, RLC_MLP_NODES), dtype=torch.float32, device="cuda")
+            if spec is None or spec is False:
+                return None
+            _dev(spec, torch.float32, name)
+            if spec.numel() != P * RLC_MLP_NODES:
+                raise ValueError("%s must be P x 64" % name)
+            return spec
+        c = out(cdf, "cdf")
+        z = out(logits, "logits")
         self._check(lib().rlc_mlp_forward(self._h, _ptr(pos), _ptr(nrm), P, _ptr(c), _ptr(z)), "rlc_mlp_forward")
         return c, z
 
@@ -473,13 +485,14 @@ class Context:
                                        _ptr(w), n, _ptr(g), loss.ctypes.data), "rlc_mlp_grad")
         return float(loss[0]), g
 
-    def rlc_mlp_train(self, pos, nrm, pid, node, w, epochs: int, batch: int, lr: float) -> float:
+    def rlc_mlp_train(self, pos, nrm, pid, node, w, epochs: int, batch: int, lr: float, sync: bool = True):
+        """Returns the last batch's loss; with sync=False only enqueues and returns None."""
         n = self._tuples(pid, node, w)
         loss = np.zeros(1, np.float32)
         self._check(lib().rlc_mlp_train(self._h, _ptr(pos), _ptr(nrm), pos.numel() // 3, _ptr(pid), _ptr(node),
-                                        _ptr(w), n, int(epochs), int(batch), float(lr), loss.ctypes.data),
-                    "rlc_mlp_train")
-        return float(loss[0])
+                                        _ptr(w), n, int(epochs), int(batch), float(lr),
+                                        loss.ctypes.data if sync else None), "rlc_mlp_train")
+        return float(loss[0]) if sync else None
 
     def rlc_set_mixture(self, cdf=None, w: float = 0.5):
         import torch

@@ -154,6 +154,32 @@ def test_training_matches_oracle(torch, orc):
     assert np.mean(np.abs(d_gpu - d_orc) > 3e-3) < 0.02
 
 
+def test_training_is_deterministic_and_can_be_asynchronous(torch):
+    s = scenes.make_tiny(n_lights=300, n_points=100)
+    ctx, pos, nrm = _ctx(torch, s)
+    rng = np.random.default_rng(9)
+    n = 500
+    g = lambda a: torch.from_numpy(a).cuda()
+    pid = g(rng.integers(0, s.P, n).astype(np.int32))
+    node = g(rng.integers(0, 64, n).astype(np.int32))
+    w = g(rng.exponential(size=n).astype(np.float32))
+    ctx.rlc_mlp_init(5)
+    ctx.rlc_mlp_train(pos, nrm, pid, node, w, epochs=2, batch=128, lr=1e-2)
+    a = ctx.rlc_mlp_get_params().cpu().numpy()
+    ctx.rlc_mlp_init(5)
+    assert ctx.rlc_mlp_train(pos, nrm, pid, node, w, epochs=2, batch=128, lr=1e-2, sync=False) is None
+    ctx.rlc_sync()
+    b = ctx.rlc_mlp_get_params().cpu().numpy()
+    assert np.array_equal(a, b)
+    # a bad tuple in an asynchronous call is reported by the next synchronising call
+    from paper_1911_10217_amd import rlc
+    bad = g(np.full(n, 64, np.int32))
+    ctx.rlc_mlp_train(pos, nrm, pid, bad, w, epochs=1, batch=128, lr=1e-2, sync=False)
+    with pytest.raises(rlc.RLCError):
+        ctx.rlc_sync()
+    ctx.rlc_sync()
+
+
 def test_init_is_seeded_and_bounded(torch):
     s = scenes.make_tiny(n_lights=100, n_points=50)
     ctx, pos, nrm = _ctx(torch, s)
