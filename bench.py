@@ -14,7 +14,8 @@ Prints ONE JSON line.  Extra fields:
                   per launch (see algorithmic_bytes) over its mean duration,
                   timed with HIP events on the library's stream;
   cpu_baseline  - the CPU oracle (single-threaded C) on a bounded sample of
-                  the same workload: every 10th point, for the same passes.
+                  the same workload: every --cpu-stride-th point (20th by default),
+                  for the same passes.
 """
 from __future__ import annotations
 
@@ -32,7 +33,8 @@ if ROOT not in sys.path:
 METRIC = "light samples/s (sample+shadow+learn) and MSE vs oracle at equal GPU time"
 PEAK_HBM_GBS = 8000.0
 TRAFFIC_FILE = os.path.join(ROOT, "profiles", "traffic_frame_static.json")
-KERNEL_SOURCES = ("paper_1911_10217_amd/csrc/frame.hip", "paper_1911_10217_amd/csrc/rlc_internal.h")
+KERNEL_SOURCES = ("paper_1911_10217_amd/csrc/frame.hip", "paper_1911_10217_amd/csrc/rlc_internal.h",
+                  "paper_1911_10217_amd/csrc/occ_trace.h", "paper_1911_10217_amd/csrc/occ.hip")
 
 
 def kernel_source_hash() -> str:

@@ -650,6 +650,7 @@ int rlc_set_occluders(rlc_ctx* c, const float* d_aabb, uint32_t K) {
             o.head = c->occ_head;
             o.ref = c->occ_ref;
             step(launch_occ_lists(c->box, K, o, counts, start, cursor, c->occ_head, c->occ_ref, c->stream));
+            step(launch_occ_skip(c->occ_head, counts, cursor, o.res, c->stream));
             step(hipStreamSynchronize(c->stream));
         }
         dfree(counts);

@@ -103,6 +103,37 @@ __global__ void __launch_bounds__(kBlock) k_occ_fill(const float4* __restrict__ 
             }
 }
 
+// Empty-cube radii of the cells no box overlaps (the skip headers; see
+// occ_trace.h).  The Chebyshev distance from cell c to the nearest cell a box
+// overlaps, D(c) = min over such cells c' of max_a |c_a - c'_a|, is separable:
+// one pass per axis, each a min over the cells of one grid line of
+// max(|k - c_a|, previous pass at k), with the first pass reading occupancy
+// (distance 0 at an occupied cell).  Distances are capped at
+// RLC_OCC_SKIP_MAX + 1, so each pass looks that many cells either way.  An
+// empty cell's radius is D(c) - 1; the last pass writes it into the header.
+__global__ void __launch_bounds__(kBlock) k_occ_skip(const uint32_t* __restrict__ src, uint32_t* dst, uint32_t res,
+                                                     uint32_t axis) {
+    const size_t c = (size_t)blockIdx.x * kBlock + threadIdx.x;
+    const size_t ncell = (size_t)res * res * res;
+    if (c >= ncell) return;
+    const size_t stride = axis == 0 ? 1 : (axis == 1 ? (size_t)res : (size_t)res * res);
+    const int ca = (int)((c / stride) % res);
+    constexpr int kFar = (int)RLC_OCC_SKIP_MAX + 1;
+    const int k0 = ca - kFar < 0 ? -ca : -kFar;
+    const int k1 = ca + kFar >= (int)res ? (int)res - 1 - ca : kFar;
+    int best = kFar;
+    for (int k = k0; k <= k1; ++k) {
+        const uint32_t v = src[(size_t)((ptrdiff_t)c + (ptrdiff_t)k * (ptrdiff_t)stride)];
+        const int dk = k < 0 ? -k : k;
+        const int e = axis == 0 ? (v ? dk : kFar) : (dk > (int)v ? dk : (int)v);
+        best = e < best ? e : best;
+    }
+    if (axis < 2)
+        dst[c] = (uint32_t)best;
+    else if (!(dst[c] & (RLC_OCC_ONE | RLC_OCC_LIST)))
+        dst[c] = (uint32_t)(best - 1);
+}
+
 __global__ void __launch_bounds__(kBlock) k_visible(DevOcc occ, float t_lo, const float* __restrict__ x,
                                                     const float* __restrict__ y, uint32_t n,
                                                     uint8_t* __restrict__ vis) {
@@ -136,6 +167,16 @@ hipError_t launch_occ_lists(const float4* box, uint32_t K, DevOcc occ, const uin
     hipLaunchKernelGGL(k_occ_heads, dim3(blocks_for(ncell)), dim3(kBlock), 0, s, counts, start, ncell, head, ref);
     hipLaunchKernelGGL(k_occ_fill, dim3(blocks_for(K)), dim3(kBlock), 0, s, box, K, occ, counts, start, cursor, head,
                        ref);
+    return hipGetLastError();
+}
+
+hipError_t launch_occ_skip(uint32_t* head, uint32_t* tmp0, uint32_t* tmp1, uint32_t res, hipStream_t s) {
+    const size_t ncell = (size_t)res * res * res;
+    if (ncell == 0) return hipSuccess;
+    const dim3 grid(blocks_for(ncell));
+    hipLaunchKernelGGL(k_occ_skip, grid, dim3(kBlock), 0, s, head, tmp0, res, 0u);
+    hipLaunchKernelGGL(k_occ_skip, grid, dim3(kBlock), 0, s, tmp0, tmp1, res, 1u);
+    hipLaunchKernelGGL(k_occ_skip, grid, dim3(kBlock), 0, s, tmp1, head, res, 2u);
     return hipGetLastError();
 }
 

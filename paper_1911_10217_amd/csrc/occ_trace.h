@@ -21,12 +21,16 @@ namespace rlc {
 #define RLC_WALK_INLINE __host__ __device__ __attribute__((always_inline)) inline
 
 // Box b of the occluder set is stored as two float4: {min.xyz, max.x} and
-// {max.yz, 0, 0}.  Grid cell c has a 32-bit header head[c]: 0 when no box
-// overlaps it; RLC_OCC_ONE | b when box b is the only one; RLC_OCC_LIST | s
-// when several do, their count at ref[s] and their indices at ref[s + 1..].
+// {max.yz, 0, 0}.  Grid cell c has a 32-bit header head[c]: RLC_OCC_ONE | b
+// when box b is the only one overlapping it; RLC_OCC_LIST | s when several
+// do, their count at ref[s] and their indices at ref[s + 1..]; and for a
+// cell no box overlaps, the radius r <= RLC_OCC_SKIP_MAX of the cube of
+// cells centred on it (2r + 1 cells a side, cut by the grid's faces) that
+// no box overlaps either, so a walk can leave that cube in one step.
 #define RLC_OCC_ONE 0x40000000u
 #define RLC_OCC_LIST 0x80000000u
 #define RLC_OCC_PAYLOAD 0x3FFFFFFFu
+#define RLC_OCC_SKIP_MAX 7u
 
 struct DevOcc {
     const float4* box;
@@ -154,18 +158,28 @@ RLC_WALK_INLINE bool cell_blocks(const DevOcc& occ, uint32_t h, uint32_t& last0,
 
 // Walk the grid cells the segment crosses, in order (3-D DDA,
 // Amanatides-Woo).  The parameter of the next boundary along each axis grows
-// by the cell size over |d| per step; boxes are listed in cells grown by
+// by the cell size over |d| per boundary; boxes are listed in cells grown by
 // 1/256 of a cell, which covers the accumulated rounding of that sum (at
 // most 3 res steps of half an ulp of t).  Each axis counts the cells left
 // before the walk leaves the grid.
 //
+// In an empty cell of radius r the walk leaves the whole empty cube at once:
+// it exits through the cube's nearest face (the r-th boundary ahead on the
+// axis that reaches it first) and, on the other axes, crosses the boundaries
+// whose parameter the exit point has passed, at most r.  No box overlaps the
+// cells it skips, so the boxes tested, and the answer, are those of the
+// cell-by-cell walk; a boundary miscounted by rounding moves the walk to a
+// cell that the segment passes within an ulp or so of, which the 1/256 cell
+// growth covers.  With r = 0 the step is the plain DDA step.  Every step
+// takes at least one cell off the exit axis's count, so the walk ends.
+//
 // The walk state lives in a struct: walk_begin sets it up, each walk_step
-// tests one cell's boxes and moves to the next cell.
+// tests one cell's boxes and moves on.
 struct WalkState {
     float t1;
-    float tx, ty, tz, dtx, dty, dtz;
-    int rx, ry, rz, sx, sy, sz;
-    int lin;
+    float tx, ty, tz, dtx, dty, dtz, itx, ity, itz;
+    int rx, ry, rz, sx, sy, sz;  // sx, sy, sz: byte steps of the header offset
+    uint32_t lin;                // byte offset of the current cell's header (< 2^32 for res <= 1024)
     int it;
     uint32_t last0, last1;
 };
@@ -210,49 +224,103 @@ RLC_WALK_INLINE bool walk_begin(const DevOcc& occ, const float o[3], const float
         }
     }
     w.t1 = t1;
-    w.lin = c[0] + res * (c[1] + res * c[2]);
+    w.lin = 4u * (uint32_t)(c[0] + res * (c[1] + res * c[2]));
     w.tx = tn[0];
     w.ty = tn[1];
     w.tz = tn[2];
     w.dtx = dt[0];
     w.dty = dt[1];
     w.dtz = dt[2];
+    w.itx = dt[0] > 0.0f ? 1.0f / dt[0] : 0.0f;
+    w.ity = dt[1] > 0.0f ? 1.0f / dt[1] : 0.0f;
+    w.itz = dt[2] > 0.0f ? 1.0f / dt[2] : 0.0f;
     w.rx = rem[0];
     w.ry = rem[1];
     w.rz = rem[2];
-    w.sx = st[0];
-    w.sy = st[1] * res;
-    w.sz = st[2] * res * res;
+    w.sx = 4 * st[0];
+    w.sy = 4 * st[1] * res;
+    w.sz = 4 * st[2] * res * res;
     w.it = 0;
     w.last0 = 0xFFFFFFFFu;
     w.last1 = 0xFFFFFFFFu;
     return true;
 }
 
-// Test the current cell, then move to the next one.  Returns 1 when a box
-// blocks the segment, 2 when the walk has ended unblocked, 0 otherwise.
+// Boundaries of one axis that the exit parameter tm has reached: those at
+// t, t + dt, ..., at most ra of them (ra as a float, fra).  With FAST every
+// parameter is finite and idt > 0, so a tm short of t gives a count below
+// zero, which the clamp removes; otherwise dt may be infinite (idt = 0) and
+// tm is compared with t first.
+template <bool FAST>
+RLC_WALK_INLINE float walk_crossed(float tm, float t, float idt, float fra) {
+    if (FAST) {
+        const float q = floorf(fmaf(tm - t, idt, 1.0f));
+#if defined(__HIP_DEVICE_COMPILE__)
+        return __builtin_amdgcn_fmed3f(q, 0.0f, fra);
+#else
+        return fminf(fmaxf(q, 0.0f), fra);
+#endif
+    }
+    const float q = tm >= t ? floorf((tm - t) * idt) + 1.0f : 0.0f;
+    return fminf(fmaxf(q, 0.0f), fra);
+}
+
+// t + k dt; with FAST dt is finite, so k = 0 leaves t as it is.
+template <bool FAST>
+RLC_WALK_INLINE float walk_advance(float t, float fk, float dt) {
+    if (FAST) return fmaf(fk, dt, t);
+    return fk != 0.0f ? t + fk * dt : t;
+}
+
+RLC_WALK_INLINE int walk_mul24(int a, int b) {
+#if defined(__HIP_DEVICE_COMPILE__)
+    return __mul24(a, b);
+#else
+    return a * b;
+#endif
+}
+
+// Test the current cell, then move on.  Returns 1 when a box blocks the
+// segment, 2 when the walk has ended unblocked, 0 otherwise.  Everything
+// after the box tests is computed for every lane and selected, without
+// branches, so a wave runs it once.
 template <bool FAST>
 RLC_WALK_INLINE int walk_step(const DevOcc& occ, WalkState& w, const float o[3], const float d[3],
                                          const float invd[3], float t_lo) {
-    if (cell_blocks<FAST>(occ, occ.head[w.lin], w.last0, w.last1, o, d, invd, t_lo)) return 1;
-    // the axis with the nearest boundary moves on (ties: x, then y).  Written
-    // with value selects and integer masks, not selects between fields, so
-    // the state stays in registers.
-    const float tx = w.tx, ty = w.ty, tz = w.tz;
-    const bool ax = tx <= ty && tx <= tz;
-    const bool ay = !ax && ty <= tz;
-    const bool az = !ax && !ay;
-    const int ix = ax ? 1 : 0, iy = ay ? 1 : 0, iz = az ? 1 : 0;
-    const float tm = fminf(tx, fminf(ty, tz));
-    const int rm = ix * w.rx + iy * w.ry + iz * w.rz;
-    if (tm > w.t1 || rm == 0 || ++w.it >= 3 * (int)occ.res + 3) return 2;
-    w.lin += ix * w.sx + iy * w.sy + iz * w.sz;
-    w.tx = ax ? tx + w.dtx : tx;
-    w.ty = ay ? ty + w.dty : ty;
-    w.tz = az ? tz + w.dtz : tz;
-    w.rx -= ix;
-    w.ry -= iy;
-    w.rz -= iz;
+    const uint32_t h = *(const uint32_t*)((const char*)occ.head + w.lin);
+    if (cell_blocks<FAST>(occ, h, w.last0, w.last1, o, d, invd, t_lo)) return 1;
+    const int r = (h & (RLC_OCC_ONE | RLC_OCC_LIST)) ? 0 : (int)h;
+    // exit parameter of the empty cube on each axis (cut by the grid); the
+    // axis that reaches its face first moves on (ties: x, then y).  Value
+    // selects and integer masks, not selects between fields, keep the state
+    // in registers.
+    const float frx = (float)(r < w.rx ? r : w.rx);
+    const float fry = (float)(r < w.ry ? r : w.ry);
+    const float frz = (float)(r < w.rz ? r : w.rz);
+    const float ex = walk_advance<FAST>(w.tx, frx, w.dtx);
+    const float ey = walk_advance<FAST>(w.ty, fry, w.dty);
+    const float ez = walk_advance<FAST>(w.tz, frz, w.dtz);
+    const bool ax = ex <= ey && ex <= ez;
+    const bool ay = !ax && ey <= ez;
+    const float tm = fminf(ex, fminf(ey, ez));
+    const int rm = ax ? w.rx : (ay ? w.ry : w.rz);
+    const float cx = walk_crossed<FAST>(tm, w.tx, w.itx, frx);
+    const float cy = walk_crossed<FAST>(tm, w.ty, w.ity, fry);
+    const float cz = walk_crossed<FAST>(tm, w.tz, w.itz, frz);
+    const float fr1 = (float)(r + 1);
+    const float fkx = ax ? fr1 : cx;
+    const float fky = ay ? fr1 : cy;
+    const float fkz = (ax || ay) ? cz : fr1;
+    ++w.it;
+    if ((tm > w.t1) | (rm <= r) | (w.it >= 3 * (int)occ.res + 3)) return 2;
+    const int kx = (int)fkx, ky = (int)fky, kz = (int)fkz;
+    w.lin += (uint32_t)(walk_mul24(kx, w.sx) + walk_mul24(ky, w.sy) + walk_mul24(kz, w.sz));
+    w.tx = walk_advance<FAST>(w.tx, fkx, w.dtx);
+    w.ty = walk_advance<FAST>(w.ty, fky, w.dty);
+    w.tz = walk_advance<FAST>(w.tz, fkz, w.dtz);
+    w.rx -= kx;
+    w.ry -= ky;
+    w.rz -= kz;
     return 0;
 }
 

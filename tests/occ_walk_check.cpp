@@ -1,6 +1,8 @@
-// Runs the library's shadow-ray code (the grid build of occ.hip and the walk
-// of occ_trace.h, compiled for the host) on segments read from stdin, so the
-// CPU suite can compare it with the oracle's brute-force visibility.
+// Runs the library's shadow-ray walk (occ_trace.h, compiled for the host) on
+// segments read from stdin, over a grid laid out as occ.hip lays it out (box
+// lists as there; the empty-cube radii from their definition, not from the
+// device's separable passes), so the CPU suite can compare it with the
+// oracle's brute-force visibility.
 // stdin:  K res n, then K lines of 6 floats (box min, max), then n lines of
 //         6 floats (x, y); floats are given as hex bit patterns.
 // stdout: n characters, '1' = visible, '0' = blocked.
@@ -75,6 +77,37 @@ int main() {
                             ref[start[c] + 1 + cur[c]++] = i;
                     }
         }
+        // empty-cube radius of every empty cell, from its definition: the
+        // largest r <= RLC_OCC_SKIP_MAX for which the cube of cells within r
+        // (cut by the grid) holds no occupied cell, counted with a 3-D
+        // prefix sum of occupancy
+        const size_t R1 = (size_t)res + 1;
+        std::vector<uint32_t> sat(R1 * R1 * R1, 0);
+        auto S = [&](int x, int y, int z) -> uint32_t& { return sat[x + R1 * (y + R1 * (size_t)z)]; };
+        for (int z = 0; z < (int)res; ++z)
+            for (int y = 0; y < (int)res; ++y)
+                for (int x = 0; x < (int)res; ++x)
+                    S(x + 1, y + 1, z + 1) = (head[x + res * (y + res * (size_t)z)] != 0) + S(x, y + 1, z + 1) +
+                                             S(x + 1, y, z + 1) + S(x + 1, y + 1, z) - S(x, y, z + 1) -
+                                             S(x, y + 1, z) - S(x + 1, y, z) + S(x, y, z);
+        auto clip = [&](int v) { return v < 0 ? 0 : (v > (int)res ? (int)res : v); };
+        for (int z = 0; z < (int)res; ++z)
+            for (int y = 0; y < (int)res; ++y)
+                for (int x = 0; x < (int)res; ++x) {
+                    uint32_t& h = head[x + res * (y + res * (size_t)z)];
+                    if (h) continue;
+                    uint32_t r = 0;
+                    while (r < RLC_OCC_SKIP_MAX) {
+                        const int q = (int)r + 1;
+                        const int x0 = clip(x - q), x1 = clip(x + q + 1), y0 = clip(y - q), y1 = clip(y + q + 1);
+                        const int z0 = clip(z - q), z1 = clip(z + q + 1);
+                        const uint32_t n_occ = S(x1, y1, z1) - S(x0, y1, z1) - S(x1, y0, z1) - S(x1, y1, z0) +
+                                               S(x0, y0, z1) + S(x0, y1, z0) + S(x1, y0, z0) - S(x0, y0, z0);
+                        if (n_occ) break;
+                        r = (uint32_t)q;
+                    }
+                    h = r;
+                }
         occ.head = head.data();
         occ.ref = ref.data();
     }

@@ -159,6 +159,36 @@ def test_visibility_parity_grid(torch, static_scene):
     assert np.array_equal(vis, ref), int((vis != ref).sum())
 
 
+@pytest.mark.parametrize("res", [16, 64, 100])
+def test_visibility_parity_sparse_grid(torch, res):
+    """Few small boxes in a fine grid: most cells are empty and the walk
+    leaves whole empty cubes at a time.  Segments run across the room and
+    to points just inside and just outside the boxes' faces."""
+    import dataclasses
+    rng = np.random.default_rng(20 + res)
+    lo = rng.random((40, 3)) * 0.9
+    boxes = np.concatenate([lo, lo + rng.uniform(0.005, 0.08, (40, 3))], 1).astype(np.float32)
+    s = dataclasses.replace(scenes.make_tiny(n_lights=8), boxes=boxes)
+    ctx, orc = _make(torch, s, dict(s.params, occ_grid_res=res))
+    n = 30000
+    x = rng.uniform(-0.05, 1.05, (n, 3))
+    y = rng.uniform(-0.05, 1.05, (n, 3))
+    # targets on a box face, pushed a little inside or outside along that axis
+    b = boxes[rng.integers(0, 40, n)].astype(np.float64)
+    t = b[:, :3] + rng.random((n, 3)) * (b[:, 3:] - b[:, :3])
+    ax = rng.integers(0, 3, n)
+    side = rng.integers(0, 2, n)
+    face = np.where(side == 1, b[np.arange(n), 3 + ax], b[np.arange(n), ax])
+    off = rng.choice([-1e-4, 1e-4, -1e-6, 1e-6], n)
+    t[np.arange(n), ax] = face + off
+    X = np.concatenate([x, x]).astype(np.float32)
+    Y = np.concatenate([y, t]).astype(np.float32)
+    vis = ctx.rlc_visible(_t(torch, X), _t(torch, Y)).cpu().numpy()
+    ref = orc.visible(X, Y)
+    assert np.array_equal(vis, ref), int((vis != ref).sum())
+    assert 0.05 < ref.mean() < 0.95
+
+
 def test_cell_keys_parity(torch, static_scene):
     s = static_scene
     ctx, orc = _make(torch, s, dict(s.params, occ_grid_res=0), with_boxes=False)

@@ -96,3 +96,26 @@ def test_walk_subnormal_and_touching_cases(walker):
     Y = np.array([[1.0, 0.5, 0.5], [0.9, 0.5, 0.5 + tiny], [0.9, 0.5 + tiny, 0.5], [0.75, 0.9, 0.5]], np.float32)
     for res in (0, 4, 64):
         assert np.array_equal(_walk(walker, box, res, X, Y), o.visible(X, Y))
+
+
+@pytest.mark.parametrize("res", [16, 64, 100])
+def test_walk_skips_empty_cubes_sparse_boxes(walker, res):
+    """Few small boxes in a fine grid, so that most cells carry a skip radius;
+    segments end just inside or just outside box faces."""
+    rng = np.random.default_rng(20 + res)
+    lo = rng.random((40, 3)) * 0.9
+    boxes = np.concatenate([lo, lo + rng.uniform(0.005, 0.08, (40, 3))], 1).astype(np.float32)
+    s = scenes.make_tiny(n_lights=8)
+    o = oracle.Oracle(s.params, s.tri, s.emit, boxes)
+    n = 20000
+    x = rng.uniform(-0.05, 1.05, (n, 3))
+    b = boxes[rng.integers(0, 40, n)].astype(np.float64)
+    t = b[:, :3] + rng.random((n, 3)) * (b[:, 3:] - b[:, :3])
+    ax = rng.integers(0, 3, n)
+    face = np.where(rng.integers(0, 2, n) == 1, b[np.arange(n), 3 + ax], b[np.arange(n), ax])
+    t[np.arange(n), ax] = face + rng.choice([-1e-4, 1e-4, -1e-6, 1e-6], n)
+    X = np.concatenate([x, x]).astype(np.float32)
+    Y = np.concatenate([rng.uniform(-0.05, 1.05, (n, 3)), t]).astype(np.float32)
+    ref = o.visible(X, Y)
+    assert np.array_equal(_walk(walker, boxes, res, X, Y), ref)
+    assert 0.05 < ref.mean() < 0.95
