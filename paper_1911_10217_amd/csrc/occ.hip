@@ -103,14 +103,19 @@ __global__ void __launch_bounds__(kBlock) k_occ_fill(const float4* __restrict__ 
             }
 }
 
-// Empty-cube radii of the cells no box overlaps (the skip headers; see
-// occ_trace.h).  The Chebyshev distance from cell c to the nearest cell a box
-// overlaps, D(c) = min over such cells c' of max_a |c_a - c'_a|, is separable:
-// one pass per axis, each a min over the cells of one grid line of
-// max(|k - c_a|, previous pass at k), with the first pass reading occupancy
-// (distance 0 at an occupied cell).  Distances are capped at
-// RLC_OCC_SKIP_MAX + 1, so each pass looks that many cells either way.  An
-// empty cell's radius is D(c) - 1; the last pass writes it into the header.
+// Octant radii of the cells no box overlaps (the skip headers; see
+// occ_trace.h).  For the octant with signs s, the distance from cell c to the
+// nearest cell a box overlaps within that octant, D_s(c) = min over such
+// cells c + (i s_x, j s_y, k s_z), i, j, k >= 0, of max(i, j, k), is
+// separable: pass x takes, along the grid line through c, the nearest
+// occupied cell at or ahead of c in direction s_x; pass y the minimum over
+// j >= 0 of max(j, pass x at c + j s_y); pass z the same over k with pass y.
+// Distances are capped at kFar = RLC_OCC_SKIP_MAX + 1, so each pass looks
+// that far ahead.  Pass x keeps its two directions in 4-bit fields, pass y
+// its four (x, y) sign pairs; pass z writes, into the header of each empty
+// cell, the eight radii D_s(c) - 1 (3 bits each, octant o at bits 3o).
+constexpr int kFar = (int)RLC_OCC_SKIP_MAX + 1;
+
 __global__ void __launch_bounds__(kBlock) k_occ_skip(const uint32_t* __restrict__ src, uint32_t* dst, uint32_t res,
                                                      uint32_t axis) {
     const size_t c = (size_t)blockIdx.x * kBlock + threadIdx.x;
@@ -118,20 +123,37 @@ __global__ void __launch_bounds__(kBlock) k_occ_skip(const uint32_t* __restrict_
     if (c >= ncell) return;
     const size_t stride = axis == 0 ? 1 : (axis == 1 ? (size_t)res : (size_t)res * res);
     const int ca = (int)((c / stride) % res);
-    constexpr int kFar = (int)RLC_OCC_SKIP_MAX + 1;
-    const int k0 = ca - kFar < 0 ? -ca : -kFar;
-    const int k1 = ca + kFar >= (int)res ? (int)res - 1 - ca : kFar;
-    int best = kFar;
-    for (int k = k0; k <= k1; ++k) {
-        const uint32_t v = src[(size_t)((ptrdiff_t)c + (ptrdiff_t)k * (ptrdiff_t)stride)];
-        const int dk = k < 0 ? -k : k;
-        const int e = axis == 0 ? (v ? dk : kFar) : (dk > (int)v ? dk : (int)v);
-        best = e < best ? e : best;
+    const int nin = axis == 0 ? 1 : (axis == 1 ? 2 : 4);  // sign combinations of the earlier axes
+    int best[8];
+    for (int q = 0; q < 8; ++q) best[q] = kFar;
+    for (int dir = 0; dir < 2; ++dir) {  // dir 1: this axis's sign is negative
+        const int reach = dir ? ca : (int)res - 1 - ca;
+        const int kmax = reach < kFar ? reach : kFar;
+        for (int k = 0; k <= kmax; ++k) {
+            const ptrdiff_t off = (ptrdiff_t)k * (ptrdiff_t)stride;
+            const uint32_t v = src[(size_t)(dir ? (ptrdiff_t)c - off : (ptrdiff_t)c + off)];
+            for (int q = 0; q < nin; ++q) {
+                int e;
+                if (axis == 0)
+                    e = (v & (RLC_OCC_ONE | RLC_OCC_LIST)) ? k : kFar;
+                else {
+                    const int prev = (int)((v >> (4 * q)) & 15u);
+                    e = k > prev ? k : prev;
+                }
+                const int slot = q + nin * dir;
+                best[slot] = e < best[slot] ? e : best[slot];
+            }
+        }
     }
-    if (axis < 2)
-        dst[c] = (uint32_t)best;
-    else if (!(dst[c] & (RLC_OCC_ONE | RLC_OCC_LIST)))
-        dst[c] = (uint32_t)(best - 1);
+    if (axis < 2) {
+        uint32_t w = 0;
+        for (int q = 0; q < 2 * nin; ++q) w |= (uint32_t)best[q] << (4 * q);
+        dst[c] = w;
+    } else if (!(dst[c] & (RLC_OCC_ONE | RLC_OCC_LIST))) {
+        uint32_t w = 0;
+        for (int q = 0; q < 8; ++q) w |= (uint32_t)(best[q] - 1) << (3 * q);
+        dst[c] = w;
+    }
 }
 
 __global__ void __launch_bounds__(kBlock) k_visible(DevOcc occ, float t_lo, const float* __restrict__ x,

@@ -24,9 +24,12 @@ namespace rlc {
 // {max.yz, 0, 0}.  Grid cell c has a 32-bit header head[c]: RLC_OCC_ONE | b
 // when box b is the only one overlapping it; RLC_OCC_LIST | s when several
 // do, their count at ref[s] and their indices at ref[s + 1..]; and for a
-// cell no box overlaps, the radius r <= RLC_OCC_SKIP_MAX of the cube of
-// cells centred on it (2r + 1 cells a side, cut by the grid's faces) that
-// no box overlaps either, so a walk can leave that cube in one step.
+// cell c no box overlaps, eight 3-bit radii, one per octant of directions
+// o = (d_x < 0) | (d_y < 0) << 1 | (d_z < 0) << 2 at bits 3o..3o+2: the
+// largest r <= RLC_OCC_SKIP_MAX for which no box overlaps the cells
+// c + (i s_x, j s_y, k s_z), 0 <= i, j, k <= r (s_a = -1 where the octant's
+// d_a < 0, else +1; cut by the grid's faces), so a walk heading into that
+// octant can leave the cube in one step.
 #define RLC_OCC_ONE 0x40000000u
 #define RLC_OCC_LIST 0x80000000u
 #define RLC_OCC_PAYLOAD 0x3FFFFFFFu
@@ -163,10 +166,11 @@ RLC_WALK_INLINE bool cell_blocks(const DevOcc& occ, uint32_t h, uint32_t& last0,
 // most 3 res steps of half an ulp of t).  Each axis counts the cells left
 // before the walk leaves the grid.
 //
-// In an empty cell of radius r the walk leaves the whole empty cube at once:
-// it exits through the cube's nearest face (the r-th boundary ahead on the
-// axis that reaches it first) and, on the other axes, crosses the boundaries
-// whose parameter the exit point has passed, at most r.  No box overlaps the
+// In an empty cell whose radius for the segment's octant is r, the walk
+// leaves the whole empty cube ahead of it at once: it exits through the
+// cube's nearest far face (the r-th boundary ahead on the axis that reaches
+// it first) and, on the other axes, crosses the boundaries whose parameter
+// the exit point has passed, at most r.  No box overlaps the
 // cells it skips, so the boxes tested, and the answer, are those of the
 // cell-by-cell walk; a boundary miscounted by rounding moves the walk to a
 // cell that the segment passes within an ulp or so of, which the 1/256 cell
@@ -180,6 +184,7 @@ struct WalkState {
     float tx, ty, tz, dtx, dty, dtz, itx, ity, itz;
     int rx, ry, rz, sx, sy, sz;  // sx, sy, sz: byte steps of the header offset
     uint32_t lin;                // byte offset of the current cell's header (< 2^32 for res <= 1024)
+    uint32_t osh;                // 3 x the segment's octant: shift of its radius in a header
     int it;
     uint32_t last0, last1;
 };
@@ -240,6 +245,7 @@ RLC_WALK_INLINE bool walk_begin(const DevOcc& occ, const float o[3], const float
     w.sx = 4 * st[0];
     w.sy = 4 * st[1] * res;
     w.sz = 4 * st[2] * res * res;
+    w.osh = 3u * ((d[0] < 0.0f ? 1u : 0u) | (d[1] < 0.0f ? 2u : 0u) | (d[2] < 0.0f ? 4u : 0u));
     w.it = 0;
     w.last0 = 0xFFFFFFFFu;
     w.last1 = 0xFFFFFFFFu;
@@ -289,7 +295,7 @@ RLC_WALK_INLINE int walk_step(const DevOcc& occ, WalkState& w, const float o[3],
                                          const float invd[3], float t_lo) {
     const uint32_t h = *(const uint32_t*)((const char*)occ.head + w.lin);
     if (cell_blocks<FAST>(occ, h, w.last0, w.last1, o, d, invd, t_lo)) return 1;
-    const int r = (h & (RLC_OCC_ONE | RLC_OCC_LIST)) ? 0 : (int)h;
+    const int r = (h & (RLC_OCC_ONE | RLC_OCC_LIST)) ? 0 : (int)((h >> w.osh) & RLC_OCC_SKIP_MAX);
     // exit parameter of the empty cube on each axis (cut by the grid); the
     // axis that reaches its face first moves on (ties: x, then y).  Value
     // selects and integer masks, not selects between fields, keep the state

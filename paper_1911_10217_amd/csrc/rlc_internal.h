@@ -442,8 +442,8 @@ hipError_t launch_occ_count(const float4* box, uint32_t K, DevOcc occ, uint32_t*
 hipError_t launch_occ_sizes(const uint32_t* counts, uint32_t ncell, uint32_t* sizes, hipStream_t s);
 hipError_t launch_occ_lists(const float4* box, uint32_t K, DevOcc occ, const uint32_t* counts, uint32_t* start,
                             uint32_t* cursor, uint32_t* head, uint32_t* ref, hipStream_t s);
-// Writes the empty-cube radius into the header of every cell no box overlaps
-// (tmp0, tmp1: res^3 words each).
+// Writes the eight octant radii into the header of every cell no box
+// overlaps (tmp0, tmp1: res^3 words each).
 hipError_t launch_occ_skip(uint32_t* head, uint32_t* tmp0, uint32_t* tmp1, uint32_t res, hipStream_t s);
 hipError_t launch_visible(DevOcc occ, float t_lo, const float* x, const float* y, uint32_t n, uint8_t* vis,
                           hipStream_t s);

@@ -77,10 +77,11 @@ int main() {
                             ref[start[c] + 1 + cur[c]++] = i;
                     }
         }
-        // empty-cube radius of every empty cell, from its definition: the
-        // largest r <= RLC_OCC_SKIP_MAX for which the cube of cells within r
-        // (cut by the grid) holds no occupied cell, counted with a 3-D
-        // prefix sum of occupancy
+        // octant radii of every empty cell, from their definition: for each
+        // octant, the largest r <= RLC_OCC_SKIP_MAX for which the cube of
+        // cells c + (i s_x, j s_y, k s_z), 0 <= i, j, k <= r (cut by the
+        // grid) holds no occupied cell, counted with a 3-D prefix sum of
+        // occupancy
         const size_t R1 = (size_t)res + 1;
         std::vector<uint32_t> sat(R1 * R1 * R1, 0);
         auto S = [&](int x, int y, int z) -> uint32_t& { return sat[x + R1 * (y + R1 * (size_t)z)]; };
@@ -90,23 +91,33 @@ int main() {
                     S(x + 1, y + 1, z + 1) = (head[x + res * (y + res * (size_t)z)] != 0) + S(x, y + 1, z + 1) +
                                              S(x + 1, y, z + 1) + S(x + 1, y + 1, z) - S(x, y, z + 1) -
                                              S(x, y + 1, z) - S(x + 1, y, z) + S(x, y, z);
+        // cells [a0, a1) along each axis, cut by the grid
         auto clip = [&](int v) { return v < 0 ? 0 : (v > (int)res ? (int)res : v); };
+        auto occupied_in = [&](int x0, int x1, int y0, int y1, int z0, int z1) {
+            x0 = clip(x0), x1 = clip(x1), y0 = clip(y0), y1 = clip(y1), z0 = clip(z0), z1 = clip(z1);
+            return S(x1, y1, z1) - S(x0, y1, z1) - S(x1, y0, z1) - S(x1, y1, z0) + S(x0, y0, z1) + S(x0, y1, z0) +
+                   S(x1, y0, z0) - S(x0, y0, z0);
+        };
         for (int z = 0; z < (int)res; ++z)
             for (int y = 0; y < (int)res; ++y)
                 for (int x = 0; x < (int)res; ++x) {
                     uint32_t& h = head[x + res * (y + res * (size_t)z)];
                     if (h) continue;
-                    uint32_t r = 0;
-                    while (r < RLC_OCC_SKIP_MAX) {
-                        const int q = (int)r + 1;
-                        const int x0 = clip(x - q), x1 = clip(x + q + 1), y0 = clip(y - q), y1 = clip(y + q + 1);
-                        const int z0 = clip(z - q), z1 = clip(z + q + 1);
-                        const uint32_t n_occ = S(x1, y1, z1) - S(x0, y1, z1) - S(x1, y0, z1) - S(x1, y1, z0) +
-                                               S(x0, y0, z1) + S(x0, y1, z0) + S(x1, y0, z0) - S(x0, y0, z0);
-                        if (n_occ) break;
-                        r = (uint32_t)q;
+                    uint32_t word = 0;
+                    for (int o = 0; o < 8; ++o) {
+                        const bool nx = o & 1, ny = o & 2, nz = o & 4;
+                        uint32_t r = 0;
+                        while (r < RLC_OCC_SKIP_MAX) {
+                            const int q = (int)r + 1;
+                            const int x0 = nx ? x - q : x, x1 = nx ? x + 1 : x + q + 1;
+                            const int y0 = ny ? y - q : y, y1 = ny ? y + 1 : y + q + 1;
+                            const int z0 = nz ? z - q : z, z1 = nz ? z + 1 : z + q + 1;
+                            if (occupied_in(x0, x1, y0, y1, z0, z1)) break;
+                            r = (uint32_t)q;
+                        }
+                        word |= r << (3 * o);
                     }
-                    h = r;
+                    h = word;
                 }
         occ.head = head.data();
         occ.ref = ref.data();
