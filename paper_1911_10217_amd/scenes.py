@@ -370,10 +370,24 @@ def make_dynamic(n_points=1 << 20, per_cluster=65536, grid=4, n_bricks=16384, M=
     nrm[wall] = 0.0
     nrm[wall, 0] = np.where(side[wall] == 0, 1.0, np.where(side[wall] == 1, -1.0, 0.0))
     nrm[wall, 2] = np.where(side[wall] == 2, 1.0, np.where(side[wall] == 3, -1.0, 0.0))
+    # delivered in Morton order of their 1/64 cells, as a renderer's screen
+    # tiles deliver neighbouring surface points together
+    order = np.argsort(_morton_key(pos, 64), kind="stable")
+    pos, nrm = pos[order], nrm[order]
     params = params_for(M=M, spp=spp, frames=frames, grid_dims=(64, 64, 64), hashed=1,
                         capacity=capacity, seed=seed, occ_grid_res=64)
     params.update(overrides)
     return Scene("dynamic", tri, emit, boxes, _f32(pos), _f32(nrm), params, emission_at=emission_at)
+
+
+def _morton_key(pos: np.ndarray, res: int) -> np.ndarray:
+    """Morton (Z-order) index of the res^3 cell of each point of [0, 1]^3."""
+    c = np.clip(np.floor(pos * res), 0, res - 1).astype(np.uint64)
+    key = np.zeros(pos.shape[0], np.uint64)
+    for b in range(int(res - 1).bit_length()):
+        for a in range(3):
+            key |= ((c[:, a] >> np.uint64(b)) & np.uint64(1)) << np.uint64(3 * b + a)
+    return key
 
 
 # --------------------------------------------------------------------------
