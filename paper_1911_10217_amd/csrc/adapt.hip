@@ -10,6 +10,7 @@ namespace {
 
 constexpr int kWave = 64;
 constexpr int kMaxPerLane = RLC_MMAX / kWave;
+static_assert(kMaxPerLane == 4, "k_adapt instances cover one and four slots per lane");
 
 __device__ __forceinline__ float pow_uint(float a, uint32_t n) {
     float res = 1.0f, b = a;
@@ -37,37 +38,53 @@ __device__ __forceinline__ unsigned long long wave_min_u64(unsigned long long v)
     return v;
 }
 
+// Per-cell scratch in LDS, S = 64 PER entries per array: the cut's nodes,
+// ends (one past the cluster's last light), the cluster nodes' parents, Q,
+// the new cut's nodes, and two arrays that hold the new cut's ends and Q
+// during split-collapse, then Q~ and C.
 struct AdaptLds {
-    uint32_t node[RLC_MMAX];
-    uint32_t end[RLC_MMAX];     // one past the cluster's last light
-    uint32_t par[RLC_MMAX];     // the cluster node's parent
-    float Q[RLC_MMAX];
-    uint32_t nnode[RLC_MMAX];
-    // the new cut's ends and Q during split-collapse, then Q~ and C
-    union {
-        uint32_t nend[RLC_MMAX];
-        float Qt[RLC_MMAX];
-    };
-    union {
-        float nQ[RLC_MMAX];
-        float C[RLC_MMAX];
-    };
+    uint32_t* node;
+    uint32_t* end;
+    uint32_t* par;
+    float* Q;
+    uint32_t* nnode;
+    uint32_t* nend;
+    float* Qt;  // aliases nend
+    float* nQ;
+    float* C;   // aliases nQ
 };
 
-// End of pass for table slot c, by one wavefront (= the block).
-__device__ void adapt_cell(const AdaptParams& ap, uint32_t c, AdaptLds& L) {
+constexpr uint32_t kLdsArrays = 7;
+
+__device__ __forceinline__ AdaptLds lds_view(uint32_t* base, uint32_t S) {
+    AdaptLds L;
+    L.node = base;
+    L.end = base + S;
+    L.par = base + 2 * S;
+    L.Q = reinterpret_cast<float*>(base + 3 * S);
+    L.nnode = base + 4 * S;
+    L.nend = base + 5 * S;
+    L.Qt = reinterpret_cast<float*>(base + 5 * S);
+    L.nQ = reinterpret_cast<float*>(base + 6 * S);
+    L.C = reinterpret_cast<float*>(base + 6 * S);
+    return L;
+}
+
+// End of pass for table slot c, by one wavefront (= the block); PER slots
+// per lane (cuts of up to 64 PER clusters).
+template <int PER>
+__device__ void adapt_cell(const AdaptParams& ap, uint32_t c, const AdaptLds& L) {
     const DevCells& cells = ap.cells;
     const uint32_t lane = threadIdx.x;
     const uint32_t Meff = ap.tmpl.Meff;
     const uint32_t M = cells.M;
-    const uint32_t per = (Meff + kWave - 1) / kWave;
     const size_t base = (size_t)c * M;
-    uint32_t cnt[kMaxPerLane];
+    uint32_t cnt[PER];
     bool any = false;
 #pragma unroll
-    for (int j = 0; j < kMaxPerLane; ++j) {
+    for (int j = 0; j < PER; ++j) {
         uint32_t s = lane + kWave * j;
-        cnt[j] = (j < (int)per && s < Meff) ? cells.cnt[base + s] : 0u;
+        cnt[j] = (s < Meff) ? cells.cnt[base + s] : 0u;
         any |= cnt[j] != 0u;
     }
     if (!__any(any)) return;  // no samples this pass: the cell is left as it is
@@ -75,9 +92,9 @@ __device__ void adapt_cell(const AdaptParams& ap, uint32_t c, AdaptLds& L) {
     const bool fresh = cells.ready[c] == 0u || ap.temporal == 0u;
     // load the cut and Q (a fresh cell starts from the initial cut, Q = 0)
 #pragma unroll
-    for (int j = 0; j < kMaxPerLane; ++j) {
+    for (int j = 0; j < PER; ++j) {
         uint32_t s = lane + kWave * j;
-        if (j < (int)per && s < Meff) {
+        if (s < Meff) {
             uint32_t nd, en;
             float q;
             if (fresh) {
@@ -114,9 +131,9 @@ __device__ void adapt_cell(const AdaptParams& ap, uint32_t c, AdaptLds& L) {
         // l_max: largest Q among splittable cut nodes, ties -> smallest slot
         unsigned long long best = 0ull;
 #pragma unroll
-        for (int j = 0; j < kMaxPerLane; ++j) {
+        for (int j = 0; j < PER; ++j) {
             uint32_t s = lane + kWave * j;
-            if (j < (int)per && s < Meff) {
+            if (s < Meff) {
                 // a cluster of two or more lights is an internal node
                 if (L.end[s] - (s ? L.end[s - 1u] : 0u) > 1u) {
                     unsigned long long key = ((unsigned long long)__float_as_uint(L.Q[s]) << 32) |
@@ -130,9 +147,9 @@ __device__ void adapt_cell(const AdaptParams& ap, uint32_t c, AdaptLds& L) {
         // p_min: sibling pairs (s, s+1) not holding l_max, smallest Q sum
         unsigned long long worst = ~0ull;
 #pragma unroll
-        for (int j = 0; j < kMaxPerLane; ++j) {
+        for (int j = 0; j < PER; ++j) {
             uint32_t s = lane + kWave * j;
-            if (j < (int)per && s + 1u < Meff && s != smax && s + 1u != smax) {
+            if (s + 1u < Meff && s != smax && s + 1u != smax) {
                 // neighbouring cut nodes with one parent are its two children
                 const uint32_t p = L.par[s];
                 if (p != RLC_NONE && p == L.par[s + 1u]) {
@@ -152,9 +169,9 @@ __device__ void adapt_cell(const AdaptParams& ap, uint32_t c, AdaptLds& L) {
     if (changed) {
         // new slot of old slot s: s + [s > smax] - [s > smin + 1]
 #pragma unroll
-        for (int j = 0; j < kMaxPerLane; ++j) {
+        for (int j = 0; j < PER; ++j) {
             uint32_t s = lane + kWave * j;
-            if (j < (int)per && s < Meff && s != smin + 1u) {
+            if (s < Meff && s != smin + 1u) {
                 uint32_t nd = L.node[s];
                 float q = L.Q[s];
                 uint32_t dst = s + (s > smax ? 1u : 0u) - (s > smin + 1u ? 1u : 0u);
@@ -181,9 +198,9 @@ __device__ void adapt_cell(const AdaptParams& ap, uint32_t c, AdaptLds& L) {
         }
         __syncthreads();
 #pragma unroll
-        for (int j = 0; j < kMaxPerLane; ++j) {
+        for (int j = 0; j < PER; ++j) {
             uint32_t s = lane + kWave * j;
-            if (j < (int)per && s < Meff) {
+            if (s < Meff) {
                 L.node[s] = L.nnode[s];
                 L.end[s] = L.nend[s];
                 L.Q[s] = L.nQ[s];
@@ -219,9 +236,9 @@ __device__ void adapt_cell(const AdaptParams& ap, uint32_t c, AdaptLds& L) {
     }
     __syncthreads();
 #pragma unroll
-    for (int j = 0; j < kMaxPerLane; ++j) {
+    for (int j = 0; j < PER; ++j) {
         uint32_t s = lane + kWave * j;
-        if (j < (int)per && s < Meff) {
+        if (s < Meff) {
             cells.node[base + s] = L.node[s];
             cells.end[base + s] = L.end[s];
             cells.Q[base + s] = L.Q[s];
@@ -235,20 +252,25 @@ __device__ void adapt_cell(const AdaptParams& ap, uint32_t c, AdaptLds& L) {
     __syncthreads();
 }
 
-// One block = one wavefront; it walks the list of created cells.
-__global__ void __launch_bounds__(kWave) k_adapt(AdaptParams ap) {
-    __shared__ AdaptLds L;
+// One block = one wavefront; it walks the list of created cells.  The LDS
+// scratch is sized for the cut (7 arrays of 64 PER words).
+template <int PER>
+__global__ void __launch_bounds__(kWave, 8) k_adapt(AdaptParams ap) {
+    extern __shared__ uint32_t lds[];
+    const AdaptLds L = lds_view(lds, kWave * PER);
     const uint32_t n_live = *ap.cells.n_live;
-    for (uint32_t li = blockIdx.x; li < n_live; li += gridDim.x) adapt_cell(ap, ap.cells.live[li], L);
+    for (uint32_t li = blockIdx.x; li < n_live; li += gridDim.x) adapt_cell<PER>(ap, ap.cells.live[li], L);
 }
 
 // The same over every scene of a batch.
-__global__ void __launch_bounds__(kWave) k_batch_adapt(const AdaptParams* __restrict__ aps, uint32_t n_scenes) {
-    __shared__ AdaptLds L;
+template <int PER>
+__global__ void __launch_bounds__(kWave, 8) k_batch_adapt(const AdaptParams* __restrict__ aps, uint32_t n_scenes) {
+    extern __shared__ uint32_t lds[];
+    const AdaptLds L = lds_view(lds, kWave * PER);
     for (uint32_t sc = 0; sc < n_scenes; ++sc) {
         const AdaptParams ap = aps[sc];
         const uint32_t n_live = *ap.cells.n_live;
-        for (uint32_t li = blockIdx.x; li < n_live; li += gridDim.x) adapt_cell(ap, ap.cells.live[li], L);
+        for (uint32_t li = blockIdx.x; li < n_live; li += gridDim.x) adapt_cell<PER>(ap, ap.cells.live[li], L);
     }
 }
 
@@ -270,15 +292,22 @@ __global__ void k_gather_cells(DevCells c, uint32_t Meff, const uint32_t* __rest
 
 }  // namespace
 
-hipError_t launch_batch_adapt(const AdaptParams* aps, uint32_t n_scenes, hipStream_t s) {
-    hipLaunchKernelGGL(k_batch_adapt, dim3(8192), dim3(kWave), 0, s, aps, n_scenes);
+hipError_t launch_batch_adapt(const AdaptParams* aps, uint32_t n_scenes, uint32_t Meff, hipStream_t s) {
+    if (Meff <= (uint32_t)kWave)
+        hipLaunchKernelGGL(k_batch_adapt<1>, dim3(8192), dim3(kWave), kLdsArrays * kWave * 4, s, aps, n_scenes);
+    else
+        hipLaunchKernelGGL(k_batch_adapt<kMaxPerLane>, dim3(8192), dim3(kWave), kLdsArrays * RLC_MMAX * 4, s, aps,
+                           n_scenes);
     return hipGetLastError();
 }
 
 hipError_t launch_adapt(const AdaptParams& ap, hipStream_t s) {
-    // enough waves to cover the chip several times over; each walks the
-    // list of created cells with a stride of the grid size
-    hipLaunchKernelGGL(k_adapt, dim3(8192), dim3(kWave), 0, s, ap);
+    // enough waves to fill the chip (8 per SIMD); each walks the list of
+    // created cells with a stride of the grid size
+    if (ap.tmpl.Meff <= (uint32_t)kWave)
+        hipLaunchKernelGGL(k_adapt<1>, dim3(8192), dim3(kWave), kLdsArrays * kWave * 4, s, ap);
+    else
+        hipLaunchKernelGGL(k_adapt<kMaxPerLane>, dim3(8192), dim3(kWave), kLdsArrays * RLC_MMAX * 4, s, ap);
     return hipGetLastError();
 }
 

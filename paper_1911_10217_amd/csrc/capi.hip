@@ -1190,7 +1190,9 @@ int batch_capture(rlc_batch* b) {
     if (e == hipSuccess)
         e = launch_batch_frame(b->d_scenes, (uint32_t)b->scenes.size(), b->total_items, rounds, b->sched.dynamic,
                                grid, b->d_counter, b->d_frame, b->stream);
-    if (e == hipSuccess) e = launch_batch_adapt(b->d_adapt, (uint32_t)b->scenes.size(), b->stream);
+    uint32_t meff_max = 1;
+    for (const auto& sc : b->scenes) meff_max = std::max(meff_max, sc.ctx->Meff);
+    if (e == hipSuccess) e = launch_batch_adapt(b->d_adapt, (uint32_t)b->scenes.size(), meff_max, b->stream);
     if (e == hipSuccess) e = launch_batch_end(b->d_frame, b->stream);
     hipGraph_t g = nullptr;
     hipError_t e2 = hipStreamEndCapture(b->stream, &g);

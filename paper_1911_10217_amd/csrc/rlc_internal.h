@@ -469,7 +469,8 @@ hipError_t launch_batch_frame(const BatchScene* scenes, uint32_t n_scenes, uint3
 
 // adapt.hip
 hipError_t launch_adapt(const AdaptParams& ap, hipStream_t s);
-hipError_t launch_batch_adapt(const AdaptParams* aps, uint32_t n_scenes, hipStream_t s);
+// Meff: the largest cut size of the batch's scenes.
+hipError_t launch_batch_adapt(const AdaptParams* aps, uint32_t n_scenes, uint32_t Meff, hipStream_t s);
 hipError_t launch_gather_cells(DevCells c, uint32_t Meff, const uint32_t* slots, uint32_t n, uint32_t* node,
                                uint32_t* end, float* Q, float* Qt, float* C, unsigned long long* sum,
                                uint32_t* cnt, hipStream_t s);

@@ -77,10 +77,11 @@ def test_batch_frames_out_of_order_and_emission_changes(torch):
     from paper_1911_10217_amd import rlc
     dyn = scenes.make_dynamic(n_points=2048, per_cluster=128, grid=2, n_bricks=256, M=16)
     tiny = scenes.make_tiny(n_points=1024, spp=1)
+    wide = scenes.make_tiny(n_points=512, spp=1, M=128)  # cut of more than 64 clusters
     st = torch.cuda.Stream()
     with torch.cuda.stream(st):
-        a = [_ctx(torch, s) for s in (dyn, tiny)]
-        b = [_ctx(torch, s) for s in (dyn, tiny)]
+        a = [_ctx(torch, s) for s in (dyn, tiny, wide)]
+        b = [_ctx(torch, s) for s in (dyn, tiny, wide)]
         batch = rlc.Batch([(c, p, n, 1) for c, p, n in a], st)
         for f in (0, 1, 2, 7, 8, 3):
             e = torch.from_numpy(dyn.emission_at(f)).cuda()

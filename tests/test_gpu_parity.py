@@ -245,6 +245,8 @@ def test_split_steps_parity(torch, reward_mode):
     dict(spp=3),
     dict(M=1),
     dict(M=64, spp=8),
+    dict(M=100, spp=4),
+    dict(M=256, spp=2),
     dict(eps=0.0),
     dict(adapt=0),
     dict(temporal=0),
