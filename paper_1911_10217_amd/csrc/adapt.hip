@@ -70,49 +70,87 @@ __device__ __forceinline__ AdaptLds lds_view(uint32_t* base, uint32_t S) {
     return L;
 }
 
-// End of pass for table slot c, by one wavefront (= the block); PER slots
-// per lane (cuts of up to 64 PER clusters).
+// Lane s's value of v, read by a whole-wave (uniform) index s.
+__device__ __forceinline__ float lane_value(float v, uint32_t s) {
+    return __int_as_float(__builtin_amdgcn_readlane(__float_as_int(v), (int)s));
+}
+
+// The floor eps S / Meff of Eq. 2.  With eps > 0 it never underflows to 0
+// (Q decays towards subnormals in cells whose rewards stay 0): at least the
+// smallest normal float, so every cluster keeps p > 0.
+__device__ __forceinline__ float eq2_floor(const AdaptParams& ap, float S, uint32_t Meff) {
+    float fl = (ap.eps * S) / (float)Meff;
+    if (ap.eps > 0.0f && fl < 1.17549435e-38f) fl = 1.17549435e-38f;
+    return fl;
+}
+
+// What a cell's end of pass reads from the tables before it starts: its
+// counts, ready flag, stored cut and Q, reward sums, and the initial cut's
+// entries (for a fresh cell).  Loaded for every slot without waiting on the
+// flag, so all of it is one round of independent loads that can be issued
+// while the wave still works on the previous cell; a fresh cell's stored
+// row is read but not used.
 template <int PER>
-__device__ void adapt_cell(const AdaptParams& ap, uint32_t c, const AdaptLds& L) {
+struct CellIn {
+    uint32_t c, ready;
+    uint32_t cnt[PER], node[PER], end[PER], tnode[PER], tend[PER];
+    float q[PER];
+    unsigned long long sum[PER];
+};
+
+template <int PER>
+__device__ __forceinline__ void load_cell(const AdaptParams& ap, uint32_t c, CellIn<PER>& in) {
+    const DevCells& cells = ap.cells;
+    const uint32_t Meff = ap.tmpl.Meff;
+    const size_t base = (size_t)c * cells.M;
+    in.c = c;
+    in.ready = cells.ready[c];
+#pragma unroll
+    for (int j = 0; j < PER; ++j) {
+        const uint32_t s = threadIdx.x + kWave * j;
+        const bool ok = s < Meff;
+        const size_t i = base + (ok ? s : 0u);
+        const uint32_t st = ok ? s : 0u;
+        in.cnt[j] = ok ? cells.cnt[i] : 0u;
+        in.node[j] = cells.node[i];
+        in.end[j] = cells.end[i];
+        in.q[j] = cells.Q[i];
+        in.sum[j] = cells.sum[i];
+        in.tnode[j] = ap.tmpl.node[st];
+        in.tend[j] = ap.tmpl.end[st];
+    }
+}
+
+// End of pass for the cell loaded into in, by one wavefront (= the block);
+// PER slots per lane (cuts of up to 64 PER clusters).
+template <int PER>
+__device__ void adapt_cell(const AdaptParams& ap, const CellIn<PER>& in, const AdaptLds& L) {
     const DevCells& cells = ap.cells;
     const uint32_t lane = threadIdx.x;
     const uint32_t Meff = ap.tmpl.Meff;
-    const uint32_t M = cells.M;
-    const size_t base = (size_t)c * M;
-    uint32_t cnt[PER];
+    const uint32_t c = in.c;
+    const size_t base = (size_t)c * cells.M;
     bool any = false;
 #pragma unroll
-    for (int j = 0; j < PER; ++j) {
-        uint32_t s = lane + kWave * j;
-        cnt[j] = (s < Meff) ? cells.cnt[base + s] : 0u;
-        any |= cnt[j] != 0u;
-    }
+    for (int j = 0; j < PER; ++j) any |= in.cnt[j] != 0u;
     if (!__any(any)) return;  // no samples this pass: the cell is left as it is
 
-    const bool fresh = cells.ready[c] == 0u || ap.temporal == 0u;
-    // load the cut and Q (a fresh cell starts from the initial cut, Q = 0)
+    const bool fresh = in.ready == 0u || ap.temporal == 0u;
+    // the cut and Q (a fresh cell starts from the initial cut, Q = 0)
 #pragma unroll
     for (int j = 0; j < PER; ++j) {
         uint32_t s = lane + kWave * j;
         if (s < Meff) {
-            uint32_t nd, en;
-            float q;
-            if (fresh) {
-                nd = ap.tmpl.node[s];
-                en = ap.tmpl.end[s];
-                q = 0.0f;
-            } else {
-                nd = cells.node[base + s];
-                en = cells.end[base + s];
-                q = cells.Q[base + s];
-            }
+            const uint32_t nd = fresh ? in.tnode[j] : in.node[j];
+            const uint32_t en = fresh ? in.tend[j] : in.end[j];
+            float q = fresh ? 0.0f : in.q[j];
             // the one tree lookup the step needs for every cluster: its parent
             L.par[s] = ap.tree.parent[nd];
             L.end[s] = en;
-            if (ap.temporal && cnt[j]) {
+            if (ap.temporal && in.cnt[j]) {
                 // Eq. 1 applied to the n samples of the pass at once
-                float a_n = pow_uint(1.0f - ap.alpha, cnt[j]);
-                float m = ((float)cells.sum[base + s] * ap.fx_inv) / (float)cnt[j];
+                float a_n = pow_uint(1.0f - ap.alpha, in.cnt[j]);
+                float m = ((float)in.sum[j] * ap.fx_inv) / (float)in.cnt[j];
                 float t1 = a_n * q;
                 float t2 = (1.0f - a_n) * m;
                 q = t1 + t2;
@@ -128,42 +166,70 @@ __device__ void adapt_cell(const AdaptParams& ap, uint32_t c, const AdaptLds& L)
     uint32_t smax = RLC_NONE, smin = RLC_NONE;
     float qpmin = 0.0f;
     if (ap.temporal && ap.adapt && Meff >= 2u) {
-        // l_max: largest Q among splittable cut nodes, ties -> smallest slot
-        unsigned long long best = 0ull;
-#pragma unroll
-        for (int j = 0; j < PER; ++j) {
-            uint32_t s = lane + kWave * j;
-            if (s < Meff) {
-                // a cluster of two or more lights is an internal node
-                if (L.end[s] - (s ? L.end[s - 1u] : 0u) > 1u) {
-                    unsigned long long key = ((unsigned long long)__float_as_uint(L.Q[s]) << 32) |
-                                             (unsigned long long)(0xFFFFFFFFu - s);
-                    best = key > best ? key : best;
-                }
-            }
-        }
-        best = wave_max_u64(best);
-        if (best != 0ull) smax = 0xFFFFFFFFu - (uint32_t)(best & 0xFFFFFFFFull);
-        // p_min: sibling pairs (s, s+1) not holding l_max, smallest Q sum
-        unsigned long long worst = ~0ull;
-#pragma unroll
-        for (int j = 0; j < PER; ++j) {
-            uint32_t s = lane + kWave * j;
+        if constexpr (PER == 1) {
+            // one slot per lane, slot = lane: a 32-bit wave maximum (minimum)
+            // of the Q bits (Q >= 0, so their order as integers is the
+            // floats' order), then the lowest lane holding it
+            const uint32_t s = lane;
+            const bool split_ok = s < Meff && L.end[s] - (s ? L.end[s - 1u] : 0u) > 1u;
+            const uint32_t qbits = split_ok ? __float_as_uint(L.Q[s]) : 0u;
+            const uint32_t qmax = __reduce_max_sync(~0ull, qbits);
+            const unsigned long long at_max = __ballot(split_ok && qbits == qmax);
+            if (at_max) smax = (uint32_t)__ffsll((long long)at_max) - 1u;
+            bool pair_ok = false;
+            uint32_t pbits = 0xFFFFFFFFu;
             if (s + 1u < Meff && s != smax && s + 1u != smax) {
-                // neighbouring cut nodes with one parent are its two children
                 const uint32_t p = L.par[s];
                 if (p != RLC_NONE && p == L.par[s + 1u]) {
-                    float qp = L.Q[s] + L.Q[s + 1u];
-                    unsigned long long key = ((unsigned long long)__float_as_uint(qp) << 32) | s;
-                    worst = key < worst ? key : worst;
+                    pair_ok = true;
+                    pbits = __float_as_uint(L.Q[s] + L.Q[s + 1u]);
                 }
             }
-        }
-        worst = wave_min_u64(worst);
-        if (smax != RLC_NONE && worst != ~0ull) {
-            smin = (uint32_t)(worst & 0xFFFFFFFFull);
-            qpmin = __uint_as_float((uint32_t)(worst >> 32));
-            changed = L.Q[smax] > ap.T * qpmin;
+            const uint32_t pmin = __reduce_min_sync(~0ull, pbits);
+            const unsigned long long at_min = __ballot(pair_ok && pbits == pmin);
+            if (smax != RLC_NONE && at_min) {
+                smin = (uint32_t)__ffsll((long long)at_min) - 1u;
+                qpmin = __uint_as_float(pmin);
+                changed = L.Q[smax] > ap.T * qpmin;
+            }
+        } else {
+            // l_max: largest Q among splittable cut nodes, ties -> smallest slot
+            unsigned long long best = 0ull;
+#pragma unroll
+            for (int j = 0; j < PER; ++j) {
+                uint32_t s = lane + kWave * j;
+                if (s < Meff) {
+                    // a cluster of two or more lights is an internal node
+                    if (L.end[s] - (s ? L.end[s - 1u] : 0u) > 1u) {
+                        unsigned long long key = ((unsigned long long)__float_as_uint(L.Q[s]) << 32) |
+                                                 (unsigned long long)(0xFFFFFFFFu - s);
+                        best = key > best ? key : best;
+                    }
+                }
+            }
+            best = wave_max_u64(best);
+            if (best != 0ull) smax = 0xFFFFFFFFu - (uint32_t)(best & 0xFFFFFFFFull);
+            // p_min: sibling pairs (s, s+1) not holding l_max, smallest Q sum
+            unsigned long long worst = ~0ull;
+#pragma unroll
+            for (int j = 0; j < PER; ++j) {
+                uint32_t s = lane + kWave * j;
+                if (s + 1u < Meff && s != smax && s + 1u != smax) {
+                    // neighbouring cut nodes with one parent are its two children
+                    const uint32_t p = L.par[s];
+                    if (p != RLC_NONE && p == L.par[s + 1u]) {
+                        float qp = L.Q[s] + L.Q[s + 1u];
+                        unsigned long long key = ((unsigned long long)__float_as_uint(qp) << 32) | s;
+                        worst = key < worst ? key : worst;
+                    }
+                }
+            }
+            worst = wave_min_u64(worst);
+            if (smax != RLC_NONE && worst != ~0ull) {
+                smin = (uint32_t)(worst & 0xFFFFFFFFull);
+                qpmin = __uint_as_float((uint32_t)(worst >> 32));
+                changed = L.Q[smax] > ap.T * qpmin;
+            }
         }
     }
     if (changed) {
@@ -209,28 +275,49 @@ __device__ void adapt_cell(const AdaptParams& ap, uint32_t c, const AdaptLds& L)
         __syncthreads();
     }
 
+    float myq = 0.0f;
+    if constexpr (PER == 1) myq = lane < Meff ? L.Q[lane] : 0.0f;
     // ---- Q~ and Eq. 2: sums taken left to right ----
     if (lane == 0) {
-        float S = 0.0f;
-        for (uint32_t s = 0; s < Meff; ++s) S = S + L.Q[s];
-        float acc = 0.0f;
-        if (S == 0.0f) {
-            for (uint32_t s = 0; s < Meff; ++s) {
-                L.Qt[s] = 1.0f;
-                acc = s ? acc + 1.0f : 1.0f;
-                L.C[s] = acc;
+        if constexpr (PER == 1) {
+            // every slot's Q sits in its lane's register; lane 0 reads them in
+            // slot order (a cross-lane register read, no LDS round trip)
+            float S = 0.0f;
+            for (uint32_t s = 0; s < Meff; ++s) S = S + lane_value(myq, s);
+            float acc = 0.0f;
+            if (S == 0.0f) {
+                for (uint32_t s = 0; s < Meff; ++s) {
+                    L.Qt[s] = 1.0f;
+                    acc = s ? acc + 1.0f : 1.0f;
+                    L.C[s] = acc;
+                }
+            } else {
+                const float fl = eq2_floor(ap, S, Meff);
+                for (uint32_t s = 0; s < Meff; ++s) {
+                    const float qt = lane_value(myq, s) + fl;
+                    L.Qt[s] = qt;
+                    acc = s ? acc + qt : qt;
+                    L.C[s] = acc;
+                }
             }
         } else {
-            float fl = (ap.eps * S) / (float)Meff;
-            // with eps > 0 the floor never underflows to 0 (Q decays towards
-            // subnormals in cells whose rewards stay 0): at least the
-            // smallest normal float, so every cluster keeps p > 0
-            if (ap.eps > 0.0f && fl < 1.17549435e-38f) fl = 1.17549435e-38f;
-            for (uint32_t s = 0; s < Meff; ++s) {
-                float qt = L.Q[s] + fl;
-                L.Qt[s] = qt;
-                acc = s ? acc + qt : qt;
-                L.C[s] = acc;
+            float S = 0.0f;
+            for (uint32_t s = 0; s < Meff; ++s) S = S + L.Q[s];
+            float acc = 0.0f;
+            if (S == 0.0f) {
+                for (uint32_t s = 0; s < Meff; ++s) {
+                    L.Qt[s] = 1.0f;
+                    acc = s ? acc + 1.0f : 1.0f;
+                    L.C[s] = acc;
+                }
+            } else {
+                const float fl = eq2_floor(ap, S, Meff);
+                for (uint32_t s = 0; s < Meff; ++s) {
+                    float qt = L.Q[s] + fl;
+                    L.Qt[s] = qt;
+                    acc = s ? acc + qt : qt;
+                    L.C[s] = acc;
+                }
             }
         }
     }
@@ -252,25 +339,46 @@ __device__ void adapt_cell(const AdaptParams& ap, uint32_t c, const AdaptLds& L)
     __syncthreads();
 }
 
+// The cells of the live list from li on, with a stride of the grid: each
+// cell's loads are issued before the previous cell's work (with one slot per
+// lane; four slots per lane would hold too many registers).
+template <int PER>
+__device__ __forceinline__ void adapt_cells(const AdaptParams& ap, const AdaptLds& L) {
+    const uint32_t n_live = *ap.cells.n_live;
+    uint32_t li = blockIdx.x;
+    if (li >= n_live) return;
+    CellIn<PER> cur, nxt;
+    load_cell<PER>(ap, ap.cells.live[li], cur);
+    for (; li < n_live; li += gridDim.x) {
+        const uint32_t ln = li + gridDim.x;
+        if (PER == 1 && ln < n_live) load_cell<PER>(ap, ap.cells.live[ln], nxt);
+        adapt_cell<PER>(ap, cur, L);
+        if (ln < n_live) {
+            if (PER == 1)
+                cur = nxt;
+            else
+                load_cell<PER>(ap, ap.cells.live[ln], cur);
+        }
+    }
+}
+
 // One block = one wavefront; it walks the list of created cells.  The LDS
 // scratch is sized for the cut (7 arrays of 64 PER words).
 template <int PER>
-__global__ void __launch_bounds__(kWave, 8) k_adapt(AdaptParams ap) {
+__global__ void __launch_bounds__(kWave, PER == 1 ? 8 : 4) k_adapt(AdaptParams ap) {
     extern __shared__ uint32_t lds[];
     const AdaptLds L = lds_view(lds, kWave * PER);
-    const uint32_t n_live = *ap.cells.n_live;
-    for (uint32_t li = blockIdx.x; li < n_live; li += gridDim.x) adapt_cell<PER>(ap, ap.cells.live[li], L);
+    adapt_cells<PER>(ap, L);
 }
 
 // The same over every scene of a batch.
 template <int PER>
-__global__ void __launch_bounds__(kWave, 8) k_batch_adapt(const AdaptParams* __restrict__ aps, uint32_t n_scenes) {
+__global__ void __launch_bounds__(kWave, PER == 1 ? 8 : 4) k_batch_adapt(const AdaptParams* __restrict__ aps, uint32_t n_scenes) {
     extern __shared__ uint32_t lds[];
     const AdaptLds L = lds_view(lds, kWave * PER);
     for (uint32_t sc = 0; sc < n_scenes; ++sc) {
         const AdaptParams ap = aps[sc];
-        const uint32_t n_live = *ap.cells.n_live;
-        for (uint32_t li = blockIdx.x; li < n_live; li += gridDim.x) adapt_cell<PER>(ap, ap.cells.live[li], L);
+        adapt_cells<PER>(ap, L);
     }
 }
 
