@@ -242,7 +242,7 @@ __device__ void frame_block(const FrameParams& fp, const float* __restrict__ pos
 }
 
 // Fused pass: one lane per sample.
-__global__ void __launch_bounds__(kBlock) k_frame(FrameParams fp, const float* __restrict__ pos,
+__global__ void __launch_bounds__(kBlock, 8) k_frame(FrameParams fp, const float* __restrict__ pos,
                                                   const float* __restrict__ nrm, uint32_t P, uint32_t spp,
                                                   uint32_t frame, float* __restrict__ radiance) {
     __shared__ AggTable agg;
