@@ -68,6 +68,7 @@ class OrcConfig(ctypes.Structure):
         ("adapt", ctypes.c_uint32),
         ("temporal", ctypes.c_uint32),
         ("scene_id", ctypes.c_uint32),
+        ("split_steps", ctypes.c_uint32),
         ("seed", ctypes.c_uint64),
     ]
 
@@ -157,6 +158,7 @@ def make_config(params: dict) -> OrcConfig:
     c.adapt = int(params["adapt"])
     c.temporal = int(params["temporal"])
     c.scene_id = int(params["scene_id"])
+    c.split_steps = int(params.get("split_steps", 1))
     c.seed = int(params["seed"])
     return c
 

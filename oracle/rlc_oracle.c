@@ -55,6 +55,8 @@ typedef struct orc_config {
     uint32_t adapt;        /* run split-collapse at the end of each pass */
     uint32_t temporal;     /* 0: every pass restarts from the initial cut */
     uint32_t scene_id;     /* high bits of cell keys and of the RNG tag */
+    uint32_t split_steps;  /* split-collapse steps per pass: 0 or 1 one step; n > 1
+                              repeated until a step changes nothing, at most n */
     uint64_t seed;         /* Philox key */
 } orc_config;
 
@@ -866,7 +868,10 @@ int orc_cdf(const float* Q, uint32_t Meff, float eps, float* Qt, float* C)
 }
 
 /* End of a rendering pass: for every cell that received samples, Eq. 1,    */
-/* then one split-collapse step, then Q~ and Eq. 2; statistics are cleared. */
+/* then split-collapse, then Q~ and Eq. 2; statistics are cleared.  The     */
+/* basic algorithm takes one split-collapse step; section 3 notes that it   */
+/* could be repeated until no pair of nodes is touched, which split_steps   */
+/* > 1 does, stopping after that many steps at the latest.                  */
 int orc_adapt(orc_ctx* c)
 {
     const orc_config* cfg = &c->cfg;
@@ -886,7 +891,11 @@ int orc_adapt(orc_ctx* c)
         if (cfg->temporal) {
             for (uint32_t s = 0; s < Meff; ++s)
                 if (ce->cnt[s]) ce->Q[s] = ema_update(ce->Q[s], ce->sum[s], ce->cnt[s], cfg->alpha, cfg->fx_shift);
-            if (cfg->adapt) split_collapse(c, ce->node, ce->Q, Meff, cfg->T);
+            if (cfg->adapt) {
+                uint32_t steps = cfg->split_steps > 1u ? cfg->split_steps : 1u;
+                for (uint32_t k = 0; k < steps; ++k)
+                    if (!split_collapse(c, ce->node, ce->Q, Meff, cfg->T)) break;
+            }
         }
         for (uint32_t s = 0; s < Meff; ++s) ce->end[s] = c->last[ce->node[s]] + 1u;
         rebuild_cdf(ce->Q, Meff, cfg->eps, ce->Qt, ce->C);

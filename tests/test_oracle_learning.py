@@ -205,3 +205,96 @@ def test_pair_holding_lmax_as_right_child_is_excluded(orc):
     assert changed
     assert _ranges(o, n2) == [(0, 1), (2, 2), (3, 3), (4, 7)]
     assert q2.tolist() == [np.float32(0.1), 0.5, 0.5, np.float32(0.6) + np.float32(0.6)]
+
+
+# --------------------------------------------------------------------------
+# split-collapse repeated within a pass (section 3: invoked until no pair of
+# nodes is touched any more)
+# --------------------------------------------------------------------------
+def _fixed_point_violation(t, node, Q, T):
+    """Whether one more split-collapse step would still apply to the cut
+    (node, Q): written from the rule of section 3, not from the oracle."""
+    first, last, parent = t["first"][node], t["last"][node], t["parent"][node]
+    Q = Q.astype(np.float32)
+    split_ok = last > first
+    if not split_ok.any():
+        return False
+    smax = int(np.flatnonzero(split_ok)[np.argmax(Q[split_ok])])  # first of the maxima
+    best = None
+    for s in range(node.size - 1):
+        if s == smax or s + 1 == smax:
+            continue
+        if parent[s] != parent[s + 1] or parent[s] == 0xFFFFFFFF:
+            continue
+        qp = np.float32(Q[s] + Q[s + 1])
+        if best is None or qp < best:
+            best = qp
+    return best is not None and bool(Q[smax] > np.float32(T) * best)
+
+
+def _valid_cut(t, node, N):
+    f, l = t["first"][node], t["last"][node]
+    return f[0] == 0 and l[-1] == N - 1 and bool(np.all(f[1:] == l[:-1] + 1))
+
+
+def test_repeated_split_collapse_reaches_a_fixed_point(orc):
+    s = scenes.make_tiny(n_lights=1024, n_points=2048, M=16, spp=8, frames=4, n_boxes=16)
+    res = {}
+    for steps in (1, 100000):
+        o = orc.Oracle(dict(s.params, split_steps=steps), s.tri, s.emit, s.boxes)
+        t = o.tree()
+        o.frame(s.pos, s.nrm, 8, 0)
+        o.adapt()
+        res[steps] = (o.cells(), t)
+        # later passes: every cell's cut stays valid and, with repetition, at
+        # the fixed point after every pass
+        for f in range(1, 3):
+            o.frame(s.pos, s.nrm, 8, f)
+            o.adapt()
+            c = o.cells()
+            for i in np.flatnonzero(c["ready"]):
+                assert _valid_cut(t, c["node"][i], s.N)
+                if steps > 1:
+                    assert not _fixed_point_violation(t, c["node"][i], c["Q"][i], s.params["T"])
+    (c1, t), (cf, _) = res[1], res[100000]
+    assert np.array_equal(c1["key"], cf["key"])
+    one_step_not_fixed = 0
+    for i in np.flatnonzero(cf["ready"]):
+        q1, qf = c1["Q"][i].astype(np.float64), cf["Q"][i].astype(np.float64)
+        # both start from the same pass: the Q mass is kept (halving is
+        # exact, a collapse rounds one sum), and sum(Q^2) only falls
+        assert abs(q1.sum() - qf.sum()) <= 1e-5 * max(q1.sum(), 1e-30)
+        assert (qf ** 2).sum() <= (q1 ** 2).sum() * (1 + 1e-6) + 1e-30
+        assert not _fixed_point_violation(t, cf["node"][i], cf["Q"][i], s.params["T"])
+        one_step_not_fixed += _fixed_point_violation(t, c1["node"][i], c1["Q"][i], s.params["T"])
+    # the single step leaves work undone somewhere, so the repetition is tested
+    assert one_step_not_fixed > 0
+
+
+@pytest.mark.parametrize("k", [2, 3])
+def test_split_steps_bound_the_changes(orc, k):
+    # a fresh cell starts from the initial cut; each step replaces one leaf by
+    # two and two by one, so after one pass at most 3k nodes are new
+    s = scenes.make_tiny(n_lights=1024, n_points=2048, M=16, spp=8, n_boxes=16)
+    o = orc.Oracle(dict(s.params, split_steps=k), s.tri, s.emit, s.boxes)
+    tmpl, _ = o.template()
+    o.frame(s.pos, s.nrm, 8, 0)
+    o.adapt()
+    c = o.cells()
+    new = [len(set(c["node"][i].tolist()) - set(tmpl.tolist())) for i in np.flatnonzero(c["ready"])]
+    assert max(new) <= 3 * k
+    assert max(new) > 3  # more than one step was taken somewhere
+
+
+def test_split_steps_end_with_t_below_one(orc):
+    # with T < 1 a split can be undone by the next collapse: the steps stop
+    # at split_steps and the cut stays valid
+    s = scenes.make_tiny(n_lights=256, n_points=1024, M=8, spp=4, n_boxes=8, T=0.5)
+    o = orc.Oracle(dict(s.params, split_steps=50), s.tri, s.emit, s.boxes)
+    t = o.tree()
+    for f in range(3):
+        o.frame(s.pos, s.nrm, 4, f)
+        o.adapt()
+    c = o.cells()
+    for i in np.flatnonzero(c["ready"]):
+        assert _valid_cut(t, c["node"][i], s.N)
