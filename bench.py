@@ -462,6 +462,9 @@ def main():
     ap.add_argument("--mlp-lr", type=float, default=1e-2)
     ap.add_argument("--budgets", default="32,128,512,2048",
                     help="learned: GPU-time budgets, as the plain method's time for this many passes")
+    ap.add_argument("--split-steps", type=int, default=1,
+                    help="static/dynamic: split-collapse steps per pass (1: the basic algorithm; n > 1: "
+                         "repeated until a step changes nothing, at most n times)")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--cpu-stride", type=int, default=20, help="CPU baseline runs every n-th point")
     ap.add_argument("--copy-calib-mib", type=int, default=0,
@@ -499,7 +502,7 @@ def main():
 
     print("[bench] generating the %s workload" % args.workload, file=sys.stderr, flush=True)
     s = scenes.make_static() if args.workload == "static" else scenes.make_dynamic()
-    p = dict(s.params, occ_grid_res=64)
+    p = dict(s.params, occ_grid_res=64, split_steps=args.split_steps)
     spp = int(p["spp"])
     P = s.P
     samples_per_step = P * spp
@@ -624,6 +627,8 @@ def main():
                     "Le (1 + sin(2 pi f t + phi)) per compartment set every pass, 1,048,576 points, "
                     "16,384 wall bricks in a 64^3 grid, 64^3 hashed cells, cut size 64, 1 spp, "
                     "temporal adaptation, passes from a fresh cell table")
+    if args.split_steps > 1:
+        workload += "; split-collapse repeated until a step changes nothing (at most %d steps)" % args.split_steps
     line = {
         "metric": METRIC,
         "value": round(value, 1),

@@ -44,6 +44,7 @@ extern "C" {
 #define RLC_ESTATE (-5)    /* calls out of order (e.g. sample before build) */
 
 #define RLC_MMAX 256u      /* largest supported cut size */
+#define RLC_SPLIT_STEPS_MAX 65536u /* largest split_steps */
 
 typedef struct rlc_ctx rlc_ctx;
 
@@ -70,7 +71,11 @@ typedef struct rlc_config {
     uint32_t temporal;     /* 0: every pass restarts from the initial cut */
     uint32_t scene_id;     /* upper key bits and RNG stream of this scene */
     uint32_t occ_grid_res; /* 0: test every box per shadow ray; n: n^3 grid */
-    uint32_t reserved;
+    uint32_t split_steps;  /* split-collapse steps per pass (section 3): 0 or 1, one
+                              step (the basic algorithm); n > 1, repeated until a
+                              step changes nothing, at most n times (with T >= 1
+                              the repetition reaches that point: sum(Q^2) falls
+                              at every step), 1..RLC_SPLIT_STEPS_MAX */
     uint64_t seed;         /* Philox4x32-10 key */
 } rlc_config;
 

@@ -40,21 +40,22 @@ __device__ __forceinline__ unsigned long long wave_min_u64(unsigned long long v)
 
 // Per-cell scratch in LDS, S = 64 PER entries per array: the cut's nodes,
 // ends (one past the cluster's last light), the cluster nodes' parents, Q,
-// the new cut's nodes, and two arrays that hold the new cut's ends and Q
-// during split-collapse, then Q~ and C.
+// the new cut's nodes and parents, and two arrays that hold the new cut's
+// ends and Q during split-collapse, then Q~ and C.
 struct AdaptLds {
     uint32_t* node;
     uint32_t* end;
     uint32_t* par;
     float* Q;
     uint32_t* nnode;
+    uint32_t* npar;
     uint32_t* nend;
     float* Qt;  // aliases nend
     float* nQ;
     float* C;   // aliases nQ
 };
 
-constexpr uint32_t kLdsArrays = 7;
+constexpr uint32_t kLdsArrays = 8;
 
 __device__ __forceinline__ AdaptLds lds_view(uint32_t* base, uint32_t S) {
     AdaptLds L;
@@ -67,6 +68,7 @@ __device__ __forceinline__ AdaptLds lds_view(uint32_t* base, uint32_t S) {
     L.Qt = reinterpret_cast<float*>(base + 5 * S);
     L.nQ = reinterpret_cast<float*>(base + 6 * S);
     L.C = reinterpret_cast<float*>(base + 6 * S);
+    L.npar = base + 7 * S;
     return L;
 }
 
@@ -161,118 +163,127 @@ __device__ void adapt_cell(const AdaptParams& ap, const CellIn<PER>& in, const A
     }
     __syncthreads();
 
-    // ---- split-collapse (one step) ----
-    bool changed = false;
-    uint32_t smax = RLC_NONE, smin = RLC_NONE;
-    float qpmin = 0.0f;
+    // ---- split-collapse: steps until one changes nothing, at most
+    // max(split_steps, 1) of them (one step: the basic algorithm) ----
     if (ap.temporal && ap.adapt && Meff >= 2u) {
-        if constexpr (PER == 1) {
-            // one slot per lane, slot = lane: a 32-bit wave maximum (minimum)
-            // of the Q bits (Q >= 0, so their order as integers is the
-            // floats' order), then the lowest lane holding it
-            const uint32_t s = lane;
-            const bool split_ok = s < Meff && L.end[s] - (s ? L.end[s - 1u] : 0u) > 1u;
-            const uint32_t qbits = split_ok ? __float_as_uint(L.Q[s]) : 0u;
-            const uint32_t qmax = __reduce_max_sync(~0ull, qbits);
-            const unsigned long long at_max = __ballot(split_ok && qbits == qmax);
-            if (at_max) smax = (uint32_t)__ffsll((long long)at_max) - 1u;
-            bool pair_ok = false;
-            uint32_t pbits = 0xFFFFFFFFu;
-            if (s + 1u < Meff && s != smax && s + 1u != smax) {
-                const uint32_t p = L.par[s];
-                if (p != RLC_NONE && p == L.par[s + 1u]) {
-                    pair_ok = true;
-                    pbits = __float_as_uint(L.Q[s] + L.Q[s + 1u]);
+        const uint32_t steps = ap.split_steps > 1u ? ap.split_steps : 1u;
+        for (uint32_t step = 0; step < steps; ++step) {
+            // after this step another may follow: keep the parents current
+            const bool more = step + 1u < steps;
+            bool changed = false;
+            uint32_t smax = RLC_NONE, smin = RLC_NONE;
+            float qpmin = 0.0f;
+            if constexpr (PER == 1) {
+                // one slot per lane, slot = lane: a 32-bit wave maximum (minimum)
+                // of the Q bits (Q >= 0, so their order as integers is the
+                // floats' order), then the lowest lane holding it
+                const uint32_t s = lane;
+                const bool split_ok = s < Meff && L.end[s] - (s ? L.end[s - 1u] : 0u) > 1u;
+                const uint32_t qbits = split_ok ? __float_as_uint(L.Q[s]) : 0u;
+                const uint32_t qmax = __reduce_max_sync(~0ull, qbits);
+                const unsigned long long at_max = __ballot(split_ok && qbits == qmax);
+                if (at_max) smax = (uint32_t)__ffsll((long long)at_max) - 1u;
+                bool pair_ok = false;
+                uint32_t pbits = 0xFFFFFFFFu;
+                if (s + 1u < Meff && s != smax && s + 1u != smax) {
+                    const uint32_t p = L.par[s];
+                    if (p != RLC_NONE && p == L.par[s + 1u]) {
+                        pair_ok = true;
+                        pbits = __float_as_uint(L.Q[s] + L.Q[s + 1u]);
+                    }
+                }
+                const uint32_t pmin = __reduce_min_sync(~0ull, pbits);
+                const unsigned long long at_min = __ballot(pair_ok && pbits == pmin);
+                if (smax != RLC_NONE && at_min) {
+                    smin = (uint32_t)__ffsll((long long)at_min) - 1u;
+                    qpmin = __uint_as_float(pmin);
+                    changed = L.Q[smax] > ap.T * qpmin;
+                }
+            } else {
+                // l_max: largest Q among splittable cut nodes, ties -> smallest slot
+                unsigned long long best = 0ull;
+#pragma unroll
+                for (int j = 0; j < PER; ++j) {
+                    uint32_t s = lane + kWave * j;
+                    if (s < Meff) {
+                        // a cluster of two or more lights is an internal node
+                        if (L.end[s] - (s ? L.end[s - 1u] : 0u) > 1u) {
+                            unsigned long long key = ((unsigned long long)__float_as_uint(L.Q[s]) << 32) |
+                                                     (unsigned long long)(0xFFFFFFFFu - s);
+                            best = key > best ? key : best;
+                        }
+                    }
+                }
+                best = wave_max_u64(best);
+                if (best != 0ull) smax = 0xFFFFFFFFu - (uint32_t)(best & 0xFFFFFFFFull);
+                // p_min: sibling pairs (s, s+1) not holding l_max, smallest Q sum
+                unsigned long long worst = ~0ull;
+#pragma unroll
+                for (int j = 0; j < PER; ++j) {
+                    uint32_t s = lane + kWave * j;
+                    if (s + 1u < Meff && s != smax && s + 1u != smax) {
+                        // neighbouring cut nodes with one parent are its two children
+                        const uint32_t p = L.par[s];
+                        if (p != RLC_NONE && p == L.par[s + 1u]) {
+                            float qp = L.Q[s] + L.Q[s + 1u];
+                            unsigned long long key = ((unsigned long long)__float_as_uint(qp) << 32) | s;
+                            worst = key < worst ? key : worst;
+                        }
+                    }
+                }
+                worst = wave_min_u64(worst);
+                if (smax != RLC_NONE && worst != ~0ull) {
+                    smin = (uint32_t)(worst & 0xFFFFFFFFull);
+                    qpmin = __uint_as_float((uint32_t)(worst >> 32));
+                    changed = L.Q[smax] > ap.T * qpmin;
                 }
             }
-            const uint32_t pmin = __reduce_min_sync(~0ull, pbits);
-            const unsigned long long at_min = __ballot(pair_ok && pbits == pmin);
-            if (smax != RLC_NONE && at_min) {
-                smin = (uint32_t)__ffsll((long long)at_min) - 1u;
-                qpmin = __uint_as_float(pmin);
-                changed = L.Q[smax] > ap.T * qpmin;
+            if (!changed) break;
+            // new slot of old slot s: s + [s > smax] - [s > smin + 1]
+#pragma unroll
+            for (int j = 0; j < PER; ++j) {
+                uint32_t s = lane + kWave * j;
+                if (s < Meff && s != smin + 1u) {
+                    uint32_t nd = L.node[s];
+                    float q = L.Q[s];
+                    uint32_t dst = s + (s > smax ? 1u : 0u) - (s > smin + 1u ? 1u : 0u);
+                    if (s == smin) {
+                        // the parent covers both children: it ends where the right one does
+                        L.nnode[dst] = L.par[s];
+                        L.nend[dst] = L.end[s + 1u];
+                        L.nQ[dst] = qpmin;
+                        if (more) L.npar[dst] = ap.tree.parent[L.par[s]];
+                    } else if (s == smax) {
+                        float h = 0.5f * q;
+                        const uint32_t lc = ap.tree.left[nd];
+                        L.nnode[dst] = lc;
+                        L.nend[dst] = ap.tree.last[lc] + 1u;
+                        L.nQ[dst] = h;
+                        L.nnode[dst + 1u] = ap.tree.right[nd];
+                        L.nend[dst + 1u] = L.end[s];
+                        L.nQ[dst + 1u] = h;
+                        if (more) L.npar[dst] = L.npar[dst + 1u] = nd;
+                    } else {
+                        L.nnode[dst] = nd;
+                        L.nend[dst] = L.end[s];
+                        L.nQ[dst] = q;
+                        if (more) L.npar[dst] = L.par[s];
+                    }
+                }
             }
-        } else {
-            // l_max: largest Q among splittable cut nodes, ties -> smallest slot
-            unsigned long long best = 0ull;
+            __syncthreads();
 #pragma unroll
             for (int j = 0; j < PER; ++j) {
                 uint32_t s = lane + kWave * j;
                 if (s < Meff) {
-                    // a cluster of two or more lights is an internal node
-                    if (L.end[s] - (s ? L.end[s - 1u] : 0u) > 1u) {
-                        unsigned long long key = ((unsigned long long)__float_as_uint(L.Q[s]) << 32) |
-                                                 (unsigned long long)(0xFFFFFFFFu - s);
-                        best = key > best ? key : best;
-                    }
+                    L.node[s] = L.nnode[s];
+                    L.end[s] = L.nend[s];
+                    L.Q[s] = L.nQ[s];
+                    if (more) L.par[s] = L.npar[s];
                 }
             }
-            best = wave_max_u64(best);
-            if (best != 0ull) smax = 0xFFFFFFFFu - (uint32_t)(best & 0xFFFFFFFFull);
-            // p_min: sibling pairs (s, s+1) not holding l_max, smallest Q sum
-            unsigned long long worst = ~0ull;
-#pragma unroll
-            for (int j = 0; j < PER; ++j) {
-                uint32_t s = lane + kWave * j;
-                if (s + 1u < Meff && s != smax && s + 1u != smax) {
-                    // neighbouring cut nodes with one parent are its two children
-                    const uint32_t p = L.par[s];
-                    if (p != RLC_NONE && p == L.par[s + 1u]) {
-                        float qp = L.Q[s] + L.Q[s + 1u];
-                        unsigned long long key = ((unsigned long long)__float_as_uint(qp) << 32) | s;
-                        worst = key < worst ? key : worst;
-                    }
-                }
-            }
-            worst = wave_min_u64(worst);
-            if (smax != RLC_NONE && worst != ~0ull) {
-                smin = (uint32_t)(worst & 0xFFFFFFFFull);
-                qpmin = __uint_as_float((uint32_t)(worst >> 32));
-                changed = L.Q[smax] > ap.T * qpmin;
-            }
+            __syncthreads();
         }
-    }
-    if (changed) {
-        // new slot of old slot s: s + [s > smax] - [s > smin + 1]
-#pragma unroll
-        for (int j = 0; j < PER; ++j) {
-            uint32_t s = lane + kWave * j;
-            if (s < Meff && s != smin + 1u) {
-                uint32_t nd = L.node[s];
-                float q = L.Q[s];
-                uint32_t dst = s + (s > smax ? 1u : 0u) - (s > smin + 1u ? 1u : 0u);
-                if (s == smin) {
-                    // the parent covers both children: it ends where the right one does
-                    L.nnode[dst] = L.par[s];
-                    L.nend[dst] = L.end[s + 1u];
-                    L.nQ[dst] = qpmin;
-                } else if (s == smax) {
-                    float h = 0.5f * q;
-                    const uint32_t lc = ap.tree.left[nd];
-                    L.nnode[dst] = lc;
-                    L.nend[dst] = ap.tree.last[lc] + 1u;
-                    L.nQ[dst] = h;
-                    L.nnode[dst + 1u] = ap.tree.right[nd];
-                    L.nend[dst + 1u] = L.end[s];
-                    L.nQ[dst + 1u] = h;
-                } else {
-                    L.nnode[dst] = nd;
-                    L.nend[dst] = L.end[s];
-                    L.nQ[dst] = q;
-                }
-            }
-        }
-        __syncthreads();
-#pragma unroll
-        for (int j = 0; j < PER; ++j) {
-            uint32_t s = lane + kWave * j;
-            if (s < Meff) {
-                L.node[s] = L.nnode[s];
-                L.end[s] = L.nend[s];
-                L.Q[s] = L.nQ[s];
-            }
-        }
-        __syncthreads();
     }
 
     float myq = 0.0f;
@@ -363,7 +374,7 @@ __device__ __forceinline__ void adapt_cells(const AdaptParams& ap, const AdaptLd
 }
 
 // One block = one wavefront; it walks the list of created cells.  The LDS
-// scratch is sized for the cut (7 arrays of 64 PER words).
+// scratch is sized for the cut (8 arrays of 64 PER words).
 template <int PER>
 __global__ void __launch_bounds__(kWave, PER == 1 ? 8 : 4) k_adapt(AdaptParams ap) {
     extern __shared__ uint32_t lds[];

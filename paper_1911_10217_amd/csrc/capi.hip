@@ -266,6 +266,7 @@ AdaptParams adapt_params(const rlc_ctx* c) {
     ap.fx_inv = c->fx_inv;
     ap.adapt = c->cfg.adapt;
     ap.temporal = c->cfg.temporal;
+    ap.split_steps = c->cfg.split_steps;
     return ap;
 }
 
@@ -411,7 +412,7 @@ int rlc_create(const rlc_config* cfg, void* stream, rlc_ctx** out) {
               finite_f(k.T) && k.T >= 0.0f && finite_f(k.eps) && k.eps >= 0.0f && k.fx_shift <= 40 &&
               finite_f(k.reward_max) && k.reward_max > 0.0f && finite_f(k.t_lo) && k.t_lo >= 0.0f &&
               k.t_lo < 0.5f && k.reward_mode <= 1 && finite_f(k.albedo) && k.albedo >= 0.0f &&
-              k.occ_grid_res <= 1024;
+              k.occ_grid_res <= 1024 && k.split_steps <= RLC_SPLIT_STEPS_MAX;
     for (int a = 0; a < 3; ++a)
         ok = ok && finite_f(k.grid_lo[a]) && finite_f(k.grid_hi[a]) && k.grid_hi[a] > k.grid_lo[a] &&
              k.grid_dims[a] >= 1 && k.grid_dims[a] <= (1u << 20);

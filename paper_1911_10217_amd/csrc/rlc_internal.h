@@ -113,6 +113,7 @@ struct AdaptParams {
     float fx_inv;               // 2^-fx_shift
     uint32_t adapt;
     uint32_t temporal;
+    uint32_t split_steps;       // split-collapse steps per pass, at most (0 and 1: one)
 };
 
 // ---------------------------------------------------------------------------

@@ -70,7 +70,7 @@ class rlc_config(ctypes.Structure):
         ("temporal", ctypes.c_uint32),
         ("scene_id", ctypes.c_uint32),
         ("occ_grid_res", ctypes.c_uint32),
-        ("reserved", ctypes.c_uint32),
+        ("split_steps", ctypes.c_uint32),
         ("seed", ctypes.c_uint64),
     ]
 
@@ -206,6 +206,7 @@ def make_config(params: dict) -> rlc_config:
     c.temporal = int(params["temporal"])
     c.scene_id = int(params["scene_id"])
     c.occ_grid_res = int(params.get("occ_grid_res", 0))
+    c.split_steps = int(params.get("split_steps", 1))
     c.seed = int(params["seed"])
     return c
 

@@ -62,6 +62,7 @@ DEFAULT_PARAMS = dict(
     capacity=0,
     adapt=1,
     temporal=1,
+    split_steps=1,
     scene_id=0,
     seed=SEED_BASE + 1,
     occ_grid_res=0,

@@ -253,6 +253,10 @@ def test_split_steps_parity(torch, reward_mode):
     dict(reward_mode=1, T=1.0),
     dict(hashed=1, capacity=4096),
     dict(two_sided=0),
+    dict(split_steps=4),
+    dict(split_steps=65536),
+    dict(M=100, spp=4, split_steps=65536),
+    dict(T=0.5, split_steps=50),
 ])
 def test_fused_frames_parity_tiny(torch, variant):
     s = scenes.make_tiny(**variant)
@@ -370,6 +374,8 @@ def test_errors(torch):
         rlc.Context(dict(s.params, M=0))
     with pytest.raises(rlc.RLCError):
         rlc.Context(dict(s.params, M=300))
+    with pytest.raises(rlc.RLCError):
+        rlc.Context(dict(s.params, split_steps=65537))
     # hash table too small: reported at the next sync, samples still shaded
     small = rlc.Context(dict(s.params, hashed=1, capacity=64))
     small.rlc_build_light_tree(_t(torch, s.tri), _t(torch, s.emit))
