@@ -465,6 +465,9 @@ def main():
     ap.add_argument("--split-steps", type=int, default=1,
                     help="static/dynamic: split-collapse steps per pass (1: the basic algorithm; n > 1: "
                          "repeated until a step changes nothing, at most n times)")
+    ap.add_argument("--sub-frames", type=int, default=1,
+                    help="static/dynamic: a step is one frame of this many passes (rlc_frame_sub), each "
+                         "with the workload's samples per point")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--cpu-stride", type=int, default=20, help="CPU baseline runs every n-th point")
     ap.add_argument("--copy-calib-mib", type=int, default=0,
@@ -505,7 +508,9 @@ def main():
     p = dict(s.params, occ_grid_res=64, split_steps=args.split_steps)
     spp = int(p["spp"])
     P = s.P
-    samples_per_step = P * spp
+    n_sub = max(1, args.sub_frames)
+    samples_per_pass = P * spp
+    samples_per_step = samples_per_pass * n_sub
 
     t = lambda a: torch.from_numpy(np.ascontiguousarray(a)).to(dev)
     tri, emit, boxes, pos, nrm = t(s.tri), t(s.emit), t(s.boxes), t(s.pos), t(s.nrm)
@@ -532,7 +537,10 @@ def main():
     def one_pass(f):
         if emissions is not None:
             ctx.rlc_set_emission(emissions[f])
-        ctx.rlc_frame(pos, nrm, spp, f, radiance)
+        if n_sub > 1:
+            ctx.rlc_frame_sub(pos, nrm, spp * n_sub, n_sub, f, radiance)
+        else:
+            ctx.rlc_frame(pos, nrm, spp, f, radiance)
 
     print("[bench] warm-up: %d passes" % args.warmup, file=sys.stderr, flush=True)
     for f in range(args.warmup):
@@ -574,7 +582,7 @@ def main():
     cells_t = int((cnt.sum(axis=1) > 0).sum())
     bins_t = int((cnt > 0).sum())
     M = ctx.rlc_meff()
-    alg = algorithmic_bytes(samples_per_step, spp, M, cells_t, bins_t)
+    alg = algorithmic_bytes(samples_per_pass, spp, M, cells_t, bins_t)
     achieved = alg["fused"] / (fused_avg_ms * 1e-3) / 1e9
 
     traffic = None
@@ -610,10 +618,13 @@ def main():
         for f in range(args.steps):
             if s.emission_at is not None:
                 orc.set_emission(s.emission_at(f))
-            orc.frame(s.pos[sel], s.nrm[sel], spp, f, pid=sel)
-            orc.adapt()
+            if n_sub > 1:
+                orc.frame_sub(s.pos[sel], s.nrm[sel], spp * n_sub, n_sub, f, pid=sel)
+            else:
+                orc.frame(s.pos[sel], s.nrm[sel], spp, f, pid=sel)
+                orc.adapt()
         dt = time.perf_counter() - t0
-        cpu = {"value": round(sel.size * spp * args.steps / dt, 1), "unit": "samples/s", "cores": 1,
+        cpu = {"value": round(sel.size * spp * n_sub * args.steps / dt, 1), "unit": "samples/s", "cores": 1,
                "kind": "oracle",
                "sample": "every %dth point (%d of %d) for the same %d passes, single-threaded C oracle, %.1f s"
                          % (args.cpu_stride, sel.size, P, args.steps, dt)}
@@ -629,6 +640,8 @@ def main():
                     "temporal adaptation, passes from a fresh cell table")
     if args.split_steps > 1:
         workload += "; split-collapse repeated until a step changes nothing (at most %d steps)" % args.split_steps
+    if n_sub > 1:
+        workload += "; a step is one frame of %d sub-frame passes, the cuts adapted after each" % n_sub
     line = {
         "metric": METRIC,
         "value": round(value, 1),

@@ -138,14 +138,25 @@ int rlc_learn(rlc_ctx* ctx, const rlc_samples* in, const float* d_reward, uint32
 
 /* End of a rendering pass (section 3): for every cell that received samples,
  * Q <- (1-alpha)^n Q + (1 - (1-alpha)^n) mean(r) per cluster (Eq. 1 over the
- * pass), one split-collapse step, Q~ and the cdf C by Eq. 2; clears the
- * statistics. */
+ * pass), split-collapse (one step, or up to split_steps of them), Q~ and the
+ * cdf C by Eq. 2; clears the statistics. */
 int rlc_adapt_cuts(rlc_ctx* ctx);
 
 /* One whole pass: sample, shade and learn fused in one kernel, then
  * rlc_adapt_cuts.  d_radiance: P x 3. */
 int rlc_frame(rlc_ctx* ctx, const float* d_pos, const float* d_nrm, uint32_t P, uint32_t spp,
               uint32_t frame, float* d_radiance);
+
+/* One frame rendered as n_sub passes, the cuts adapted after each (section
+ * 3: a frame split into sub-frames is rendered pass by pass).  Pass j =
+ * 0..n_sub-1 is rlc_frame with spp / n_sub samples per point and pass index
+ * frame * n_sub + j; d_radiance (P x 3) receives the passes' radiance summed
+ * in pass order, times 1 / n_sub.  spp must be a multiple of n_sub, and
+ * frame * n_sub + n_sub - 1 must fit in 32 bits (RLC_EINVAL otherwise).
+ * n_sub = 1 is rlc_frame.  The passes' own radiance goes through a P x 3
+ * buffer the context allocates on first use (and grows when P does). */
+int rlc_frame_sub(rlc_ctx* ctx, const float* d_pos, const float* d_nrm, uint32_t P, uint32_t spp,
+                  uint32_t n_sub, uint32_t frame, float* d_radiance);
 
 /* Shadow-ray test only: d_vis[i] = 1 if the segment d_x[i] -> d_y[i] is
  * unoccluded over t in (t_lo, 1 - t_lo). */

@@ -275,6 +275,21 @@ class Oracle:
     def adapt(self):
         lib().orc_adapt(self._h)
 
+    def frame_sub(self, pos, nrm, spp: int, n_sub: int, frame: int, pid=None):
+        """One frame as n_sub passes (section 3: a frame split into
+        sub-frames, the cuts adapted after each pass): pass j has spp / n_sub
+        samples per point and pass index frame * n_sub + j.  Returns the
+        passes' radiance summed in pass order, times 1 / n_sub, in FP32."""
+        assert n_sub >= 1 and spp % n_sub == 0
+        acc = None
+        for j in range(n_sub):
+            rad, _ = self.frame(pos, nrm, spp // n_sub, frame * n_sub + j, pid=pid)
+            self.adapt()
+            acc = rad if acc is None else (acc + rad).astype(np.float32)
+        if n_sub > 1:
+            acc = (acc * np.float32(np.float32(1.0) / np.float32(n_sub))).astype(np.float32)
+        return acc
+
     def run(self, pos, nrm, spp: int, frames: int, pid=None, first_frame: int = 0,
             emission_at=None):
         """frames passes of frame + adapt; returns the per-frame radiance list."""

@@ -42,6 +42,10 @@ struct rlc_ctx {
     uint32_t* occ_ref = nullptr;
     DevOcc occ{};
 
+    // radiance of one sub-frame pass (rlc_frame_sub), P x 3 floats
+    float* sub_buf = nullptr;
+    size_t sub_cap = 0;
+
     // cells
     DevCells cells{};
     uint32_t* d_err = nullptr;
@@ -490,6 +494,7 @@ int rlc_destroy(rlc_ctx* c) {
     dfree(d.n_live);
     dfree(c->d_err);
     dfree(c->d_partial);
+    dfree(c->sub_buf);
     for (hipEvent_t e : c->pending) (void)hipEventDestroy(e);
     for (hipEvent_t e : c->mlp_pending) (void)hipEventDestroy(e);
     for (hipEvent_t e : c->spare) (void)hipEventDestroy(e);
@@ -719,6 +724,33 @@ int rlc_frame(rlc_ctx* c, const float* d_pos, const float* d_nrm, uint32_t P, ui
     if (c->timing) {
         RLC_HIP(c, hipEventRecord(ev[2], c->stream));
         for (auto& e : ev) c->pending.push_back(e);
+    }
+    return RLC_OK;
+}
+
+int rlc_frame_sub(rlc_ctx* c, const float* d_pos, const float* d_nrm, uint32_t P, uint32_t spp, uint32_t n_sub,
+                  uint32_t frame, float* d_radiance) {
+    RLC_TRY(check_frame_args(c, d_pos, P, spp));
+    if (n_sub == 0 || spp % n_sub != 0) return fail(c, RLC_EINVAL, "spp (%u) is not a multiple of n_sub (%u)", spp, n_sub);
+    if ((uint64_t)frame * n_sub + (n_sub - 1u) > 0xFFFFFFFFull)
+        return fail(c, RLC_EINVAL, "pass index of frame %u x %u sub-frames exceeds 32 bits", frame, n_sub);
+    if (n_sub == 1) return rlc_frame(c, d_pos, d_nrm, P, spp, frame, d_radiance);
+    if (P == 0) return RLC_OK;
+    if (!d_nrm || !d_radiance) return fail(c, RLC_EINVAL, "null normal or radiance array");
+    const size_t n = (size_t)P * 3;
+    if (n > c->sub_cap) {
+        // earlier passes may still read the old buffer
+        RLC_HIP(c, hipStreamSynchronize(c->stream));
+        dfree(c->sub_buf);
+        c->sub_buf = nullptr;
+        c->sub_cap = 0;
+        RLC_TRY(dalloc(c, &c->sub_buf, n));
+        c->sub_cap = n;
+    }
+    const float scale = 1.0f / (float)n_sub;
+    for (uint32_t j = 0; j < n_sub; ++j) {
+        RLC_TRY(rlc_frame(c, d_pos, d_nrm, P, spp / n_sub, frame * n_sub + j, j ? c->sub_buf : d_radiance));
+        if (j) RLC_HIP(c, launch_accum(d_radiance, c->sub_buf, n, scale, j + 1u == n_sub, c->stream));
     }
     return RLC_OK;
 }

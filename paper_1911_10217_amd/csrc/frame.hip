@@ -241,6 +241,15 @@ __device__ void frame_block(const FrameParams& fp, const float* __restrict__ pos
     __syncthreads();
 }
 
+// Sub-frame passes: acc = acc + x, and on the last pass (acc + x) * scale.
+__global__ void __launch_bounds__(kBlock) k_accum(float* __restrict__ acc, const float* __restrict__ x, size_t n,
+                                                  float scale, uint32_t finish) {
+    const size_t i = (size_t)blockIdx.x * kBlock + threadIdx.x;
+    if (i >= n) return;
+    const float v = acc[i] + x[i];
+    acc[i] = finish ? v * scale : v;
+}
+
 // Fused pass: one lane per sample.
 __global__ void __launch_bounds__(kBlock, 8) k_frame(FrameParams fp, const float* __restrict__ pos,
                                                   const float* __restrict__ nrm, uint32_t P, uint32_t spp,
@@ -350,6 +359,12 @@ hipError_t launch_learn(const FrameParams& fp, const rlc_samples& in, const floa
                         hipStream_t s) {
     if (n == 0) return hipSuccess;
     hipLaunchKernelGGL(k_learn, dim3(blocks_for(n)), dim3(kBlock), 0, s, fp, in, reward, n);
+    return hipGetLastError();
+}
+
+hipError_t launch_accum(float* acc, const float* x, size_t n, float scale, bool finish, hipStream_t s) {
+    if (n == 0) return hipSuccess;
+    hipLaunchKernelGGL(k_accum, dim3(blocks_for(n)), dim3(kBlock), 0, s, acc, x, n, scale, finish ? 1u : 0u);
     return hipGetLastError();
 }
 

@@ -456,6 +456,8 @@ hipError_t launch_shade(const FrameParams& fp, const float* pos, const float* nr
                         const rlc_samples& in, float* radiance, float* contrib, float* reward, hipStream_t s);
 hipError_t launch_learn(const FrameParams& fp, const rlc_samples& in, const float* reward, uint32_t n,
                         hipStream_t s);
+// acc[i] = acc[i] + x[i] over n floats; with finish, then times scale.
+hipError_t launch_accum(float* acc, const float* x, size_t n, float scale, bool finish, hipStream_t s);
 hipError_t launch_frame(const FrameParams& fp, const float* pos, const float* nrm, uint32_t P, uint32_t spp,
                         uint32_t frame, float* radiance, hipStream_t s);
 hipError_t launch_cell_keys(const FrameParams& fp, const float* pos, uint32_t n, uint64_t* keys, hipStream_t s);

@@ -477,3 +477,27 @@ def test_dynamic_full_size_sampled_cells(torch):
         assert ok, (f, err)
     ctx.rlc_sync()
     _assert_cells_equal(ctx.rlc_dump_cells(), orc.cells(), keys=pick)
+
+
+# --------------------------------------------------------------------------
+# a frame as sub-frame passes
+# --------------------------------------------------------------------------
+@pytest.mark.parametrize("n_sub", [2, 4])
+def test_frame_sub_parity(torch, n_sub):
+    from paper_1911_10217_amd import rlc
+    s = scenes.make_tiny(spp=8, split_steps=4)
+    ctx, orc = _make(torch, s)
+    small = 1000  # the pass buffer grows when the point count does
+    for f, P in enumerate((small, s.P, s.P)):
+        pos, nrm = _t(torch, s.pos[:P]), _t(torch, s.nrm[:P])
+        rad = ctx.rlc_frame_sub(pos, nrm, 8, n_sub, f).cpu().numpy()
+        ref = orc.frame_sub(s.pos[:P], s.nrm[:P], 8, n_sub, f)
+        assert np.array_equal(rad, ref), (f, int((rad != ref).sum()))
+        _assert_cells_equal(ctx.rlc_dump_cells(), orc.cells())
+    pos, nrm = _t(torch, s.pos), _t(torch, s.nrm)
+    for bad in (dict(spp=8, n_sub=3, frame=0), dict(spp=8, n_sub=0, frame=0),
+                dict(spp=8, n_sub=4, frame=1 << 30)):
+        with pytest.raises(rlc.RLCError) as e:
+            ctx.rlc_frame_sub(pos, nrm, bad["spp"], bad["n_sub"], bad["frame"])
+        assert e.value.code == rlc.RLC_EINVAL
+    ctx.rlc_sync()

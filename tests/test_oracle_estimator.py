@@ -306,3 +306,36 @@ def test_learning_reduces_variance_under_occlusion(orc, reward_mode):
     assert var_l < 0.5 * var_p, (var_l, var_p)
     # and both estimate the same image
     assert abs(fl.mean() / fp.mean() - 1.0) < 0.15
+
+
+def test_sub_frames_unbiased_and_adapted_between_passes(orc):
+    # a frame split into sub-frames (section 3): the mean of its passes is
+    # unbiased against the closed-form radiance, and the cuts adapt after
+    # every pass, so n sub-frames learn as much as n whole frames
+    s = _below_lights(scenes.make_tiny(n_lights=96, n_points=24, n_boxes=0, M=8, spp=8))
+    o = orc.Oracle(s.params, s.tri, s.emit)
+    frames = [o.frame_sub(s.pos, s.nrm, 8, 4, f) for f in range(75)]
+    mean, se = _mean_and_se(frames[5:])
+    truth = o.truth_unoccluded(s.pos, s.nrm)
+    z = (mean - truth) / np.maximum(se, 1e-12)
+    assert np.max(np.abs(z)) < 5.0, np.max(np.abs(z))
+    assert abs(float(np.mean(z))) < 0.5
+    # one sub-frame is one frame of spp / n_sub samples; the whole frame is
+    # their mean in pass order
+    a = orc.Oracle(s.params, s.tri, s.emit)
+    b = orc.Oracle(s.params, s.tri, s.emit)
+    got = a.frame_sub(s.pos, s.nrm, 8, 2, 3)
+    r0, _ = b.frame(s.pos, s.nrm, 4, 6)
+    b.adapt()
+    r1, _ = b.frame(s.pos, s.nrm, 4, 7)
+    b.adapt()
+    assert np.array_equal(got, (r0 + r1) * np.float32(0.5))
+    ca, cb = a.cells(), b.cells()
+    for k in ("key", "node", "Q", "C"):
+        assert np.array_equal(ca[k], cb[k])
+    # with a single sub-frame it is the plain frame
+    c = orc.Oracle(s.params, s.tri, s.emit)
+    d = orc.Oracle(s.params, s.tri, s.emit)
+    r, _ = d.frame(s.pos, s.nrm, 8, 5)
+    d.adapt()
+    assert np.array_equal(c.frame_sub(s.pos, s.nrm, 8, 1, 5), r)
