@@ -39,7 +39,7 @@
 /* Configuration (mirrors the method's parameters: M, alpha, T of section 3) */
 /* ------------------------------------------------------------------------ */
 typedef struct orc_config {
-    uint32_t M;            /* cut size (section 3, "fixed size tree cuts") */
+    uint32_t M;            /* cut size: every cell's cut has M nodes (section 3) */
     float alpha;           /* learning rate of Eq. 1 */
     float T;               /* split-collapse threshold (section 3) */
     float eps;             /* reading: defensive floor mixed into Q before Eq. 2 */
@@ -534,9 +534,9 @@ int orc_visible(const orc_ctx* c, const float* x, const float* y, uint32_t n, ui
 }
 
 /* ------------------------------------------------------------------------ */
-/* One light sample at one shading point (section 3: "use the cdf in the    */
-/* corresponding cell to sample a light cluster s, and then select a light  */
-/* in the cluster randomly"; then "compute the contribution c_l").          */
+/* One light sample at one shading point (section 3): a cluster s drawn     */
+/* from the cdf of the point's cell, one light of that cluster picked at    */
+/* random, then the light's contribution c_l.                               */
 /* ------------------------------------------------------------------------ */
 typedef struct orc_records {
     uint64_t* key;      /* cell key */
@@ -607,7 +607,7 @@ static void one_sample(orc_ctx* c, const float* x, const float* nx, uint32_t pid
             }
         begin = (s == 0) ? 0u : end[s - 1];
         size = end[s] - begin;
-        /* light inside the cluster, uniformly (reading of "randomly") */
+        /* light inside the cluster, uniformly (the paper leaves the choice open) */
         l = begin + (uint32_t)((draw40 * (uint64_t)size) >> 40);
     } else {
         /* node of the fixed cut from the learned cdf, then a light inside it
