@@ -70,6 +70,8 @@ class OrcConfig(ctypes.Structure):
         ("scene_id", ctypes.c_uint32),
         ("split_steps", ctypes.c_uint32),
         ("seed", ctypes.c_uint64),
+        ("normal_bits", ctypes.c_uint32),
+        ("jitter", ctypes.c_float),
     ]
 
 
@@ -160,6 +162,8 @@ def make_config(params: dict) -> OrcConfig:
     c.scene_id = int(params["scene_id"])
     c.split_steps = int(params.get("split_steps", 1))
     c.seed = int(params["seed"])
+    c.normal_bits = int(params.get("normal_bits", 0))
+    c.jitter = float(params.get("jitter", 0.0))
     return c
 
 

@@ -58,6 +58,8 @@ typedef struct orc_config {
     uint32_t split_steps;  /* split-collapse steps per pass: 0 or 1 one step; n > 1
                               repeated until a step changes nothing, at most n */
     uint64_t seed;         /* Philox key */
+    uint32_t normal_bits;  /* 5-D cells: 2^b bins per octahedral normal coordinate (0: position only) */
+    float jitter;          /* jitter of the cell lookup, in cells and normal bins (0: none) */
 } orc_config;
 
 /* ------------------------------------------------------------------------ */
@@ -350,6 +352,11 @@ orc_ctx* orc_create(const orc_config* cfg, const float* tri, const float* emit, 
                     const float* boxes, uint32_t K)
 {
     if (!cfg || !tri || !emit || N == 0 || cfg->M == 0 || cfg->M > ORC_MMAX) return NULL;
+    /* one cell pointer per 5-D cell: at most 2^27 of them */
+    if (cfg->normal_bits > 8u || !(cfg->jitter >= 0.0f && cfg->jitter <= 1.0f)) return NULL;
+    if ((((uint64_t)cfg->grid_dims[0] * cfg->grid_dims[1] * cfg->grid_dims[2]) << (2u * cfg->normal_bits)) >
+        (1ull << 27))
+        return NULL;
     orc_ctx* c = (orc_ctx*)calloc(1, sizeof(orc_ctx));
     if (!c) return NULL;
     c->cfg = *cfg;
@@ -364,7 +371,7 @@ orc_ctx* orc_create(const orc_config* cfg, const float* tri, const float* emit, 
     c->last = (uint32_t*)calloc(nn, sizeof(uint32_t));
     c->rec = (float*)calloc(16u * N, sizeof(float));
     c->boxes = (float*)calloc(6u * (K ? K : 1u), sizeof(float));
-    c->ncell_slots = cfg->grid_dims[0] * cfg->grid_dims[1] * cfg->grid_dims[2];
+    c->ncell_slots = cfg->grid_dims[0] * cfg->grid_dims[1] * cfg->grid_dims[2] << (2u * cfg->normal_bits);
     c->cells = (cell**)calloc(c->ncell_slots ? c->ncell_slots : 1u, sizeof(cell*));
     if (!c->perm || !c->left || !c->right || !c->parent || !c->first || !c->last || !c->rec ||
         !c->boxes || !c->cells) {
@@ -459,10 +466,16 @@ int orc_set_mixture(orc_ctx* c, const float* cdf, uint32_t rows, float w)
 }
 
 /* ------------------------------------------------------------------------ */
-/* Cell location.  Reading of the hashed grid of section 3 for a position-  */
-/* only grid of fixed resolution: each axis is quantised by floor inside    */
-/* the grid box (positions outside clamp to the border cells) and the cell  */
-/* key is the linear cell index, with the scene id in the upper 32 bits.    */
+/* Cell location.  Section 3 keys cells by a 5-D grid over shading points:  */
+/* three position and two normal dimensions, found by quantising jittered   */
+/* coordinates.  Readings: positions on a grid of fixed resolution (each    */
+/* axis quantised by floor inside the grid box, outside points clamp to the */
+/* border cells); the normal mapped to the unit square by the octahedral    */
+/* map and cut into 2^normal_bits bins per coordinate; the jitter a uniform */
+/* offset of up to jitter/2 cells in the tangent plane of the point and of  */
+/* up to jitter/2 bins on each normal coordinate, drawn per sample (Philox  */
+/* tag 4).  The key is the linear 5-D cell index, with the scene id in the  */
+/* upper 32 bits; without normal bins and jitter it is the position cell.   */
 /* ------------------------------------------------------------------------ */
 static uint32_t axis_index(float p, float lo, float inv, uint32_t dims)
 {
@@ -472,13 +485,72 @@ static uint32_t axis_index(float p, float lo, float inv, uint32_t dims)
     return (uint32_t)f;
 }
 
-static uint32_t cell_linear(const orc_ctx* c, const float* p)
+/* Octahedral map of a unit vector onto [0,1]^2 (Cigolle, Donow, Evangelakos, */
+/* Mara, McGuire, Meyer, JCGT 3(2) 2014): project onto |x|+|y|+|z| = 1, and */
+/* for z < 0 fold the lower half over the square's diagonals.               */
+static void octahedral(const float n[3], float* u, float* v)
 {
-    const uint32_t* d = c->cfg.grid_dims;
-    uint32_t ix = axis_index(p[0], c->cfg.grid_lo[0], c->inv_cell[0], d[0]);
-    uint32_t iy = axis_index(p[1], c->cfg.grid_lo[1], c->inv_cell[1], d[1]);
-    uint32_t iz = axis_index(p[2], c->cfg.grid_lo[2], c->inv_cell[2], d[2]);
-    return ix + d[0] * (iy + d[1] * iz);
+    float s = (fabsf(n[0]) + fabsf(n[1])) + fabsf(n[2]);
+    float px = n[0] / s;
+    float py = n[1] / s;
+    if (n[2] < 0.0f) {
+        float fx = (1.0f - fabsf(py)) * (px >= 0.0f ? 1.0f : -1.0f);
+        float fy = (1.0f - fabsf(px)) * (py >= 0.0f ? 1.0f : -1.0f);
+        px = fx;
+        py = fy;
+    }
+    *u = px * 0.5f + 0.5f;
+    *v = py * 0.5f + 0.5f;
+}
+
+/* Two unit tangents of the normal n (Duff, Burgess, Christensen, Hery,     */
+/* Kensler, Liani, Villemin, "Building an orthonormal basis, revisited",    */
+/* JCGT 6(1) 2017).                                                          */
+static void tangent_frame(const float n[3], float t[3], float b[3])
+{
+    float sign = n[2] >= 0.0f ? 1.0f : -1.0f;
+    float a = -1.0f / (sign + n[2]);
+    float bb = n[0] * n[1] * a;
+    t[0] = 1.0f + sign * n[0] * n[0] * a;
+    t[1] = sign * bb;
+    t[2] = -sign * n[0];
+    b[0] = bb;
+    b[1] = sign + n[1] * n[1] * a;
+    b[2] = -n[1];
+}
+
+static uint32_t cell_linear(const orc_ctx* c, const float* x, const float* nrm, uint32_t pid, uint32_t k,
+                            uint32_t frame)
+{
+    const orc_config* cfg = &c->cfg;
+    const uint32_t* d = cfg->grid_dims;
+    const uint32_t nb = 1u << cfg->normal_bits;
+    float p[3] = {x[0], x[1], x[2]};
+    float u = 0.0f, v = 0.0f;
+    if (cfg->normal_bits) octahedral(nrm, &u, &v);
+    if (cfg->jitter > 0.0f) {
+        uint32_t ctr[4] = {pid, k, frame, (uint32_t)(cfg->scene_id << 16) | 4u};
+        uint32_t key[2] = {(uint32_t)(cfg->seed & 0xFFFFFFFFull), (uint32_t)(cfg->seed >> 32)};
+        uint32_t w[4];
+        philox4x32_10(ctr, key, w);
+        float xi0 = unit_float(w[0]) - 0.5f, xi1 = unit_float(w[1]) - 0.5f;
+        float t[3], b[3];
+        tangent_frame(nrm, t, b);
+        for (int a = 0; a < 3; ++a) {
+            float reach = cfg->jitter * ((cfg->grid_hi[a] - cfg->grid_lo[a]) / (float)d[a]);
+            p[a] = x[a] + reach * (xi0 * t[a] + xi1 * b[a]);
+        }
+        if (cfg->normal_bits) {
+            u = u + ((unit_float(w[2]) - 0.5f) * cfg->jitter) / (float)nb;
+            v = v + ((unit_float(w[3]) - 0.5f) * cfg->jitter) / (float)nb;
+        }
+    }
+    uint32_t ix = axis_index(p[0], cfg->grid_lo[0], c->inv_cell[0], d[0]);
+    uint32_t iy = axis_index(p[1], cfg->grid_lo[1], c->inv_cell[1], d[1]);
+    uint32_t iz = axis_index(p[2], cfg->grid_lo[2], c->inv_cell[2], d[2]);
+    uint32_t qu = axis_index(u, 0.0f, (float)nb, nb);
+    uint32_t qv = axis_index(v, 0.0f, (float)nb, nb);
+    return ix + d[0] * (iy + d[1] * (iz + d[2] * (qu + nb * qv)));
 }
 
 static uint64_t cell_key(const orc_ctx* c, uint32_t lin)
@@ -486,9 +558,17 @@ static uint64_t cell_key(const orc_ctx* c, uint32_t lin)
     return ((uint64_t)c->cfg.scene_id << 32) | (uint64_t)lin;
 }
 
+/* Keys of the points' position cells (no normal bins, no jitter). */
 int orc_cell_keys(const orc_ctx* c, const float* pos, uint32_t P, uint64_t* keys)
 {
-    for (uint32_t i = 0; i < P; ++i) keys[i] = cell_key(c, cell_linear(c, pos + 3u * i));
+    const uint32_t* d = c->cfg.grid_dims;
+    for (uint32_t i = 0; i < P; ++i) {
+        const float* p = pos + 3u * i;
+        uint32_t ix = axis_index(p[0], c->cfg.grid_lo[0], c->inv_cell[0], d[0]);
+        uint32_t iy = axis_index(p[1], c->cfg.grid_lo[1], c->inv_cell[1], d[1]);
+        uint32_t iz = axis_index(p[2], c->cfg.grid_lo[2], c->inv_cell[2], d[2]);
+        keys[i] = cell_key(c, ix + d[0] * (iy + d[1] * iz));
+    }
     return ORC_OK;
 }
 
@@ -566,7 +646,7 @@ static void one_sample(orc_ctx* c, const float* x, const float* nx, uint32_t pid
                        uint32_t frame, float est[3], orc_records* out, uint32_t ri)
 {
     const orc_config* cfg = &c->cfg;
-    uint32_t lin = cell_linear(c, x);
+    uint32_t lin = cell_linear(c, x, nx, pid, k, frame);
     cell* ce = get_or_create_cell(c, lin);
     int use_cell = ce && ce->ready;
     const float* C = use_cell ? ce->C : c->tmpl_C;

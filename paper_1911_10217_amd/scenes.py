@@ -63,6 +63,8 @@ DEFAULT_PARAMS = dict(
     adapt=1,
     temporal=1,
     split_steps=1,
+    normal_bits=0,
+    jitter=0.0,
     scene_id=0,
     seed=SEED_BASE + 1,
     occ_grid_res=0,
