@@ -465,6 +465,10 @@ def main():
     ap.add_argument("--split-steps", type=int, default=1,
                     help="static/dynamic: split-collapse steps per pass (1: the basic algorithm; n > 1: "
                          "repeated until a step changes nothing, at most n times)")
+    ap.add_argument("--normal-bits", type=int, default=0,
+                    help="static/dynamic: 5-D cells with 2^n bins per octahedral normal coordinate")
+    ap.add_argument("--jitter", type=float, default=0.0,
+                    help="static/dynamic: jittered cell lookups (in cells and normal bins, 0..1)")
     ap.add_argument("--sub-frames", type=int, default=1,
                     help="static/dynamic: a step is one frame of this many passes (rlc_frame_sub), each "
                          "with the workload's samples per point")
@@ -505,7 +509,8 @@ def main():
 
     print("[bench] generating the %s workload" % args.workload, file=sys.stderr, flush=True)
     s = scenes.make_static() if args.workload == "static" else scenes.make_dynamic()
-    p = dict(s.params, occ_grid_res=64, split_steps=args.split_steps)
+    p = dict(s.params, occ_grid_res=64, split_steps=args.split_steps, normal_bits=args.normal_bits,
+             jitter=args.jitter)
     spp = int(p["spp"])
     P = s.P
     n_sub = max(1, args.sub_frames)
@@ -642,6 +647,9 @@ def main():
         workload += "; split-collapse repeated until a step changes nothing (at most %d steps)" % args.split_steps
     if n_sub > 1:
         workload += "; a step is one frame of %d sub-frame passes, the cuts adapted after each" % n_sub
+    if args.normal_bits or args.jitter > 0:
+        workload += "; 5-D cells: %d x %d normal bins, jitter %g" % (1 << args.normal_bits, 1 << args.normal_bits,
+                                                                   args.jitter)
     line = {
         "metric": METRIC,
         "value": round(value, 1),

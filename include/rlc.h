@@ -77,6 +77,14 @@ typedef struct rlc_config {
                               the repetition reaches that point: sum(Q^2) falls
                               at every step), 1..RLC_SPLIT_STEPS_MAX */
     uint64_t seed;         /* Philox4x32-10 key */
+    uint32_t normal_bits;  /* section 3's 5-D cells: the normal's octahedral map (Cigolle et
+                              al. 2014) cut into 2^normal_bits bins per coordinate, 0..8
+                              (0: cells over position only).  Cell count, positions times
+                              normal bins, must fit 32 bits (and 2^28 for a dense table) */
+    float jitter;          /* 0..1: each sample looks up its cell from its position moved
+                              by up to jitter/2 cells in the tangent plane (basis of Duff
+                              et al. 2017) and its normal coordinates moved by up to
+                              jitter/2 bins, drawn from Philox tag 4; 0: no jitter */
 } rlc_config;
 
 /* Per-sample records of rlc_sample (device arrays of n = P * spp entries,
@@ -121,7 +129,9 @@ int rlc_set_occluders(rlc_ctx* ctx, const float* d_aabb, uint32_t K);
 /* Section 3: for every sample, locate (or create) the cell of the point,
  * draw a cluster from the cell's cdf C by binary search (cells created in
  * this pass use the initial cut, all clusters equally likely), a light
- * uniformly inside it, and a uniform point on that light. */
+ * uniformly inside it, and a uniform point on that light.  d_nrm (P x 3) is
+ * read only for 5-D cells or jitter (normal_bits > 0 or jitter > 0), and
+ * may be NULL otherwise. */
 int rlc_sample(rlc_ctx* ctx, const float* d_pos, const float* d_nrm, uint32_t P, uint32_t spp,
                uint32_t frame, const rlc_samples* out);
 
@@ -162,7 +172,8 @@ int rlc_frame_sub(rlc_ctx* ctx, const float* d_pos, const float* d_nrm, uint32_t
  * unoccluded over t in (t_lo, 1 - t_lo). */
 int rlc_visible(rlc_ctx* ctx, const float* d_x, const float* d_y, uint32_t n, uint8_t* d_vis);
 
-/* Cell keys of points (d_keys: n entries, device). */
+/* Keys of the points' position cells, (scene_id << 32) | ix + dx (iy + dy iz):
+ * no normal bins, no jitter (d_keys: n entries, device). */
 int rlc_cell_keys(rlc_ctx* ctx, const float* d_pos, uint32_t n, uint64_t* d_keys);
 
 /* Error statistics of an image against a reference, FP64 on the device:

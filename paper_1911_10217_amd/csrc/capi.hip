@@ -53,6 +53,7 @@ struct rlc_ctx {
 
     // derived constants
     float inv_cell[3] = {0, 0, 0};
+    float jit_reach[3] = {0, 0, 0};
     float f_r = 0.0f;
     float fx_scale = 1.0f, fx_inv = 1.0f;
 
@@ -238,7 +239,10 @@ FrameParams frame_params(const rlc_ctx* c) {
         fp.grid_lo[a] = c->cfg.grid_lo[a];
         fp.inv_cell[a] = c->inv_cell[a];
         fp.dims[a] = c->cfg.grid_dims[a];
+        fp.jit_reach[a] = c->jit_reach[a];
     }
+    fp.normal_bits = c->cfg.normal_bits;
+    fp.jitter = c->cfg.jitter;
     fp.scene_id = c->cfg.scene_id;
     fp.seed_lo = (uint32_t)(c->cfg.seed & 0xFFFFFFFFull);
     fp.seed_hi = (uint32_t)(c->cfg.seed >> 32);
@@ -416,12 +420,14 @@ int rlc_create(const rlc_config* cfg, void* stream, rlc_ctx** out) {
               finite_f(k.T) && k.T >= 0.0f && finite_f(k.eps) && k.eps >= 0.0f && k.fx_shift <= 40 &&
               finite_f(k.reward_max) && k.reward_max > 0.0f && finite_f(k.t_lo) && k.t_lo >= 0.0f &&
               k.t_lo < 0.5f && k.reward_mode <= 1 && finite_f(k.albedo) && k.albedo >= 0.0f &&
-              k.occ_grid_res <= 1024 && k.split_steps <= RLC_SPLIT_STEPS_MAX;
+              k.occ_grid_res <= 1024 && k.split_steps <= RLC_SPLIT_STEPS_MAX && k.normal_bits <= 8 &&
+              finite_f(k.jitter) && k.jitter >= 0.0f && k.jitter <= 1.0f;
     for (int a = 0; a < 3; ++a)
         ok = ok && finite_f(k.grid_lo[a]) && finite_f(k.grid_hi[a]) && k.grid_hi[a] > k.grid_lo[a] &&
              k.grid_dims[a] >= 1 && k.grid_dims[a] <= (1u << 20);
     if (!ok) return RLC_EINVAL;
-    uint64_t dense = (uint64_t)k.grid_dims[0] * k.grid_dims[1] * k.grid_dims[2];
+    // cells of the 5-D grid: positions times normal bins (linear index: 32 bits)
+    uint64_t dense = ((uint64_t)k.grid_dims[0] * k.grid_dims[1] * k.grid_dims[2]) << (2u * k.normal_bits);
     if (dense > 0xFFFFFFFFull) return RLC_EINVAL;
     uint64_t capacity;
     if (k.hashed) {
@@ -437,7 +443,10 @@ int rlc_create(const rlc_config* cfg, void* stream, rlc_ctx** out) {
     if (!c) return RLC_ENOMEM;
     c->cfg = k;
     c->stream = (hipStream_t)stream;
-    for (int a = 0; a < 3; ++a) c->inv_cell[a] = (float)k.grid_dims[a] / (k.grid_hi[a] - k.grid_lo[a]);
+    for (int a = 0; a < 3; ++a) {
+        c->inv_cell[a] = (float)k.grid_dims[a] / (k.grid_hi[a] - k.grid_lo[a]);
+        c->jit_reach[a] = k.jitter * ((k.grid_hi[a] - k.grid_lo[a]) / (float)k.grid_dims[a]);
+    }
     c->f_r = (float)((double)k.albedo / 3.14159265358979323846);
     c->fx_scale = ldexpf(1.0f, (int)k.fx_shift);
     c->fx_inv = ldexpf(1.0f, -(int)k.fx_shift);
@@ -672,10 +681,11 @@ int rlc_set_occluders(rlc_ctx* c, const float* d_aabb, uint32_t K) {
 
 int rlc_sample(rlc_ctx* c, const float* d_pos, const float* d_nrm, uint32_t P, uint32_t spp, uint32_t frame,
                const rlc_samples* out) {
-    (void)d_nrm;
     RLC_TRY(check_frame_args(c, d_pos, P, spp));
     if (!out) return fail(c, RLC_EINVAL, "null sample records");
-    RLC_HIP(c, launch_sample(frame_params(c), d_pos, P, spp, frame, *out, c->stream));
+    if (P && !d_nrm && (c->cfg.normal_bits || c->cfg.jitter > 0.0f))
+        return fail(c, RLC_EINVAL, "normals are needed for 5-D cells and jitter");
+    RLC_HIP(c, launch_sample(frame_params(c), d_pos, d_nrm, P, spp, frame, *out, c->stream));
     return RLC_OK;
 }
 

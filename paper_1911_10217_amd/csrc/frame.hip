@@ -99,15 +99,23 @@ __device__ __forceinline__ void point_sums(float (*s_e)[3], const float e[3], ui
     }
 }
 
-__global__ void __launch_bounds__(kBlock) k_sample(FrameParams fp, const float* __restrict__ pos, uint32_t P,
-                                                   uint32_t spp, uint32_t frame, rlc_samples out) {
+__global__ void __launch_bounds__(kBlock) k_sample(FrameParams fp, const float* __restrict__ pos,
+                                                   const float* __restrict__ nrm, uint32_t P, uint32_t spp,
+                                                   uint32_t frame, rlc_samples out) {
     uint32_t b = xcd_block(blockIdx.x, gridDim.x);
     size_t i = (size_t)b * kBlock + threadIdx.x;
     size_t n = (size_t)P * spp;
     if (i >= n) return;
     uint32_t p = (uint32_t)(i / spp), k = (uint32_t)(i % spp);
     Sample sm;
-    draw_sample(fp, pos[3 * (size_t)p], pos[3 * (size_t)p + 1], pos[3 * (size_t)p + 2], p, k, frame, sm);
+    const float x[3] = {pos[3 * (size_t)p], pos[3 * (size_t)p + 1], pos[3 * (size_t)p + 2]};
+    float nn[3] = {0.0f, 0.0f, 0.0f};
+    if (nrm) {
+        nn[0] = nrm[3 * (size_t)p];
+        nn[1] = nrm[3 * (size_t)p + 1];
+        nn[2] = nrm[3 * (size_t)p + 2];
+    }
+    draw_sample(fp, x, nn, p, k, frame, sm);
     if (out.d_key) out.d_key[i] = sm.key;
     if (out.d_cell) out.d_cell[i] = sm.cell;
     if (out.d_ready) out.d_ready[i] = sm.ready;
@@ -210,7 +218,7 @@ __device__ void frame_block(const FrameParams& fp, const float* __restrict__ pos
         float x[3] = {pos[3 * (size_t)p], pos[3 * (size_t)p + 1], pos[3 * (size_t)p + 2]};
         float nn[3] = {nrm[3 * (size_t)p], nrm[3 * (size_t)p + 1], nrm[3 * (size_t)p + 2]};
         Sample sm;
-        draw_sample(fp, x[0], x[1], x[2], p, k, frame, sm);
+        draw_sample(fp, x, nn, p, k, frame, sm);
         float c[3];
         contribution(fp, x, nn, sm.light, sm.y, c);
         e[0] = c[0] * sm.inv_pdf;
@@ -336,11 +344,11 @@ hipError_t zero_radiance_if_needed(float* radiance, uint32_t P, uint32_t spp, hi
 
 }  // namespace
 
-hipError_t launch_sample(const FrameParams& fp, const float* pos, uint32_t P, uint32_t spp, uint32_t frame,
-                         const rlc_samples& out, hipStream_t s) {
+hipError_t launch_sample(const FrameParams& fp, const float* pos, const float* nrm, uint32_t P, uint32_t spp,
+                         uint32_t frame, const rlc_samples& out, hipStream_t s) {
     size_t n = (size_t)P * spp;
     if (n == 0) return hipSuccess;
-    hipLaunchKernelGGL(k_sample, dim3(blocks_for(n)), dim3(kBlock), 0, s, fp, pos, P, spp, frame, out);
+    hipLaunchKernelGGL(k_sample, dim3(blocks_for(n)), dim3(kBlock), 0, s, fp, pos, nrm, P, spp, frame, out);
     return hipGetLastError();
 }
 

@@ -68,6 +68,9 @@ struct FrameParams {
     float grid_lo[3];
     float inv_cell[3];
     uint32_t dims[3];
+    uint32_t normal_bits;       // 2^normal_bits bins per octahedral normal coordinate
+    float jitter;               // lookup jitter, in cells and normal bins
+    float jit_reach[3];         // jitter x cell size, per axis
     uint32_t scene_id;
     uint32_t seed_lo, seed_hi;
     float f_r;
@@ -150,11 +153,77 @@ __device__ __forceinline__ uint32_t axis_cell(float p, float lo, float inv, uint
     return (uint32_t)f;
 }
 
+// Position cell (the first three dimensions of the cell grid).
 __device__ __forceinline__ uint32_t cell_linear(const FrameParams& fp, float x, float y, float z) {
     uint32_t ix = axis_cell(x, fp.grid_lo[0], fp.inv_cell[0], fp.dims[0]);
     uint32_t iy = axis_cell(y, fp.grid_lo[1], fp.inv_cell[1], fp.dims[1]);
     uint32_t iz = axis_cell(z, fp.grid_lo[2], fp.inv_cell[2], fp.dims[2]);
     return ix + fp.dims[0] * (iy + fp.dims[1] * iz);
+}
+
+// Octahedral map of a unit vector onto [0,1]^2 (Cigolle, Donow, Evangelakos,
+// Mara, McGuire, Meyer, JCGT 3(2) 2014): project onto |x|+|y|+|z| = 1, and
+// for z < 0 fold the lower half over the square's diagonals.
+__device__ __forceinline__ void octahedral_uv(const float n[3], float& u, float& v) {
+    const float s = (fabsf(n[0]) + fabsf(n[1])) + fabsf(n[2]);
+    float px = n[0] / s;
+    float py = n[1] / s;
+    if (n[2] < 0.0f) {
+        const float fx = (1.0f - fabsf(py)) * (px >= 0.0f ? 1.0f : -1.0f);
+        const float fy = (1.0f - fabsf(px)) * (py >= 0.0f ? 1.0f : -1.0f);
+        px = fx;
+        py = fy;
+    }
+    u = px * 0.5f + 0.5f;
+    v = py * 0.5f + 0.5f;
+}
+
+// Two unit tangents of the normal n (Duff, Burgess, Christensen, Hery,
+// Kensler, Liani, Villemin, JCGT 6(1) 2017).
+__device__ __forceinline__ void tangent_frame(const float n[3], float t[3], float b[3]) {
+    const float sign = n[2] >= 0.0f ? 1.0f : -1.0f;
+    const float a = -1.0f / (sign + n[2]);
+    const float bb = n[0] * n[1] * a;
+    t[0] = 1.0f + sign * n[0] * n[0] * a;
+    t[1] = sign * bb;
+    t[2] = -sign * n[0];
+    b[0] = bb;
+    b[1] = sign + n[1] * n[1] * a;
+    b[2] = -n[1];
+}
+
+// The sample's cell in the 5-D grid of section 3 (three position and two
+// normal dimensions): the position, moved by up to jitter/2 cells in the
+// tangent plane, and the octahedral normal coordinates, moved by up to
+// jitter/2 bins (Philox tag 4 per sample), quantised by floor.  The linear
+// index is ix + dx (iy + dy (iz + dz (qu + 2^b qv))); without normal bins
+// and jitter it is the position cell.
+__device__ __forceinline__ uint32_t cell_linear5(const FrameParams& fp, const float x[3], const float n[3],
+                                                 uint32_t pid, uint32_t k, uint32_t frame) {
+    if (fp.normal_bits == 0u && !(fp.jitter > 0.0f)) return cell_linear(fp, x[0], x[1], x[2]);
+    const uint32_t nb = 1u << fp.normal_bits;
+    float p[3] = {x[0], x[1], x[2]};
+    float u = 0.0f, v = 0.0f;
+    if (fp.normal_bits) octahedral_uv(n, u, v);
+    if (fp.jitter > 0.0f) {
+        uint32_t w0 = pid, w1 = k, w2 = frame, w3 = (fp.scene_id << 16) | 4u;
+        philox4x32_10(w0, w1, w2, w3, fp.seed_lo, fp.seed_hi);
+        const float xi0 = unit24(w0) - 0.5f, xi1 = unit24(w1) - 0.5f;
+        float t[3], b[3];
+        tangent_frame(n, t, b);
+#pragma unroll
+        for (int a = 0; a < 3; ++a) p[a] = x[a] + fp.jit_reach[a] * (xi0 * t[a] + xi1 * b[a]);
+        if (fp.normal_bits) {
+            u = u + ((unit24(w2) - 0.5f) * fp.jitter) / (float)nb;
+            v = v + ((unit24(w3) - 0.5f) * fp.jitter) / (float)nb;
+        }
+    }
+    const uint32_t ix = axis_cell(p[0], fp.grid_lo[0], fp.inv_cell[0], fp.dims[0]);
+    const uint32_t iy = axis_cell(p[1], fp.grid_lo[1], fp.inv_cell[1], fp.dims[1]);
+    const uint32_t iz = axis_cell(p[2], fp.grid_lo[2], fp.inv_cell[2], fp.dims[2]);
+    const uint32_t qu = axis_cell(u, 0.0f, (float)nb, nb);
+    const uint32_t qv = axis_cell(v, 0.0f, (float)nb, nb);
+    return ix + fp.dims[0] * (iy + fp.dims[1] * (iz + fp.dims[2] * (qu + nb * qv)));
 }
 
 __device__ __forceinline__ unsigned long long mix64(unsigned long long x) {
@@ -220,9 +289,9 @@ struct Sample {
     unsigned long long key;
 };
 
-__device__ __forceinline__ void draw_sample(const FrameParams& fp, float x, float y, float z, uint32_t pid,
+__device__ __forceinline__ void draw_sample(const FrameParams& fp, const float xp[3], const float nrm[3], uint32_t pid,
                                             uint32_t k, uint32_t frame, Sample& o) {
-    uint32_t lin = cell_linear(fp, x, y, z);
+    uint32_t lin = cell_linear5(fp, xp, nrm, pid, k, frame);
     unsigned long long key = ((unsigned long long)fp.scene_id << 32) | (unsigned long long)lin;
     uint32_t cell = find_or_create(fp.cells, key, lin, fp.err);
     uint32_t rdy = (cell != RLC_NONE) ? fp.cells.ready[cell] : 0u;
@@ -450,8 +519,8 @@ hipError_t launch_visible(DevOcc occ, float t_lo, const float* x, const float* y
                           hipStream_t s);
 
 // frame.hip
-hipError_t launch_sample(const FrameParams& fp, const float* pos, uint32_t P, uint32_t spp, uint32_t frame,
-                         const rlc_samples& out, hipStream_t s);
+hipError_t launch_sample(const FrameParams& fp, const float* pos, const float* nrm, uint32_t P, uint32_t spp,
+                         uint32_t frame, const rlc_samples& out, hipStream_t s);
 hipError_t launch_shade(const FrameParams& fp, const float* pos, const float* nrm, uint32_t P, uint32_t spp,
                         const rlc_samples& in, float* radiance, float* contrib, float* reward, hipStream_t s);
 hipError_t launch_learn(const FrameParams& fp, const rlc_samples& in, const float* reward, uint32_t n,

@@ -72,6 +72,8 @@ class rlc_config(ctypes.Structure):
         ("occ_grid_res", ctypes.c_uint32),
         ("split_steps", ctypes.c_uint32),
         ("seed", ctypes.c_uint64),
+        ("normal_bits", ctypes.c_uint32),
+        ("jitter", ctypes.c_float),
     ]
 
 
@@ -209,6 +211,8 @@ def make_config(params: dict) -> rlc_config:
     c.occ_grid_res = int(params.get("occ_grid_res", 0))
     c.split_steps = int(params.get("split_steps", 1))
     c.seed = int(params["seed"])
+    c.normal_bits = int(params.get("normal_bits", 0))
+    c.jitter = float(params.get("jitter", 0.0))
     return c
 
 

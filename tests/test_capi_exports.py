@@ -3,6 +3,9 @@ declares (no compute: these run without a GPU)."""
 import ctypes
 import os
 import re
+import shutil
+import subprocess
+import tempfile
 
 import pytest
 
@@ -41,7 +44,26 @@ def test_config_struct_layout_matches_header():
     body = text[text.index("typedef struct rlc_config"):text.index("} rlc_config;")]
     fields = re.findall(r"^\s*(?:uint32_t|uint64_t|float)\s+(\w+)", body, flags=re.M)
     assert [f[0] for f in rlc.rlc_config._fields_] == fields
-    assert ctypes.sizeof(rlc.rlc_config) == 4 * 26 + 8  # 17 scalars + 3 triples, then the u64 seed
+    # offsets and size as a C compiler lays the header's struct out
+    cc = shutil.which("gcc") or shutil.which("cc")
+    if not cc:
+        pytest.skip("no C compiler")
+    d = tempfile.mkdtemp()
+    try:
+        src = os.path.join(d, "layout.c")
+        with open(src, "w") as f:
+            f.write('#include <stddef.h>\n#include <stdio.h>\n#include "rlc.h"\nint main(void) {\n')
+            f.write('    printf("%zu\\n", sizeof(rlc_config));\n')
+            for n in fields:
+                f.write('    printf("%%zu\\n", offsetof(rlc_config, %s));\n' % n)
+            f.write("    return 0;\n}\n")
+        exe = os.path.join(d, "layout")
+        subprocess.check_call([cc, "-I", os.path.dirname(HEADER), "-o", exe, src])
+        got = [int(v) for v in subprocess.check_output([exe]).split()]
+    finally:
+        shutil.rmtree(d, ignore_errors=True)
+    assert got[0] == ctypes.sizeof(rlc.rlc_config)
+    assert got[1:] == [getattr(rlc.rlc_config, n).offset for n in fields]
 
 
 def test_no_gpu_means_loud_failure():

@@ -77,7 +77,8 @@ def test_batch_frames_out_of_order_and_emission_changes(torch):
     from paper_1911_10217_amd import rlc
     dyn = scenes.make_dynamic(n_points=2048, per_cluster=128, grid=2, n_bricks=256, M=16)
     tiny = scenes.make_tiny(n_points=1024, spp=1)
-    wide = scenes.make_tiny(n_points=512, spp=1, M=128)  # cut of more than 64 clusters
+    # a cut of more than 64 clusters, over 5-D cells with jittered lookups
+    wide = scenes.make_tiny(n_points=512, spp=1, M=128, normal_bits=2, jitter=1.0)
     st = torch.cuda.Stream()
     with torch.cuda.stream(st):
         a = [_ctx(torch, s) for s in (dyn, tiny, wide)]

@@ -212,9 +212,10 @@ def _records_equal(gs, gshade, o):
     assert np.array_equal(reward.cpu().numpy(), o["reward"])
 
 
-@pytest.mark.parametrize("reward_mode", [0, 1])
-def test_split_steps_parity(torch, reward_mode):
-    s = scenes.make_tiny(reward_mode=reward_mode)
+@pytest.mark.parametrize("variant", [dict(reward_mode=0), dict(reward_mode=1),
+                                     dict(normal_bits=2, jitter=1.0, hashed=1, capacity=8192)])
+def test_split_steps_parity(torch, variant):
+    s = scenes.make_tiny(**variant)
     p = s.params
     ctx, orc = _make(torch, s)
     pos, nrm = _t(torch, s.pos), _t(torch, s.nrm)
@@ -257,6 +258,10 @@ def test_split_steps_parity(torch, reward_mode):
     dict(split_steps=65536),
     dict(M=100, spp=4, split_steps=65536),
     dict(T=0.5, split_steps=50),
+    dict(normal_bits=2),
+    dict(jitter=1.0),
+    dict(normal_bits=3, jitter=0.5, hashed=1, capacity=16384),
+    dict(normal_bits=2, jitter=1.0, M=64, spp=8),
 ])
 def test_fused_frames_parity_tiny(torch, variant):
     s = scenes.make_tiny(**variant)
@@ -376,6 +381,9 @@ def test_errors(torch):
         rlc.Context(dict(s.params, M=300))
     with pytest.raises(rlc.RLCError):
         rlc.Context(dict(s.params, split_steps=65537))
+    for bad in (dict(normal_bits=9), dict(jitter=1.5), dict(jitter=-0.1), dict(normal_bits=1, grid_dims=(1024, 1024, 1024), hashed=1, capacity=4096)):
+        with pytest.raises(rlc.RLCError):
+            rlc.Context(dict(s.params, **bad))
     # hash table too small: reported at the next sync, samples still shaded
     small = rlc.Context(dict(s.params, hashed=1, capacity=64))
     small.rlc_build_light_tree(_t(torch, s.tri), _t(torch, s.emit))
