@@ -128,10 +128,11 @@ __device__ __forceinline__ void philox4x32_10(uint32_t& x0, uint32_t& x1, uint32
                                               uint32_t k0, uint32_t k1) {
 #pragma unroll
     for (int r = 0; r < 10; ++r) {
-        uint32_t lo0 = 0xD2511F53u * x0;
-        uint32_t hi0 = __umulhi(0xD2511F53u, x0);
-        uint32_t lo1 = 0xCD9E8D57u * x2;
-        uint32_t hi1 = __umulhi(0xCD9E8D57u, x2);
+        // each 32 x 32 -> 64 product in one instruction (v_mad_u64_u32)
+        const unsigned long long p0 = 0xD2511F53ull * x0;
+        const unsigned long long p1 = 0xCD9E8D57ull * x2;
+        const uint32_t lo0 = (uint32_t)p0, hi0 = (uint32_t)(p0 >> 32);
+        const uint32_t lo1 = (uint32_t)p1, hi1 = (uint32_t)(p1 >> 32);
         uint32_t y0 = hi1 ^ x1 ^ k0;
         uint32_t y2 = hi0 ^ x3 ^ k1;
         x0 = y0;
