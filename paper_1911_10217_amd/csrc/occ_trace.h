@@ -182,10 +182,11 @@ RLC_WALK_INLINE bool cell_blocks(const DevOcc& occ, uint32_t h, uint32_t& last0,
 struct WalkState {
     float t1;
     float tx, ty, tz, dtx, dty, dtz, itx, ity, itz;
-    int rx, ry, rz, sx, sy, sz;  // sx, sy, sz: byte steps of the header offset
+    float rx, ry, rz;            // cells left before the grid's face, per axis (whole numbers)
+    int sx, sy, sz;              // byte steps of the header offset
     uint32_t lin;                // byte offset of the current cell's header (< 2^32 for res <= 1024)
     uint32_t osh;                // 3 x the segment's octant: shift of its radius in a header
-    int it;
+    int it;                      // steps taken (a guard: the counts above already bound them)
     uint32_t last0, last1;
 };
 
@@ -239,9 +240,9 @@ RLC_WALK_INLINE bool walk_begin(const DevOcc& occ, const float o[3], const float
     w.itx = dt[0] > 0.0f ? 1.0f / dt[0] : 0.0f;
     w.ity = dt[1] > 0.0f ? 1.0f / dt[1] : 0.0f;
     w.itz = dt[2] > 0.0f ? 1.0f / dt[2] : 0.0f;
-    w.rx = rem[0];
-    w.ry = rem[1];
-    w.rz = rem[2];
+    w.rx = (float)rem[0];
+    w.ry = (float)rem[1];
+    w.rz = (float)rem[2];
     w.sx = 4 * st[0];
     w.sy = 4 * st[1] * res;
     w.sz = 4 * st[2] * res * res;
@@ -278,6 +279,16 @@ RLC_WALK_INLINE float walk_advance(float t, float fk, float dt) {
     return fk != 0.0f ? t + fk * dt : t;
 }
 
+// min(a, b) of two non-NaN floats: the median of a, b and a value below
+// both (one v_med3_f32 on the device)
+RLC_WALK_INLINE float walk_min(float a, float b) {
+#if defined(__HIP_DEVICE_COMPILE__)
+    return __builtin_amdgcn_fmed3f(a, b, -3.0e38f);
+#else
+    return a < b ? a : b;
+#endif
+}
+
 RLC_WALK_INLINE int walk_mul24(int a, int b) {
 #if defined(__HIP_DEVICE_COMPILE__)
     return __mul24(a, b);
@@ -295,25 +306,25 @@ RLC_WALK_INLINE int walk_step(const DevOcc& occ, WalkState& w, const float o[3],
                                          const float invd[3], float t_lo) {
     const uint32_t h = *(const uint32_t*)((const char*)occ.head + w.lin);
     if (cell_blocks<FAST>(occ, h, w.last0, w.last1, o, d, invd, t_lo)) return 1;
-    const int r = (h & (RLC_OCC_ONE | RLC_OCC_LIST)) ? 0 : (int)((h >> w.osh) & RLC_OCC_SKIP_MAX);
+    const float r = (float)((h & (RLC_OCC_ONE | RLC_OCC_LIST)) ? 0u : ((h >> w.osh) & RLC_OCC_SKIP_MAX));
     // exit parameter of the empty cube on each axis (cut by the grid); the
     // axis that reaches its face first moves on (ties: x, then y).  Value
     // selects and integer masks, not selects between fields, keep the state
     // in registers.
-    const float frx = (float)(r < w.rx ? r : w.rx);
-    const float fry = (float)(r < w.ry ? r : w.ry);
-    const float frz = (float)(r < w.rz ? r : w.rz);
+    const float frx = walk_min(r, w.rx);
+    const float fry = walk_min(r, w.ry);
+    const float frz = walk_min(r, w.rz);
     const float ex = walk_advance<FAST>(w.tx, frx, w.dtx);
     const float ey = walk_advance<FAST>(w.ty, fry, w.dty);
     const float ez = walk_advance<FAST>(w.tz, frz, w.dtz);
     const bool ax = ex <= ey && ex <= ez;
     const bool ay = !ax && ey <= ez;
     const float tm = fminf(ex, fminf(ey, ez));
-    const int rm = ax ? w.rx : (ay ? w.ry : w.rz);
+    const float rm = ax ? w.rx : (ay ? w.ry : w.rz);
     const float cx = walk_crossed<FAST>(tm, w.tx, w.itx, frx);
     const float cy = walk_crossed<FAST>(tm, w.ty, w.ity, fry);
     const float cz = walk_crossed<FAST>(tm, w.tz, w.itz, frz);
-    const float fr1 = (float)(r + 1);
+    const float fr1 = r + 1.0f;
     const float fkx = ax ? fr1 : cx;
     const float fky = ay ? fr1 : cy;
     const float fkz = (ax || ay) ? cz : fr1;
@@ -324,9 +335,9 @@ RLC_WALK_INLINE int walk_step(const DevOcc& occ, WalkState& w, const float o[3],
     w.tx = walk_advance<FAST>(w.tx, fkx, w.dtx);
     w.ty = walk_advance<FAST>(w.ty, fky, w.dty);
     w.tz = walk_advance<FAST>(w.tz, fkz, w.dtz);
-    w.rx -= kx;
-    w.ry -= ky;
-    w.rz -= kz;
+    w.rx -= fkx;
+    w.ry -= fky;
+    w.rz -= fkz;
     return 0;
 }
 
