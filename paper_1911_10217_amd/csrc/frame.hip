@@ -238,7 +238,14 @@ __device__ void frame_block(const FrameParams& fp, const float* __restrict__ pos
     }
     __syncthreads();
     agg_flush(agg, fp);
-    if (pow2_le64(spp)) {
+    if (spp == 1u) {
+        // one sample per point: its estimate is the point's sum (times 1/1)
+        if (valid) {
+            radiance[3 * (size_t)p] = e[0];
+            radiance[3 * (size_t)p + 1] = e[1];
+            radiance[3 * (size_t)p + 2] = e[2];
+        }
+    } else if (pow2_le64(spp)) {
         point_sums(s_e, e, spp, valid, k, p, radiance);
     } else if (valid) {
         const float inv_spp = 1.0f / (float)spp;
