@@ -636,9 +636,10 @@ int rlc_set_occluders(rlc_ctx* c, const float* d_aabb, uint32_t K) {
         }
         occ_grid_bounds(o, lo, hi, o.res);
         const uint32_t ncell = o.res * o.res * o.res;
-        uint32_t *counts = nullptr, *start = nullptr, *cursor = nullptr;
+        uint32_t *counts = nullptr, *start = nullptr, *cursor = nullptr, *scan_tmp = nullptr;
         r = dalloc(c, &counts, ncell);
         if (r == RLC_OK) r = dalloc(c, &start, (size_t)ncell + 1);
+        if (r == RLC_OK) r = dalloc(c, &scan_tmp, scan_scratch_entries((size_t)ncell + 1) + 1);
         if (r == RLC_OK) r = dalloc(c, &cursor, ncell);
         if (r == RLC_OK) r = dalloc(c, &c->occ_head, ncell);
         hipError_t e = hipSuccess;
@@ -651,7 +652,7 @@ int rlc_set_occluders(rlc_ctx* c, const float* d_aabb, uint32_t K) {
             step(launch_fill_u32(cursor, 0u, ncell, c->stream));
             step(launch_occ_count(c->box, K, o, counts, c->stream));
             step(launch_occ_sizes(counts, ncell, start, c->stream));
-            step(launch_exclusive_scan(start, ncell + 1, c->stream));
+            step(launch_exclusive_scan(start, ncell + 1, scan_tmp, c->stream));
             step(hipMemcpyAsync(&total, start + ncell, sizeof(uint32_t), hipMemcpyDeviceToHost, c->stream));
             step(hipStreamSynchronize(c->stream));
         }
@@ -671,6 +672,7 @@ int rlc_set_occluders(rlc_ctx* c, const float* d_aabb, uint32_t K) {
         dfree(counts);
         dfree(start);
         dfree(cursor);
+        dfree(scan_tmp);
         if (r != RLC_OK) return r;
         if (e != hipSuccess) return fail(c, RLC_EHIP, "occluder grid: %s", hipGetErrorString(e));
     }

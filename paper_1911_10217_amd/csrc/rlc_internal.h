@@ -491,8 +491,11 @@ hipError_t launch_morton(const float* sums, const float* bbox, uint32_t N, uint3
                          hipStream_t s);
 hipError_t radix_sort_pairs(uint32_t* keys, uint32_t* vals, uint32_t* keys_tmp, uint32_t* vals_tmp,
                             uint32_t* hist, uint32_t N, int bits, hipStream_t s);
+// Entries of the hist buffer radix_sort_pairs needs (histogram and scan scratch).
 size_t radix_sort_hist_entries(uint32_t N);
-hipError_t launch_exclusive_scan(uint32_t* data, uint32_t n, hipStream_t s);
+// Exclusive scan in place; scratch: scan_scratch_entries(n) words.
+size_t scan_scratch_entries(size_t n);
+hipError_t launch_exclusive_scan(uint32_t* data, uint32_t n, uint32_t* scratch, hipStream_t s);
 hipError_t launch_gather_records(const float* tri, const float* emit, const uint32_t* perm, uint32_t N,
                                  float4* rec, hipStream_t s);
 hipError_t launch_scatter_emission(const float* emit, const uint32_t* perm, uint32_t N, float4* rec,

@@ -156,28 +156,86 @@ __global__ void __launch_bounds__(kBlock) k_rs_scatter(const uint32_t* __restric
     }
 }
 
-// Exclusive scan of n u32 in one workgroup of 1024 threads.
-__global__ void __launch_bounds__(1024) k_scan(uint32_t* data, uint32_t n) {
-    __shared__ uint32_t s[1024];
-    const uint32_t t = threadIdx.x;
-    const uint32_t chunk = (n + 1023u) / 1024u;
-    const size_t lo = (size_t)t * chunk;
-    const size_t hi = lo + chunk < n ? lo + chunk : n;
-    uint32_t sum = 0;
-    for (size_t i = lo; i < hi; ++i) sum += data[i];
-    s[t] = sum;
-    __syncthreads();
-    for (uint32_t off = 1; off < 1024u; off <<= 1) {
-        uint32_t v = t >= off ? s[t - off] : 0u;
-        __syncthreads();
-        s[t] += v;
-        __syncthreads();
+// Exclusive scan of n u32, in tiles of kScanTile = 1024 entries (256
+// threads x 4, each thread's four loaded as one uint4 when aligned): the
+// tiles' sums, their exclusive scan (the same three steps, recursively),
+// then every tile's scan from its offset.  All loads are coalesced.
+constexpr int kScanThreads = 256;
+constexpr int kScanTile = 4 * kScanThreads;
+
+// Inclusive scan of one value per thread over the block; returns the
+// block's total in *total.
+__device__ __forceinline__ uint32_t block_inclusive_scan(uint32_t v, uint32_t* s_wave, uint32_t* total) {
+    const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+#pragma unroll
+    for (int off = 1; off < 64; off <<= 1) {
+        const uint32_t o = __shfl_up(v, off, 64);
+        if (lane >= off) v += o;
     }
-    uint32_t run = s[t] - sum;
-    for (size_t i = lo; i < hi; ++i) {
-        uint32_t v = data[i];
-        data[i] = run;
-        run += v;
+    if (lane == 63) s_wave[wave] = v;
+    __syncthreads();
+    uint32_t before = 0, all = 0;
+#pragma unroll
+    for (int w = 0; w < kScanThreads / 64; ++w) {
+        const uint32_t t = s_wave[w];
+        before += w < wave ? t : 0u;
+        all += t;
+    }
+    *total = all;
+    return v + before;
+}
+
+// Four consecutive entries from i0 (a multiple of 4) as one uint4 when they
+// are all in range and 16-byte aligned (a recursive level's scratch may not
+// be), else one by one.
+__device__ __forceinline__ bool vec4_ok(const uint32_t* data, size_t n, size_t i0) {
+    return i0 + 3 < n && (reinterpret_cast<uintptr_t>(data + i0) & 15u) == 0;
+}
+
+__device__ __forceinline__ void load_tile(const uint32_t* data, size_t n, size_t i0, uint32_t x[4]) {
+    if (vec4_ok(data, n, i0)) {
+        const uint4 q = *reinterpret_cast<const uint4*>(data + i0);
+        x[0] = q.x, x[1] = q.y, x[2] = q.z, x[3] = q.w;
+    } else {
+#pragma unroll
+        for (int j = 0; j < 4; ++j) x[j] = i0 + j < n ? data[i0 + j] : 0u;
+    }
+}
+
+__global__ void __launch_bounds__(kScanThreads) k_scan_sums(const uint32_t* __restrict__ data, uint32_t n,
+                                                            uint32_t* __restrict__ sums) {
+    __shared__ uint32_t s_wave[kScanThreads / 64];
+    const size_t i0 = (size_t)blockIdx.x * kScanTile + 4u * threadIdx.x;
+    uint32_t x[4];
+    load_tile(data, n, i0, x);
+    uint32_t total;
+    block_inclusive_scan((x[0] + x[1]) + (x[2] + x[3]), s_wave, &total);
+    if (threadIdx.x == 0) sums[blockIdx.x] = total;
+}
+
+// offsets: exclusive scan of the tiles' sums, or null for a single tile.
+__global__ void __launch_bounds__(kScanThreads) k_scan_tiles(uint32_t* data, uint32_t n,
+                                                             const uint32_t* __restrict__ offsets) {
+    __shared__ uint32_t s_wave[kScanThreads / 64];
+    const size_t i0 = (size_t)blockIdx.x * kScanTile + 4u * threadIdx.x;
+    uint32_t x[4];
+    load_tile(data, n, i0, x);
+    const uint32_t mine = (x[0] + x[1]) + (x[2] + x[3]);
+    uint32_t total;
+    uint32_t run = block_inclusive_scan(mine, s_wave, &total) - mine;
+    if (offsets) run += offsets[blockIdx.x];
+    uint32_t y[4];
+#pragma unroll
+    for (int j = 0; j < 4; ++j) {
+        y[j] = run;
+        run += x[j];
+    }
+    if (vec4_ok(data, n, i0)) {
+        *reinterpret_cast<uint4*>(data + i0) = make_uint4(y[0], y[1], y[2], y[3]);
+    } else {
+#pragma unroll
+        for (int j = 0; j < 4; ++j)
+            if (i0 + j < n) data[i0 + j] = y[j];
     }
 }
 
@@ -352,7 +410,20 @@ hipError_t launch_morton(const float* sums, const float* bbox, uint32_t N, uint3
     return hipGetLastError();
 }
 
-size_t radix_sort_hist_entries(uint32_t N) { return (size_t)kRadix * blocks_for(N, kTile); }
+size_t scan_scratch_entries(size_t n) {
+    size_t total = 0;
+    while (n > (size_t)kScanTile) {
+        n = (n + kScanTile - 1) / kScanTile;
+        total += n;
+    }
+    return total;
+}
+
+// The histogram, then the scratch of its scan.
+size_t radix_sort_hist_entries(uint32_t N) {
+    const size_t h = (size_t)kRadix * blocks_for(N, kTile);
+    return h + scan_scratch_entries(h);
+}
 
 hipError_t radix_sort_pairs(uint32_t* keys, uint32_t* vals, uint32_t* keys_tmp, uint32_t* vals_tmp,
                             uint32_t* hist, uint32_t N, int bits, hipStream_t s) {
@@ -365,7 +436,7 @@ hipError_t radix_sort_pairs(uint32_t* keys, uint32_t* vals, uint32_t* keys_tmp, 
     for (int p = 0; p < passes; ++p) {
         int shift = 8 * p;
         hipLaunchKernelGGL(k_rs_hist, dim3(ntiles), dim3(kBlock), 0, s, kin, N, shift, ntiles, hist);
-        hipLaunchKernelGGL(k_scan, dim3(1), dim3(1024), 0, s, hist, (uint32_t)(ntiles * kRadix));
+        (void)launch_exclusive_scan(hist, (uint32_t)(ntiles * kRadix), hist + (size_t)ntiles * kRadix, s);
         hipLaunchKernelGGL(k_rs_scatter, dim3(ntiles), dim3(kBlock), 0, s, kin, vin, N, shift, ntiles, hist, kout,
                            vout);
         uint32_t* t = kin;
@@ -383,8 +454,17 @@ hipError_t radix_sort_pairs(uint32_t* keys, uint32_t* vals, uint32_t* keys_tmp, 
     return e;
 }
 
-hipError_t launch_exclusive_scan(uint32_t* data, uint32_t n, hipStream_t s) {
-    hipLaunchKernelGGL(k_scan, dim3(1), dim3(1024), 0, s, data, n);
+hipError_t launch_exclusive_scan(uint32_t* data, uint32_t n, uint32_t* scratch, hipStream_t s) {
+    if (n == 0) return hipSuccess;
+    const uint32_t tiles = (uint32_t)((n + kScanTile - 1) / kScanTile);
+    if (tiles == 1) {
+        hipLaunchKernelGGL(k_scan_tiles, dim3(1), dim3(kScanThreads), 0, s, data, n, (const uint32_t*)nullptr);
+        return hipGetLastError();
+    }
+    hipLaunchKernelGGL(k_scan_sums, dim3(tiles), dim3(kScanThreads), 0, s, data, n, scratch);
+    hipError_t e = launch_exclusive_scan(scratch, tiles, scratch + tiles, s);
+    if (e != hipSuccess) return e;
+    hipLaunchKernelGGL(k_scan_tiles, dim3(tiles), dim3(kScanThreads), 0, s, data, n, scratch);
     return hipGetLastError();
 }
 

@@ -159,7 +159,7 @@ def test_visibility_parity_grid(torch, static_scene):
     assert np.array_equal(vis, ref), int((vis != ref).sum())
 
 
-@pytest.mark.parametrize("res", [16, 64, 100])
+@pytest.mark.parametrize("res", [16, 64, 100, 128])
 def test_visibility_parity_sparse_grid(torch, res):
     """Few small boxes in a fine grid: most cells are empty and the walk
     leaves whole empty cubes at a time.  Segments run across the room and
