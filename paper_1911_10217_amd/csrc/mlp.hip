@@ -499,14 +499,22 @@ __global__ void __launch_bounds__(kBlock) k_mlp_reduce(const float* __restrict__
                                                        float beta1, float beta2, float eps, float c1, float c2,
                                                        float* __restrict__ loss) {
     __shared__ float s_part[kRedGroups][kRedCols];
+    __shared__ float s_stage[kBlock];
     __shared__ float s_inv;
     const uint32_t col = threadIdx.x % kRedCols, grp = threadIdx.x / kRedCols;
     const uint32_t p = blockIdx.x * kRedCols + col;
     float acc = 0.0f;
     if (p < kNP) {
-        // rows grp, grp + 8, ... added in that order; the loads of a run of 8
-        // rows are issued before their additions
+        // rows grp, grp + 8, ... added in that order; the loads of a run of
+        // 32 (then 8) rows are issued before their additions
         uint32_t b = grp;
+        for (; b + 31u * kRedGroups < nblocks; b += 32u * kRedGroups) {
+            float v[32];
+#pragma unroll
+            for (uint32_t j = 0; j < 32u; ++j) v[j] = partial[(size_t)(b + j * kRedGroups) * kNP + p];
+#pragma unroll
+            for (uint32_t j = 0; j < 32u; ++j) acc += v[j];
+        }
         for (; b + 7u * kRedGroups < nblocks; b += 8u * kRedGroups) {
             float v[8];
 #pragma unroll
@@ -517,16 +525,30 @@ __global__ void __launch_bounds__(kBlock) k_mlp_reduce(const float* __restrict__
         for (; b < nblocks; b += kRedGroups) acc += partial[(size_t)b * kNP + p];
     }
     s_part[grp][col] = acc;
+    // the blocks' weight sums (and, in block 0, loss sums) added in block
+    // order by one thread, after every thread has staged 256 of them in LDS
+    float sw = 0.0f, sl = 0.0f;
+    const bool want_loss = blockIdx.x == 0 && loss;
+    for (uint32_t base = 0; base < nblocks; base += kBlock) {
+        const uint32_t i = base + threadIdx.x;
+        const uint32_t cnt = nblocks - base < kBlock ? nblocks - base : kBlock;
+        s_stage[threadIdx.x] = i < nblocks ? part_w[i] : 0.0f;
+        __syncthreads();
+        if (threadIdx.x == 0)
+            for (uint32_t j = 0; j < cnt; ++j) sw += s_stage[j];
+        __syncthreads();
+        if (want_loss) {
+            s_stage[threadIdx.x] = i < nblocks ? part_loss[i] : 0.0f;
+            __syncthreads();
+            if (threadIdx.x == 0)
+                for (uint32_t j = 0; j < cnt; ++j) sl += s_stage[j];
+            __syncthreads();
+        }
+    }
     if (threadIdx.x == 0) {
-        float sw = 0.0f;
-        for (uint32_t b = 0; b < nblocks; ++b) sw += part_w[b];
         const float inv = sw > 0.0f ? 1.0f / sw : 0.0f;
         s_inv = inv;
-        if (blockIdx.x == 0 && loss) {
-            float sl = 0.0f;
-            for (uint32_t b = 0; b < nblocks; ++b) sl += part_loss[b];
-            *loss = sl * inv;
-        }
+        if (want_loss) *loss = sl * inv;
     }
     __syncthreads();
     if (grp != 0 || p >= kNP) return;
