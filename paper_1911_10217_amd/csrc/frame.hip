@@ -280,7 +280,7 @@ __global__ void __launch_bounds__(kBlock, 8) k_frame(FrameParams fp, const float
 // Batched pass over several scenes: persistent blocks take work items of
 // `rounds` x 256 samples, either from a counter (dynamic) or as contiguous
 // ranges assigned per XCD (static).  Item -> scene by the scenes' first items.
-__global__ void __launch_bounds__(kBlock) k_batch_frame(const BatchScene* __restrict__ scenes, uint32_t n_scenes,
+__global__ void __launch_bounds__(kBlock, 7) k_batch_frame(const BatchScene* __restrict__ scenes, uint32_t n_scenes,
                                                         uint32_t total_items, uint32_t rounds, uint32_t dynamic,
                                                         uint32_t* __restrict__ counter,
                                                         const uint32_t* __restrict__ frame_ptr) {
