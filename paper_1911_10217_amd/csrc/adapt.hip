@@ -77,6 +77,14 @@ __device__ __forceinline__ float lane_value(float v, uint32_t s) {
     return __int_as_float(__builtin_amdgcn_readlane(__float_as_int(v), (int)s));
 }
 
+// Orders one wavefront's LDS accesses (the cell's scratch is the wave's
+// own, so no other wave takes part).
+__device__ __forceinline__ void wave_sync() {
+    __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+    __builtin_amdgcn_wave_barrier();
+    __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+}
+
 // The floor eps S / Meff of Eq. 2.  With eps > 0 it never underflows to 0
 // (Q decays towards subnormals in cells whose rewards stay 0): at least the
 // smallest normal float, so every cluster keeps p > 0.
@@ -109,7 +117,7 @@ __device__ __forceinline__ void load_cell(const AdaptParams& ap, uint32_t c, Cel
     in.ready = cells.ready[c];
 #pragma unroll
     for (int j = 0; j < PER; ++j) {
-        const uint32_t s = threadIdx.x + kWave * j;
+        const uint32_t s = (threadIdx.x & (kWave - 1u)) + kWave * j;
         const bool ok = s < Meff;
         const size_t i = base + (ok ? s : 0u);
         const uint32_t st = ok ? s : 0u;
@@ -123,19 +131,21 @@ __device__ __forceinline__ void load_cell(const AdaptParams& ap, uint32_t c, Cel
     }
 }
 
-// End of pass for the cell loaded into in, by one wavefront (= the block);
-// PER slots per lane (cuts of up to 64 PER clusters).
+// End of pass for the cell loaded into in, by one wavefront, in the wave's
+// own LDS scratch L; PER slots per lane (cuts of up to 64 PER clusters).
+// The front: Eq. 1 and split-collapse, leaving the new cut and Q in L.
+// Returns false (and does nothing) when the cell had no samples this pass.
 template <int PER>
-__device__ void adapt_cell(const AdaptParams& ap, const CellIn<PER>& in, const AdaptLds& L) {
+__device__ bool adapt_front(const AdaptParams& ap, const CellIn<PER>& in, const AdaptLds& L) {
     const DevCells& cells = ap.cells;
-    const uint32_t lane = threadIdx.x;
+    const uint32_t lane = threadIdx.x & (kWave - 1u);
     const uint32_t Meff = ap.tmpl.Meff;
     const uint32_t c = in.c;
     const size_t base = (size_t)c * cells.M;
     bool any = false;
 #pragma unroll
     for (int j = 0; j < PER; ++j) any |= in.cnt[j] != 0u;
-    if (!__any(any)) return;  // no samples this pass: the cell is left as it is
+    if (!__any(any)) return false;  // no samples this pass: the cell is left as it is
 
     const bool fresh = in.ready == 0u || ap.temporal == 0u;
     // the cut and Q (a fresh cell starts from the initial cut, Q = 0)
@@ -161,7 +171,7 @@ __device__ void adapt_cell(const AdaptParams& ap, const CellIn<PER>& in, const A
             L.Q[s] = q;
         }
     }
-    __syncthreads();
+    wave_sync();
 
     // ---- split-collapse: steps until one changes nothing, at most
     // max(split_steps, 1) of them (one step: the basic algorithm) ----
@@ -271,7 +281,7 @@ __device__ void adapt_cell(const AdaptParams& ap, const CellIn<PER>& in, const A
                     }
                 }
             }
-            __syncthreads();
+            wave_sync();
 #pragma unroll
             for (int j = 0; j < PER; ++j) {
                 uint32_t s = lane + kWave * j;
@@ -282,13 +292,43 @@ __device__ void adapt_cell(const AdaptParams& ap, const CellIn<PER>& in, const A
                     if (more) L.par[s] = L.npar[s];
                 }
             }
-            __syncthreads();
+            wave_sync();
         }
     }
+    wave_sync();
+    return true;
+}
 
+// Q~ and Eq. 2 of one cell by the calling lane alone, from L.Q: sums taken
+// left to right.
+__device__ __forceinline__ void eq2_one_lane(const AdaptParams& ap, const AdaptLds& L, uint32_t Meff) {
+    float S = 0.0f;
+    for (uint32_t s = 0; s < Meff; ++s) S = S + L.Q[s];
+    float acc = 0.0f;
+    if (S == 0.0f) {
+        for (uint32_t s = 0; s < Meff; ++s) {
+            L.Qt[s] = 1.0f;
+            acc = s ? acc + 1.0f : 1.0f;
+            L.C[s] = acc;
+        }
+    } else {
+        const float fl = eq2_floor(ap, S, Meff);
+        for (uint32_t s = 0; s < Meff; ++s) {
+            float qt = L.Q[s] + fl;
+            L.Qt[s] = qt;
+            acc = s ? acc + qt : qt;
+            L.C[s] = acc;
+        }
+    }
+}
+
+// Q~ and Eq. 2 by lane 0 of the wave: sums taken left to right.
+template <int PER>
+__device__ void adapt_eq2(const AdaptParams& ap, const AdaptLds& L) {
+    const uint32_t lane = threadIdx.x & (kWave - 1u);
+    const uint32_t Meff = ap.tmpl.Meff;
     float myq = 0.0f;
     if constexpr (PER == 1) myq = lane < Meff ? L.Q[lane] : 0.0f;
-    // ---- Q~ and Eq. 2: sums taken left to right ----
     if (lane == 0) {
         if constexpr (PER == 1) {
             // every slot's Q sits in its lane's register; lane 0 reads them in
@@ -312,27 +352,20 @@ __device__ void adapt_cell(const AdaptParams& ap, const CellIn<PER>& in, const A
                 }
             }
         } else {
-            float S = 0.0f;
-            for (uint32_t s = 0; s < Meff; ++s) S = S + L.Q[s];
-            float acc = 0.0f;
-            if (S == 0.0f) {
-                for (uint32_t s = 0; s < Meff; ++s) {
-                    L.Qt[s] = 1.0f;
-                    acc = s ? acc + 1.0f : 1.0f;
-                    L.C[s] = acc;
-                }
-            } else {
-                const float fl = eq2_floor(ap, S, Meff);
-                for (uint32_t s = 0; s < Meff; ++s) {
-                    float qt = L.Q[s] + fl;
-                    L.Qt[s] = qt;
-                    acc = s ? acc + qt : qt;
-                    L.C[s] = acc;
-                }
-            }
+            eq2_one_lane(ap, L, Meff);
         }
     }
-    __syncthreads();
+    wave_sync();
+}
+
+// The back: the cell's new tables from L to the cell table, statistics
+// cleared, the cell marked ready.
+template <int PER>
+__device__ void adapt_back(const AdaptParams& ap, uint32_t c, const AdaptLds& L) {
+    const DevCells& cells = ap.cells;
+    const uint32_t lane = threadIdx.x & (kWave - 1u);
+    const uint32_t Meff = ap.tmpl.Meff;
+    const size_t base = (size_t)c * cells.M;
 #pragma unroll
     for (int j = 0; j < PER; ++j) {
         uint32_t s = lane + kWave * j;
@@ -347,7 +380,15 @@ __device__ void adapt_cell(const AdaptParams& ap, const CellIn<PER>& in, const A
         }
     }
     if (lane == 0) cells.ready[c] = 1u;
-    __syncthreads();
+    wave_sync();
+}
+
+// The whole end of pass of one cell by one wavefront.
+template <int PER>
+__device__ void adapt_cell(const AdaptParams& ap, const CellIn<PER>& in, const AdaptLds& L) {
+    if (!adapt_front<PER>(ap, in, L)) return;
+    adapt_eq2<PER>(ap, L);
+    adapt_back<PER>(ap, in.c, L);
 }
 
 // The cells of the live list from li on, with a stride of the grid: each
@@ -393,6 +434,43 @@ __global__ void __launch_bounds__(kWave, PER == 1 ? 8 : 4) k_batch_adapt(const A
     }
 }
 
+// Cuts of up to 64 clusters, 16 cells per block: one wavefront per cell
+// for Eq. 1, split-collapse and the write-back, and, between two block
+// barriers, one lane per cell for the serial sums of Eq. 2, so those sums
+// are issued once for the block's 16 cells.  Every wave runs the same
+// number of rounds, so all of them reach both barriers of every round.
+constexpr uint32_t kCellWaves = 16;
+// words of one wave's scratch, padded by one so that the serial phase's 16
+// lanes, each in its own cell's scratch, read different LDS banks
+constexpr uint32_t kCellRegion = kLdsArrays * kWave + 1u;
+
+__global__ void __launch_bounds__(kCellWaves * kWave, 8) k_adapt16(AdaptParams ap) {
+    extern __shared__ uint32_t lds[];
+    __shared__ uint32_t s_active[kCellWaves];
+    const uint32_t wave = threadIdx.x / kWave, lane = threadIdx.x % kWave;
+    const AdaptLds L = lds_view(lds + wave * kCellRegion, kWave);
+    const uint32_t n_live = *ap.cells.n_live;
+    const uint32_t per_round = gridDim.x * kCellWaves;
+    const uint32_t rounds = (n_live + per_round - 1u) / per_round;
+    for (uint32_t rd = 0; rd < rounds; ++rd) {
+        const uint32_t li = rd * per_round + blockIdx.x * kCellWaves + wave;
+        bool active = false;
+        uint32_t c = 0;
+        if (li < n_live) {
+            CellIn<1> in;
+            load_cell<1>(ap, ap.cells.live[li], in);
+            c = in.c;
+            active = adapt_front<1>(ap, in, L);
+        }
+        if (lane == 0) s_active[wave] = active ? 1u : 0u;
+        __syncthreads();
+        if (wave == 0 && lane < kCellWaves && s_active[lane])
+            eq2_one_lane(ap, lds_view(lds + lane * kCellRegion, kWave), ap.tmpl.Meff);
+        __syncthreads();
+        if (active) adapt_back<1>(ap, c, L);
+    }
+}
+
 __global__ void k_gather_cells(DevCells c, uint32_t Meff, const uint32_t* __restrict__ slots, uint32_t n,
                                uint32_t* node, uint32_t* end, float* Q, float* Qt, float* C,
                                unsigned long long* sum, uint32_t* cnt) {
@@ -424,7 +502,7 @@ hipError_t launch_adapt(const AdaptParams& ap, hipStream_t s) {
     // enough waves to fill the chip (8 per SIMD); each walks the list of
     // created cells with a stride of the grid size
     if (ap.tmpl.Meff <= (uint32_t)kWave)
-        hipLaunchKernelGGL(k_adapt<1>, dim3(8192), dim3(kWave), kLdsArrays * kWave * 4, s, ap);
+        hipLaunchKernelGGL(k_adapt16, dim3(512), dim3(kCellWaves * kWave), kCellWaves * kCellRegion * 4, s, ap);
     else
         hipLaunchKernelGGL(k_adapt<kMaxPerLane>, dim3(8192), dim3(kWave), kLdsArrays * RLC_MMAX * 4, s, ap);
     return hipGetLastError();
