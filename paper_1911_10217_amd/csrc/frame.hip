@@ -197,6 +197,27 @@ __global__ void __launch_bounds__(kBlock) k_learn(FrameParams fp, rlc_samples in
     agg_flush(agg, fp);
 }
 
+// The grid's pointers and t_lo for the shadow ray, as values defined just
+// before it (an empty asm statement hides where they came from).  Without
+// this the compiler keeps them, with the pass's other uniform values, in
+// VGPR lanes from the kernel's start and reads each dword back, one VALU
+// instruction apiece, at every step of the walk.  The casts keep the loads
+// in the global address space.
+__device__ __forceinline__ DevOcc walk_operands(const FrameParams& fp, float& t_lo) {
+    typedef __attribute__((address_space(1))) const uint32_t* GU32;
+    typedef __attribute__((address_space(1))) const float4* GF4;
+    DevOcc occ = fp.occ;
+    GU32 head = (GU32)occ.head;
+    GU32 ref = (GU32)occ.ref;
+    GF4 box = (GF4)occ.box;
+    t_lo = fp.t_lo;
+    asm volatile("" : "+s"(head), "+s"(ref), "+s"(box), "+s"(t_lo));
+    occ.head = (const uint32_t*)head;
+    occ.ref = (const uint32_t*)ref;
+    occ.box = (const float4*)box;
+    return occ;
+}
+
 // One block's samples i0 + threadIdx.x of a pass: sample, shade and learn
 // (section 3).  Sample i belongs to point q = i / spp, sample k = i % spp;
 // with a point order `perm` the point is perm[q] (its random numbers and
@@ -219,8 +240,12 @@ __device__ void frame_block(const FrameParams& fp, const float* __restrict__ pos
         float nn[3] = {nrm[3 * (size_t)p], nrm[3 * (size_t)p + 1], nrm[3 * (size_t)p + 2]};
         Sample sm;
         draw_sample(fp, x, nn, p, k, frame, sm);
-        float c[3];
-        contribution(fp, x, nn, sm.light, sm.y, c);
+        float c[3], d[3];
+        if (contribution_unshadowed(fp, x, nn, sm.light, sm.y, c, d)) {
+            float t_lo;
+            const DevOcc occ = walk_operands(fp, t_lo);
+            if (segment_blocked(occ, x, d, t_lo)) c[0] = c[1] = c[2] = 0.0f;
+        }
         e[0] = c[0] * sm.inv_pdf;
         e[1] = c[1] * sm.inv_pdf;
         e[2] = c[2] * sm.inv_pdf;
