@@ -500,9 +500,14 @@ hipError_t launch_batch_adapt(const AdaptParams* aps, uint32_t n_scenes, uint32_
 
 hipError_t launch_adapt(const AdaptParams& ap, hipStream_t s) {
     // enough waves to fill the chip (8 per SIMD); each walks the list of
-    // created cells with a stride of the grid size
-    if (ap.tmpl.Meff <= (uint32_t)kWave)
+    // created cells with a stride of the grid size.  With repeated
+    // split-collapse steps the cells of a 16-cell block take different
+    // numbers of steps and the block waits for its slowest, so those passes
+    // take the one-wave kernel.
+    if (ap.tmpl.Meff <= (uint32_t)kWave && ap.split_steps <= 1u)
         hipLaunchKernelGGL(k_adapt16, dim3(512), dim3(kCellWaves * kWave), kCellWaves * kCellRegion * 4, s, ap);
+    else if (ap.tmpl.Meff <= (uint32_t)kWave)
+        hipLaunchKernelGGL(k_adapt<1>, dim3(8192), dim3(kWave), kLdsArrays * kWave * 4, s, ap);
     else
         hipLaunchKernelGGL(k_adapt<kMaxPerLane>, dim3(8192), dim3(kWave), kLdsArrays * RLC_MMAX * 4, s, ap);
     return hipGetLastError();
