@@ -290,6 +290,21 @@ __global__ void __launch_bounds__(kBlock) k_accum(float* __restrict__ acc, const
     acc[i] = finish ? v * scale : v;
 }
 
+// Blocks dealt to the 8 XCDs in chunks of kXcdChunk neighbouring blocks,
+// round robin: every XCD gets chunks from all over the image, so the cost of
+// its walks follows the image's average, while the blocks it runs at a time
+// still cover a few compact regions that share its L2.  The last,
+// incomplete round is split into one contiguous range per XCD.
+constexpr uint32_t kXcdChunk = 32;
+
+__device__ __forceinline__ uint32_t xcd_chunk_block(uint32_t b, uint32_t nb) {
+    const uint32_t round = 8u * kXcdChunk;
+    const uint32_t full = (nb / round) * round;
+    if (b >= full) return full + xcd_block(b - full, nb - full);
+    const uint32_t x = b & 7u, j = b >> 3;
+    return ((j / kXcdChunk) * 8u + x) * kXcdChunk + j % kXcdChunk;
+}
+
 // Fused pass: one lane per sample.
 __global__ void __launch_bounds__(kBlock, 8) k_frame(FrameParams fp, const float* __restrict__ pos,
                                                   const float* __restrict__ nrm, uint32_t P, uint32_t spp,
@@ -298,7 +313,7 @@ __global__ void __launch_bounds__(kBlock, 8) k_frame(FrameParams fp, const float
     __shared__ float s_e[kBlock][3];
     agg_clear(agg);
     __syncthreads();
-    const uint32_t b = xcd_block(blockIdx.x, gridDim.x);
+    const uint32_t b = xcd_chunk_block(blockIdx.x, gridDim.x);
     frame_block(fp, pos, nrm, nullptr, P, spp, frame, radiance, (size_t)b * kBlock, agg, s_e);
 }
 
