@@ -218,15 +218,41 @@ __device__ __forceinline__ DevOcc walk_operands(const FrameParams& fp, float& t_
     return occ;
 }
 
+// The pass's parameters are read through a pointer that an empty asm
+// statement defines anew at the kernel's start: each field is then loaded
+// with s_load where it is used.  Read from the by-value argument, the
+// compiler keeps the fields it needs, dozens of them, in VGPR lanes from the
+// kernel's start and reads them back one v_readlane (a VALU instruction) per
+// dword.  Taking the address of the by-value argument would make a private
+// copy, so k_frame reads its first argument where the kernarg segment holds
+// it, at offset 0.  The parameters are read-only during a pass, so the
+// constant address space is right for them.
+typedef __attribute__((address_space(4))) const FrameParams* ConstFrameParams;
+
+// A 64-bit value that every lane holds, as the first lane's.  The builtin
+// returns int: each half is taken as uint32_t before it is widened, so the
+// low half is not sign-extended into the high one.
+__device__ __forceinline__ uint64_t uniform_u64(uint64_t v) {
+    const uint32_t lo = (uint32_t)__builtin_amdgcn_readfirstlane((int)(uint32_t)v);
+    const uint32_t hi = (uint32_t)__builtin_amdgcn_readfirstlane((int)(uint32_t)(v >> 32));
+    return ((uint64_t)hi << 32) | (uint64_t)lo;
+}
+
+__device__ __forceinline__ const FrameParams& opaque_params(ConstFrameParams p) {
+    asm volatile("" : "+s"(p));
+    return *(const FrameParams*)p;
+}
+
 // One block's samples i0 + threadIdx.x of a pass: sample, shade and learn
 // (section 3).  Sample i belongs to point q = i / spp, sample k = i % spp;
 // with a point order `perm` the point is perm[q] (its random numbers and
 // radiance are those of that point, so any order gives the same results).
 // The aggregation table must be clear on entry and is clear on exit; the
 // block is synchronised on exit.
-__device__ void frame_block(const FrameParams& fp, const float* __restrict__ pos, const float* __restrict__ nrm,
-                            const uint32_t* __restrict__ perm, uint32_t P, uint32_t spp, uint32_t frame,
-                            float* __restrict__ radiance, size_t i0, AggTable& agg, float (*s_e)[3]) {
+__device__ __forceinline__ void frame_block(const FrameParams& fp, const float* __restrict__ pos,
+                                            const float* __restrict__ nrm, const uint32_t* __restrict__ perm,
+                                            uint32_t P, uint32_t spp, uint32_t frame, float* __restrict__ radiance,
+                                            size_t i0, AggTable& agg, float (*s_e)[3]) {
     const size_t i = i0 + threadIdx.x;
     const size_t n = (size_t)P * spp;
     const bool valid = i < n;
@@ -305,8 +331,9 @@ __device__ __forceinline__ uint32_t xcd_chunk_block(uint32_t b, uint32_t nb) {
     return ((j / kXcdChunk) * 8u + x) * kXcdChunk + j % kXcdChunk;
 }
 
-// Fused pass: one lane per sample.
-__global__ void __launch_bounds__(kBlock, 8) k_frame(FrameParams fp, const float* __restrict__ pos,
+// Fused pass: one lane per sample.  The parameters (the first argument,
+// kept first) are read in place in the kernarg segment.
+__global__ void __launch_bounds__(kBlock, 8) k_frame(FrameParams /* read in place */, const float* __restrict__ pos,
                                                   const float* __restrict__ nrm, uint32_t P, uint32_t spp,
                                                   uint32_t frame, float* __restrict__ radiance) {
     __shared__ AggTable agg;
@@ -314,6 +341,7 @@ __global__ void __launch_bounds__(kBlock, 8) k_frame(FrameParams fp, const float
     agg_clear(agg);
     __syncthreads();
     const uint32_t b = xcd_chunk_block(blockIdx.x, gridDim.x);
+    const FrameParams& fp = opaque_params((ConstFrameParams)__builtin_amdgcn_kernarg_segment_ptr());
     frame_block(fp, pos, nrm, nullptr, P, spp, frame, radiance, (size_t)b * kBlock, agg, s_e);
 }
 
@@ -347,10 +375,12 @@ __global__ void __launch_bounds__(kBlock, 7) k_batch_frame(const BatchScene* __r
         }
         uint32_t sc = 0;
         while (sc + 1u < n_scenes && scenes[sc + 1u].item_begin <= item) ++sc;
+        // the scene's entry is the same for every lane (item and sc are)
+        const FrameParams& fps = opaque_params((ConstFrameParams)uniform_u64((uint64_t)&scenes[sc].fp));
         const BatchScene& S = scenes[sc];
         const size_t first = (size_t)(item - S.item_begin) * rounds * kBlock;
         for (uint32_t r = 0; r < rounds; ++r)
-            frame_block(S.fp, S.pos, S.nrm, S.perm, S.P, S.spp, frame, S.radiance, first + (size_t)r * kBlock, agg,
+            frame_block(fps, S.pos, S.nrm, S.perm, S.P, S.spp, frame, S.radiance, first + (size_t)r * kBlock, agg,
                         s_e);
     }
 }
