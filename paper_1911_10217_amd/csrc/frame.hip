@@ -46,6 +46,9 @@ __device__ __forceinline__ void agg_add(AggTableT<SLOTS>& t, const FrameParams& 
     const uint32_t bin = cell * fp.cells.M + s;
     constexpr int kBits = __builtin_ctz(SLOTS);
     uint32_t h = (bin * 2654435761u) >> (32 - kBits);  // Fibonacci hash
+    // kept as a loop: unrolled, its 32 exits nest 32 exec masks, which spill
+    // to VGPR lanes and are read back on every pass through the exits
+#pragma unroll 1
     for (int probe = 0; probe < kAggProbes; ++probe) {
         const uint32_t old = atomicCAS(&t.bin[h], kNoBin, bin);
         if (old == kNoBin || old == bin) {
