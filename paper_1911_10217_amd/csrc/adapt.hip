@@ -136,7 +136,7 @@ __device__ __forceinline__ void load_cell(const AdaptParams& ap, uint32_t c, Cel
 // The front: Eq. 1 and split-collapse, leaving the new cut and Q in L.
 // Returns false (and does nothing) when the cell had no samples this pass.
 template <int PER>
-__device__ bool adapt_front(const AdaptParams& ap, const CellIn<PER>& in, const AdaptLds& L) {
+__device__ __forceinline__ bool adapt_front(const AdaptParams& ap, const CellIn<PER>& in, const AdaptLds& L) {
     const DevCells& cells = ap.cells;
     const uint32_t lane = threadIdx.x & (kWave - 1u);
     const uint32_t Meff = ap.tmpl.Meff;
@@ -324,7 +324,7 @@ __device__ __forceinline__ void eq2_one_lane(const AdaptParams& ap, const AdaptL
 
 // Q~ and Eq. 2 by lane 0 of the wave: sums taken left to right.
 template <int PER>
-__device__ void adapt_eq2(const AdaptParams& ap, const AdaptLds& L) {
+__device__ __forceinline__ void adapt_eq2(const AdaptParams& ap, const AdaptLds& L) {
     const uint32_t lane = threadIdx.x & (kWave - 1u);
     const uint32_t Meff = ap.tmpl.Meff;
     float myq = 0.0f;
@@ -361,7 +361,7 @@ __device__ void adapt_eq2(const AdaptParams& ap, const AdaptLds& L) {
 // The back: the cell's new tables from L to the cell table, statistics
 // cleared, the cell marked ready.
 template <int PER>
-__device__ void adapt_back(const AdaptParams& ap, uint32_t c, const AdaptLds& L) {
+__device__ __forceinline__ void adapt_back(const AdaptParams& ap, uint32_t c, const AdaptLds& L) {
     const DevCells& cells = ap.cells;
     const uint32_t lane = threadIdx.x & (kWave - 1u);
     const uint32_t Meff = ap.tmpl.Meff;
@@ -385,7 +385,7 @@ __device__ void adapt_back(const AdaptParams& ap, uint32_t c, const AdaptLds& L)
 
 // The whole end of pass of one cell by one wavefront.
 template <int PER>
-__device__ void adapt_cell(const AdaptParams& ap, const CellIn<PER>& in, const AdaptLds& L) {
+__device__ __forceinline__ void adapt_cell(const AdaptParams& ap, const CellIn<PER>& in, const AdaptLds& L) {
     if (!adapt_front<PER>(ap, in, L)) return;
     adapt_eq2<PER>(ap, L);
     adapt_back<PER>(ap, in.c, L);
@@ -417,7 +417,8 @@ __device__ __forceinline__ void adapt_cells(const AdaptParams& ap, const AdaptLd
 // One block = one wavefront; it walks the list of created cells.  The LDS
 // scratch is sized for the cut (8 arrays of 64 PER words).
 template <int PER>
-__global__ void __launch_bounds__(kWave, PER == 1 ? 8 : 4) k_adapt(AdaptParams ap) {
+__global__ void __launch_bounds__(kWave, PER == 1 ? 8 : 4) k_adapt(AdaptParams /* read in place */) {
+    const AdaptParams& ap = first_kernel_arg<AdaptParams>();
     extern __shared__ uint32_t lds[];
     const AdaptLds L = lds_view(lds, kWave * PER);
     adapt_cells<PER>(ap, L);
@@ -428,8 +429,9 @@ template <int PER>
 __global__ void __launch_bounds__(kWave, PER == 1 ? 8 : 4) k_batch_adapt(const AdaptParams* __restrict__ aps, uint32_t n_scenes) {
     extern __shared__ uint32_t lds[];
     const AdaptLds L = lds_view(lds, kWave * PER);
+    typedef const __attribute__((address_space(4))) AdaptParams* ConstAdaptParams;
     for (uint32_t sc = 0; sc < n_scenes; ++sc) {
-        const AdaptParams ap = aps[sc];
+        const AdaptParams& ap = opaque_const((ConstAdaptParams)uniform_u64((uint64_t)&aps[sc]));
         adapt_cells<PER>(ap, L);
     }
 }
@@ -444,7 +446,8 @@ constexpr uint32_t kCellWaves = 16;
 // lanes, each in its own cell's scratch, read different LDS banks
 constexpr uint32_t kCellRegion = kLdsArrays * kWave + 1u;
 
-__global__ void __launch_bounds__(kCellWaves * kWave, 8) k_adapt16(AdaptParams ap) {
+__global__ void __launch_bounds__(kCellWaves * kWave, 8) k_adapt16(AdaptParams /* read in place */) {
+    const AdaptParams& ap = first_kernel_arg<AdaptParams>();
     extern __shared__ uint32_t lds[];
     __shared__ uint32_t s_active[kCellWaves];
     const uint32_t wave = threadIdx.x / kWave, lane = threadIdx.x % kWave;

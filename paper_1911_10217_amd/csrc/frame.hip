@@ -221,31 +221,6 @@ __device__ __forceinline__ DevOcc walk_operands(const FrameParams& fp, float& t_
     return occ;
 }
 
-// The pass's parameters are read through a pointer that an empty asm
-// statement defines anew at the kernel's start: each field is then loaded
-// with s_load where it is used.  Read from the by-value argument, the
-// compiler keeps the fields it needs, dozens of them, in VGPR lanes from the
-// kernel's start and reads them back one v_readlane (a VALU instruction) per
-// dword.  Taking the address of the by-value argument would make a private
-// copy, so k_frame reads its first argument where the kernarg segment holds
-// it, at offset 0.  The parameters are read-only during a pass, so the
-// constant address space is right for them.
-typedef __attribute__((address_space(4))) const FrameParams* ConstFrameParams;
-
-// A 64-bit value that every lane holds, as the first lane's.  The builtin
-// returns int: each half is taken as uint32_t before it is widened, so the
-// low half is not sign-extended into the high one.
-__device__ __forceinline__ uint64_t uniform_u64(uint64_t v) {
-    const uint32_t lo = (uint32_t)__builtin_amdgcn_readfirstlane((int)(uint32_t)v);
-    const uint32_t hi = (uint32_t)__builtin_amdgcn_readfirstlane((int)(uint32_t)(v >> 32));
-    return ((uint64_t)hi << 32) | (uint64_t)lo;
-}
-
-__device__ __forceinline__ const FrameParams& opaque_params(ConstFrameParams p) {
-    asm volatile("" : "+s"(p));
-    return *(const FrameParams*)p;
-}
-
 // One block's samples i0 + threadIdx.x of a pass: sample, shade and learn
 // (section 3).  Sample i belongs to point q = i / spp, sample k = i % spp;
 // with a point order `perm` the point is perm[q] (its random numbers and
@@ -344,7 +319,7 @@ __global__ void __launch_bounds__(kBlock, 8) k_frame(FrameParams /* read in plac
     agg_clear(agg);
     __syncthreads();
     const uint32_t b = xcd_chunk_block(blockIdx.x, gridDim.x);
-    const FrameParams& fp = opaque_params((ConstFrameParams)__builtin_amdgcn_kernarg_segment_ptr());
+    const FrameParams& fp = first_kernel_arg<FrameParams>();
     frame_block(fp, pos, nrm, nullptr, P, spp, frame, radiance, (size_t)b * kBlock, agg, s_e);
 }
 
@@ -379,7 +354,8 @@ __global__ void __launch_bounds__(kBlock, 7) k_batch_frame(const BatchScene* __r
         uint32_t sc = 0;
         while (sc + 1u < n_scenes && scenes[sc + 1u].item_begin <= item) ++sc;
         // the scene's entry is the same for every lane (item and sc are)
-        const FrameParams& fps = opaque_params((ConstFrameParams)uniform_u64((uint64_t)&scenes[sc].fp));
+        typedef const __attribute__((address_space(4))) FrameParams* ConstFrameParams;
+        const FrameParams& fps = opaque_const((ConstFrameParams)uniform_u64((uint64_t)&scenes[sc].fp));
         const BatchScene& S = scenes[sc];
         const size_t first = (size_t)(item - S.item_begin) * rounds * kBlock;
         for (uint32_t r = 0; r < rounds; ++r)

@@ -468,6 +468,36 @@ __device__ __forceinline__ unsigned long long reward_fixed(const FrameParams& fp
     return (unsigned long long)rintf(rc * fp.fx_scale);
 }
 
+// Parameters that stay the same for a whole launch, read through a pointer
+// that an empty asm statement makes opaque, typed in the constant address
+// space: each field is then loaded with s_load where it is used.  Read from
+// a by-value kernel argument, the compiler loads the fields at the kernel's
+// start and, short of SGPRs, keeps them in VGPR lanes and reads each dword
+// back with a v_readlane (a VALU instruction), also inside loops.  The
+// pointer must be the same for every lane of the wave.
+template <class T>
+__device__ __forceinline__ const T& opaque_const(const __attribute__((address_space(4))) T* p) {
+    asm volatile("" : "+s"(p));
+    return *(const T*)p;
+}
+
+// A kernel's first argument, of type T and passed by value, read in place at
+// offset 0 of the kernarg segment (taking the argument's address would make
+// a private copy of it).
+template <class T>
+__device__ __forceinline__ const T& first_kernel_arg() {
+    return opaque_const((const __attribute__((address_space(4))) T*)__builtin_amdgcn_kernarg_segment_ptr());
+}
+
+// A 64-bit value that every lane holds, as the first lane's.  The builtin
+// returns int: each half is taken as uint32_t before it is widened, so the
+// low half is not sign-extended into the high one.
+__device__ __forceinline__ uint64_t uniform_u64(uint64_t v) {
+    const uint32_t lo = (uint32_t)__builtin_amdgcn_readfirstlane((int)(uint32_t)v);
+    const uint32_t hi = (uint32_t)__builtin_amdgcn_readfirstlane((int)(uint32_t)(v >> 32));
+    return ((uint64_t)hi << 32) | (uint64_t)lo;
+}
+
 // Blocks are dealt to the 8 XCDs round-robin; give each XCD a contiguous
 // range of logical blocks so neighbouring points share one L2.
 __device__ __forceinline__ uint32_t xcd_block(uint32_t b, uint32_t nb) {
