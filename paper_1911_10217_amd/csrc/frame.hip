@@ -201,11 +201,11 @@ __global__ void __launch_bounds__(kBlock) k_learn(FrameParams fp, rlc_samples in
 }
 
 // The grid's pointers and t_lo for the shadow ray, as values defined just
-// before it (an empty asm statement hides where they came from).  Without
-// this the compiler keeps them, with the pass's other uniform values, in
-// VGPR lanes from the kernel's start and reads each dword back, one VALU
-// instruction apiece, at every step of the walk.  The casts keep the loads
-// in the global address space.
+// before it (an empty asm statement hides where they came from), so that
+// their live range is the walk alone.  Short of SGPRs (the batch kernel
+// holds its loop state besides), the compiler would otherwise park them in
+// VGPR lanes and read each dword back, one VALU instruction apiece, at every
+// step of the walk.  The casts keep the loads in the global address space.
 __device__ __forceinline__ DevOcc walk_operands(const FrameParams& fp, float& t_lo) {
     typedef __attribute__((address_space(1))) const uint32_t* GU32;
     typedef __attribute__((address_space(1))) const float4* GF4;
