@@ -133,28 +133,27 @@ RLC_WALK_INLINE bool blocked_brute(const DevOcc& occ, const float o[3], const fl
     return false;
 }
 
-// Test the boxes listed in one grid cell (header h).  Two mailbox slots
-// skip a box that was just tested in a previous cell.
+// Test the boxes listed in one occupied grid cell (header h, at least
+// RLC_OCC_ONE).  Two mailbox slots skip a box that was just tested in a
+// previous cell.
 template <bool FAST>
 RLC_WALK_INLINE bool cell_blocks(const DevOcc& occ, uint32_t h, uint32_t& last0, uint32_t& last1,
                                             const float o[3], const float d[3], const float invd[3], float t_lo) {
-    if (h & RLC_OCC_ONE) {
+    if (!(h & RLC_OCC_LIST)) {
         const uint32_t b = h & RLC_OCC_PAYLOAD;
         if (b == last0 || b == last1) return false;
         last1 = last0;
         last0 = b;
         return test_box<FAST>(occ, b, o, d, invd, t_lo);
     }
-    if (h & RLC_OCC_LIST) {
-        const uint32_t s0 = h & RLC_OCC_PAYLOAD;
-        const uint32_t n = occ.ref[s0];
-        for (uint32_t j = 1; j <= n; ++j) {
-            const uint32_t b = occ.ref[s0 + j];
-            if (b == last0 || b == last1) continue;
-            last1 = last0;
-            last0 = b;
-            if (test_box<FAST>(occ, b, o, d, invd, t_lo)) return true;
-        }
+    const uint32_t s0 = h & RLC_OCC_PAYLOAD;
+    const uint32_t n = occ.ref[s0];
+    for (uint32_t j = 1; j <= n; ++j) {
+        const uint32_t b = occ.ref[s0 + j];
+        if (b == last0 || b == last1) continue;
+        last1 = last0;
+        last0 = b;
+        if (test_box<FAST>(occ, b, o, d, invd, t_lo)) return true;
     }
     return false;
 }
@@ -305,8 +304,10 @@ template <bool FAST>
 RLC_WALK_INLINE int walk_step(const DevOcc& occ, WalkState& w, const float o[3], const float d[3],
                                          const float invd[3], float t_lo) {
     const uint32_t h = *(const uint32_t*)((const char*)occ.head + w.lin);
-    if (cell_blocks<FAST>(occ, h, w.last0, w.last1, o, d, invd, t_lo)) return 1;
-    const float r = (float)((h & (RLC_OCC_ONE | RLC_OCC_LIST)) ? 0u : ((h >> w.osh) & RLC_OCC_SKIP_MAX));
+    // an empty cell's header holds only its radii, in the low 24 bits
+    const bool occupied = h >= RLC_OCC_ONE;
+    if (occupied && cell_blocks<FAST>(occ, h, w.last0, w.last1, o, d, invd, t_lo)) return 1;
+    const float r = occupied ? 0.0f : (float)((h >> w.osh) & RLC_OCC_SKIP_MAX);
     // exit parameter of the empty cube on each axis (cut by the grid); the
     // axis that reaches its face first moves on (ties: x, then y).  Value
     // selects and integer masks, not selects between fields, keep the state
