@@ -187,6 +187,7 @@ struct WalkState {
     uint32_t osh;                // 3 x the segment's octant: shift of its radius in a header
     int it;                      // steps taken (a guard: the counts above already bound them)
     uint32_t last0, last1;
+    uint32_t h;                  // header of the current cell, loaded one step ahead
 };
 
 // false: the segment misses the grid (nothing to test).
@@ -249,6 +250,7 @@ RLC_WALK_INLINE bool walk_begin(const DevOcc& occ, const float o[3], const float
     w.it = 0;
     w.last0 = 0xFFFFFFFFu;
     w.last1 = 0xFFFFFFFFu;
+    w.h = *(const uint32_t*)((const char*)occ.head + w.lin);
     return true;
 }
 
@@ -297,16 +299,19 @@ RLC_WALK_INLINE int walk_mul24(int a, int b) {
 }
 
 // Test the current cell, then move on.  Returns 1 when a box blocks the
-// segment, 2 when the walk has ended unblocked, 0 otherwise.  Everything
-// after the box tests is computed for every lane and selected, without
-// branches, so a wave runs it once.
+// segment, 2 when the walk has ended unblocked, 0 otherwise.  The step out
+// of a cell depends on its header alone (an occupied cell is left through
+// one boundary), so it is taken first and the next cell's header is loaded
+// before the current cell's boxes are tested: the two loads overlap.  The
+// header is loaded only when the walk goes on, so it stays in the grid.
+// Outside the box tests everything is computed for every lane and
+// selected, without branches, so a wave runs it once.
 template <bool FAST>
 RLC_WALK_INLINE int walk_step(const DevOcc& occ, WalkState& w, const float o[3], const float d[3],
                                          const float invd[3], float t_lo) {
-    const uint32_t h = *(const uint32_t*)((const char*)occ.head + w.lin);
+    const uint32_t h = w.h;
     // an empty cell's header holds only its radii, in the low 24 bits
     const bool occupied = h >= RLC_OCC_ONE;
-    if (occupied && cell_blocks<FAST>(occ, h, w.last0, w.last1, o, d, invd, t_lo)) return 1;
     const float r = occupied ? 0.0f : (float)((h >> w.osh) & RLC_OCC_SKIP_MAX);
     // exit parameter of the empty cube on each axis (cut by the grid); the
     // axis that reaches its face first moves on (ties: x, then y).  Value
@@ -330,16 +335,20 @@ RLC_WALK_INLINE int walk_step(const DevOcc& occ, WalkState& w, const float o[3],
     const float fky = ay ? fr1 : cy;
     const float fkz = (ax || ay) ? cz : fr1;
     ++w.it;
-    if ((tm > w.t1) | (rm <= r) | (w.it >= 3 * (int)occ.res + 3)) return 2;
-    const int kx = (int)fkx, ky = (int)fky, kz = (int)fkz;
-    w.lin += (uint32_t)(walk_mul24(kx, w.sx) + walk_mul24(ky, w.sy) + walk_mul24(kz, w.sz));
-    w.tx = walk_advance<FAST>(w.tx, fkx, w.dtx);
-    w.ty = walk_advance<FAST>(w.ty, fky, w.dty);
-    w.tz = walk_advance<FAST>(w.tz, fkz, w.dtz);
-    w.rx -= fkx;
-    w.ry -= fky;
-    w.rz -= fkz;
-    return 0;
+    const bool ends = (tm > w.t1) | (rm <= r) | (w.it >= 3 * (int)occ.res + 3);
+    if (!ends) {
+        const int kx = (int)fkx, ky = (int)fky, kz = (int)fkz;
+        w.lin += (uint32_t)(walk_mul24(kx, w.sx) + walk_mul24(ky, w.sy) + walk_mul24(kz, w.sz));
+        w.tx = walk_advance<FAST>(w.tx, fkx, w.dtx);
+        w.ty = walk_advance<FAST>(w.ty, fky, w.dty);
+        w.tz = walk_advance<FAST>(w.tz, fkz, w.dtz);
+        w.rx -= fkx;
+        w.ry -= fky;
+        w.rz -= fkz;
+        w.h = *(const uint32_t*)((const char*)occ.head + w.lin);
+    }
+    if (occupied && cell_blocks<FAST>(occ, h, w.last0, w.last1, o, d, invd, t_lo)) return 1;
+    return ends ? 2 : 0;
 }
 
 template <bool FAST>
