@@ -103,11 +103,16 @@ RLC_WALK_INLINE bool normal_dir(const float d[3]) {
 }
 
 template <bool FAST>
-RLC_WALK_INLINE bool test_box(const DevOcc& occ, uint32_t b, const float o[3], const float d[3],
-                                         const float invd[3], float t_lo) {
-    const float4 b0 = occ.box[2 * b], b1 = occ.box[2 * b + 1];
+RLC_WALK_INLINE bool box_blocks(const float4 b0, const float4 b1, const float o[3], const float d[3],
+                                const float invd[3], float t_lo) {
     if (FAST) return box_blocks_fast(b0, b1, o, invd, t_lo, 1.0f - t_lo);
     return box_blocks_def(b0, b1, o, d, invd, t_lo);
+}
+
+template <bool FAST>
+RLC_WALK_INLINE bool test_box(const DevOcc& occ, uint32_t b, const float o[3], const float d[3],
+                                         const float invd[3], float t_lo) {
+    return box_blocks<FAST>(occ.box[2 * b], occ.box[2 * b + 1], o, d, invd, t_lo);
 }
 
 // Grid cells overlapped by a box grown by 1/256 of a cell on every side, so
@@ -146,9 +151,23 @@ RLC_WALK_INLINE bool cell_blocks(const DevOcc& occ, uint32_t h, uint32_t& last0,
         last0 = b;
         return test_box<FAST>(occ, b, o, d, invd, t_lo);
     }
+    // a list holds two boxes or more: its count and first two entries are
+    // loaded together, and the first box's bounds with them
     const uint32_t s0 = h & RLC_OCC_PAYLOAD;
     const uint32_t n = occ.ref[s0];
-    for (uint32_t j = 1; j <= n; ++j) {
+    const uint32_t ba = occ.ref[s0 + 1], bb = occ.ref[s0 + 2];
+    const float4 a0 = occ.box[2 * ba], a1 = occ.box[2 * ba + 1];
+    if (ba != last0 && ba != last1) {
+        last1 = last0;
+        last0 = ba;
+        if (box_blocks<FAST>(a0, a1, o, d, invd, t_lo)) return true;
+    }
+    if (bb != last0 && bb != last1) {
+        last1 = last0;
+        last0 = bb;
+        if (test_box<FAST>(occ, bb, o, d, invd, t_lo)) return true;
+    }
+    for (uint32_t j = 3; j <= n; ++j) {
         const uint32_t b = occ.ref[s0 + j];
         if (b == last0 || b == last1) continue;
         last1 = last0;
