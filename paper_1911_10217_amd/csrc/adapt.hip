@@ -455,13 +455,18 @@ __global__ void __launch_bounds__(kCellWaves * kWave, 8) k_adapt16(AdaptParams /
     const uint32_t n_live = *ap.cells.n_live;
     const uint32_t per_round = gridDim.x * kCellWaves;
     const uint32_t rounds = (n_live + per_round - 1u) / per_round;
+    // each round's cell is loaded during the round before (a launch
+    // touches every cell once, so no round writes the next one's cell)
+    CellIn<1> nxt;
+    const uint32_t li0 = blockIdx.x * kCellWaves + wave;
+    if (li0 < n_live) load_cell<1>(ap, ap.cells.live[li0], nxt);
     for (uint32_t rd = 0; rd < rounds; ++rd) {
-        const uint32_t li = rd * per_round + blockIdx.x * kCellWaves + wave;
+        const uint32_t li = rd * per_round + li0;
         bool active = false;
         uint32_t c = 0;
+        const CellIn<1> in = nxt;
+        if (li + per_round < n_live) load_cell<1>(ap, ap.cells.live[li + per_round], nxt);
         if (li < n_live) {
-            CellIn<1> in;
-            load_cell<1>(ap, ap.cells.live[li], in);
             c = in.c;
             active = adapt_front<1>(ap, in, L);
         }
