@@ -85,6 +85,14 @@ typedef struct rlc_config {
                               by up to jitter/2 cells in the tangent plane (basis of Duff
                               et al. 2017) and its normal coordinates moved by up to
                               jitter/2 bins, drawn from Philox tag 4; 0: no jitter */
+    uint32_t footprint_levels; /* section 3's footprint-sized position cells: with per-point
+                              footprints set (rlc_set_footprints), levels 0..n-1 of cells
+                              2^level finest cells wide, 0..16 (0 and 1: the fixed grid).
+                              The cell count over all levels must fit 32 bits */
+    float footprint_tile;  /* a point's level is the smallest whose cell edge (the grid's
+                              smallest cell edge times 2^level) reaches footprint_tile
+                              times its footprint (the coarsest if none does); > 0 when
+                              footprint_levels > 1 */
 } rlc_config;
 
 /* Per-sample records of rlc_sample (device arrays of n = P * spp entries,
@@ -168,6 +176,22 @@ int rlc_frame(rlc_ctx* ctx, const float* d_pos, const float* d_nrm, uint32_t P, 
 int rlc_frame_sub(rlc_ctx* ctx, const float* d_pos, const float* d_nrm, uint32_t P, uint32_t spp,
                   uint32_t n_sub, uint32_t frame, float* d_radiance);
 
+/* Footprint-sized cells (section 3: position cells sized from the ray
+ * footprint given by the area pdf of the shading point, about a tile for
+ * visible points) for the following passes: d_fp[p] (`rows` floats, finite,
+ * >= 0, device) is the side of point p's footprint, e.g. for a primary hit
+ * the square root of the surface area its pixel covers.  The point's level
+ * L is the smallest below footprint_levels whose cell edge reaches
+ * footprint_tile * d_fp[p]; at level L each axis holds cells of 2^L finest
+ * cells (index: the finest index shifted right by L), the jittered lookup
+ * moves by up to jitter/2 of those cells, and the cell key is the
+ * level-major linear index: the cells of all finer levels first, then
+ * ix + dx_L (iy + dy_L (iz + dz_L (qu + 2^b qv))), dx_L = ((dx - 1) >> L) + 1.
+ * Passes over more than `rows` points are refused.  d_fp = NULL: every
+ * point at the finest level.  Checks the values (synchronises); the array
+ * must stay valid while set. */
+int rlc_set_footprints(rlc_ctx* ctx, const float* d_fp, uint32_t rows);
+
 /* Shadow-ray test only: d_vis[i] = 1 if the segment d_x[i] -> d_y[i] is
  * unoccluded over t in (t_lo, 1 - t_lo). */
 int rlc_visible(rlc_ctx* ctx, const float* d_x, const float* d_y, uint32_t n, uint8_t* d_vis);
@@ -233,11 +257,13 @@ int rlc_batch_frame(rlc_batch* b, uint32_t frame);
  * BF16 weights, inputs and activations and FP32 sums (matrix cores).
  *
  * Sampling with the mixture on (rlc_set_mixture): each sample draws from the
- * cell's cut with probability w and from the network's distribution
- * otherwise (a node, then a light in it uniformly), choosing by Philox at
- * counter (point, sample, frame, scene_id << 16 | 1); its density is
- * p(l) = w p_cut(l) + (1 - w) q(node(l)) / size(node(l)), so the estimate
- * stays unbiased for any network.  Only draws from the cut feed Eq. 1.
+ * network's distribution with probability w (the network's share; a node,
+ * then a light in it uniformly) and from the cell's cut otherwise, choosing
+ * by Philox at counter (point, sample, frame, scene_id << 16 | 1): the
+ * network when its first word, as a unit float, is below w.  Its density is
+ * p(l) = (1 - w) p_cut(l) + w q(node(l)) / size(node(l)), positive for every
+ * light since w < 1 and the cut's Q~ > 0, so the estimate stays unbiased for
+ * any network.  Only draws from the cut feed Eq. 1.
  *
  * Training: minibatch Adam (beta1 0.9, beta2 0.999, eps 1e-8) on the
  * weighted cross-entropy -sum_i w_i log q(x_i)[node_i] / sum_i w_i over
@@ -278,10 +304,12 @@ int rlc_mlp_train(rlc_ctx* ctx, const float* d_pos, const float* d_nrm, uint32_t
                   float lr, float* h_loss);
 /* Mixture for the following rlc_frame / rlc_sample calls: d_cdf holds
  * `rows` rows of 64 running sums (row = point index of the pass; e.g. from
- * rlc_mlp_forward), non-decreasing with a positive last used entry; w is
- * the probability of drawing from the cell's cut.  d_cdf = NULL turns the
- * mixture off.  The array must stay valid while the mixture is on.
- * Batched passes ignore it. */
+ * rlc_mlp_forward), non-decreasing with a positive last used entry; w in
+ * [0, 1) is the network's share (0.5: the 50/50 mixture).  w = 0 or
+ * d_cdf = NULL turns the mixture off: the plain tabular method, bit for
+ * bit.  w >= 1 is RLC_EINVAL (the network alone may give a light density
+ * 0).  The array must stay valid while the mixture is on.  Batched passes
+ * ignore it. */
 int rlc_set_mixture(rlc_ctx* ctx, const float* d_cdf, uint32_t rows, float w);
 /* Training records of the following rlc_frame calls: for sample k of point
  * p, entry p * spp + k receives the point index, the fixed-cut node of the
@@ -299,6 +327,20 @@ int rlc_meff(rlc_ctx* ctx, uint32_t* h_meff);
 int rlc_dump_cells(rlc_ctx* ctx, uint32_t max_cells, uint64_t* h_keys, uint32_t* h_ready,
                    uint32_t* h_node, uint32_t* h_end, float* h_Q, float* h_Qt, float* h_C,
                    uint64_t* h_sum, uint32_t* h_cnt);
+/* Checkpoint and resume (section 3: a cell's cut and Q persist from pass
+ * to pass): load n cells' learned state, as rlc_dump_cells gives it for
+ * ready cells.  Host arrays: h_keys[n], keys of this context's scene, each
+ * once; h_node[n x Meff], each row a cut whose nodes, in range order,
+ * partition the lights (the first starts at light 0, each next one right
+ * after the previous one ends, the last ends at light N-1); h_Q[n x Meff],
+ * finite and >= 0.  Per cell the cluster ends follow from the tree and Q~
+ * and C from Eq. 2, as at the end of a pass; the statistics start at zero;
+ * the cell samples from its own table from the next pass on; an existing
+ * cell is overwritten.  RLC_EINVAL (nothing loaded) for a key of another
+ * scene or outside the grid, a repeated key, a cut that is not a partition
+ * or a bad Q; RLC_ECAPACITY if the hash table fills.  Synchronises. */
+int rlc_load_cells(rlc_ctx* ctx, uint32_t n, const uint64_t* h_keys, const uint32_t* h_node, const float* h_Q);
+
 /* Tree arrays: perm[N] (tree order -> input index), left/right[N-1],
  * parent/first/last[2N-1] (internal nodes 0..N-2, leaf j is N-1+j),
  * rec[N x 16] = v0 v1 v2 Le area normal per light in tree order. */

@@ -72,6 +72,8 @@ class OrcConfig(ctypes.Structure):
         ("seed", ctypes.c_uint64),
         ("normal_bits", ctypes.c_uint32),
         ("jitter", ctypes.c_float),
+        ("footprint_levels", ctypes.c_uint32),
+        ("footprint_tile", ctypes.c_float),
     ]
 
 
@@ -107,6 +109,10 @@ def _declare(L):
     L.orc_meff.argtypes = [_vp]
     L.orc_dump_cells.argtypes = [_vp] + [_vp] * 9
     L.orc_load_cell.argtypes = [_vp, _u32, _vp, _vp]
+    L.orc_set_footprints.argtypes = [_vp, _vp, _u32]
+    L.orc_point_levels.argtypes = [_vp, _u32, _vp]
+    L.orc_status.restype = _u32
+    L.orc_status.argtypes = [_vp]
     L.orc_truth_unoccluded.argtypes = [_vp, _vp, _vp, _u32, _vp]
     L.orc_truth_mc.argtypes = [_vp, _vp, _vp, _vp, _u32, _u32, _u32, _vp]
     L.orc_fixed_cut.restype = _u32
@@ -164,6 +170,8 @@ def make_config(params: dict) -> OrcConfig:
     c.seed = int(params["seed"])
     c.normal_bits = int(params.get("normal_bits", 0))
     c.jitter = float(params.get("jitter", 0.0))
+    c.footprint_levels = int(params.get("footprint_levels", 0))
+    c.footprint_tile = float(params.get("footprint_tile", 0.0))
     return c
 
 
@@ -218,8 +226,9 @@ class Oracle:
         return node[:m].copy(), end[:m].copy()
 
     def set_mixture(self, cdf=None, w: float = 0.5):
-        """Turn the 50/50 (w) mixture with a learned per-point cdf on (rows of 64
-        inclusive running sums, indexed by point id), or off with None."""
+        """Turn the mixture with a learned per-point cdf on (rows of 64
+        inclusive running sums, indexed by point id; w is the network's
+        share, 0.5 the 50/50 mixture), or off with None or w = 0."""
         if cdf is None:
             lib().orc_set_mixture(self._h, None, 0, 0.0)
             self._mix = None
@@ -227,6 +236,22 @@ class Oracle:
         self._mix = _c(cdf, np.float32).reshape(-1, MIX_M)
         if lib().orc_set_mixture(self._h, _p(self._mix), self._mix.shape[0], float(w)) != 0:
             raise ValueError("bad mixture")
+
+    def set_footprints(self, fp=None):
+        """Footprint sides per point id (footprint-sized cells), or None for
+        the finest level everywhere."""
+        if fp is None:
+            lib().orc_set_footprints(self._h, None, 0)
+            self._fp = None
+            return
+        self._fp = _c(fp, np.float32).reshape(-1)
+        if lib().orc_set_footprints(self._h, _p(self._fp), self._fp.size) != 0:
+            raise ValueError("bad footprints")
+
+    def point_levels(self, n: int) -> np.ndarray:
+        out = np.zeros(n, np.uint32)
+        lib().orc_point_levels(self._h, n, _p(out))
+        return out
 
     @property
     def Meff(self) -> int:
@@ -307,6 +332,11 @@ class Oracle:
         return out
 
     # -- inspection -----------------------------------------------------------
+    def status(self) -> int:
+        """Status bits raised since the previous call (1: a fixed-point
+        reward sum wrapped 64 bits), then cleared."""
+        return int(lib().orc_status(self._h))
+
     def num_cells(self) -> int:
         return int(lib().orc_num_cells(self._h))
 

@@ -60,7 +60,11 @@ typedef struct orc_config {
     uint64_t seed;         /* Philox key */
     uint32_t normal_bits;  /* 5-D cells: 2^b bins per octahedral normal coordinate (0: position only) */
     float jitter;          /* jitter of the cell lookup, in cells and normal bins (0: none) */
+    uint32_t footprint_levels; /* footprint-sized cells: levels 0..n-1 of cell edge base 2^level (0, 1: off) */
+    float footprint_tile;  /* a point's cell edge is wanted at least tile x its footprint */
 } orc_config;
+
+#define ORC_MAX_LEVELS 16u
 
 /* ------------------------------------------------------------------------ */
 /* Philox4x32-10 counter-based generator, from its published definition     */
@@ -137,13 +141,30 @@ typedef struct orc_ctx {
     uint32_t fix_end[ORC_MIX_M];
     float* mix_cdf;        /* rows of ORC_MIX_M floats, indexed by point id; NULL: off */
     uint32_t mix_rows;
-    float mix_w;           /* probability of drawing from the cell's cut */
+    float mix_w;           /* probability of drawing from the learned proposal */
     /* grid of cells, indexed by the cell key's linear part */
     uint32_t ncell_slots;
     cell** cells;
     float inv_cell[3];
     float f_r;
+    uint32_t status;       /* ORC_STATUS_* bits raised since the last orc_status */
+    /* footprint-sized cells: per point id the side of its footprint, the
+     * finest cell edge, and the first linear index of every level */
+    float* footprint;
+    uint32_t fp_rows;
+    float fp_base;
+    uint32_t lvl_first[ORC_MAX_LEVELS + 1];
 } orc_ctx;
+
+#define ORC_STATUS_FX_OVERFLOW 1u  /* a (cell, cluster) fixed-point reward sum wrapped 64 bits */
+
+/* Status bits raised since the previous call, then cleared. */
+uint32_t orc_status(orc_ctx* c)
+{
+    uint32_t s = c->status;
+    c->status = 0;
+    return s;
+}
 
 static int is_leaf(const orc_ctx* c, uint32_t id) { return id >= c->N - 1u; }
 
@@ -352,11 +373,24 @@ orc_ctx* orc_create(const orc_config* cfg, const float* tri, const float* emit, 
                     const float* boxes, uint32_t K)
 {
     if (!cfg || !tri || !emit || N == 0 || cfg->M == 0 || cfg->M > ORC_MMAX) return NULL;
+    /* one clamped reward in fixed point fits 63 bits */
+    if (!(cfg->reward_max > 0.0f) || ldexp((double)cfg->reward_max, (int)cfg->fx_shift) > 9223372036854775808.0)
+        return NULL;
     /* one cell pointer per 5-D cell: at most 2^27 of them */
     if (cfg->normal_bits > 8u || !(cfg->jitter >= 0.0f && cfg->jitter <= 1.0f)) return NULL;
-    if ((((uint64_t)cfg->grid_dims[0] * cfg->grid_dims[1] * cfg->grid_dims[2]) << (2u * cfg->normal_bits)) >
-        (1ull << 27))
+    if (cfg->footprint_levels > ORC_MAX_LEVELS) return NULL;
+    if (cfg->footprint_levels > 1u && !(cfg->footprint_tile > 0.0f && cfg->footprint_tile <= 3.402823466e38f))
         return NULL;
+    /* cells of all levels (level-major linear index) */
+    uint64_t first[ORC_MAX_LEVELS + 1];
+    const uint32_t nlev = cfg->footprint_levels > 1u ? cfg->footprint_levels : 1u;
+    first[0] = 0;
+    for (uint32_t L = 0; L < nlev; ++L) {
+        uint64_t n = 1;
+        for (int a = 0; a < 3; ++a) n *= (uint64_t)(((cfg->grid_dims[a] - 1u) >> L) + 1u);
+        first[L + 1] = first[L] + (n << (2u * cfg->normal_bits));
+    }
+    if (first[nlev] > (1ull << 27)) return NULL;
     orc_ctx* c = (orc_ctx*)calloc(1, sizeof(orc_ctx));
     if (!c) return NULL;
     c->cfg = *cfg;
@@ -371,7 +405,8 @@ orc_ctx* orc_create(const orc_config* cfg, const float* tri, const float* emit, 
     c->last = (uint32_t*)calloc(nn, sizeof(uint32_t));
     c->rec = (float*)calloc(16u * N, sizeof(float));
     c->boxes = (float*)calloc(6u * (K ? K : 1u), sizeof(float));
-    c->ncell_slots = cfg->grid_dims[0] * cfg->grid_dims[1] * cfg->grid_dims[2] << (2u * cfg->normal_bits);
+    c->ncell_slots = (uint32_t)first[nlev];
+    for (uint32_t L = 0; L <= nlev; ++L) c->lvl_first[L] = (uint32_t)first[L];
     c->cells = (cell**)calloc(c->ncell_slots ? c->ncell_slots : 1u, sizeof(cell*));
     if (!c->perm || !c->left || !c->right || !c->parent || !c->first || !c->last || !c->rec ||
         !c->boxes || !c->cells) {
@@ -386,6 +421,11 @@ orc_ctx* orc_create(const orc_config* cfg, const float* tri, const float* emit, 
     initial_cut(c);
     for (int a = 0; a < 3; ++a)
         c->inv_cell[a] = (float)cfg->grid_dims[a] / (cfg->grid_hi[a] - cfg->grid_lo[a]);
+    /* the finest cell edge: the smallest of the three */
+    for (int a = 0; a < 3; ++a) {
+        float e = (cfg->grid_hi[a] - cfg->grid_lo[a]) / (float)cfg->grid_dims[a];
+        if (a == 0 || e < c->fp_base) c->fp_base = e;
+    }
     c->f_r = (float)((double)cfg->albedo / 3.14159265358979323846);
     return c;
 }
@@ -404,6 +444,7 @@ void orc_destroy(orc_ctx* c)
     free(c->last);
     free(c->rec);
     free(c->boxes);
+    free(c->footprint);
     free(c->mix_cdf);
     free(c);
 }
@@ -448,8 +489,11 @@ uint32_t orc_fixed_cut(const orc_ctx* c, uint32_t* node, uint32_t* end)
 
 /* Mixture proposal: cdf holds, per point id, the inclusive running sums of
  * the learned probabilities of the fixed cut's nodes (rows of 64 floats, the
- * first fix_M used).  A light is drawn from the cell's cut with probability
- * w and from the learned proposal otherwise.  cdf = NULL switches it off. */
+ * first fix_M used).  A light is drawn from the learned proposal with
+ * probability w (the network's share) and from the cell's cut otherwise.
+ * cdf = NULL or w = 0 switches it off: the plain tabular method.  w = 1 (the
+ * network alone) is accepted here only to pin the proposal's own draws: a
+ * node the network gives probability 0 is then never drawn. */
 int orc_set_mixture(orc_ctx* c, const float* cdf, uint32_t rows, float w)
 {
     free(c->mix_cdf);
@@ -457,6 +501,7 @@ int orc_set_mixture(orc_ctx* c, const float* cdf, uint32_t rows, float w)
     c->mix_rows = 0;
     if (!cdf) return ORC_OK;
     if (!(w >= 0.0f && w <= 1.0f) || rows == 0) return ORC_EINVAL;
+    if (w == 0.0f) return ORC_OK;
     c->mix_cdf = (float*)malloc(sizeof(float) * ORC_MIX_M * (size_t)rows);
     if (!c->mix_cdf) return ORC_ENOMEM;
     memcpy(c->mix_cdf, cdf, sizeof(float) * ORC_MIX_M * (size_t)rows);
@@ -519,12 +564,35 @@ static void tangent_frame(const float n[3], float t[3], float b[3])
     b[2] = -n[1];
 }
 
+/* Footprint-sized cells (section 3: position cells sized from the ray
+ * footprint that the area pdf of the shading point gives, about a
+ * user-defined tile for visible points).  Reading: the caller gives each
+ * point the side f of its footprint (for a primary hit, the square root of
+ * the surface area its pixel covers); the wanted cell edge is tile * f, and
+ * the point's level is the smallest L < levels whose edge base 2^L reaches
+ * it (base: the grid's smallest cell edge), the coarsest level if none
+ * does.  Level L quantises each axis into cells of 2^L finest cells (the
+ * finest index shifted right by L) with ((dims - 1) >> L) + 1 of them. */
+static uint32_t point_level(const orc_ctx* c, uint32_t pid)
+{
+    if (!c->footprint || pid >= c->fp_rows) return 0u;
+    const float want = c->cfg.footprint_tile * c->footprint[pid];
+    float edge = c->fp_base;
+    uint32_t L = 0;
+    while (L + 1u < c->cfg.footprint_levels && edge < want) {
+        edge = edge * 2.0f;
+        ++L;
+    }
+    return L;
+}
+
 static uint32_t cell_linear(const orc_ctx* c, const float* x, const float* nrm, uint32_t pid, uint32_t k,
                             uint32_t frame)
 {
     const orc_config* cfg = &c->cfg;
     const uint32_t* d = cfg->grid_dims;
     const uint32_t nb = 1u << cfg->normal_bits;
+    const uint32_t L = point_level(c, pid);
     float p[3] = {x[0], x[1], x[2]};
     float u = 0.0f, v = 0.0f;
     if (cfg->normal_bits) octahedral(nrm, &u, &v);
@@ -537,7 +605,9 @@ static uint32_t cell_linear(const orc_ctx* c, const float* x, const float* nrm, 
         float t[3], b[3];
         tangent_frame(nrm, t, b);
         for (int a = 0; a < 3; ++a) {
+            /* up to jitter/2 cells of the point's level */
             float reach = cfg->jitter * ((cfg->grid_hi[a] - cfg->grid_lo[a]) / (float)d[a]);
+            reach = reach * (float)(1u << L);
             p[a] = x[a] + reach * (xi0 * t[a] + xi1 * b[a]);
         }
         if (cfg->normal_bits) {
@@ -545,12 +615,37 @@ static uint32_t cell_linear(const orc_ctx* c, const float* x, const float* nrm, 
             v = v + ((unit_float(w[3]) - 0.5f) * cfg->jitter) / (float)nb;
         }
     }
-    uint32_t ix = axis_index(p[0], cfg->grid_lo[0], c->inv_cell[0], d[0]);
-    uint32_t iy = axis_index(p[1], cfg->grid_lo[1], c->inv_cell[1], d[1]);
-    uint32_t iz = axis_index(p[2], cfg->grid_lo[2], c->inv_cell[2], d[2]);
+    uint32_t ix = axis_index(p[0], cfg->grid_lo[0], c->inv_cell[0], d[0]) >> L;
+    uint32_t iy = axis_index(p[1], cfg->grid_lo[1], c->inv_cell[1], d[1]) >> L;
+    uint32_t iz = axis_index(p[2], cfg->grid_lo[2], c->inv_cell[2], d[2]) >> L;
     uint32_t qu = axis_index(u, 0.0f, (float)nb, nb);
     uint32_t qv = axis_index(v, 0.0f, (float)nb, nb);
-    return ix + d[0] * (iy + d[1] * (iz + d[2] * (qu + nb * qv)));
+    const uint32_t dx = ((d[0] - 1u) >> L) + 1u, dy = ((d[1] - 1u) >> L) + 1u, dz = ((d[2] - 1u) >> L) + 1u;
+    return c->lvl_first[L] + (ix + dx * (iy + dy * (iz + dz * (qu + nb * qv))));
+}
+
+/* Footprint sides per point id (rows of one float, finite and >= 0), or
+ * NULL to quantise every point at the finest level. */
+int orc_set_footprints(orc_ctx* c, const float* fp, uint32_t rows)
+{
+    free(c->footprint);
+    c->footprint = NULL;
+    c->fp_rows = 0;
+    if (!fp) return ORC_OK;
+    for (uint32_t i = 0; i < rows; ++i)
+        if (!(fp[i] >= 0.0f && fp[i] <= 3.402823466e38f)) return ORC_EINVAL;
+    c->footprint = (float*)malloc(sizeof(float) * (rows ? rows : 1u));
+    if (!c->footprint) return ORC_ENOMEM;
+    memcpy(c->footprint, fp, sizeof(float) * rows);
+    c->fp_rows = rows;
+    return ORC_OK;
+}
+
+/* The level of each point id (what point_level gives). */
+int orc_point_levels(const orc_ctx* c, uint32_t n, uint32_t* out)
+{
+    for (uint32_t i = 0; i < n; ++i) out[i] = point_level(c, i);
+    return ORC_OK;
 }
 
 static uint64_t cell_key(const orc_ctx* c, uint32_t lin)
@@ -672,7 +767,7 @@ static void one_sample(orc_ctx* c, const float* x, const float* nx, uint32_t pid
         uint32_t w1[4];
         philox4x32_10(ctr1, key, w1);
         q = c->mix_cdf + (size_t)pid * ORC_MIX_M;
-        use_mlp = !(unit_float(w1[0]) < c->mix_w);
+        use_mlp = unit_float(w1[0]) < c->mix_w;
     }
     uint32_t Mf = c->fix_M;
     uint32_t s, begin, size, l, kf = ORC_NONE, fbegin = 0, fsize = 0;
@@ -724,12 +819,12 @@ static void one_sample(orc_ctx* c, const float* x, const float* nx, uint32_t pid
     }
     float inv_pdf;
     if (q) {
-        /* p(l) = w p_cut(l) + (1 - w) p_learned(l), each uniform inside its
+        /* p(l) = (1 - w) p_cut(l) + w p_learned(l), each uniform inside its
          * cluster / node */
         float pt = Qt[s] / ((float)size * C[Meff - 1]);
         float qk = q[kf] - (kf ? q[kf - 1] : 0.0f);
         float pm = qk / ((float)fsize * q[Mf - 1]);
-        inv_pdf = 1.0f / (c->mix_w * pt + (1.0f - c->mix_w) * pm);
+        inv_pdf = 1.0f / ((1.0f - c->mix_w) * pt + c->mix_w * pm);
     } else {
         inv_pdf = ((float)size * C[Meff - 1]) / Qt[s];
     }
@@ -780,6 +875,8 @@ static void one_sample(orc_ctx* c, const float* x, const float* nx, uint32_t pid
     /* reading: only draws from the cell's own cut feed Eq. 1 (inside a
      * cluster they are uniform, as the update assumes) */
     if (ce && !use_mlp) {
+        /* a 64-bit sum that wraps is flagged: its statistics are not valid */
+        if (ce->sum[s] + qfx < ce->sum[s]) c->status |= ORC_STATUS_FX_OVERFLOW;
         ce->sum[s] += qfx;
         ce->cnt[s] += 1u;
     }
@@ -1019,9 +1116,23 @@ int orc_dump_cells(const orc_ctx* c, uint64_t* keys, uint32_t* ready, uint32_t* 
 }
 
 /* Overwrite one cell's learned state (creating it, ready) - test hook.    */
+/* Load one cell's learned state (a checkpoint): its cut, which must be a
+ * partition of the lights in range order (the first node starts at light
+ * 0, each next one right after the previous one ends, the last ends at
+ * N - 1), and its Q (finite, >= 0).  The ends follow from the tree and Q~,
+ * C from Eq. 2, as at the end of a pass; the statistics start at zero and
+ * the cell samples from its own table from the next pass on. */
 int orc_load_cell(orc_ctx* c, uint32_t lin, const uint32_t* node, const float* Q)
 {
     if (lin >= c->ncell_slots) return ORC_EINVAL;
+    const uint32_t nn = 2u * c->N - 1u;
+    uint32_t next = 0;
+    for (uint32_t s = 0; s < c->Meff; ++s) {
+        if (node[s] >= nn || c->first[node[s]] != next) return ORC_EINVAL;
+        if (!(Q[s] >= 0.0f && Q[s] <= 3.402823466e38f)) return ORC_EINVAL;
+        next = c->last[node[s]] + 1u;
+    }
+    if (next != c->N) return ORC_EINVAL;
     cell* ce = get_or_create_cell(c, lin);
     if (!ce) return ORC_ENOMEM;
     for (uint32_t s = 0; s < c->Meff; ++s) {
@@ -1030,6 +1141,8 @@ int orc_load_cell(orc_ctx* c, uint32_t lin, const uint32_t* node, const float* Q
         ce->end[s] = c->last[node[s]] + 1u;
     }
     rebuild_cdf(ce->Q, c->Meff, c->cfg.eps, ce->Qt, ce->C);
+    memset(ce->sum, 0, sizeof(ce->sum));
+    memset(ce->cnt, 0, sizeof(ce->cnt));
     ce->ready = 1;
     return ORC_OK;
 }

@@ -479,6 +479,44 @@ __global__ void __launch_bounds__(kCellWaves * kWave, 8) k_adapt16(AdaptParams /
     }
 }
 
+// Checkpoint load: one wavefront per cell.  The cell is found (or created)
+// by its key, its cut and Q are taken as given, the ends follow from the
+// tree, Q~ and C from Eq. 2 as at the end of a pass, and the write-back
+// clears the statistics and marks the cell ready.  The host has checked
+// that every cut is a partition of the lights.
+template <int PER>
+__global__ void __launch_bounds__(kWave) k_load_cells(AdaptParams /* read in place */,
+                                                      const unsigned long long* __restrict__ keys,
+                                                      const uint32_t* __restrict__ node, const float* __restrict__ Q,
+                                                      uint32_t n, uint32_t* err) {
+    const AdaptParams& ap = first_kernel_arg<AdaptParams>();
+    extern __shared__ uint32_t lds[];
+    const AdaptLds L = lds_view(lds, kWave * PER);
+    const uint32_t lane = threadIdx.x & (kWave - 1u);
+    const uint32_t Meff = ap.tmpl.Meff;
+    for (uint32_t i = blockIdx.x; i < n; i += gridDim.x) {
+        const unsigned long long key = keys[i];
+        uint32_t slot = RLC_NONE;
+        if (lane == 0) slot = find_or_create(ap.cells, key, (uint32_t)(key & 0xFFFFFFFFull), err);
+        slot = (uint32_t)__shfl((int)slot, 0, kWave);
+        if (slot == RLC_NONE) continue;
+#pragma unroll
+        for (int j = 0; j < PER; ++j) {
+            const uint32_t s = lane + kWave * j;
+            if (s < Meff) {
+                const uint32_t nd = node[(size_t)i * Meff + s];
+                L.node[s] = nd;
+                L.end[s] = ap.tree.last[nd] + 1u;
+                L.Q[s] = Q[(size_t)i * Meff + s];
+            }
+        }
+        wave_sync();
+        if (lane == 0) eq2_one_lane(ap, L, Meff);
+        wave_sync();
+        adapt_back<PER>(ap, slot, L);
+    }
+}
+
 __global__ void k_gather_cells(DevCells c, uint32_t Meff, const uint32_t* __restrict__ slots, uint32_t n,
                                uint32_t* node, uint32_t* end, float* Q, float* Qt, float* C,
                                unsigned long long* sum, uint32_t* cnt) {
@@ -518,6 +556,19 @@ hipError_t launch_adapt(const AdaptParams& ap, hipStream_t s) {
         hipLaunchKernelGGL(k_adapt<1>, dim3(8192), dim3(kWave), kLdsArrays * kWave * 4, s, ap);
     else
         hipLaunchKernelGGL(k_adapt<kMaxPerLane>, dim3(8192), dim3(kWave), kLdsArrays * RLC_MMAX * 4, s, ap);
+    return hipGetLastError();
+}
+
+hipError_t launch_load_cells(const AdaptParams& ap, const unsigned long long* keys, const uint32_t* node,
+                             const float* Q, uint32_t n, uint32_t* err, hipStream_t s) {
+    if (n == 0) return hipSuccess;
+    const uint32_t grid = n < 4096u ? n : 4096u;
+    if (ap.tmpl.Meff <= (uint32_t)kWave)
+        hipLaunchKernelGGL(k_load_cells<1>, dim3(grid), dim3(kWave), kLdsArrays * kWave * 4, s, ap, keys, node, Q, n,
+                           err);
+    else
+        hipLaunchKernelGGL(k_load_cells<kMaxPerLane>, dim3(grid), dim3(kWave), kLdsArrays * RLC_MMAX * 4, s, ap, keys,
+                           node, Q, n, err);
     return hipGetLastError();
 }
 

@@ -52,6 +52,7 @@ struct rlc_ctx {
     double* d_partial = nullptr;
 
     // derived constants
+    uint64_t cell_index_limit = 0;   // linear cell indices are below this
     float inv_cell[3] = {0, 0, 0};
     float jit_reach[3] = {0, 0, 0};
     float f_r = 0.0f;
@@ -84,11 +85,24 @@ struct rlc_ctx {
     // mixture with the learned proposal, and per-sample training records
     const float* mix_cdf = nullptr;
     uint32_t mix_rows = 0;
+    // footprint-sized cells: per-point footprints (caller memory), the
+    // finest cell edge and the first linear index of every level
+    const float* fp_arr = nullptr;
+    uint32_t fp_rows = 0;
+    float fp_base = 0.0f;
+    uint32_t lvl_first[RLC_MAX_LEVELS + 1] = {0};
     float mix_w = 0.5f;
     uint32_t* log_pid = nullptr;
     uint32_t* log_node = nullptr;
     float* log_w = nullptr;
     uint64_t log_cap = 0;
+
+    // batches built over this context: their captured graphs hold the
+    // context's buffer addresses, so rebuilding the tree or the occluders
+    // bumps the generation (the batch recaptures), and the context cannot be
+    // destroyed while a batch refers to it
+    uint32_t generation = 0;
+    uint32_t batch_refs = 0;
 
     // per-kernel timing
     bool timing = false;
@@ -176,6 +190,7 @@ void free_tree(rlc_ctx* c) {
     c->mix_cdf = nullptr;
     c->mix_rows = 0;
     c->tree_built = false;
+    c->generation += 1u;
 }
 
 void free_mlp(rlc_ctx* c) {
@@ -204,6 +219,7 @@ void free_occ(rlc_ctx* c) {
     c->occ = DevOcc{};
     c->occ_set = false;
     c->K = 0;
+    c->generation += 1u;
 }
 
 DevTree dev_tree(const rlc_ctx* c) {
@@ -244,6 +260,11 @@ FrameParams frame_params(const rlc_ctx* c) {
     fp.normal_bits = c->cfg.normal_bits;
     fp.jitter = c->cfg.jitter;
     fp.scene_id = c->cfg.scene_id;
+    fp.footprint = c->fp_arr;
+    fp.fp_levels = c->cfg.footprint_levels > 1u ? c->cfg.footprint_levels : 1u;
+    fp.fp_tile = c->cfg.footprint_tile;
+    fp.fp_base = c->fp_base;
+    for (uint32_t L = 0; L <= RLC_MAX_LEVELS; ++L) fp.lvl_first[L] = c->lvl_first[L];
     fp.seed_lo = (uint32_t)(c->cfg.seed & 0xFFFFFFFFull);
     fp.seed_hi = (uint32_t)(c->cfg.seed >> 32);
     fp.f_r = c->f_r;
@@ -292,6 +313,8 @@ int check_frame_args(rlc_ctx* c, const void* pos, uint32_t P, uint32_t spp) {
     if ((uint64_t)P * spp > 0xFFFFFFFFull) return fail(c, RLC_EINVAL, "P * spp exceeds 2^32 - 1");
     if (c->mix_cdf && P > c->mix_rows)
         return fail(c, RLC_EINVAL, "the mixture cdf has %u rows, the pass has %u points", c->mix_rows, P);
+    if (c->fp_arr && P > c->fp_rows)
+        return fail(c, RLC_EINVAL, "%u footprints are set, the pass has %u points", c->fp_rows, P);
     if (c->log_node && (uint64_t)P * spp > c->log_cap)
         return fail(c, RLC_EINVAL, "sample log holds %llu records, the pass has %llu",
                     (unsigned long long)c->log_cap, (unsigned long long)P * spp);
@@ -317,8 +340,13 @@ int read_device_errors(rlc_ctx* c) {
         RLC_HIP(c, launch_fill_u32(c->d_err, 0u, 1, c->stream));
         RLC_HIP(c, hipStreamSynchronize(c->stream));
         if (err & RLC_DERR_CAPACITY)
-            return fail(c, RLC_ECAPACITY, "cell table full (capacity %u); some samples were not learned from",
-                        c->cells.capacity);
+            return fail(c, RLC_ECAPACITY,
+                        "cell table full (capacity %u, or %u slots in a row taken); some samples were not learned from",
+                        c->cells.capacity, RLC_HASH_MAX_PROBES);
+        if (err & RLC_DERR_FX_OVERFLOW)
+            return fail(c, RLC_ECAPACITY,
+                        "a fixed-point reward sum of one (cell, cluster) exceeded 64 bits in one pass: "
+                        "lower fx_shift or reward_max; that pass's statistics are not valid");
         if (err & RLC_DERR_INPUT) return fail(c, RLC_EINVAL, "non-finite or inverted input");
         if (err & RLC_DERR_NONFINITE) return fail(c, RLC_EINVAL, "non-finite contribution");
     }
@@ -421,13 +449,26 @@ int rlc_create(const rlc_config* cfg, void* stream, rlc_ctx** out) {
               finite_f(k.reward_max) && k.reward_max > 0.0f && finite_f(k.t_lo) && k.t_lo >= 0.0f &&
               k.t_lo < 0.5f && k.reward_mode <= 1 && finite_f(k.albedo) && k.albedo >= 0.0f &&
               k.occ_grid_res <= 1024 && k.split_steps <= RLC_SPLIT_STEPS_MAX && k.normal_bits <= 8 &&
-              finite_f(k.jitter) && k.jitter >= 0.0f && k.jitter <= 1.0f;
+              finite_f(k.jitter) && k.jitter >= 0.0f && k.jitter <= 1.0f && k.footprint_levels <= RLC_MAX_LEVELS &&
+              (k.footprint_levels <= 1u || (finite_f(k.footprint_tile) && k.footprint_tile > 0.0f));
     for (int a = 0; a < 3; ++a)
         ok = ok && finite_f(k.grid_lo[a]) && finite_f(k.grid_hi[a]) && k.grid_hi[a] > k.grid_lo[a] &&
              k.grid_dims[a] >= 1 && k.grid_dims[a] <= (1u << 20);
     if (!ok) return RLC_EINVAL;
-    // cells of the 5-D grid: positions times normal bins (linear index: 32 bits)
-    uint64_t dense = ((uint64_t)k.grid_dims[0] * k.grid_dims[1] * k.grid_dims[2]) << (2u * k.normal_bits);
+    // one clamped reward in fixed point must fit 63 bits (two of them may
+    // wrap a sum: that is detected on the device and reported)
+    if (std::ldexp((double)k.reward_max, (int)k.fx_shift) > 9223372036854775808.0) return RLC_EINVAL;
+    // cells of the 5-D grid, positions times normal bins, over every level
+    // of footprint-sized cells (level-major linear index: 32 bits)
+    uint64_t lvl_first[RLC_MAX_LEVELS + 1] = {0};
+    const uint32_t nlev = k.footprint_levels > 1u ? k.footprint_levels : 1u;
+    for (uint32_t L = 0; L < nlev; ++L) {
+        uint64_t cells = 1;
+        for (int a = 0; a < 3; ++a) cells *= (uint64_t)(((k.grid_dims[a] - 1u) >> L) + 1u);
+        lvl_first[L + 1] = lvl_first[L] + (cells << (2u * k.normal_bits));
+    }
+    for (uint32_t L = nlev + 1; L <= RLC_MAX_LEVELS; ++L) lvl_first[L] = lvl_first[nlev];
+    const uint64_t dense = lvl_first[nlev];
     if (dense > 0xFFFFFFFFull) return RLC_EINVAL;
     uint64_t capacity;
     if (k.hashed) {
@@ -443,6 +484,12 @@ int rlc_create(const rlc_config* cfg, void* stream, rlc_ctx** out) {
     if (!c) return RLC_ENOMEM;
     c->cfg = k;
     c->stream = (hipStream_t)stream;
+    c->cell_index_limit = dense;
+    for (uint32_t L = 0; L <= RLC_MAX_LEVELS; ++L) c->lvl_first[L] = (uint32_t)lvl_first[L];
+    for (int a = 0; a < 3; ++a) {
+        const float e = (k.grid_hi[a] - k.grid_lo[a]) / (float)k.grid_dims[a];
+        if (a == 0 || e < c->fp_base) c->fp_base = e;
+    }
     for (int a = 0; a < 3; ++a) {
         c->inv_cell[a] = (float)k.grid_dims[a] / (k.grid_hi[a] - k.grid_lo[a]);
         c->jit_reach[a] = k.jitter * ((k.grid_hi[a] - k.grid_lo[a]) / (float)k.grid_dims[a]);
@@ -485,7 +532,9 @@ int rlc_create(const rlc_config* cfg, void* stream, rlc_ctx** out) {
 
 int rlc_destroy(rlc_ctx* c) {
     if (!c) return RLC_OK;
-    if (c->stream || true) (void)hipStreamSynchronize(c->stream);
+    if (c->batch_refs)
+        return fail(c, RLC_ESTATE, "the context belongs to %u batch(es): destroy them first", c->batch_refs);
+    (void)hipStreamSynchronize(c->stream);
     free_tree(c);
     free_occ(c);
     free_mlp(c);
@@ -718,12 +767,16 @@ int rlc_adapt_cuts(rlc_ctx* c) {
     return RLC_OK;
 }
 
-int rlc_frame(rlc_ctx* c, const float* d_pos, const float* d_nrm, uint32_t P, uint32_t spp, uint32_t frame,
-              float* d_radiance) {
-    RLC_TRY(check_frame_args(c, d_pos, P, spp));
-    if (P && (!d_nrm || !d_radiance)) return fail(c, RLC_EINVAL, "null normal or radiance array");
+}  // extern "C"
+
+namespace {
+
+// One pass (the fused kernel, then the end of pass), arguments checked;
+// with `timed`, HIP events around both kernels.
+int frame_pass(rlc_ctx* c, const float* d_pos, const float* d_nrm, uint32_t P, uint32_t spp, uint32_t frame,
+               float* d_radiance, bool timed) {
     hipEvent_t ev[3] = {nullptr, nullptr, nullptr};
-    if (c->timing) {
+    if (timed) {
         for (auto& e : ev) {
             e = take_event(c);
             if (!e) return fail(c, RLC_EHIP, "hipEventCreate failed");
@@ -731,24 +784,54 @@ int rlc_frame(rlc_ctx* c, const float* d_pos, const float* d_nrm, uint32_t P, ui
         RLC_HIP(c, hipEventRecord(ev[0], c->stream));
     }
     RLC_HIP(c, launch_frame(frame_params(c), d_pos, d_nrm, P, spp, frame, d_radiance, c->stream));
-    if (c->timing) RLC_HIP(c, hipEventRecord(ev[1], c->stream));
+    if (timed) RLC_HIP(c, hipEventRecord(ev[1], c->stream));
     RLC_HIP(c, launch_adapt(adapt_params(c), c->stream));
-    if (c->timing) {
+    if (timed) {
         RLC_HIP(c, hipEventRecord(ev[2], c->stream));
         for (auto& e : ev) c->pending.push_back(e);
     }
     return RLC_OK;
 }
 
-int rlc_frame_sub(rlc_ctx* c, const float* d_pos, const float* d_nrm, uint32_t P, uint32_t spp, uint32_t n_sub,
-                  uint32_t frame, float* d_radiance) {
+int check_sub_args(rlc_ctx* c, const float* d_pos, const float* d_nrm, uint32_t P, uint32_t spp, uint32_t n_sub,
+                   uint32_t frame, const float* d_radiance) {
     RLC_TRY(check_frame_args(c, d_pos, P, spp));
     if (n_sub == 0 || spp % n_sub != 0) return fail(c, RLC_EINVAL, "spp (%u) is not a multiple of n_sub (%u)", spp, n_sub);
     if ((uint64_t)frame * n_sub + (n_sub - 1u) > 0xFFFFFFFFull)
         return fail(c, RLC_EINVAL, "pass index of frame %u x %u sub-frames exceeds 32 bits", frame, n_sub);
+    if (P && (!d_nrm || !d_radiance)) return fail(c, RLC_EINVAL, "null normal or radiance array");
+    return RLC_OK;
+}
+
+// The n_sub passes of one frame; passes after the first write their
+// radiance to `buf` (P x 3 floats), which is then added to d_radiance.
+int sub_passes(rlc_ctx* c, const float* d_pos, const float* d_nrm, uint32_t P, uint32_t spp, uint32_t n_sub,
+               uint32_t frame, float* d_radiance, float* buf, bool timed) {
+    const size_t n = (size_t)P * 3;
+    const float scale = 1.0f / (float)n_sub;
+    for (uint32_t j = 0; j < n_sub; ++j) {
+        RLC_TRY(frame_pass(c, d_pos, d_nrm, P, spp / n_sub, frame * n_sub + j, j ? buf : d_radiance, timed));
+        if (j) RLC_HIP(c, launch_accum(d_radiance, buf, n, scale, j + 1u == n_sub, c->stream));
+    }
+    return RLC_OK;
+}
+
+}  // namespace
+
+extern "C" {
+
+int rlc_frame(rlc_ctx* c, const float* d_pos, const float* d_nrm, uint32_t P, uint32_t spp, uint32_t frame,
+              float* d_radiance) {
+    RLC_TRY(check_frame_args(c, d_pos, P, spp));
+    if (P && (!d_nrm || !d_radiance)) return fail(c, RLC_EINVAL, "null normal or radiance array");
+    return frame_pass(c, d_pos, d_nrm, P, spp, frame, d_radiance, c->timing);
+}
+
+int rlc_frame_sub(rlc_ctx* c, const float* d_pos, const float* d_nrm, uint32_t P, uint32_t spp, uint32_t n_sub,
+                  uint32_t frame, float* d_radiance) {
+    RLC_TRY(check_sub_args(c, d_pos, d_nrm, P, spp, n_sub, frame, d_radiance));
     if (n_sub == 1) return rlc_frame(c, d_pos, d_nrm, P, spp, frame, d_radiance);
     if (P == 0) return RLC_OK;
-    if (!d_nrm || !d_radiance) return fail(c, RLC_EINVAL, "null normal or radiance array");
     const size_t n = (size_t)P * 3;
     if (n > c->sub_cap) {
         // earlier passes may still read the old buffer
@@ -759,12 +842,7 @@ int rlc_frame_sub(rlc_ctx* c, const float* d_pos, const float* d_nrm, uint32_t P
         RLC_TRY(dalloc(c, &c->sub_buf, n));
         c->sub_cap = n;
     }
-    const float scale = 1.0f / (float)n_sub;
-    for (uint32_t j = 0; j < n_sub; ++j) {
-        RLC_TRY(rlc_frame(c, d_pos, d_nrm, P, spp / n_sub, frame * n_sub + j, j ? c->sub_buf : d_radiance));
-        if (j) RLC_HIP(c, launch_accum(d_radiance, c->sub_buf, n, scale, j + 1u == n_sub, c->stream));
-    }
-    return RLC_OK;
+    return sub_passes(c, d_pos, d_nrm, P, spp, n_sub, frame, d_radiance, c->sub_buf, c->timing);
 }
 
 int rlc_visible(rlc_ctx* c, const float* d_x, const float* d_y, uint32_t n, uint8_t* d_vis) {
@@ -890,6 +968,62 @@ int rlc_dump_cells(rlc_ctx* c, uint32_t max_cells, uint64_t* h_keys, uint32_t* h
     if (r != RLC_OK) return r;
     if (e != hipSuccess) return fail(c, RLC_EHIP, "dump: %s", hipGetErrorString(e));
     return RLC_OK;
+}
+
+int rlc_load_cells(rlc_ctx* c, uint32_t n, const uint64_t* h_keys, const uint32_t* h_node, const float* h_Q) {
+    RLC_TRY(need_tree(c));
+    if (n == 0) return RLC_OK;
+    if (!h_keys || !h_node || !h_Q) return fail(c, RLC_EINVAL, "null array");
+    RLC_TRY(rlc_sync(c));
+    const uint32_t N = c->N, Meff = c->Meff, nn = 2u * N - 1u;
+    std::vector<uint32_t> first(nn), last(nn);
+    RLC_HIP(c, hipMemcpy(first.data(), c->first, sizeof(uint32_t) * nn, hipMemcpyDeviceToHost));
+    RLC_HIP(c, hipMemcpy(last.data(), c->last, sizeof(uint32_t) * nn, hipMemcpyDeviceToHost));
+    std::vector<uint64_t> sorted(h_keys, h_keys + n);
+    std::sort(sorted.begin(), sorted.end());
+    for (uint32_t i = 0; i < n; ++i) {
+        const uint64_t key = sorted[i];
+        if ((key >> 32) != (uint64_t)c->cfg.scene_id || (key & 0xFFFFFFFFull) >= c->cell_index_limit)
+            return fail(c, RLC_EINVAL, "cell key %llu is not a cell of this scene", (unsigned long long)key);
+        if (i && key == sorted[i - 1]) return fail(c, RLC_EINVAL, "cell key %llu given twice", (unsigned long long)key);
+    }
+    if (!c->cfg.hashed && (uint64_t)n > c->cells.capacity) return fail(c, RLC_EINVAL, "more cells than the grid holds");
+    for (uint32_t i = 0; i < n; ++i) {
+        // the cut partitions the lights in range order: each node starts
+        // right after the previous one ends, the first at 0, the last at N-1
+        uint32_t next = 0;
+        for (uint32_t s = 0; s < Meff; ++s) {
+            const uint32_t nd = h_node[(size_t)i * Meff + s];
+            const float q = h_Q[(size_t)i * Meff + s];
+            if (nd >= nn || first[nd] != next)
+                return fail(c, RLC_EINVAL, "cell %u: the cut is not a partition of the lights at slot %u", i, s);
+            if (!(q >= 0.0f && q <= 3.402823466e38f))
+                return fail(c, RLC_EINVAL, "cell %u: Q[%u] is negative or not finite", i, s);
+            next = last[nd] + 1u;
+        }
+        if (next != N) return fail(c, RLC_EINVAL, "cell %u: the cut does not cover every light", i);
+    }
+    unsigned long long* dk = nullptr;
+    uint32_t* dn = nullptr;
+    float* dq = nullptr;
+    const size_t cnt = (size_t)n * Meff;
+    int r = dalloc(c, &dk, n);
+    if (r == RLC_OK) r = dalloc(c, &dn, cnt);
+    if (r == RLC_OK) r = dalloc(c, &dq, cnt);
+    hipError_t e = hipSuccess;
+    if (r == RLC_OK) {
+        e = hipMemcpyAsync(dk, h_keys, sizeof(uint64_t) * n, hipMemcpyHostToDevice, c->stream);
+        if (e == hipSuccess) e = hipMemcpyAsync(dn, h_node, sizeof(uint32_t) * cnt, hipMemcpyHostToDevice, c->stream);
+        if (e == hipSuccess) e = hipMemcpyAsync(dq, h_Q, sizeof(float) * cnt, hipMemcpyHostToDevice, c->stream);
+        if (e == hipSuccess) e = launch_load_cells(adapt_params(c), dk, dn, dq, n, c->d_err, c->stream);
+        if (e == hipSuccess) e = hipStreamSynchronize(c->stream);
+    }
+    dfree(dk);
+    dfree(dn);
+    dfree(dq);
+    if (r != RLC_OK) return r;
+    if (e != hipSuccess) return fail(c, RLC_EHIP, "load cells: %s", hipGetErrorString(e));
+    return read_device_errors(c);
 }
 
 int rlc_dump_tree(rlc_ctx* c, uint32_t* h_perm, uint32_t* h_left, uint32_t* h_right, uint32_t* h_parent,
@@ -1055,10 +1189,33 @@ int rlc_set_mixture(rlc_ctx* c, const float* d_cdf, uint32_t rows, float w) {
         return RLC_OK;
     }
     if (rows == 0) return fail(c, RLC_EINVAL, "the mixture cdf has no rows");
-    if (!(w >= 0.0f && w <= 1.0f)) return fail(c, RLC_EINVAL, "mixture weight must be in [0, 1]");
+    if (!(w >= 0.0f && w < 1.0f))
+        return fail(c, RLC_EINVAL, "the network's share w must be in [0, 1): alone it may give a light density 0");
+    if (w == 0.0f) {
+        // the tabular method alone
+        c->mix_cdf = nullptr;
+        c->mix_rows = 0;
+        return RLC_OK;
+    }
     c->mix_cdf = d_cdf;
     c->mix_rows = rows;
     c->mix_w = w;
+    return RLC_OK;
+}
+
+int rlc_set_footprints(rlc_ctx* c, const float* d_fp, uint32_t rows) {
+    if (!c) return RLC_EINVAL;
+    if (d_fp && rows) {
+        RLC_HIP(c, launch_fill_u32(c->d_err, 0u, 1, c->stream));
+        RLC_HIP(c, launch_check_nonneg(d_fp, rows, c->d_err, c->stream));
+        RLC_HIP(c, hipStreamSynchronize(c->stream));
+        const int r = read_device_errors(c);
+        if (r != RLC_OK) return fail(c, r, "footprints must be finite and >= 0");
+    }
+    // batches over this context capture their parameters again
+    c->generation += 1u;
+    c->fp_arr = (d_fp && rows) ? d_fp : nullptr;
+    c->fp_rows = c->fp_arr ? rows : 0u;
     return RLC_OK;
 }
 
@@ -1143,6 +1300,7 @@ struct rlc_batch {
     uint32_t* d_counter = nullptr;
     uint32_t* d_frame = nullptr;
     std::vector<uint32_t*> perms;  // cell-order visiting permutation per scene
+    std::vector<uint32_t> gens;    // each context's generation when the graph was captured
     hipGraph_t graph = nullptr;
     hipGraphExec_t exec = nullptr;
     uint32_t next_frame = 0;
@@ -1217,8 +1375,12 @@ int batch_upload(rlc_batch* b) {
         ha[i] = adapt_params(sc.ctx);
     }
     b->total_items = item;
+    // the previous graph may still read the tables
+    RLC_HIP(c0, hipStreamSynchronize(b->stream));
     RLC_HIP(c0, hipMemcpy(b->d_scenes, hs.data(), sizeof(BatchScene) * hs.size(), hipMemcpyHostToDevice));
     RLC_HIP(c0, hipMemcpy(b->d_adapt, ha.data(), sizeof(AdaptParams) * ha.size(), hipMemcpyHostToDevice));
+    b->gens.resize(b->scenes.size());
+    for (size_t i = 0; i < b->scenes.size(); ++i) b->gens[i] = b->scenes[i].ctx->generation;
     return RLC_OK;
 }
 
@@ -1299,6 +1461,7 @@ int rlc_batch_create(const rlc_batch_scene* scenes, uint32_t n, void* stream, rl
         if (e != hipSuccess) r = fail(c0, RLC_EHIP, "batch: %s", hipGetErrorString(e));
     }
     if (r == RLC_OK) r = batch_capture(b);
+    for (uint32_t i = 0; i < n; ++i) scenes[i].ctx->batch_refs += 1u;
     if (r != RLC_OK) {
         rlc_batch_destroy(b);
         return r;
@@ -1310,6 +1473,7 @@ int rlc_batch_create(const rlc_batch_scene* scenes, uint32_t n, void* stream, rl
 int rlc_batch_destroy(rlc_batch* b) {
     if (!b) return RLC_OK;
     (void)hipStreamSynchronize(b->stream);
+    for (auto& sc : b->scenes) sc.ctx->batch_refs -= 1u;
     batch_drop_graph(b);
     dfree(b->d_scenes);
     dfree(b->d_adapt);
@@ -1337,6 +1501,15 @@ int rlc_batch_get_schedule(rlc_batch* b, rlc_schedule* sched) {
 int rlc_batch_frame(rlc_batch* b, uint32_t frame) {
     if (!b) return RLC_EINVAL;
     rlc_ctx* c0 = b->scenes[0].ctx;
+    // a scene's tree or occluders were rebuilt since the capture: the graph
+    // holds freed addresses, so capture again from the current buffers
+    bool stale = false;
+    for (size_t i = 0; i < b->scenes.size(); ++i) {
+        const rlc_ctx* c = b->scenes[i].ctx;
+        if (c->generation != b->gens[i]) stale = true;
+        if (!c->tree_built) return fail(b->scenes[i].ctx, RLC_ESTATE, "batch scene %zu has no light tree", i);
+    }
+    if (stale) RLC_TRY(batch_capture(b));
     if (!b->frame_known || frame != b->next_frame) RLC_HIP(c0, launch_set_u32(b->d_frame, frame, b->stream));
     RLC_HIP(c0, hipGraphLaunch(b->exec, b->stream));
     b->next_frame = frame + 1;

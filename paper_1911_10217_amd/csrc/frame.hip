@@ -52,13 +52,13 @@ __device__ __forceinline__ void agg_add(AggTableT<SLOTS>& t, const FrameParams& 
     for (int probe = 0; probe < kAggProbes; ++probe) {
         const uint32_t old = atomicCAS(&t.bin[h], kNoBin, bin);
         if (old == kNoBin || old == bin) {
-            atomicAdd(&t.sum[h], q);
+            add_fixed(&t.sum[h], q, fp.err);
             atomicAdd(&t.cnt[h], 1u);
             return;
         }
         h = (h + 1u) & (SLOTS - 1);
     }
-    atomicAdd(&fp.cells.sum[bin], q);
+    add_fixed(&fp.cells.sum[bin], q, fp.err);
     atomicAdd(&fp.cells.cnt[bin], 1u);
 }
 
@@ -70,7 +70,7 @@ __device__ __forceinline__ void agg_flush(AggTableT<SLOTS>& t, const FrameParams
         const uint32_t n = t.cnt[j];
         if (n) {
             const size_t idx = t.bin[j];
-            atomicAdd(&fp.cells.sum[idx], t.sum[j]);
+            add_fixed(&fp.cells.sum[idx], t.sum[j], fp.err);
             atomicAdd(&fp.cells.cnt[idx], n);
             t.bin[j] = kNoBin;
             t.sum[j] = 0ull;

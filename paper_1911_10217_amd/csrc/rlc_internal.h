@@ -16,7 +16,10 @@
 #define RLC_DERR_CAPACITY 1u
 #define RLC_DERR_NONFINITE 2u
 #define RLC_DERR_INPUT 4u
+#define RLC_DERR_FX_OVERFLOW 8u   // a (cell, cluster) fixed-point reward sum wrapped 64 bits
+#define RLC_HASH_MAX_PROBES 256u  // probes of the cell hash before a lookup reports the table full
 #define RLC_MIX_M 64u           // nodes of the learned proposal's fixed cut (row stride of its cdf)
+#define RLC_MAX_LEVELS 16u      // footprint-sized cells: levels of cell size
 
 namespace rlc {
 
@@ -73,6 +76,14 @@ struct FrameParams {
     float jit_reach[3];         // jitter x cell size, per axis
     uint32_t scene_id;
     uint32_t seed_lo, seed_hi;
+    // footprint-sized cells: per point id the side of its footprint (null:
+    // the finest level everywhere), the level count, the tile, the finest
+    // cell edge, and the first linear index of every level
+    const float* footprint;
+    uint32_t fp_levels;
+    float fp_tile;
+    float fp_base;
+    uint32_t lvl_first[RLC_MAX_LEVELS + 1];
     float f_r;
     float t_lo;
     float reward_max;
@@ -85,7 +96,7 @@ struct FrameParams {
     const float* mix_cdf;
     const uint32_t* fix_end;    // cluster ends of the fixed cut
     uint32_t fix_M;
-    float mix_w;                // probability of drawing from the cell's cut
+    float mix_w;                // probability of drawing from the learned proposal
     // optional per-sample training records, index point * spp + sample
     uint32_t* log_pid;
     uint32_t* log_node;
@@ -193,15 +204,32 @@ __device__ __forceinline__ void tangent_frame(const float n[3], float t[3], floa
     b[2] = -n[1];
 }
 
+// Level of the point's position cells (section 3: cells sized from the
+// footprint of the shading point): the smallest level whose edge, the
+// finest edge doubled once per level, reaches tile x footprint.
+__device__ __forceinline__ uint32_t point_level(const FrameParams& fp, uint32_t pid) {
+    if (!fp.footprint) return 0u;
+    const float want = fp.fp_tile * fp.footprint[pid];
+    float edge = fp.fp_base;
+    uint32_t L = 0;
+    while (L + 1u < fp.fp_levels && edge < want) {
+        edge = edge * 2.0f;
+        ++L;
+    }
+    return L;
+}
+
 // The sample's cell in the 5-D grid of section 3 (three position and two
-// normal dimensions): the position, moved by up to jitter/2 cells in the
-// tangent plane, and the octahedral normal coordinates, moved by up to
-// jitter/2 bins (Philox tag 4 per sample), quantised by floor.  The linear
-// index is ix + dx (iy + dy (iz + dz (qu + 2^b qv))); without normal bins
-// and jitter it is the position cell.
+// normal dimensions): the position, moved by up to jitter/2 cells of its
+// level in the tangent plane, and the octahedral normal coordinates, moved
+// by up to jitter/2 bins (Philox tag 4 per sample), quantised by floor, the
+// position index shifted right by the point's level.  The linear index is
+// first(L) + ix + dx_L (iy + dy_L (iz + dz_L (qu + 2^b qv))); without
+// footprints, normal bins and jitter it is the position cell.
 __device__ __forceinline__ uint32_t cell_linear5(const FrameParams& fp, const float x[3], const float n[3],
                                                  uint32_t pid, uint32_t k, uint32_t frame) {
-    if (fp.normal_bits == 0u && !(fp.jitter > 0.0f)) return cell_linear(fp, x[0], x[1], x[2]);
+    const uint32_t L = point_level(fp, pid);
+    if (L == 0u && fp.normal_bits == 0u && !(fp.jitter > 0.0f)) return cell_linear(fp, x[0], x[1], x[2]);
     const uint32_t nb = 1u << fp.normal_bits;
     float p[3] = {x[0], x[1], x[2]};
     float u = 0.0f, v = 0.0f;
@@ -213,18 +241,24 @@ __device__ __forceinline__ uint32_t cell_linear5(const FrameParams& fp, const fl
         float t[3], b[3];
         tangent_frame(n, t, b);
 #pragma unroll
-        for (int a = 0; a < 3; ++a) p[a] = x[a] + fp.jit_reach[a] * (xi0 * t[a] + xi1 * b[a]);
+        for (int a = 0; a < 3; ++a) {
+            const float reach = fp.jit_reach[a] * (float)(1u << L);
+            p[a] = x[a] + reach * (xi0 * t[a] + xi1 * b[a]);
+        }
         if (fp.normal_bits) {
             u = u + ((unit24(w2) - 0.5f) * fp.jitter) / (float)nb;
             v = v + ((unit24(w3) - 0.5f) * fp.jitter) / (float)nb;
         }
     }
-    const uint32_t ix = axis_cell(p[0], fp.grid_lo[0], fp.inv_cell[0], fp.dims[0]);
-    const uint32_t iy = axis_cell(p[1], fp.grid_lo[1], fp.inv_cell[1], fp.dims[1]);
-    const uint32_t iz = axis_cell(p[2], fp.grid_lo[2], fp.inv_cell[2], fp.dims[2]);
+    const uint32_t ix = axis_cell(p[0], fp.grid_lo[0], fp.inv_cell[0], fp.dims[0]) >> L;
+    const uint32_t iy = axis_cell(p[1], fp.grid_lo[1], fp.inv_cell[1], fp.dims[1]) >> L;
+    const uint32_t iz = axis_cell(p[2], fp.grid_lo[2], fp.inv_cell[2], fp.dims[2]) >> L;
     const uint32_t qu = axis_cell(u, 0.0f, (float)nb, nb);
     const uint32_t qv = axis_cell(v, 0.0f, (float)nb, nb);
-    return ix + fp.dims[0] * (iy + fp.dims[1] * (iz + fp.dims[2] * (qu + nb * qv)));
+    const uint32_t dx = ((fp.dims[0] - 1u) >> L) + 1u;
+    const uint32_t dy = ((fp.dims[1] - 1u) >> L) + 1u;
+    const uint32_t dz = ((fp.dims[2] - 1u) >> L) + 1u;
+    return fp.lvl_first[L] + (ix + dx * (iy + dy * (iz + dz * (qu + nb * qv))));
 }
 
 __device__ __forceinline__ unsigned long long mix64(unsigned long long x) {
@@ -237,7 +271,9 @@ __device__ __forceinline__ unsigned long long mix64(unsigned long long x) {
     return x;
 }
 
-// Find the table slot of a cell key, creating the cell if it is absent.
+// Find the table slot of a cell key, creating the cell if it is absent
+// (RLC_NONE and the capacity error when RLC_HASH_MAX_PROBES slots in a row
+// are taken by other keys).
 // Creation only claims the slot and records it in the live list; the cell's
 // own table is filled at the end of the pass.  A slot's key changes once,
 // from empty to its key, by compare-and-swap, so the probe reads it with a
@@ -256,7 +292,10 @@ __device__ __forceinline__ uint32_t find_or_create(const DevCells& c, unsigned l
     }
     uint32_t mask = c.capacity - 1u;
     uint32_t h = (uint32_t)mix64(key) & mask;
-    for (uint32_t probe = 0; probe < c.capacity; ++probe) {
+    // a lookup gives up after a bounded run of occupied slots, so a nearly
+    // full table reports itself instead of walking all of its slots
+    const uint32_t probes = c.capacity < RLC_HASH_MAX_PROBES ? c.capacity : RLC_HASH_MAX_PROBES;
+    for (uint32_t probe = 0; probe < probes; ++probe) {
         unsigned long long k = c.keys[h];
         if (k == key) return h;
         if (k == RLC_EMPTY_KEY) {
@@ -324,7 +363,7 @@ __device__ __forceinline__ void draw_sample(const FrameParams& fp, const float x
         uint32_t c0 = pid, c1 = k, c2 = frame, c3 = (fp.scene_id << 16) | 1u;
         philox4x32_10(c0, c1, c2, c3, fp.seed_lo, fp.seed_hi);
         q = fp.mix_cdf + (size_t)pid * RLC_MIX_M;
-        use_mlp = !(unit24(c0) < fp.mix_w);
+        use_mlp = unit24(c0) < fp.mix_w;
     }
     const float total = C[Meff - 1u];
     const uint32_t Mf = fp.fix_M;
@@ -386,12 +425,12 @@ __device__ __forceinline__ void draw_sample(const FrameParams& fp, const float x
     const uint32_t size = end[s] - begin;
     float inv_pdf;
     if (q) {
-        // p(l) = w p_cut(l) + (1 - w) p_learned(l), each uniform inside its
+        // p(l) = (1 - w) p_cut(l) + w p_learned(l), each uniform inside its
         // cluster or node
         float pt = Qt[s] / ((float)size * total);
         float qk = q[kf] - (kf ? q[kf - 1u] : 0.0f);
         float pm = qk / ((float)fsize * q[Mf - 1u]);
-        inv_pdf = 1.0f / (fp.mix_w * pt + (1.0f - fp.mix_w) * pm);
+        inv_pdf = 1.0f / ((1.0f - fp.mix_w) * pt + fp.mix_w * pm);
     } else {
         inv_pdf = ((float)size * total) / Qt[s];
     }
@@ -468,6 +507,13 @@ __device__ __forceinline__ unsigned long long reward_fixed(const FrameParams& fp
     return (unsigned long long)rintf(rc * fp.fx_scale);
 }
 
+// sum += v on a fixed-point reward sum, latching the overflow error when
+// the 64-bit sum wraps (old + v < old); the statistics are then not used.
+__device__ __forceinline__ void add_fixed(unsigned long long* sum, unsigned long long v, uint32_t* err) {
+    const unsigned long long old = atomicAdd(sum, v);
+    if (old + v < old) atomicOr(err, RLC_DERR_FX_OVERFLOW);
+}
+
 // Parameters that stay the same for a whole launch, read through a pointer
 // that an empty asm statement makes opaque, typed in the constant address
 // space: each field is then loaded with s_load where it is used.  Read from
@@ -536,6 +582,8 @@ hipError_t launch_radix_tree(const uint32_t* morton, const uint32_t* perm, uint3
 hipError_t launch_initial_cut(DevTree tree, uint32_t M, uint32_t* node, uint32_t* end, float* Qt, float* C,
                               hipStream_t s);
 hipError_t launch_check_finite(const float* a, uint32_t n, uint32_t* err, hipStream_t s);
+// Latches RLC_DERR_INPUT for a negative or non-finite entry.
+hipError_t launch_check_nonneg(const float* a, uint32_t n, uint32_t* err, hipStream_t s);
 hipError_t launch_fill_u32(uint32_t* a, uint32_t v, size_t n, hipStream_t s);
 hipError_t launch_fill_u64(unsigned long long* a, unsigned long long v, size_t n, hipStream_t s);
 
@@ -577,6 +625,9 @@ hipError_t launch_batch_frame(const BatchScene* scenes, uint32_t n_scenes, uint3
 hipError_t launch_adapt(const AdaptParams& ap, hipStream_t s);
 // Meff: the largest cut size of the batch's scenes.
 hipError_t launch_batch_adapt(const AdaptParams* aps, uint32_t n_scenes, uint32_t Meff, hipStream_t s);
+// Checkpoint load of n cells (keys, cuts and Q of Meff entries each).
+hipError_t launch_load_cells(const AdaptParams& ap, const unsigned long long* keys, const uint32_t* node,
+                             const float* Q, uint32_t n, uint32_t* err, hipStream_t s);
 hipError_t launch_gather_cells(DevCells c, uint32_t Meff, const uint32_t* slots, uint32_t n, uint32_t* node,
                                uint32_t* end, float* Q, float* Qt, float* C, unsigned long long* sum,
                                uint32_t* cnt, hipStream_t s);

@@ -378,6 +378,11 @@ __global__ void k_check_finite(const float* __restrict__ a, uint32_t n, uint32_t
     if (i < n && !(fabsf(a[i]) <= 3.402823466e38f)) atomicOr(err, RLC_DERR_INPUT);
 }
 
+__global__ void k_check_nonneg(const float* __restrict__ a, uint32_t n, uint32_t* err) {
+    size_t i = (size_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (i < n && !(a[i] >= 0.0f && a[i] <= 3.402823466e38f)) atomicOr(err, RLC_DERR_INPUT);
+}
+
 __global__ void k_fill_u32(uint32_t* a, uint32_t v, size_t n) {
     for (size_t i = (size_t)blockIdx.x * blockDim.x + threadIdx.x; i < n; i += (size_t)gridDim.x * blockDim.x)
         a[i] = v;
@@ -497,6 +502,12 @@ hipError_t launch_initial_cut(DevTree tree, uint32_t M, uint32_t* node, uint32_t
 hipError_t launch_check_finite(const float* a, uint32_t n, uint32_t* err, hipStream_t s) {
     if (n == 0) return hipSuccess;
     hipLaunchKernelGGL(k_check_finite, dim3(blocks_for(n)), dim3(kBlock), 0, s, a, n, err);
+    return hipGetLastError();
+}
+
+hipError_t launch_check_nonneg(const float* a, uint32_t n, uint32_t* err, hipStream_t s) {
+    if (n == 0) return hipSuccess;
+    hipLaunchKernelGGL(k_check_nonneg, dim3(blocks_for(n)), dim3(kBlock), 0, s, a, n, err);
     return hipGetLastError();
 }
 

@@ -33,11 +33,12 @@ EXPORTS = (
     "rlc_set_occluders",
     "rlc_sample", "rlc_shade", "rlc_learn", "rlc_adapt_cuts", "rlc_frame", "rlc_frame_sub", "rlc_visible",
     "rlc_cell_keys", "rlc_image_error", "rlc_sync", "rlc_last_error", "rlc_num_cells", "rlc_meff",
-    "rlc_dump_cells", "rlc_dump_tree", "rlc_get_template", "rlc_set_timing", "rlc_get_timing",
+    "rlc_dump_cells", "rlc_load_cells", "rlc_dump_tree", "rlc_get_template", "rlc_set_timing", "rlc_get_timing",
     "rlc_batch_create", "rlc_batch_destroy", "rlc_batch_set_schedule", "rlc_batch_get_schedule",
     "rlc_batch_autotune", "rlc_batch_frame",
     "rlc_mlp_fixed_cut", "rlc_mlp_init", "rlc_mlp_set_params", "rlc_mlp_get_params", "rlc_mlp_forward",
     "rlc_mlp_grad", "rlc_mlp_train", "rlc_set_mixture", "rlc_set_sample_log", "rlc_get_mlp_timing",
+    "rlc_set_footprints",
 )
 RLC_MLP_PARAMS = 21760
 RLC_MLP_NODES = 64
@@ -74,6 +75,8 @@ class rlc_config(ctypes.Structure):
         ("seed", ctypes.c_uint64),
         ("normal_bits", ctypes.c_uint32),
         ("jitter", ctypes.c_float),
+        ("footprint_levels", ctypes.c_uint32),
+        ("footprint_tile", ctypes.c_float),
     ]
 
 
@@ -136,6 +139,7 @@ def _declare(L):
     L.rlc_num_cells.argtypes = [_vp, _vp]
     L.rlc_meff.argtypes = [_vp, _vp]
     L.rlc_dump_cells.argtypes = [_vp, _u32] + [_vp] * 9
+    L.rlc_load_cells.argtypes = [_vp, _u32, _vp, _vp, _vp]
     L.rlc_dump_tree.argtypes = [_vp] + [_vp] * 7
     L.rlc_get_template.argtypes = [_vp, _vp, _vp, _vp]
     L.rlc_batch_create.argtypes = [ctypes.POINTER(rlc_batch_scene), _u32, _vp, ctypes.POINTER(_vp)]
@@ -156,6 +160,7 @@ def _declare(L):
     L.rlc_mlp_grad.argtypes = [_vp, _vp, _vp, _u32, _vp, _vp, _vp, _u32, _vp, _vp]
     L.rlc_mlp_train.argtypes = [_vp, _vp, _vp, _u32, _vp, _vp, _vp, _u32, _u32, _u32, f, _vp]
     L.rlc_set_mixture.argtypes = [_vp, _vp, _u32, f]
+    L.rlc_set_footprints.argtypes = [_vp, _vp, _u32]
     L.rlc_set_sample_log.argtypes = [_vp, _vp, _vp, _vp, ctypes.c_uint64]
     L.rlc_get_mlp_timing.argtypes = [_vp, _vp, _vp, _vp]
     for name in EXPORTS:
@@ -213,6 +218,8 @@ def make_config(params: dict) -> rlc_config:
     c.seed = int(params["seed"])
     c.normal_bits = int(params.get("normal_bits", 0))
     c.jitter = float(params.get("jitter", 0.0))
+    c.footprint_levels = int(params.get("footprint_levels", 0))
+    c.footprint_tile = float(params.get("footprint_tile", 0.0))
     return c
 
 
@@ -241,9 +248,11 @@ class Context:
             raise RLCError(rc, "%s: %s" % (what, msg.decode() if msg else ""))
 
     def close(self):
+        """rlc_destroy; refused (RLCError, the context stays usable) while a
+        batch refers to the context."""
         h = getattr(self, "_h", None)
         if h is not None and h.value:
-            lib().rlc_destroy(h)
+            self._check(lib().rlc_destroy(h), "rlc_destroy")
         self._h = None
 
     def __del__(self):
@@ -395,6 +404,17 @@ class Context:
                         "rlc_dump_cells")
         return d
 
+    def rlc_load_cells(self, keys, node, Q):
+        """Checkpoint load: keys (n,), node and Q (n, Meff), host arrays, as
+        rlc_dump_cells gives them for ready cells."""
+        keys = np.ascontiguousarray(keys, np.uint64).reshape(-1)
+        n = keys.size
+        m = self.rlc_meff()
+        node = np.ascontiguousarray(node, np.uint32).reshape(n, m)
+        Q = np.ascontiguousarray(Q, np.float32).reshape(n, m)
+        self._check(lib().rlc_load_cells(self._h, n, keys.ctypes.data, node.ctypes.data, Q.ctypes.data),
+                    "rlc_load_cells")
+
     def rlc_dump_tree(self) -> dict:
         N = self.N
         nn = 2 * N - 1
@@ -521,6 +541,18 @@ class Context:
         rows = cdf.numel() // RLC_MLP_NODES
         self._mix_keep = cdf
         self._check(lib().rlc_set_mixture(self._h, _ptr(cdf), rows, float(w)), "rlc_set_mixture")
+
+    def rlc_set_footprints(self, fp=None):
+        """Per-point footprint sides (a float32 device tensor, one per point)
+        for footprint-sized cells, or None for the finest level everywhere."""
+        import torch
+        if fp is None:
+            self._fp_keep = None
+            self._check(lib().rlc_set_footprints(self._h, None, 0), "rlc_set_footprints")
+            return
+        _dev(fp, torch.float32, "footprints")
+        self._check(lib().rlc_set_footprints(self._h, _ptr(fp), fp.numel()), "rlc_set_footprints")
+        self._fp_keep = fp
 
     def rlc_set_sample_log(self, pid=None, node=None, w=None):
         import torch

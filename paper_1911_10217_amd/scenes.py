@@ -85,6 +85,7 @@ class Scene:
     emission_at: Optional[Callable[[int], np.ndarray]] = None  # frame -> (N, 3)
     image_size: Optional[tuple] = None
     pixel: Optional[np.ndarray] = None   # image position (row * width + col) of each point
+    footprint: Optional[np.ndarray] = None  # (P,) side of each primary hit's pixel footprint
 
     def to_image(self, values: np.ndarray) -> np.ndarray:
         """Per-point values (P, ...) laid out as the (height, width, ...) image."""
@@ -159,9 +160,13 @@ def _primary_hits(boxes: np.ndarray, width: int, height: int, cam=(0.5, 0.45, 0.
     """Cast one ray through every pixel centre of a pinhole camera at `cam`
     looking at `look` (default: along +z), +y up.
 
-    Returns float32 positions snapped onto the face that was hit and the
-    axis-aligned face normal pointing back towards the camera.  Pixels are in
-    row-major order, top row first.
+    Returns float32 positions snapped onto the face that was hit, the
+    axis-aligned face normal pointing back towards the camera, and the side
+    of each hit's pixel footprint: the square root of the surface area the
+    pixel covers, t s sqrt(cos^3(alpha) / cos(theta)) for a hit at distance
+    t, pixel pitch s on the image plane at distance 1, alpha the ray's angle
+    to the optical axis and theta its angle to the surface normal.  Pixels
+    are in row-major order, top row first.
     """
     o = np.asarray(cam, dtype=np.float64)
     fwd = (np.asarray(look, np.float64) - o) if look is not None else np.array([0.0, 0.0, 1.0])
@@ -250,7 +255,11 @@ def _primary_hits(boxes: np.ndarray, width: int, height: int, cam=(0.5, 0.45, 0.
     rows = np.arange(n_pix)
     p[rows, axis_best] = plane_best
     nrm[rows, axis_best] = -np.sign(d[rows, axis_best])
-    return _f32(p), _f32(nrm)
+    pitch = 2.0 * tan_h / height
+    cos_a = d @ fwd
+    cos_t = np.maximum(np.abs(d[rows, axis_best]), 1e-6)
+    fp = t_best * pitch * np.sqrt(cos_a ** 3 / cos_t)
+    return _f32(p), _f32(nrm), _f32(fp)
 
 
 def tiled_pixel_order(width: int, height: int, tile: int = 16, sub: int = 8) -> np.ndarray:
@@ -288,13 +297,14 @@ def make_static(width=1920, height=1080, n_clusters=256, per_cluster=256, n_boxe
         _random_boxes(rng, n_louvre, [0.0, 0.78, 0.0], [1.0, 0.86, 1.0]),
         _random_boxes(rng, n_air, [0.0, 0.15, 0.2], [1.0, 0.7, 1.0]),
     ]).astype(np.float32)
-    pos, nrm = _primary_hits(boxes, width, height, cam=(0.1, 0.7, 0.05), look=(0.7, 0.1, 0.8))
+    pos, nrm, fp = _primary_hits(boxes, width, height, cam=(0.1, 0.7, 0.05), look=(0.7, 0.1, 0.8))
     order = tiled_pixel_order(width, height)
     params = params_for(M=M, spp=spp, frames=frames, grid_dims=(64, 64, 64), hashed=1,
                         capacity=capacity, seed=seed, occ_grid_res=64)
     params.update(overrides)
     return Scene("static", tri, emit, boxes, np.ascontiguousarray(pos[order]), np.ascontiguousarray(nrm[order]),
-                 params, image_size=(height, width), pixel=order.astype(np.int64))
+                 params, image_size=(height, width), pixel=order.astype(np.int64),
+                 footprint=np.ascontiguousarray(fp[order]))
 
 
 # --------------------------------------------------------------------------

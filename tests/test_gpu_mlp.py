@@ -1,10 +1,15 @@
 """The learned proposal on the GPU, through the C ABI, against the oracle.
 
-Network numbers (forward, gradient, Adam training) are compared with the
+The forward pass and the gradient are compared element by element with the
 oracle's FP64 evaluation that rounds to BF16 where the kernels hold BF16
-values, within a relative L2 error of 1e-2 per tensor.  The mixture pass is
-compared exactly (cells) and to 1e-4 (radiance) with both sides reading
-the same cdf table, an input of the test."""
+values: at least 99.9% of the entries within 1e-4 relative error (relative
+to the entry, or to 1e-3 of the tensor's largest entry when that is
+larger), and every entry within one BF16 rounding step (2^-8 relative): the
+kernels sum in FP32 in another order, so a value that the oracle rounds to
+BF16 next to a rounding boundary may land one BF16 step away.  Adam
+training is compared per tensor.  The mixture pass is compared exactly
+(cells) and to 1e-4 (radiance) with both sides reading the same cdf table,
+an input of the test."""
 import math
 
 import numpy as np
@@ -50,6 +55,17 @@ def _rel_l2(a, b):
     return np.linalg.norm(a - b) / max(np.linalg.norm(b), 1e-30)
 
 
+def _elementwise(gpu, ref, what, rtol=1e-4, frac=0.999, flip=2.0 ** -8, floor=1e-3):
+    """|gpu - ref| <= rtol max(|ref|, floor max|ref|) for at least `frac` of
+    the entries, and <= flip max(|ref|, floor max|ref|) for all of them."""
+    a = np.asarray(gpu, np.float64).reshape(-1)
+    b = np.asarray(ref, np.float64).reshape(-1)
+    scale = np.maximum(np.abs(b), floor * np.abs(b).max())
+    r = np.abs(a - b) / np.maximum(scale, 1e-300)
+    assert (r <= rtol).mean() >= frac, (what, float((r <= rtol).mean()), float(r.max()))
+    assert r.max() <= flip, (what, float(r.max()))
+
+
 def _ctx(torch, s):
     from paper_1911_10217_amd import rlc
     t = lambda a: torch.from_numpy(np.ascontiguousarray(a)).cuda()
@@ -74,13 +90,14 @@ def test_forward_matches_oracle(torch, orc, P):
     z = z.cpu().numpy()
     cdf = cdf.cpu().numpy()
     zo, qo = orc.mlp_forward(params.astype(np.float64), _encode(orc, s), bf16=True)
-    assert _rel_l2(z, zo) < 1e-2
+    _elementwise(z, zo, "logits")
     # the table is the running sum of the probabilities, ending at 1
     assert (np.diff(cdf, axis=1) >= 0).all()
     assert np.allclose(cdf[:, -1], 1.0, atol=2e-5)
     q = np.diff(np.concatenate([np.zeros((P, 1), np.float32), cdf], 1), axis=1)
-    assert np.abs(q - qo).max() < 1e-2
-    assert _rel_l2(q, qo) < 1e-2
+    # differences of FP32 running sums: absolute error up to a few ulp of 1
+    assert np.abs(q - qo).max() < 1e-5
+    _elementwise(q, qo, "probabilities")
 
 
 def test_gradient_matches_oracle(torch, orc):
@@ -100,9 +117,10 @@ def test_gradient_matches_oracle(torch, orc):
     x = _encode(orc, s)
     lo, go = orc.mlp_loss_grad(params.astype(np.float64), x[pid], node.astype(np.uint32), w.astype(np.float64),
                                bf16=True)
-    assert loss == pytest.approx(lo, rel=1e-3)
-    for (kind, a), (_, b) in zip(_tensors(grad), _tensors(go)):
-        assert _rel_l2(a, b) < 1e-2, kind
+    assert loss == pytest.approx(lo, rel=1e-5)
+    _elementwise(grad, go, "gradient")
+    for i, ((kind, a), (_, b)) in enumerate(zip(_tensors(grad), _tensors(go))):
+        _elementwise(a, b, "%s%d" % (kind, i // 2 + 1), frac=0.99)
     # no tuples, or only zero weights: zero gradient
     z = np.zeros(5, np.float32)
     loss0, g0 = ctx.rlc_mlp_grad(pos, nrm, g(pid[:5]), g(node[:5]), g(z))
@@ -206,8 +224,9 @@ def _cdf_input(P, seed, sharp=3.0):
     return q / q.sum(1, keepdims=True)
 
 
-@pytest.mark.parametrize("w", [0.5, 0.0, 1.0])
+@pytest.mark.parametrize("w", [0.5, 0.0, 0.9])
 def test_mixture_frames_match_oracle(torch, orc, w):
+    """w is the network's share; w = 0 is the plain method on both sides."""
     s = scenes.make_tiny(n_lights=500, n_points=1000, spp=4, M=16)
     ctx, pos, nrm = _ctx(torch, s)
     o = orc.Oracle(s.params, s.tri, s.emit, s.boxes)
@@ -235,7 +254,7 @@ def test_mixture_frames_match_oracle(torch, orc, w):
         # a cell whose pass held no draws from its cut keeps sampling from the
         # initial cut; its table is compared once it has one
         r = g["ready"] == 1
-        assert r.any() or w == 0.0
+        assert r.any()
         for k in ("node", "end", "Q", "Qt", "C"):
             assert np.array_equal(g[k][r], c[k][r]), (f, k)
     ctx.rlc_set_sample_log()
@@ -282,6 +301,10 @@ def test_mixture_rejects_short_tables(torch):
     with pytest.raises(rlc.RLCError):
         ctx.rlc_frame(pos, nrm, 1, 0)
     ctx.rlc_set_mixture()
+    # the network alone (w = 1) may give a light density 0: refused
+    for w in (1.0, 1.5, -0.1, float("nan")):
+        with pytest.raises(rlc.RLCError):
+            ctx.rlc_set_mixture(torch.ones((64, 64), device="cuda"), w)
     lp = torch.zeros(10, dtype=torch.int32, device="cuda")
     ctx.rlc_set_sample_log(lp, lp.clone(), torch.zeros(10, device="cuda"))
     with pytest.raises(rlc.RLCError):

@@ -394,6 +394,56 @@ def test_errors(torch):
     assert e.value.code == rlc.RLC_ECAPACITY
     assert torch.isfinite(rad).all()
     small.rlc_sync()  # the error was reported once
+    # one clamped reward in fixed point must fit 63 bits
+    with pytest.raises(rlc.RLCError):
+        rlc.Context(dict(s.params, fx_shift=40, reward_max=float(2 ** 24)))
+
+
+def test_fixed_point_overflow_is_reported(torch):
+    """reward_max 2^23 at fx_shift 40: one clamped reward is 2^63, so two in
+    one (cell, cluster) wrap the 64-bit sum.  The oracle flags the case, and
+    the library reports it at the next synchronising call instead of
+    learning from a wrapped sum; the pass's radiance is unaffected."""
+    from paper_1911_10217_amd import rlc
+    rng = np.random.default_rng(5)
+    v = rng.uniform([0.0, 0.9, 0.0], [1.0, 1.0, 1.0], size=(16, 3, 3))
+    tri = v.reshape(16, 9).astype(np.float32)
+    emit = (rng.random((16, 3)) * 1e12).astype(np.float32)
+    pos = rng.uniform([0.05, 0.05, 0.05], [0.95, 0.6, 0.95], size=(8, 3)).astype(np.float32)
+    nrm = np.zeros((8, 3), np.float32)
+    nrm[:, 1] = 1.0
+    p = scenes.params_for(M=1, fx_shift=40, reward_max=float(2 ** 23))
+    ctx = rlc.Context(p)
+    ctx.rlc_build_light_tree(_t(torch, tri), _t(torch, emit))
+    ctx.rlc_set_occluders(None)
+    o = oracle.Oracle(p, tri, emit, None)
+    rad = ctx.rlc_frame(_t(torch, pos), _t(torch, nrm), 4, 0).cpu().numpy()
+    ref, _ = o.frame(pos, nrm, 4, 0)
+    assert np.array_equal(rad, ref)
+    assert o.status() == 1
+    with pytest.raises(rlc.RLCError) as e:
+        ctx.rlc_sync()
+    assert e.value.code == rlc.RLC_ECAPACITY and "64 bits" in str(e.value)
+    ctx.rlc_sync()
+
+
+def test_hash_full_at_realistic_capacity_ends_normally(torch):
+    """A table of 4,096 slots offered about 60,000 distinct cells fills up;
+    every lookup stops after a bounded probe run, the pass ends, the error
+    is reported once, and the radiance stays finite."""
+    from paper_1911_10217_amd import rlc
+    s = scenes.make_tiny(n_points=60000, spp=1, n_boxes=0)
+    p = dict(s.params, grid_dims=(64, 64, 64), hashed=1, capacity=4096)
+    ctx = rlc.Context(p)
+    ctx.rlc_build_light_tree(_t(torch, s.tri), _t(torch, s.emit))
+    ctx.rlc_set_occluders(None)
+    rad = ctx.rlc_frame(_t(torch, s.pos), _t(torch, s.nrm), 1, 0)
+    with pytest.raises(rlc.RLCError) as e:
+        ctx.rlc_sync()
+    assert e.value.code == rlc.RLC_ECAPACITY
+    assert torch.isfinite(rad).all()
+    assert ctx.rlc_num_cells() <= 4096
+    ctx.rlc_sync()
 
 
 def test_image_error_fp64(torch):
@@ -509,3 +559,131 @@ def test_frame_sub_parity(torch, n_sub):
             ctx.rlc_frame_sub(pos, nrm, bad["spp"], bad["n_sub"], bad["frame"])
         assert e.value.code == rlc.RLC_EINVAL
     ctx.rlc_sync()
+
+
+# --------------------------------------------------------------------------
+# checkpoint and resume: cells dumped after pass k and loaded into a fresh
+# context continue as the uninterrupted context and as the oracle loaded
+# from the same dump
+# --------------------------------------------------------------------------
+@pytest.mark.parametrize("hashed", [0, 1])
+def test_checkpoint_resume(torch, hashed):
+    from paper_1911_10217_amd import rlc
+    s = scenes.make_tiny(n_points=3000, spp=4, M=16, hashed=hashed, capacity=4096)
+    pos, nrm = _t(torch, s.pos), _t(torch, s.nrm)
+    a, _ = _make(torch, s)
+    b, _ = _make(torch, s)
+    rad_a = []
+    for f in range(6):
+        rad_a.append(a.rlc_frame(pos, nrm, 4, f).cpu().numpy())
+        if f < 3:
+            b.rlc_frame(pos, nrm, 4, f)
+    d = b.rlc_dump_cells()
+    r = d["ready"] == 1
+    assert r.sum() > 100
+    c, orc = _make(torch, s)
+    c.rlc_load_cells(d["key"][r], d["node"][r], d["Q"][r])
+    for k, node, q in zip(d["key"][r], d["node"][r], d["Q"][r]):
+        orc.load_cell(int(k) & 0xFFFFFFFF, node, q)
+    dc = c.rlc_dump_cells()
+    for k in ("key", "ready", "node", "end", "Q", "Qt", "C", "sum", "cnt"):
+        assert np.array_equal(dc[k], d[k][r]), k
+    for f in range(3, 6):
+        rc = c.rlc_frame(pos, nrm, 4, f).cpu().numpy()
+        ro, _ = orc.frame(s.pos, s.nrm, 4, f)
+        orc.adapt()
+        assert np.array_equal(rc, rad_a[f]), f
+        assert np.array_equal(rc, ro), f
+    _assert_cells_equal(c.rlc_dump_cells(), a.rlc_dump_cells())
+    _assert_cells_equal(c.rlc_dump_cells(), orc.cells())
+
+
+def test_checkpoint_load_rejects_bad_cells(torch):
+    from paper_1911_10217_amd import rlc
+    s = scenes.make_tiny(n_points=500, spp=1, M=16)
+    ctx, orc = _make(torch, s)
+    node, _ = orc.template()
+    t = orc.tree()
+    q = np.ones(16, np.float32)
+    key = int(orc.cell_keys(s.pos[:1])[0])
+    gap = node.copy()
+    gap[0] = t["left"][node[0]]
+    swapped = node[np.r_[1, 0, 2:16]]
+    cases = [
+        ([key], [gap], [q]),                                     # not a partition
+        ([key], [swapped], [q]),                                 # out of range order
+        ([key], [node], [np.where(np.arange(16) == 3, -1.0, 1.0).astype(np.float32)]),
+        ([key | (7 << 32)], [node], [q]),                        # another scene's key
+        ([8 ** 3], [node], [q]),                                 # outside the grid
+        ([key, key], [node, node], [q, q]),                      # repeated
+    ]
+    for keys, nodes, qs in cases:
+        with pytest.raises(rlc.RLCError) as e:
+            ctx.rlc_load_cells(np.array(keys, np.uint64), np.array(nodes), np.array(qs))
+        assert e.value.code == rlc.RLC_EINVAL
+    assert ctx.rlc_num_cells() == 0
+    ctx.rlc_load_cells(np.array([key], np.uint64), node[None], q[None])
+    assert ctx.rlc_num_cells() == 1
+
+
+# --------------------------------------------------------------------------
+# footprint-sized cells: per-point footprints choose each point's level of
+# cell size; keys, cells and radiance against the oracle
+# --------------------------------------------------------------------------
+def _footprint_scene(kind):
+    if kind == "static":
+        s = scenes.make_static(width=320, height=180, capacity=1 << 15, footprint_levels=5, footprint_tile=48.0)
+        return s, s.footprint
+    rng = np.random.default_rng(17)
+    if kind == "tiny_dense":
+        s = scenes.make_tiny(n_points=3000, spp=4, M=16, footprint_levels=3, footprint_tile=8.0)
+        return s, (rng.random(s.P) * 4.0 / 8.0 / 8.0).astype(np.float32)
+    extra = dict(normal_bits=2, jitter=1.0) if kind == "tiny_5d_jitter" else {}
+    s = scenes.make_tiny(n_points=3000, spp=4, M=16, grid_dims=(64, 64, 64), hashed=1, capacity=1 << 14,
+                         footprint_levels=4, footprint_tile=16.0, **extra)
+    return s, (rng.random(s.P) * 10.0 / 64.0 / 16.0).astype(np.float32)
+
+
+@pytest.mark.parametrize("kind", ["tiny_dense", "tiny_hashed", "tiny_5d_jitter", "static"])
+def test_footprint_cells_parity(torch, kind):
+    s, fp = _footprint_scene(kind)
+    ctx, orc = _make(torch, s)
+    pos, nrm = _t(torch, s.pos), _t(torch, s.nrm)
+    fpt = _t(torch, fp)
+    ctx.rlc_set_footprints(fpt)
+    orc.set_footprints(fp)
+    levels = orc.point_levels(s.P)
+    assert len(np.unique(levels)) >= 2, np.unique(levels)
+    spp = s.params["spp"]
+    for f in range(5):
+        rad = ctx.rlc_frame(pos, nrm, spp, f).cpu().numpy()
+        ref, _ = orc.frame(s.pos, s.nrm, spp, f)
+        orc.adapt()
+        ok, err = _rad_close(rad, ref, spp)
+        assert ok, (kind, f, err)
+    ctx.rlc_sync()
+    _assert_cells_equal(ctx.rlc_dump_cells(), orc.cells())
+    # the per-sample keys of the split path carry the levels too
+    smp = ctx.rlc_sample(pos, nrm, spp, 5)
+    _, rec = orc.frame(s.pos, s.nrm, spp, 5, records=True)
+    assert np.array_equal(smp["key"].cpu().numpy().astype(np.uint64), rec["key"])
+
+
+def test_footprint_errors(torch):
+    from paper_1911_10217_amd import rlc
+    s = scenes.make_tiny(n_points=100, spp=1, footprint_levels=3, footprint_tile=8.0)
+    ctx, _ = _make(torch, s)
+    pos, nrm = _t(torch, s.pos), _t(torch, s.nrm)
+    for bad in (np.float32([1, -1]), np.float32([np.nan, 1]), np.float32([np.inf, 0])):
+        with pytest.raises(rlc.RLCError) as e:
+            ctx.rlc_set_footprints(_t(torch, bad))
+        assert e.value.code == rlc.RLC_EINVAL
+    ctx.rlc_set_footprints(_t(torch, np.zeros(50, np.float32)))
+    with pytest.raises(rlc.RLCError):
+        ctx.rlc_frame(pos, nrm, 1, 0)  # 100 points, 50 footprints
+    ctx.rlc_set_footprints(None)
+    ctx.rlc_frame(pos, nrm, 1, 0)
+    for bad in (dict(footprint_levels=17), dict(footprint_levels=2, footprint_tile=0.0),
+                dict(footprint_levels=2, footprint_tile=float("nan"))):
+        with pytest.raises(rlc.RLCError):
+            rlc.Context(dict(s.params, **bad))

@@ -435,27 +435,31 @@ def test_mixture_pdf_sums_to_one_and_matches_draw_frequencies(orc):
     assert abs(rec["comp"].mean() - 0.5) < 0.02
 
 
-def test_mixture_weight_one_reproduces_the_plain_draws(orc):
+def test_mixture_weight_zero_is_the_plain_method(orc):
+    """w is the network's share: w = 0 turns the mixture off, so the draws,
+    densities, radiance and cells are the plain method's, bit for bit."""
     rng = np.random.default_rng(13)
     s, o = _mix_scene(orc)
     s2, o2 = _mix_scene(orc)
-    o.set_mixture(orc.mlp_cdf(_random_cdf(rng, s.P)), 1.0)
+    o.set_mixture(orc.mlp_cdf(_random_cdf(rng, s.P)), 0.0)
     r1, a = o.frame(s.pos, s.nrm, 4, 0, records=True)
     r2, b = o2.frame(s.pos, s.nrm, 4, 0, records=True)
     assert np.array_equal(a["light"], b["light"]) and not a["comp"].any()
-    assert np.allclose(a["inv_pdf"], b["inv_pdf"], rtol=1e-6)
+    assert np.array_equal(a["inv_pdf"], b["inv_pdf"]) and np.array_equal(r1, r2)
     o.adapt()
     o2.adapt()
     ca, cb = o.cells(), o2.cells()
-    assert all(np.array_equal(ca[k], cb[k]) for k in ("node", "Q", "C"))
+    assert all(np.array_equal(ca[k], cb[k]) for k in ("key", "node", "end", "Q", "Qt", "C"))
 
 
-def test_mixture_weight_zero_draws_only_inside_likely_nodes(orc):
+def test_mixture_weight_one_draws_only_inside_likely_nodes(orc):
+    """w = 1, the network alone (the oracle accepts it to pin the proposal's
+    own draws): only nodes of positive learned probability are drawn."""
     s, o = _mix_scene(orc)
     q = np.zeros((s.P, 64))
     q[:, 7] = 0.75
     q[:, 40] = 0.25
-    o.set_mixture(orc.mlp_cdf(q), 0.0)
+    o.set_mixture(orc.mlp_cdf(q), 1.0)
     _, rec = o.frame(s.pos, s.nrm, 8, 0, records=True)
     assert set(np.unique(rec["fnode"]).tolist()) == {7, 40} and rec["comp"].all()
     fend = o.fixed_cut()[1]

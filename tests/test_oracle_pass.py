@@ -150,7 +150,8 @@ def test_scatter_cluster_total_rewards(orc):
 def test_scatter_skips_draws_of_the_learned_proposal(orc):
     """With the mixture on, a sample draws from the learned proposal when
     the first word of Philox at (point, sample, frame, scene << 16 | 1), as
-    a unit float, is not below w; those draws feed no statistics."""
+    a unit float, is below w (the network's share); those draws feed no
+    statistics."""
     o, tri, emit, pos, nrm, p = _scene(orc, n_lights=200, M=8)
     P, spp, w = pos.shape[0], 32, 0.5
     rng = np.random.default_rng(3)
@@ -163,7 +164,7 @@ def test_scatter_skips_draws_of_the_learned_proposal(orc):
     ctr = np.stack([pid, k, np.zeros_like(pid), np.full_like(pid, (p["scene_id"] << 16) | 1)], 1)
     seed = p["seed"]
     x0 = orc.philox(ctr, [seed & 0xFFFFFFFF, seed >> 32])[:, 0]
-    cut = ((x0 >> 8).astype(np.float64) * 2.0 ** -24) < w
+    cut = ~(((x0 >> 8).astype(np.float64) * 2.0 ** -24) < w)
     assert 0.3 < cut.mean() < 0.7
     assert np.array_equal(rec["comp"] == 0, cut)
     want, _, _ = _expected_stats(o, p, tri, emit, pos, nrm, spp, rec, counted=cut)
@@ -349,3 +350,93 @@ def test_no_temporal_learning_restarts_from_the_initial_cut(orc):
         assert (c["node"] == tnode[None, :]).all() and (c["end"] == tend[None, :]).all()
         assert not c["Q"].any() and (c["Qt"] == 1.0).all()
         assert (c["C"] == np.arange(1, 9, dtype=np.float32)[None, :]).all()
+
+
+# --------------------------------------------------------------------------
+# fixed-point range: a (cell, cluster) sum that wraps 64 bits is flagged
+# --------------------------------------------------------------------------
+def test_fixed_point_sum_overflow_is_flagged(orc):
+    """With reward_max 2^23 and fx_shift 40 one clamped reward is 2^63, so
+    two of them in one (cell, cluster) wrap the 64-bit sum: the oracle raises
+    its overflow status.  Below the clamp, or with one cluster sample per
+    pass, it does not."""
+    o, tri, emit, pos, nrm, p = _scene(orc, n_lights=16, n_points=8, M=1, fx_shift=40,
+                                       reward_max=float(2 ** 23), scale=1e12)
+    _, rec = o.frame(pos, nrm, 4, 0, records=True)
+    assert (rec["reward"] >= 2.0 ** 23).sum() >= 2
+    assert o.status() == 1 and o.status() == 0
+    o2, *_ = _scene(orc, n_lights=16, n_points=8, M=1, fx_shift=40, reward_max=float(2 ** 23), scale=1e-9)
+    o2.frame(pos, nrm, 4, 0)
+    assert o2.status() == 0
+    o3, *_ = _scene(orc, n_lights=16, n_points=1, M=1, fx_shift=40, reward_max=float(2 ** 23), scale=1e12)
+    o3.frame(pos[:1], nrm[:1], 1, 0)
+    assert o3.status() == 0
+
+
+def test_fixed_point_scale_above_63_bits_is_refused(orc):
+    """A single clamped reward must fit 63 bits: reward_max 2^24 at
+    fx_shift 40 is refused."""
+    with pytest.raises(ValueError):
+        _scene(orc, fx_shift=40, reward_max=float(2 ** 24))
+
+
+# --------------------------------------------------------------------------
+# checkpoint: a cell's learned state (cut and Q) loaded into a fresh scene
+# --------------------------------------------------------------------------
+def test_checkpoint_load_resumes_bit_exactly(orc):
+    """Three passes, then every ready cell's cut and Q loaded into a fresh
+    oracle: Q~ and C come back from Eq. 2 alone, and the following passes
+    give the uninterrupted run's radiance and cells bit for bit."""
+    s = scenes.make_tiny(n_lights=300, n_points=600, n_boxes=16, spp=4, M=16)
+    a = orc.Oracle(s.params, s.tri, s.emit, s.boxes)
+    for f in range(3):
+        a.frame(s.pos, s.nrm, 4, f)
+        a.adapt()
+    c = a.cells()
+    ready = c["ready"] == 1
+    assert ready.all() and ready.sum() > 20
+    b = orc.Oracle(s.params, s.tri, s.emit, s.boxes)
+    for k, node, q in zip(c["key"], c["node"], c["Q"]):
+        b.load_cell(int(k) & 0xFFFFFFFF, node, q)
+    cb = b.cells()
+    for k in ("key", "ready", "node", "end", "Q", "Qt", "C", "sum", "cnt"):
+        assert np.array_equal(cb[k], c[k]), k
+    for f in range(3, 6):
+        ra, _ = a.frame(s.pos, s.nrm, 4, f)
+        rb, _ = b.frame(s.pos, s.nrm, 4, f)
+        a.adapt()
+        b.adapt()
+        assert np.array_equal(ra, rb), f
+    ca, cb = a.cells(), b.cells()
+    for k in ca:
+        assert np.array_equal(ca[k], cb[k]), k
+
+
+def test_checkpoint_load_rejects_cuts_that_are_not_partitions(orc):
+    """Cuts built by hand from the tree: out of range order, a gap (a node
+    replaced by its left child), an overlap (a node replaced by its parent),
+    a node id past the tree, a negative or non-finite Q are refused, and
+    nothing is created."""
+    o, *_ = _scene(orc, n_lights=64, M=4)
+    t = o.tree()
+    node, end = o.template()
+    q = np.ones(4, np.float32)
+    o.load_cell(0, node, q)  # the initial cut is a partition
+    bad = []
+    bad.append((node[[1, 0, 2, 3]], q))
+    g = node.copy()
+    g[0] = t["left"][node[0]]
+    bad.append((g, q))
+    ov = node.copy()
+    ov[1] = t["parent"][node[1]]
+    bad.append((ov, q))
+    big = node.copy()
+    big[3] = 2 * o.N - 1
+    bad.append((big, q))
+    bad.append((node, np.float32([1, -1, 1, 1])))
+    bad.append((node, np.float32([1, np.nan, 1, 1])))
+    bad.append((node, np.float32([1, np.inf, 1, 1])))
+    for nd, qq in bad:
+        with pytest.raises(ValueError):
+            o.load_cell(1, nd, qq)
+    assert o.num_cells() == 1
