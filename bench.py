@@ -13,9 +13,16 @@ Prints ONE JSON line.  Extra fields:
   roofline      - the fused kernel against HBM bandwidth: algorithmic bytes
                   per launch (see algorithmic_bytes) over its mean duration,
                   timed with HIP events on the library's stream;
-  cpu_baseline  - the CPU oracle (single-threaded C) on a bounded sample of
-                  the same workload: every --cpu-stride-th point (20th by default),
-                  for the same passes.
+  cpu_baseline  - the CPU oracle (plain single-threaded C) on bounded samples
+                  of the same workload, whole cells at a time (all points of
+                  every k-th touched cell, so each sampled cell sees the GPU
+                  run's sample density), for the same passes: on one core,
+                  and on a pool of worker processes over disjoint cell sets
+                  (cells learn independently, so the results are the same);
+  mse           - the image error the learning buys at equal GPU time: the
+                  method against the same passes with learning switched off
+                  (temporal = 0, every pass from the initial cut), both
+                  against a 1,024-pass mean at independent frame numbers.
 """
 from __future__ import annotations
 
@@ -58,6 +65,132 @@ def algorithmic_bytes(samples: int, spp: int, M: int, cells: int, bins: int) -> 
     fused = 24 * points + 64 * samples + 12 * points + 12 * M * cells + 12 * bins
     adapt = 56 * M * cells
     return dict(fused=fused, adapt=adapt)
+
+
+def cpu_model() -> str:
+    try:
+        with open("/proc/cpuinfo") as f:
+            for line in f:
+                if line.startswith("model name"):
+                    return line.split(":", 1)[1].strip()
+    except OSError:
+        pass
+    return "unknown"
+
+
+def _cpu_worker(job):
+    """One process of the CPU baseline's pool: the oracle over the points of
+    its cells for every pass; returns the seconds the passes took."""
+    import oracle
+    params, tri, emit, boxes, pos, nrm, pid, spp, passes = job
+    orc = oracle.Oracle(params, tri, emit, boxes)
+    t0 = time.perf_counter()
+    for f in range(passes):
+        orc.frame(pos, nrm, spp, f, pid=pid)
+        orc.adapt()
+    return time.perf_counter() - t0
+
+
+def _cell_sample(np, keys, stride):
+    """Points of every stride-th distinct cell key (in key order), and the
+    cell of each selected point."""
+    uniq, inv = np.unique(keys, return_inverse=True)
+    take = np.zeros(uniq.size, bool)
+    take[::stride] = True
+    sel = np.nonzero(take[inv])[0].astype(np.uint32)
+    return sel, inv[sel], int(take.sum())
+
+
+def cpu_baseline(np, p, s, spp, passes, stride1, strideN, workers):
+    """The oracle on whole sampled cells: one core, then a pool of worker
+    processes (spawned, so they hold no GPU state) over disjoint cell sets
+    balanced by point count."""
+    import multiprocessing as mp
+
+    import oracle
+    keys = oracle.Oracle(p, s.tri[:1], s.emit[:1]).cell_keys(s.pos)
+    sel, _, ncell = _cell_sample(np, keys, stride1)
+    orc = oracle.Oracle(p, s.tri, s.emit, s.boxes)
+    print("[bench] CPU oracle, 1 core: %d points in %d cells x %d passes" % (sel.size, ncell, passes),
+          file=sys.stderr, flush=True)
+    t0 = time.perf_counter()
+    for f in range(passes):
+        orc.frame(s.pos[sel], s.nrm[sel], spp, f, pid=sel)
+        orc.adapt()
+    dt1 = time.perf_counter() - t0
+    one = {"value": round(sel.size * spp * passes / dt1, 1), "unit": "samples/s", "cores": 1,
+           "sample": "all %d points of every %dth touched cell (%d cells), %d passes, %.1f s"
+                     % (sel.size, stride1, ncell, passes, dt1)}
+    selN, cellN, ncellN = _cell_sample(np, keys, strideN)
+    # cells to workers, largest first onto the least-loaded worker
+    cells, counts = np.unique(cellN, return_counts=True)
+    load = np.zeros(workers, np.int64)
+    owner = {}
+    for c in cells[np.argsort(-counts, kind="stable")]:
+        w = int(np.argmin(load))
+        owner[int(c)] = w
+        load[w] += int(counts[np.searchsorted(cells, c)])
+    wid = np.array([owner[int(c)] for c in cellN])
+    jobs = []
+    for w in range(workers):
+        ids = selN[wid == w]
+        if ids.size:
+            jobs.append((p, s.tri, s.emit, s.boxes, s.pos[ids], s.nrm[ids], ids, spp, passes))
+    print("[bench] CPU oracle, %d processes: %d points in %d cells x %d passes"
+          % (len(jobs), selN.size, ncellN, passes), file=sys.stderr, flush=True)
+    ctx = mp.get_context("spawn")
+    with ctx.Pool(len(jobs)) as pool:
+        pool.map(abs, range(len(jobs)))  # start the workers before timing
+        t0 = time.perf_counter()
+        per = pool.map(_cpu_worker, jobs)
+        dtN = time.perf_counter() - t0
+    return {"value": round(selN.size * spp * passes / dtN, 1), "unit": "samples/s", "cores": len(jobs),
+            "kind": "oracle",
+            "sample": "all %d points of every %dth touched cell (%d cells), %d passes, %d worker processes "
+                      "over disjoint cell sets, %.1f s wall (slowest worker %.1f s)"
+                      % (selN.size, strideN, ncellN, passes, len(jobs), dtN, max(per)),
+            "single_core": one, "host_cpus": os.cpu_count(), "cpu_model": cpu_model()}
+
+
+def mse_equal_time(np, torch, ctx, make_ctx, p, pos, nrm, spp, passes, budget_ms, P):
+    """Image MSE (FP64, on the GPU) of the method's mean over `passes`
+    passes from a fresh cell table, and of the same passes with learning
+    switched off (temporal = 0) over as many passes as fit in the method's
+    GPU time, both against the mean of 1,024 passes of the method at frame
+    numbers 100000... (independent random numbers)."""
+    dev = pos.device
+    rad = torch.empty((P, 3), dtype=torch.float32, device=dev)
+
+    def mean_of(c, frames):
+        acc = torch.zeros((P, 3), dtype=torch.float64, device=dev)
+        for f in frames:
+            c.rlc_frame(pos, nrm, spp, f, rad)
+            acc += rad
+        return (acc / len(frames)).float()
+
+    print("[bench] MSE: reference of 1,024 passes", file=sys.stderr, flush=True)
+    ref_ctx = make_ctx(p)
+    ref = mean_of(ref_ctx, range(100000, 101024))
+    ref_ctx.close()
+    ctx.rlc_reset_cells()
+    learned = mean_of(ctx, range(passes))
+    off = make_ctx(dict(p, temporal=0))
+    e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    e0.record()
+    for f in range(passes):
+        off.rlc_frame(pos, nrm, spp, f, rad)
+    e1.record()
+    torch.cuda.synchronize()
+    off_ms = e0.elapsed_time(e1) / passes
+    n_off = max(1, int(budget_ms / off_ms))
+    off.rlc_reset_cells()
+    plain = mean_of(off, range(n_off))
+    m_learned = ctx.rlc_image_error(learned, ref)[2]
+    m_off = ctx.rlc_image_error(plain, ref)[2]
+    off.close()
+    return {"learned": float(m_learned), "no_learning": float(m_off), "ratio_no_learning_over_learned": round(m_off / m_learned, 3),
+            "budget_ms": round(budget_ms, 3), "passes": {"learned": passes, "no_learning": n_off},
+            "reference": "mean of 1,024 passes of the method at frames 100000..101023"}
 
 
 def _pmc_rows(path):
@@ -473,7 +606,17 @@ def main():
                     help="static/dynamic: a step is one frame of this many passes (rlc_frame_sub), each "
                          "with the workload's samples per point")
     ap.add_argument("--no-cpu-baseline", action="store_true")
-    ap.add_argument("--cpu-stride", type=int, default=20, help="CPU baseline runs every n-th point")
+    ap.add_argument("--cpu-stride", type=int, default=40,
+                    help="the one-core CPU baseline runs every n-th touched cell")
+    ap.add_argument("--cpu-stride-pool", type=int, default=5,
+                    help="the pooled CPU baseline runs every n-th touched cell")
+    ap.add_argument("--cpu-workers", type=int, default=0,
+                    help="worker processes of the pooled CPU baseline (0: the host's CPUs, at most 16)")
+    ap.add_argument("--no-mse", action="store_true")
+    ap.add_argument("--footprint-tile", type=float, default=0.0,
+                    help="footprint-sized cells: a primary hit's cell edge is wanted at this many times its "
+                         "pixel footprint (0: the fixed 64^3 grid)")
+    ap.add_argument("--footprint-levels", type=int, default=6)
     ap.add_argument("--copy-calib-mib", type=int, default=0,
                     help="also run a plain device copy of this many MiB (counter calibration)")
     ap.add_argument("--write-traffic", nargs=2, metavar=("FETCH_CSV", "WRITE_CSV"),
@@ -511,6 +654,10 @@ def main():
     s = scenes.make_static() if args.workload == "static" else scenes.make_dynamic()
     p = dict(s.params, occ_grid_res=64, split_steps=args.split_steps, normal_bits=args.normal_bits,
              jitter=args.jitter)
+    if args.footprint_tile > 0:
+        if s.footprint is None:
+            raise SystemExit("--footprint-tile needs a workload with camera footprints (static)")
+        p.update(footprint_levels=args.footprint_levels, footprint_tile=args.footprint_tile)
     spp = int(p["spp"])
     P = s.P
     n_sub = max(1, args.sub_frames)
@@ -520,9 +667,17 @@ def main():
     t = lambda a: torch.from_numpy(np.ascontiguousarray(a)).to(dev)
     tri, emit, boxes, pos, nrm = t(s.tri), t(s.emit), t(s.boxes), t(s.pos), t(s.nrm)
     radiance = torch.empty((P, 3), dtype=torch.float32, device=dev)
-    ctx = rlc.Context(p)
-    ctx.rlc_build_light_tree(tri, emit)
-    ctx.rlc_set_occluders(boxes)
+    fp_dev = t(s.footprint) if args.footprint_tile > 0 else None
+
+    def make_ctx(params):
+        c = rlc.Context(params)
+        c.rlc_build_light_tree(tri, emit)
+        c.rlc_set_occluders(boxes)
+        if fp_dev is not None:
+            c.rlc_set_footprints(fp_dev)
+        return c
+
+    ctx = make_ctx(p)
 
     if args.copy_calib_mib:
         n = args.copy_calib_mib * (1 << 20) // 4
@@ -574,9 +729,13 @@ def main():
     for f in range(args.steps):
         one_pass(f)
     fused_ms, adapt_ms, nframes = ctx.rlc_get_timing()
-    ctx.rlc_set_timing(False)
     fused_avg_ms = fused_ms / max(nframes, 1)
     adapt_avg_ms = adapt_ms / max(nframes, 1)
+    # steady state: 8 more passes that continue the learned tables
+    for f in range(args.steps, args.steps + 8):
+        one_pass(f)
+    steady_fused_ms, steady_adapt_ms, steady_n = ctx.rlc_get_timing()
+    ctx.rlc_set_timing(False)
 
     # ---- touched cells and (cell, cluster) bins of one steady-state pass ----
     smp = ctx.rlc_sample(pos, nrm, spp, args.steps)
@@ -611,28 +770,46 @@ def main():
         "adapt_alg_bytes_per_launch": alg["adapt"],
         "cells_touched": cells_t,
         "bins_touched": bins_t,
+        "steady_kernel_ms": round(steady_fused_ms / max(steady_n, 1), 4),
+        "steady_adapt_kernel_ms": round(steady_adapt_ms / max(steady_n, 1), 4),
     }
+    if traffic:
+        # the bytes HBM actually moved (counters) over the same mean duration
+        roofline["measured_frac"] = round(traffic / (fused_avg_ms * 1e-3) / 1e9 / PEAK_HBM_GBS, 4)
+
+    # ---- MSE at equal GPU time: learning on against learning off ----
+    mse = None
+    if not args.no_mse and n_sub == 1 and emissions is None:
+        mse = mse_equal_time(np, torch, ctx, make_ctx, p, pos, nrm, spp, args.steps, total_ms, P)
 
     cpu = None
     if not args.no_cpu_baseline:
-        import oracle
-        sel = np.arange(0, P, args.cpu_stride, dtype=np.uint32)
-        orc = oracle.Oracle(p, s.tri, s.emit, s.boxes)
-        print("[bench] CPU oracle: %d points x %d passes" % (sel.size, args.steps), file=sys.stderr, flush=True)
-        t0 = time.perf_counter()
-        for f in range(args.steps):
-            if s.emission_at is not None:
-                orc.set_emission(s.emission_at(f))
-            if n_sub > 1:
-                orc.frame_sub(s.pos[sel], s.nrm[sel], spp * n_sub, n_sub, f, pid=sel)
-            else:
-                orc.frame(s.pos[sel], s.nrm[sel], spp, f, pid=sel)
-                orc.adapt()
-        dt = time.perf_counter() - t0
-        cpu = {"value": round(sel.size * spp * n_sub * args.steps / dt, 1), "unit": "samples/s", "cores": 1,
-               "kind": "oracle",
-               "sample": "every %dth point (%d of %d) for the same %d passes, single-threaded C oracle, %.1f s"
-                         % (args.cpu_stride, sel.size, P, args.steps, dt)}
+        if emissions is None and n_sub == 1 and args.footprint_tile == 0:
+            workers = args.cpu_workers or min(16, os.cpu_count() or 1)
+            cpu = cpu_baseline(np, p, s, spp, args.steps, args.cpu_stride, args.cpu_stride_pool, workers)
+        else:
+            import oracle
+            sel = np.arange(0, P, 20, dtype=np.uint32)
+            orc = oracle.Oracle(p, s.tri, s.emit, s.boxes)
+            if fp_dev is not None:
+                orc.set_footprints(s.footprint)
+            print("[bench] CPU oracle: %d points x %d passes" % (sel.size, args.steps), file=sys.stderr,
+                  flush=True)
+            t0 = time.perf_counter()
+            for f in range(args.steps):
+                if s.emission_at is not None:
+                    orc.set_emission(s.emission_at(f))
+                if n_sub > 1:
+                    orc.frame_sub(s.pos[sel], s.nrm[sel], spp * n_sub, n_sub, f, pid=sel)
+                else:
+                    orc.frame(s.pos[sel], s.nrm[sel], spp, f, pid=sel)
+                    orc.adapt()
+            dt = time.perf_counter() - t0
+            cpu = {"value": round(sel.size * spp * n_sub * args.steps / dt, 1), "unit": "samples/s", "cores": 1,
+                   "kind": "oracle",
+                   "sample": "every 20th point (%d of %d) for the same %d passes, single-threaded C oracle, %.1f s"
+                             % (sel.size, P, args.steps, dt),
+                   "host_cpus": os.cpu_count(), "cpu_model": cpu_model()}
 
     if args.workload == "static":
         workload = ("static: 65,536 emissive triangles in 256 clusters, 2,073,600 primary hits "
@@ -647,6 +824,9 @@ def main():
         workload += "; split-collapse repeated until a step changes nothing (at most %d steps)" % args.split_steps
     if n_sub > 1:
         workload += "; a step is one frame of %d sub-frame passes, the cuts adapted after each" % n_sub
+    if args.footprint_tile > 0:
+        workload += ("; footprint-sized cells: %d levels, a point's cell edge at least %g times its pixel "
+                     "footprint" % (args.footprint_levels, args.footprint_tile))
     if args.normal_bits or args.jitter > 0:
         workload += "; 5-D cells: %d x %d normal bins, jitter %g" % (1 << args.normal_bits, 1 << args.normal_bits,
                                                                    args.jitter)
@@ -671,6 +851,8 @@ def main():
         "roofline": roofline,
         "cpu_baseline": cpu,
     }
+    if mse is not None:
+        line["mse"] = mse
     print(json.dumps(line), flush=True)
     ctx.close()
 
