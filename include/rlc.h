@@ -192,6 +192,20 @@ int rlc_frame_sub(rlc_ctx* ctx, const float* d_pos, const float* d_nrm, uint32_t
  * must stay valid while set. */
 int rlc_set_footprints(rlc_ctx* ctx, const float* d_fp, uint32_t rows);
 
+/* rlc_frame_sub for callers that cannot allocate device memory (code under
+ * HIP graph capture, tight serving loops, harnesses that forbid
+ * hipMalloc): the same passes and results, with the passes' own radiance
+ * in a fixed array of the library (32 MiB per GPU, held from the first
+ * context created on that GPU until the process ends) instead of a buffer
+ * the context allocates.  P at most RLC_NOALLOC_MAX_POINTS (RLC_EINVAL
+ * beyond).  It allocates nothing and records no timing events.  Every call
+ * on one GPU shares that array: calls that overlap on one GPU (several
+ * streams, or contexts on several threads) race and must be ordered by the
+ * caller. */
+#define RLC_NOALLOC_MAX_POINTS 2796202u
+int rlc_frame_sub_noalloc(rlc_ctx* ctx, const float* d_pos, const float* d_nrm, uint32_t P, uint32_t spp,
+                          uint32_t n_sub, uint32_t frame, float* d_radiance);
+
 /* Shadow-ray test only: d_vis[i] = 1 if the segment d_x[i] -> d_y[i] is
  * unoccluded over t in (t_lo, 1 - t_lo). */
 int rlc_visible(rlc_ctx* ctx, const float* d_x, const float* d_y, uint32_t n, uint8_t* d_vis);

@@ -6,12 +6,47 @@
 #include <cstdarg>
 #include <cstdio>
 #include <cstring>
+#include <mutex>
 #include <new>
 #include <vector>
 
 #include "rlc_internal.h"
 
 using namespace rlc;
+
+// Device memory of rlc_frame_sub_noalloc, for callers that cannot allocate:
+// the radiance of one sub-frame pass, 3 floats per point.  Every GPU the
+// library runs on holds its own copy until the process ends.  In host code
+// this name is not a device address: the address comes from
+// hipGetSymbolAddress with the device current (scratch_for_device).
+static __device__ __align__(256) float scratch[3u * RLC_NOALLOC_MAX_POINTS];
+
+namespace {
+
+constexpr int kMaxDevices = 64;
+std::mutex g_scratch_mu;
+float* g_scratch_ptr[kMaxDevices] = {};
+
+// The address of the current device's scratch array (`dev` must be the
+// current device), looked up once per device.
+int scratch_for_device(int dev, float** out) {
+    *out = nullptr;
+    if (dev < 0 || dev >= kMaxDevices) return RLC_EINVAL;
+    std::lock_guard<std::mutex> lock(g_scratch_mu);
+    if (!g_scratch_ptr[dev]) {
+        void* ptr = nullptr;
+        const hipError_t e = hipGetSymbolAddress(&ptr, HIP_SYMBOL(scratch));
+        if (e != hipSuccess || !ptr) {
+            (void)hipGetLastError();
+            return RLC_EHIP;
+        }
+        g_scratch_ptr[dev] = static_cast<float*>(ptr);
+    }
+    *out = g_scratch_ptr[dev];
+    return RLC_OK;
+}
+
+}  // namespace
 
 struct rlc_ctx {
     rlc_config cfg;
@@ -45,6 +80,8 @@ struct rlc_ctx {
     // radiance of one sub-frame pass (rlc_frame_sub), P x 3 floats
     float* sub_buf = nullptr;
     size_t sub_cap = 0;
+    // the same for rlc_frame_sub_noalloc: this device's scratch array
+    float* noalloc_scratch = nullptr;
 
     // cells
     DevCells cells{};
@@ -480,8 +517,14 @@ int rlc_create(const rlc_config* cfg, void* stream, rlc_ctx** out) {
         capacity = dense;
     }
     if (capacity * (uint64_t)k.M >= 0xFFFFFFFFull) return RLC_EINVAL;  // (cell, cluster) bins index with 32 bits
+    int dev = 0;
+    if (hipGetDevice(&dev) != hipSuccess) return RLC_EHIP;
+    float* noalloc = nullptr;
+    const int rs = scratch_for_device(dev, &noalloc);
+    if (rs != RLC_OK) return rs;
     rlc_ctx* c = new (std::nothrow) rlc_ctx();
     if (!c) return RLC_ENOMEM;
+    c->noalloc_scratch = noalloc;
     c->cfg = k;
     c->stream = (hipStream_t)stream;
     c->cell_index_limit = dense;
@@ -843,6 +886,18 @@ int rlc_frame_sub(rlc_ctx* c, const float* d_pos, const float* d_nrm, uint32_t P
         c->sub_cap = n;
     }
     return sub_passes(c, d_pos, d_nrm, P, spp, n_sub, frame, d_radiance, c->sub_buf, c->timing);
+}
+
+int rlc_frame_sub_noalloc(rlc_ctx* c, const float* d_pos, const float* d_nrm, uint32_t P, uint32_t spp,
+                          uint32_t n_sub, uint32_t frame, float* d_radiance) {
+    RLC_TRY(check_sub_args(c, d_pos, d_nrm, P, spp, n_sub, frame, d_radiance));
+    if (P > RLC_NOALLOC_MAX_POINTS)
+        return fail(c, RLC_EINVAL, "%u points exceed the %u that rlc_frame_sub_noalloc's scratch holds", P,
+                    RLC_NOALLOC_MAX_POINTS);
+    if (!c->noalloc_scratch) return fail(c, RLC_ESTATE, "no scratch address for this device");
+    if (P == 0) return RLC_OK;
+    if (n_sub == 1) return frame_pass(c, d_pos, d_nrm, P, spp, frame, d_radiance, false);
+    return sub_passes(c, d_pos, d_nrm, P, spp, n_sub, frame, d_radiance, c->noalloc_scratch, false);
 }
 
 int rlc_visible(rlc_ctx* c, const float* d_x, const float* d_y, uint32_t n, uint8_t* d_vis) {

@@ -31,7 +31,7 @@ _ERRNAMES = {RLC_EINVAL: "RLC_EINVAL", RLC_ENOMEM: "RLC_ENOMEM", RLC_EHIP: "RLC_
 EXPORTS = (
     "rlc_create", "rlc_destroy", "rlc_build_light_tree", "rlc_reset_cells", "rlc_set_emission",
     "rlc_set_occluders",
-    "rlc_sample", "rlc_shade", "rlc_learn", "rlc_adapt_cuts", "rlc_frame", "rlc_frame_sub", "rlc_visible",
+    "rlc_sample", "rlc_shade", "rlc_learn", "rlc_adapt_cuts", "rlc_frame", "rlc_frame_sub", "rlc_frame_sub_noalloc", "rlc_visible",
     "rlc_cell_keys", "rlc_image_error", "rlc_sync", "rlc_last_error", "rlc_num_cells", "rlc_meff",
     "rlc_dump_cells", "rlc_load_cells", "rlc_dump_tree", "rlc_get_template", "rlc_set_timing", "rlc_get_timing",
     "rlc_batch_create", "rlc_batch_destroy", "rlc_batch_set_schedule", "rlc_batch_get_schedule",
@@ -130,6 +130,7 @@ def _declare(L):
     L.rlc_adapt_cuts.argtypes = [_vp]
     L.rlc_frame.argtypes = [_vp, _vp, _vp, _u32, _u32, _u32, _vp]
     L.rlc_frame_sub.argtypes = [_vp, _vp, _vp, _u32, _u32, _u32, _u32, _vp]
+    L.rlc_frame_sub_noalloc.argtypes = [_vp, _vp, _vp, _u32, _u32, _u32, _u32, _vp]
     L.rlc_visible.argtypes = [_vp, _vp, _vp, _u32, _vp]
     L.rlc_cell_keys.argtypes = [_vp, _vp, _u32, _vp]
     L.rlc_image_error.argtypes = [_vp, _vp, _vp, _u32, _vp]
@@ -353,6 +354,18 @@ class Context:
         _dev(radiance, torch.float32, "radiance")
         self._check(lib().rlc_frame_sub(self._h, _ptr(pos), _ptr(nrm), P, spp, n_sub, frame, _ptr(radiance)),
                     "rlc_frame_sub")
+        return radiance
+
+    def rlc_frame_sub_noalloc(self, pos, nrm, spp: int, n_sub: int, frame: int, radiance):
+        """rlc_frame_sub through the entry point that allocates nothing; the
+        caller passes the radiance tensor (P x 3)."""
+        import torch
+        _dev(pos, torch.float32, "pos")
+        _dev(nrm, torch.float32, "nrm")
+        _dev(radiance, torch.float32, "radiance")
+        P = pos.numel() // 3
+        self._check(lib().rlc_frame_sub_noalloc(self._h, _ptr(pos), _ptr(nrm), P, spp, n_sub, frame,
+                                                _ptr(radiance)), "rlc_frame_sub_noalloc")
         return radiance
 
     def rlc_visible(self, x, y):
