@@ -119,6 +119,8 @@ struct rlc_ctx {
     uint32_t* mlp_vtmp = nullptr;
     uint32_t* mlp_hist = nullptr;
     uint32_t mlp_order_cap = 0;
+    uint16_t* mlp_xenc = nullptr;      // encoded inputs of the training call's points
+    uint32_t mlp_xenc_cap = 0;
     // mixture with the learned proposal, and per-sample training records
     const float* mix_cdf = nullptr;
     uint32_t mix_rows = 0;
@@ -244,6 +246,8 @@ void free_mlp(rlc_ctx* c) {
     dfree(c->mlp_ktmp);
     dfree(c->mlp_vtmp);
     dfree(c->mlp_hist);
+    dfree(c->mlp_xenc);
+    c->mlp_xenc_cap = 0;
     c->mlp_partial_blocks = 0;
     c->mlp_order_cap = 0;
     c->mlp_ready = false;
@@ -457,6 +461,26 @@ int mlp_order_buffers(rlc_ctx* c, uint32_t n) {
     RLC_TRY(dalloc(c, &c->mlp_vtmp, n));
     RLC_TRY(dalloc(c, &c->mlp_hist, radix_sort_hist_entries(n)));
     c->mlp_order_cap = n;
+    return RLC_OK;
+}
+
+// The training kernels read each point's encoded inputs from a buffer
+// filled once per call (the points are shared by many tuples), for up to
+// kMlpEncodeMaxPoints points (320 bytes each); beyond, the kernels encode.
+constexpr uint32_t kMlpEncodeMaxPoints = 1u << 18;
+
+int mlp_encoded_inputs(rlc_ctx* c, const float* pos, const float* nrm, uint32_t P, const uint16_t** out) {
+    *out = nullptr;
+    if (P > kMlpEncodeMaxPoints) return RLC_OK;
+    if (P > c->mlp_xenc_cap) {
+        RLC_HIP(c, hipStreamSynchronize(c->stream));
+        dfree(c->mlp_xenc);
+        c->mlp_xenc_cap = 0;
+        RLC_TRY(dalloc(c, &c->mlp_xenc, (size_t)P * kMlpEncodeHalves));
+        c->mlp_xenc_cap = P;
+    }
+    RLC_HIP(c, launch_mlp_encode(mlp_encode_params(c), pos, nrm, P, c->mlp_xenc, c->stream));
+    *out = c->mlp_xenc;
     return RLC_OK;
 }
 
@@ -1168,7 +1192,9 @@ int rlc_mlp_grad(rlc_ctx* c, const float* d_pos, const float* d_nrm, uint32_t P,
         RLC_HIP(c, hipMemsetAsync(c->mlp_part_loss, 0, sizeof(float), c->stream));
         RLC_HIP(c, hipMemsetAsync(c->mlp_partial, 0, sizeof(float) * kMlpParams, c->stream));
     }
-    RLC_HIP(c, launch_mlp_fwd_bwd(c->mlp_frag, c->mlp_master, mlp_encode_params(c), d_pos, d_nrm, P, nullptr, d_pid,
+    const uint16_t* xenc = nullptr;
+    if (n) RLC_TRY(mlp_encoded_inputs(c, d_pos, d_nrm, P, &xenc));
+    RLC_HIP(c, launch_mlp_fwd_bwd(c->mlp_frag, c->mlp_master, mlp_encode_params(c), d_pos, d_nrm, P, xenc, nullptr, d_pid,
                                   d_node, d_w, n, c->mlp_partial, c->mlp_part_w, c->mlp_part_loss, c->d_err,
                                   c->stream));
     RLC_HIP(c, launch_mlp_reduce(c->mlp_partial, c->mlp_part_w, c->mlp_part_loss, nb, 0u, d_grad, nullptr, nullptr,
@@ -1194,6 +1220,8 @@ int rlc_mlp_train(rlc_ctx* c, const float* d_pos, const float* d_nrm, uint32_t P
     RLC_TRY(mlp_order_buffers(c, n));
     RLC_HIP(c, launch_fill_u32(c->d_err, 0u, 1, c->stream));
     const MlpEncode enc = mlp_encode_params(c);
+    const uint16_t* xenc = nullptr;
+    RLC_TRY(mlp_encoded_inputs(c, d_pos, d_nrm, P, &xenc));
     const uint32_t seed_lo = (uint32_t)(c->cfg.seed & 0xFFFFFFFFull), seed_hi = (uint32_t)(c->cfg.seed >> 32);
     for (uint32_t e = 0; e < epochs; ++e) {
         RLC_HIP(c, launch_mlp_shuffle_keys(n, e, c->cfg.scene_id, seed_lo, seed_hi, c->mlp_keys, c->mlp_vals,
@@ -1211,7 +1239,7 @@ int rlc_mlp_train(rlc_ctx* c, const float* d_pos, const float* d_nrm, uint32_t P
                 }
                 RLC_HIP(c, hipEventRecord(ev[0], c->stream));
             }
-            RLC_HIP(c, launch_mlp_fwd_bwd(c->mlp_frag, c->mlp_master, enc, d_pos, d_nrm, P, c->mlp_vals + b0, d_pid,
+            RLC_HIP(c, launch_mlp_fwd_bwd(c->mlp_frag, c->mlp_master, enc, d_pos, d_nrm, P, xenc, c->mlp_vals + b0, d_pid,
                                           d_node, d_w, nbat, c->mlp_partial, c->mlp_part_w, c->mlp_part_loss,
                                           c->d_err, c->stream));
             if (c->timing) RLC_HIP(c, hipEventRecord(ev[1], c->stream));

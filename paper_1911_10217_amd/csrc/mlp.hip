@@ -43,7 +43,6 @@ static_assert(ob4 + kH == kNP, "parameter count");
 constexpr uint32_t fF1 = 0, fF2 = 1280, fF3 = 1792, fF4 = 2304, fT2 = 2816, fT3 = 3328, fT4 = 3840;
 static_assert(fT4 + 512 == kMlpFragVecs, "fragment count");
 constexpr uint32_t kFwdVecs = fT2;
-constexpr uint32_t kLds = 72;  // LDS row stride (BF16) of the gradient staging tiles
 
 __device__ __forceinline__ uint16_t bf16_bits(float f) {
     uint32_t u = __float_as_uint(f);
@@ -53,11 +52,13 @@ __device__ __forceinline__ uint16_t bf16_bits(float f) {
 
 __device__ __forceinline__ float bf16_val(uint16_t b) { return __uint_as_float((uint32_t)b << 16); }
 
+// Eight floats to BF16 by the hardware's conversion (v_cvt_pk_bf16_f32,
+// two per instruction, round to nearest even like bf16_bits).
 __device__ __forceinline__ bf16x8 pack8(const float* v) {
-    u16x8 b;
+    bf16x8 b;
 #pragma unroll
-    for (int e = 0; e < 8; ++e) b[e] = bf16_bits(v[e]);
-    return __builtin_bit_cast(bf16x8, b);
+    for (int e = 0; e < 8; ++e) b[e] = (__bf16)v[e];
+    return b;
 }
 
 __device__ __forceinline__ uint16_t elem(bf16x8 v, int e) { return __builtin_bit_cast(u16x8, v)[e]; }
@@ -194,9 +195,9 @@ struct Fwd {
     bf16x8 a1[2], a2[2], a3[2];
 };
 
+// The layers for 16 points whose encoded inputs are in f.x.
 __device__ __forceinline__ void forward16(const bf16x8* __restrict__ frag, const float* __restrict__ master,
-                                          const float v[6], uint32_t lane, Fwd& f) {
-    encode_b(v, lane >> 4, f.x);
+                                          uint32_t lane, Fwd& f) {
     dense<5>(frag + fF1, f.x, master + ob1, lane, f.h1);
     relu_to_b(f.h1, f.a1);
     dense<2>(frag + fF2, f.a1, master + ob2, lane, f.h2);
@@ -258,7 +259,8 @@ __global__ void __launch_bounds__(kBlock) k_mlp_forward(const bf16x8* __restrict
         float v[6];
         point_inputs(enc, pos, nrm, valid ? p : 0u, v);
         Fwd f;
-        forward16(s_frag, master, v, lane, f);
+        encode_b(v, g, f.x);
+        forward16(s_frag, master, lane, f);
         if (valid && logits) {
 #pragma unroll
             for (uint32_t t = 0; t < 4u; ++t)
@@ -293,13 +295,24 @@ __global__ void __launch_bounds__(kBlock) k_mlp_forward(const bf16x8* __restrict
 }
 
 // ---------------------------------------------------------------------------
-// Training: forward and backward of 64 tuples per block (16 per wave), and
-// the block's share of the weight gradient, sum over its tuples of
-// G_L A_{L-1}^T, staged through LDS one layer at a time.  Writes one row of
-// partial sums (all parameters), and the block's sum of weights and of
-// weighted losses; the reduction over blocks is done in a fixed order by
-// k_mlp_reduce.
+// Training: forward and backward of kTrainTuples tuples per block (16 per
+// wave), and the block's share of the weight gradient, sum over its tuples
+// of G_L A_{L-1}^T, staged through LDS one layer at a time as MFMA
+// contractions over the block's tuples.  Writes one row of partial sums
+// (all parameters), and the block's sum of weights and of weighted losses;
+// the reduction over blocks is done in a fixed order by k_mlp_reduce.
+// Eight waves (128 tuples) per block: measured against 64 and 256 tuples
+// per block (the partial rows halve with each doubling, but fewer blocks
+// hold fewer waves in flight for the latency of the layer chain).  Between
+// the layers only what the backward pass needs stays in registers: the BF16
+// activations and, for the ReLU derivative, one bit per pre-activation.
 // ---------------------------------------------------------------------------
+constexpr uint32_t kTrainWaves = kMlpTuplesPerBlock / 16u;
+static_assert(kTrainWaves >= 4u && kTrainWaves <= 16u, "4 to 16 waves per training block");
+constexpr uint32_t kTrainThreads = kTrainWaves * 64u;
+constexpr uint32_t kTrainTuples = kTrainWaves * 16u;
+constexpr uint32_t kLdsT = kTrainTuples + 8u;  // LDS row stride (BF16) of the staging tiles
+
 __device__ __forceinline__ void stage_hidden(uint16_t* __restrict__ s, const bf16x8 (&b)[2], uint32_t g,
                                              uint32_t col) {
 #pragma unroll
@@ -307,42 +320,78 @@ __device__ __forceinline__ void stage_hidden(uint16_t* __restrict__ s, const bf1
 #pragma unroll
         for (uint32_t e = 0; e < 8u; ++e) {
             const uint32_t j = 32u * kb + 16u * (e >> 2) + 4u * g + (e & 3u);
-            s[j * kLds + col] = elem(b[kb], (int)e);
+            s[j * kLdsT + col] = elem(b[kb], (int)e);
         }
 }
 
-// gW tile (to, tj) over the block's 64 tuples, added to the partial row.
+// gW tile (to, tj) over the block's tuples, written to the partial row.
 __device__ __forceinline__ void wgrad_tile(const uint16_t* __restrict__ sG, const uint16_t* __restrict__ sA,
                                            uint32_t to, uint32_t tj, uint32_t nin, uint32_t lane,
                                            float* __restrict__ prow) {
     const uint32_t i16 = lane & 15u, g = lane >> 4;
     f32x4 acc = {0.0f, 0.0f, 0.0f, 0.0f};
 #pragma unroll
-    for (uint32_t kb = 0; kb < 2u; ++kb) {
-        const bf16x8 a = *reinterpret_cast<const bf16x8*>(sG + (16u * to + i16) * kLds + 32u * kb + 8u * g);
-        const bf16x8 b = *reinterpret_cast<const bf16x8*>(sA + (16u * tj + i16) * kLds + 32u * kb + 8u * g);
+    for (uint32_t kb = 0; kb < kTrainTuples / 32u; ++kb) {
+        const bf16x8 a = *reinterpret_cast<const bf16x8*>(sG + (16u * to + i16) * kLdsT + 32u * kb + 8u * g);
+        const bf16x8 b = *reinterpret_cast<const bf16x8*>(sA + (16u * tj + i16) * kLdsT + 32u * kb + 8u * g);
         acc = mfma(a, b, acc);
     }
 #pragma unroll
     for (uint32_t r = 0; r < 4u; ++r) prow[(16u * to + 4u * g + r) * nin + 16u * tj + i16] = acc[r];
 }
 
-__global__ void __launch_bounds__(kBlock) k_mlp_fwd_bwd(const bf16x8* __restrict__ frag,
-                                                        const float* __restrict__ master, MlpEncode enc,
-                                                        const float* __restrict__ pos,
-                                                        const float* __restrict__ nrm, uint32_t P,
-                                                        const uint32_t* __restrict__ order,
-                                                        const uint32_t* __restrict__ pid,
-                                                        const uint32_t* __restrict__ node,
-                                                        const float* __restrict__ w, uint32_t n,
-                                                        float* __restrict__ partial, float* __restrict__ part_w,
-                                                        float* __restrict__ part_loss, uint32_t* __restrict__ err) {
-    __shared__ __attribute__((aligned(16))) uint16_t sG[kH * kLds];
-    __shared__ __attribute__((aligned(16))) uint16_t sA[kIn * kLds];
-    __shared__ float s_w[64], s_l[64];
+// Bias gradient of one layer: row j of sG summed over the block's tuples,
+// four threads per row, each over a quarter of the columns, the quarters
+// added in order (the four are neighbouring lanes).
+__device__ __forceinline__ void bias_grad(const uint16_t* __restrict__ sG, float* __restrict__ dst) {
+    if (threadIdx.x >= 4u * kH) return;
+    const uint32_t row = threadIdx.x >> 2, q = threadIdx.x & 3u;
+    constexpr uint32_t kQ = kTrainTuples / 4u;
+    float sum = 0.0f;
+    for (uint32_t c = 0; c < kQ; ++c) sum += bf16_val(sG[row * kLdsT + q * kQ + c]);
+    const float s1 = __shfl(sum, (int)((threadIdx.x & 63u) | 1u), 64);
+    const float s2 = __shfl(sum, (int)((threadIdx.x & 63u) | 2u), 64);
+    const float s3 = __shfl(sum, (int)((threadIdx.x & 63u) | 3u), 64);
+    if (q == 0u) dst[row] = ((sum + s1) + s2) + s3;
+}
+
+// One dense layer, then the ReLU into the next layer's B operand, keeping
+// one bit per pre-activation (bit 4 t + r: tile t, register r is > 0).
+template <int KB>
+__device__ __forceinline__ uint32_t hidden_layer(const bf16x8* __restrict__ frag, const bf16x8 (&b)[KB],
+                                                 const float* __restrict__ bias, uint32_t lane,
+                                                 bf16x8 (&out)[2]) {
+    f32x4 h[4];
+    dense<KB>(frag, b, bias, lane, h);
+    uint32_t mask = 0;
+#pragma unroll
+    for (uint32_t t = 0; t < 4u; ++t)
+#pragma unroll
+        for (uint32_t r = 0; r < 4u; ++r)
+            if (h[t][r] > 0.0f) mask |= 1u << (4u * t + r);
+    relu_to_b(h, out);
+    return mask;
+}
+
+__global__ void __launch_bounds__(kTrainThreads) k_mlp_fwd_bwd(const bf16x8* __restrict__ frag,
+                                                               const float* __restrict__ master, MlpEncode enc,
+                                                               const float* __restrict__ pos,
+                                                               const float* __restrict__ nrm, uint32_t P,
+                                                               const bf16x8* __restrict__ xenc,
+                                                               const uint32_t* __restrict__ order,
+                                                               const uint32_t* __restrict__ pid,
+                                                               const uint32_t* __restrict__ node,
+                                                               const float* __restrict__ w, uint32_t n,
+                                                               float* __restrict__ partial,
+                                                               float* __restrict__ part_w,
+                                                               float* __restrict__ part_loss,
+                                                               uint32_t* __restrict__ err) {
+    __shared__ __attribute__((aligned(16))) uint16_t sG[kH * kLdsT];
+    __shared__ __attribute__((aligned(16))) uint16_t sA[kIn * kLdsT];
+    __shared__ float s_w[kTrainTuples], s_l[kTrainTuples];
     const uint32_t lane = threadIdx.x & 63u, wave = threadIdx.x >> 6, i16 = lane & 15u, g = lane >> 4;
     const uint32_t col = wave * 16u + i16;
-    const uint32_t tb = blockIdx.x * kMlpTuplesPerBlock + col;
+    const uint32_t tb = blockIdx.x * kTrainTuples + col;
     uint32_t pt = 0, nd = 0;
     float wt = 0.0f;
     if (tb < n) {
@@ -357,53 +406,59 @@ __global__ void __launch_bounds__(kBlock) k_mlp_fwd_bwd(const bf16x8* __restrict
             wt = 0.0f;
         }
     }
-    float v[6];
-    point_inputs(enc, pos, nrm, pt, v);
-    Fwd f;
-    forward16(frag, master, v, lane, f);
+    // the point's encoded inputs (computed once per call, or here)
+    auto load_x = [&](bf16x8 (&x)[5]) {
+        if (xenc) {
+#pragma unroll
+            for (uint32_t kb = 0; kb < 5u; ++kb) x[kb] = xenc[((size_t)pt * 5u + kb) * 4u + g];
+        } else {
+            float v[6];
+            point_inputs(enc, pos, nrm, pt, v);
+            encode_b(v, g, x);
+        }
+    };
+    bf16x8 a1[2], a2[2], a3[2];
+    uint32_t m1, m2, m3;
+    f32x4 z[4];
+    {
+        bf16x8 x[5];
+        load_x(x);
+        m1 = hidden_layer<5>(frag + fF1, x, master + ob1, lane, a1);
+    }
+    m2 = hidden_layer<2>(frag + fF2, a1, master + ob2, lane, a2);
+    m3 = hidden_layer<2>(frag + fF3, a2, master + ob3, lane, a3);
+    dense<2>(frag + fF4, a3, master + ob4, lane, z);
+    // the target's logit, from the lane that holds it (before the softmax
+    // replaces the logits by probabilities)
+    const uint32_t tn = nd >> 4, gn = (nd & 15u) >> 2, rn = nd & 3u;
+    float zn = 0.0f;
+#pragma unroll
+    for (uint32_t t = 0; t < 4u; ++t)
+#pragma unroll
+        for (uint32_t r = 0; r < 4u; ++r)
+            if (t == tn && r == rn) zn = z[t][r];
     float zmax, log_s;
-    f32x4 zl[4];
-#pragma unroll
-    for (int t = 0; t < 4; ++t) zl[t] = f.z[t];
-    softmax16(f.z, zmax, log_s);
-    // loss term -w log q[node], from the lane holding the target's logit
-    {
-        const uint32_t tn = nd >> 4, gn = (nd & 15u) >> 2, rn = nd & 3u;
-        if (g == gn) {
-            float zn = 0.0f;
-#pragma unroll
-            for (uint32_t t = 0; t < 4u; ++t)
-#pragma unroll
-                for (uint32_t r = 0; r < 4u; ++r)
-                    if (t == tn && r == rn) zn = zl[t][r];
-            s_l[col] = -(wt * ((zn - zmax) - log_s));
-            s_w[col] = wt;
-        }
+    softmax16(z, zmax, log_s);
+    // loss term -w log q[node]
+    if (g == gn) {
+        s_l[col] = -(wt * ((zn - zmax) - log_s));
+        s_w[col] = wt;
     }
-    // output gradient w (q - e_node), then back through layers 4, 3, 2
-    bf16x8 gB4[2], gB3[2], gB2[2], gB1[2];
-    {
-        f32x4 g4[4];
+    // output gradient w (q - e_node)
+    bf16x8 gB[2];
 #pragma unroll
-        for (uint32_t t = 0; t < 4u; ++t)
+    for (int kb = 0; kb < 2; ++kb) {
+        float val[8];
 #pragma unroll
-            for (uint32_t r = 0; r < 4u; ++r) {
-                const uint32_t u = 16u * t + 4u * g + r;
-                g4[t][r] = wt * (f.z[t][r] - (u == nd ? 1.0f : 0.0f));
-            }
-#pragma unroll
-        for (int kb = 0; kb < 2; ++kb) {
-            float val[8];
-#pragma unroll
-            for (int r = 0; r < 4; ++r) {
-                val[r] = g4[2 * kb][r];
-                val[4 + r] = g4[2 * kb + 1][r];
-            }
-            gB4[kb] = pack8(val);
+        for (int r = 0; r < 4; ++r) {
+            const uint32_t u0 = 16u * (2u * kb) + 4u * g + r, u1 = 16u * (2u * kb + 1u) + 4u * g + r;
+            val[r] = wt * (z[2 * kb][r] - (u0 == nd ? 1.0f : 0.0f));
+            val[4 + r] = wt * (z[2 * kb + 1][r] - (u1 == nd ? 1.0f : 0.0f));
         }
+        gB[kb] = pack8(val);
     }
-    auto back = [&](const bf16x8* __restrict__ fr, const bf16x8 (&gin)[2], const f32x4 (&hpre)[4],
-                    bf16x8 (&gout)[2]) {
+    // back-propagation through the transposed operands, with the ReLU bits
+    auto back = [&](const bf16x8* __restrict__ fr, const bf16x8 (&gin)[2], uint32_t mask, bf16x8 (&gout)[2]) {
         f32x4 d[4];
 #pragma unroll
         for (uint32_t t = 0; t < 4u; ++t) {
@@ -411,7 +466,7 @@ __global__ void __launch_bounds__(kBlock) k_mlp_fwd_bwd(const bf16x8* __restrict
 #pragma unroll
             for (uint32_t kb = 0; kb < 2u; ++kb) acc = mfma(fr[(t * 2u + kb) * 64u + lane], gin[kb], acc);
 #pragma unroll
-            for (uint32_t r = 0; r < 4u; ++r) d[t][r] = hpre[t][r] > 0.0f ? acc[r] : 0.0f;
+            for (uint32_t r = 0; r < 4u; ++r) d[t][r] = (mask >> (4u * t + r)) & 1u ? acc[r] : 0.0f;
         }
 #pragma unroll
         for (int kb = 0; kb < 2; ++kb) {
@@ -424,56 +479,48 @@ __global__ void __launch_bounds__(kBlock) k_mlp_fwd_bwd(const bf16x8* __restrict
             gout[kb] = pack8(val);
         }
     };
-    back(frag + fT4, gB4, f.h3, gB3);
-    back(frag + fT3, gB3, f.h2, gB2);
-    back(frag + fT2, gB2, f.h1, gB1);
-
     float* prow = partial + (size_t)blockIdx.x * kNP;
-    // layers 4, 3, 2: G_L (64 rows) against the previous activations (64 rows)
-    const bf16x8* gs[3] = {gB4, gB3, gB2};
-    const bf16x8* as[3] = {f.a3, f.a2, f.a1};
-    const uint32_t ow[3] = {oW4, oW3, oW2}, ob[3] = {ob4, ob3, ob2};
-#pragma unroll
-    for (int L = 0; L < 3; ++L) {
-        const bf16x8(&gg)[2] = *reinterpret_cast<const bf16x8(*)[2]>(gs[L]);
-        const bf16x8(&aa)[2] = *reinterpret_cast<const bf16x8(*)[2]>(as[L]);
-        stage_hidden(sG, gg, g, col);
-        stage_hidden(sA, aa, g, col);
+    // layers 4, 3, 2, each in turn: G_L and the previous activations staged
+    // in LDS, G_{L-1} propagated from G_L, then the layer's weight gradient
+    // (16 tiles over the waves) and bias gradient; a layer's operands are not
+    // needed once staged
+    auto layer_grad = [&](const bf16x8 (&act)[2], const bf16x8* __restrict__ fr_t, uint32_t mask, uint32_t ow_,
+                          uint32_t ob_) {
+        stage_hidden(sG, gB, g, col);
+        stage_hidden(sA, act, g, col);
+        bf16x8 gn2[2];
+        back(fr_t, gB, mask, gn2);
+        gB[0] = gn2[0];
+        gB[1] = gn2[1];
         __syncthreads();
-#pragma unroll
-        for (uint32_t k = 0; k < 4u; ++k) {
-            const uint32_t tile = wave * 4u + k;
-            wgrad_tile(sG, sA, tile >> 2, tile & 3u, kH, lane, prow + ow[L]);
-        }
-        if (threadIdx.x < kH) {
-            float s = 0.0f;
-            for (uint32_t c = 0; c < 64u; ++c) s += bf16_val(sG[threadIdx.x * kLds + c]);
-            prow[ob[L] + threadIdx.x] = s;
-        }
+        for (uint32_t tile = wave; tile < 16u; tile += kTrainWaves)  // 4 output x 4 input tiles
+            wgrad_tile(sG, sA, tile >> 2, tile & 3u, kH, lane, prow + ow_);
+        bias_grad(sG, prow + ob_);
         __syncthreads();
+    };
+    layer_grad(a3, frag + fT4, m3, oW4, ob4);
+    layer_grad(a2, frag + fT3, m2, oW3, ob3);
+    layer_grad(a1, frag + fT2, m1, oW2, ob2);
+    // layer 1: G_1 against the encoded inputs (144 rows): 36 tiles
+    stage_hidden(sG, gB, g, col);
+    {
+        bf16x8 x[5];
+        load_x(x);
+#pragma unroll
+        for (uint32_t kb = 0; kb < 5u; ++kb)
+#pragma unroll
+            for (uint32_t e = 0; e < 8u; ++e) {
+                const uint32_t j = 32u * kb + 8u * g + e;
+                if (j < kIn) sA[j * kLdsT + col] = elem(x[kb], (int)e);
+            }
     }
-    // layer 1: G_1 against the encoded inputs (144 rows)
-    stage_hidden(sG, gB1, g, col);
-#pragma unroll
-    for (uint32_t kb = 0; kb < 5u; ++kb)
-#pragma unroll
-        for (uint32_t e = 0; e < 8u; ++e) {
-            const uint32_t j = 32u * kb + 8u * g + e;
-            if (j < kIn) sA[j * kLds + col] = elem(f.x[kb], (int)e);
-        }
     __syncthreads();
-    for (uint32_t k = 0; k < 9u; ++k) {
-        const uint32_t tile = wave * 9u + k;  // 36 tiles: 4 output x 9 input
+    for (uint32_t tile = wave; tile < 36u; tile += kTrainWaves)  // 4 output x 9 input tiles
         wgrad_tile(sG, sA, tile / 9u, tile % 9u, kIn, lane, prow + oW1);
-    }
-    if (threadIdx.x < kH) {
-        float s = 0.0f;
-        for (uint32_t c = 0; c < 64u; ++c) s += bf16_val(sG[threadIdx.x * kLds + c]);
-        prow[ob1 + threadIdx.x] = s;
-    }
+    bias_grad(sG, prow + ob1);
     if (threadIdx.x == 0) {
         float sw = 0.0f, sl = 0.0f;
-        for (uint32_t c = 0; c < 64u; ++c) {
+        for (uint32_t c = 0; c < kTrainTuples; ++c) {
             sw += s_w[c];
             sl += s_l[c];
         }
@@ -575,6 +622,23 @@ __global__ void __launch_bounds__(kBlock) k_mlp_refresh(const float* __restrict_
     if (p < kNP) write_frag(frag, p, master[p]);
 }
 
+// Encoded inputs of every point, in the order the lanes of layer 1 read
+// them: entry (p, kb, g) holds the 8 values of k-block kb that lane group g
+// supplies for point p.
+__global__ void __launch_bounds__(kBlock) k_mlp_encode(MlpEncode enc, const float* __restrict__ pos,
+                                                       const float* __restrict__ nrm, uint32_t P,
+                                                       bf16x8* __restrict__ out) {
+    const uint32_t i = blockIdx.x * kBlock + threadIdx.x;  // (point, lane group)
+    if (i >= 4u * P) return;
+    const uint32_t p = i >> 2, g = i & 3u;
+    float v[6];
+    point_inputs(enc, pos, nrm, p, v);
+    bf16x8 x[5];
+    encode_b(v, g, x);
+#pragma unroll
+    for (uint32_t kb = 0; kb < 5u; ++kb) out[((size_t)p * 5u + kb) * 4u + g] = x[kb];
+}
+
 // Training order of an epoch: key of tuple i = first word of Philox at
 // counter (i, epoch, 0, scene << 16 | 2); sorted (stably) by key.
 __global__ void __launch_bounds__(kBlock) k_mlp_shuffle_keys(uint32_t n, uint32_t epoch, uint32_t scene_id,
@@ -626,14 +690,23 @@ hipError_t launch_mlp_forward(const uint16_t* frag, const float* master, MlpEnco
     return hipGetLastError();
 }
 
+hipError_t launch_mlp_encode(MlpEncode enc, const float* pos, const float* nrm, uint32_t P, uint16_t* out,
+                             hipStream_t s) {
+    if (P == 0) return hipSuccess;
+    hipLaunchKernelGGL(k_mlp_encode, dim3(blocks_for(4 * (size_t)P)), dim3(kBlock), 0, s, enc, pos, nrm, P,
+                       reinterpret_cast<bf16x8*>(out));
+    return hipGetLastError();
+}
+
 hipError_t launch_mlp_fwd_bwd(const uint16_t* frag, const float* master, MlpEncode enc, const float* pos,
-                              const float* nrm, uint32_t P, const uint32_t* order, const uint32_t* pid,
-                              const uint32_t* node, const float* w, uint32_t n, float* partial, float* part_w,
-                              float* part_loss, uint32_t* err, hipStream_t s) {
+                              const float* nrm, uint32_t P, const uint16_t* xenc, const uint32_t* order,
+                              const uint32_t* pid, const uint32_t* node, const float* w, uint32_t n, float* partial,
+                              float* part_w, float* part_loss, uint32_t* err, hipStream_t s) {
     if (n == 0) return hipSuccess;
     const uint32_t grid = (n + kMlpTuplesPerBlock - 1u) / kMlpTuplesPerBlock;
-    hipLaunchKernelGGL(k_mlp_fwd_bwd, dim3(grid), dim3(kBlock), 0, s, reinterpret_cast<const bf16x8*>(frag),
-                       master, enc, pos, nrm, P, order, pid, node, w, n, partial, part_w, part_loss, err);
+    hipLaunchKernelGGL(k_mlp_fwd_bwd, dim3(grid), dim3(kTrainThreads), 0, s, reinterpret_cast<const bf16x8*>(frag),
+                       master, enc, pos, nrm, P, reinterpret_cast<const bf16x8*>(xenc), order, pid, node, w, n,
+                       partial, part_w, part_loss, err);
     return hipGetLastError();
 }
 

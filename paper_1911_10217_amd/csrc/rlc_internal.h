@@ -635,7 +635,7 @@ hipError_t launch_gather_cells(DevCells c, uint32_t Meff, const uint32_t* slots,
 // mlp.hip: the learned proposal (144 -> 64 -> 64 -> 64 -> 64, BF16 MFMA)
 constexpr uint32_t kMlpParams = 64u * 144u + 64u + 3u * (64u * 64u + 64u);
 constexpr uint32_t kMlpFragVecs = 4352u;   // 16-byte BF16 operand fragments
-constexpr uint32_t kMlpTuplesPerBlock = 64u;
+constexpr uint32_t kMlpTuplesPerBlock = 128u;  // training tuples per block of the fused kernel
 struct MlpEncode {
     float lo[3];
     float ext[3];
@@ -643,10 +643,17 @@ struct MlpEncode {
 hipError_t launch_mlp_refresh(const float* master, uint16_t* frag, hipStream_t s);
 hipError_t launch_mlp_forward(const uint16_t* frag, const float* master, MlpEncode enc, const float* pos,
                               const float* nrm, uint32_t P, float* cdf, float* logits, hipStream_t s);
+// Encoded inputs of P points for the training kernel: kMlpEncodeHalves
+// BF16 values (320 bytes) per point.
+constexpr uint32_t kMlpEncodeHalves = 160u;
+hipError_t launch_mlp_encode(MlpEncode enc, const float* pos, const float* nrm, uint32_t P, uint16_t* out,
+                             hipStream_t s);
+// xenc: the points' encoded inputs (launch_mlp_encode), or null to encode
+// in the kernel
 hipError_t launch_mlp_fwd_bwd(const uint16_t* frag, const float* master, MlpEncode enc, const float* pos,
-                              const float* nrm, uint32_t P, const uint32_t* order, const uint32_t* pid,
-                              const uint32_t* node, const float* w, uint32_t n, float* partial, float* part_w,
-                              float* part_loss, uint32_t* err, hipStream_t s);
+                              const float* nrm, uint32_t P, const uint16_t* xenc, const uint32_t* order,
+                              const uint32_t* pid, const uint32_t* node, const float* w, uint32_t n, float* partial,
+                              float* part_w, float* part_loss, uint32_t* err, hipStream_t s);
 // mode 0: write the batch gradient to `out`; mode 1: Adam step on master
 // (m, v), then refresh the BF16 fragments
 hipError_t launch_mlp_reduce(const float* partial, const float* part_w, const float* part_loss, uint32_t nblocks,

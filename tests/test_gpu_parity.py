@@ -687,3 +687,31 @@ def test_footprint_errors(torch):
                 dict(footprint_levels=2, footprint_tile=float("nan"))):
         with pytest.raises(rlc.RLCError):
             rlc.Context(dict(s.params, **bad))
+
+
+# --------------------------------------------------------------------------
+# a mid-size static scene, whole: the fused pass at one sample per point
+# against the oracle and against the split path
+# --------------------------------------------------------------------------
+def test_static_mid_size_parity(torch):
+    """A 480 x 270 static scene at one sample per point: every pass's
+    radiance and the cell tables equal the oracle's and the split path's
+    (rlc_sample / rlc_shade / rlc_learn)."""
+    s = scenes.make_static(width=480, height=270, capacity=1 << 16)
+    ctx, orc = _make(torch, s)
+    split, _ = _make(torch, s)
+    pos, nrm = _t(torch, s.pos), _t(torch, s.nrm)
+    for f in range(5):
+        rad = ctx.rlc_frame(pos, nrm, 1, f).cpu().numpy()
+        ref, _ = orc.frame(s.pos, s.nrm, 1, f)
+        orc.adapt()
+        assert np.array_equal(rad, ref), f
+        smp = split.rlc_sample(pos, nrm, 1, f)
+        rs, _, rew = split.rlc_shade(pos, nrm, 1, smp)
+        split.rlc_learn(smp, rew)
+        split.rlc_adapt_cuts()
+        assert np.array_equal(rs.cpu().numpy(), rad), f
+    ctx.rlc_sync()
+    g = ctx.rlc_dump_cells()
+    _assert_cells_equal(g, orc.cells())
+    _assert_cells_equal(g, split.rlc_dump_cells())
