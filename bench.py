@@ -40,6 +40,7 @@ if ROOT not in sys.path:
 METRIC = "light samples/s (sample+shadow+learn) and MSE vs oracle at equal GPU time"
 PEAK_HBM_GBS = 8000.0
 TRAFFIC_FILE = os.path.join(ROOT, "profiles", "traffic_frame_static.json")
+VALU_FILE = os.path.join(ROOT, "profiles", "valu_frame_static.json")
 KERNEL_SOURCES = ("paper_1911_10217_amd/csrc/frame.hip", "paper_1911_10217_amd/csrc/rlc_internal.h",
                   "paper_1911_10217_amd/csrc/occ_trace.h", "paper_1911_10217_amd/csrc/occ.hip")
 
@@ -262,6 +263,46 @@ def write_traffic(fetch_csv, write_csv, copy_mib):
     with open(TRAFFIC_FILE, "w") as f:
         json.dump(out, f, indent=1)
     print(json.dumps(out))
+
+def _sum_counters(path, names):
+    """Per-dispatch sums of the given counters over the fused kernel's
+    dispatches: {counter: mean over dispatches}."""
+    per = {}
+    for r in _pmc_rows(path):
+        name = r.get("Kernel_Name", r.get("kernel_name", ""))
+        if "k_frame" not in name:
+            continue
+        cn = r.get("Counter_Name", r.get("counter_name"))
+        if cn not in names:
+            continue
+        did = r.get("Dispatch_Id", r.get("dispatch_id"))
+        per.setdefault(cn, {}).setdefault(did, 0.0)
+        per[cn][did] += float(r.get("Counter_Value", r.get("counter_value", 0.0)))
+    return {k: sum(v.values()) / len(v) for k, v in per.items()}
+
+
+def write_valu(valu_csv, wait_csv):
+    """VALU issue and waits of the fused kernel from two counter collections
+    (see profiles/k_frame_static_valu_counters.md): the lanes' share of VALU
+    work, the SIMDs' VALU occupancy, and their product, the useful-lane
+    fraction of the chip's VALU issue capacity while the kernel runs."""
+    a = _sum_counters(valu_csv, {"SQ_ACTIVE_INST_VALU", "SQ_THREAD_CYCLES_VALU", "SQ_WAVES", "SQ_WAVE_CYCLES",
+                                 "SQ_INSTS_VALU", "SQ_INSTS_SALU"})
+    b = _sum_counters(wait_csv, {"SQ_WAIT_ANY", "SQ_WAVE_CYCLES"})
+    waves = a["SQ_WAVES"]
+    lane_util = a["SQ_THREAD_CYCLES_VALU"] / (64.0 * a["SQ_ACTIVE_INST_VALU"])
+    # 8 waves per SIMD; counters in quad-cycles (a wave64 VALU instruction takes one)
+    simd_busy = 8.0 * a["SQ_ACTIVE_INST_VALU"] / a["SQ_WAVE_CYCLES"]
+    out = {"kernel": "k_frame", "kernel_source_hash": kernel_source_hash(),
+           "valu_insts_per_wave": round(a["SQ_INSTS_VALU"] / waves, 1),
+           "salu_insts_per_wave": round(a["SQ_INSTS_SALU"] / waves, 1),
+           "lane_utilisation": round(lane_util, 4), "simd_valu_busy": round(simd_busy, 4),
+           "useful_lane_valu_frac": round(lane_util * simd_busy, 4),
+           "wait_any_frac": round(b["SQ_WAIT_ANY"] / b["SQ_WAVE_CYCLES"], 4)}
+    with open(VALU_FILE, "w") as f:
+        json.dump(out, f, indent=1)
+    print(json.dumps(out))
+
 
 MLP_FLOP_PER_TUPLE = 2 * (144 * 64 + 3 * 64 * 64) + 2 * 3 * 64 * 64 + 2 * (144 * 64 + 3 * 64 * 64)
 PEAK_BF16_TFLOPS = 2500.0
@@ -637,12 +678,18 @@ def main():
     ap.add_argument("--footprint-levels", type=int, default=6)
     ap.add_argument("--copy-calib-mib", type=int, default=0,
                     help="also run a plain device copy of this many MiB (counter calibration)")
+    ap.add_argument("--write-valu", nargs=2, metavar=("VALU_CSV", "WAIT_CSV"),
+                    help="turn the two VALU / wait counter collections of the fused kernel into "
+                         "profiles/valu_frame_static.json")
     ap.add_argument("--write-traffic", nargs=2, metavar=("FETCH_CSV", "WRITE_CSV"),
                     help="turn two rocprofv3 --pmc counter collections (FETCH_SIZE, WRITE_SIZE) of "
                          "a run with --copy-calib-mib into the fused kernel's HBM bytes per launch")
     args = ap.parse_args()
     if args.write_traffic:
         write_traffic(*args.write_traffic, copy_mib=args.copy_calib_mib or 256)
+        return
+    if args.write_valu:
+        write_valu(*args.write_valu)
         return
     world = int(os.environ.get("WORLD_SIZE", "1"))
     if args.gpus != 1 or world != 1:
@@ -794,6 +841,13 @@ def main():
     if traffic:
         # the bytes HBM actually moved (counters) over the same mean duration
         roofline["measured_frac"] = round(traffic / (fused_avg_ms * 1e-3) / 1e9 / PEAK_HBM_GBS, 4)
+    if os.path.exists(VALU_FILE):
+        with open(VALU_FILE) as f:
+            vf = json.load(f)
+        if vf.get("kernel_source_hash") == kernel_source_hash():
+            # the kernel's actual limit: VALU issue (counters of the same sources)
+            roofline["valu"] = {k: vf[k] for k in ("lane_utilisation", "simd_valu_busy", "useful_lane_valu_frac",
+                                                   "wait_any_frac", "valu_insts_per_wave")}
 
     # ---- MSE at equal GPU time: learning on against learning off ----
     mse = None
