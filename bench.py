@@ -676,6 +676,9 @@ def main():
                     help="footprint-sized cells: a primary hit's cell edge is wanted at this many times its "
                          "pixel footprint (0: the fixed 64^3 grid)")
     ap.add_argument("--footprint-levels", type=int, default=6)
+    ap.add_argument("--max-cells", type=int, default=-1,
+                    help="rows of the cell tables (-1: the workload's own; 0: one per lookup slot; "
+                         "5-D cells default to 0)")
     ap.add_argument("--copy-calib-mib", type=int, default=0,
                     help="also run a plain device copy of this many MiB (counter calibration)")
     ap.add_argument("--write-valu", nargs=2, metavar=("VALU_CSV", "WAIT_CSV"),
@@ -719,6 +722,10 @@ def main():
     s = scenes.make_static() if args.workload == "static" else scenes.make_dynamic()
     p = dict(s.params, occ_grid_res=64, split_steps=args.split_steps, normal_bits=args.normal_bits,
              jitter=args.jitter)
+    if args.max_cells >= 0:
+        p["max_cells"] = args.max_cells
+    elif args.normal_bits > 0:
+        p["max_cells"] = 0  # normal bins multiply the cells: one row per lookup slot
     if args.footprint_tile > 0:
         if s.footprint is None:
             raise SystemExit("--footprint-tile needs a workload with camera footprints (static)")
@@ -726,6 +733,9 @@ def main():
     spp = int(p["spp"])
     P = s.P
     n_sub = max(1, args.sub_frames)
+    # the configuration the committed counter profiles were taken on
+    profiled = (args.workload == "static" and args.split_steps <= 1 and args.normal_bits == 0
+                and args.jitter == 0.0 and n_sub == 1 and args.footprint_tile == 0 and args.max_cells < 0)
     samples_per_pass = P * spp
     samples_per_step = samples_per_pass * n_sub
 
@@ -818,7 +828,7 @@ def main():
     if os.path.exists(TRAFFIC_FILE):
         with open(TRAFFIC_FILE) as f:
             tr = json.load(f)
-        if tr.get("kernel_source_hash") == kernel_source_hash():
+        if profiled and tr.get("kernel_source_hash") == kernel_source_hash():
             traffic = tr.get("bytes_per_launch")
 
     roofline = {
@@ -844,7 +854,7 @@ def main():
     if os.path.exists(VALU_FILE):
         with open(VALU_FILE) as f:
             vf = json.load(f)
-        if vf.get("kernel_source_hash") == kernel_source_hash():
+        if profiled and vf.get("kernel_source_hash") == kernel_source_hash():
             # the kernel's actual limit: VALU issue (counters of the same sources)
             roofline["valu"] = {k: vf[k] for k in ("lane_utilisation", "simd_valu_busy", "useful_lane_valu_frac",
                                                    "wait_any_frac", "valu_insts_per_wave")}
@@ -902,6 +912,9 @@ def main():
     if args.normal_bits or args.jitter > 0:
         workload += "; 5-D cells: %d x %d normal bins, jitter %g" % (1 << args.normal_bits, 1 << args.normal_bits,
                                                                    args.jitter)
+    rows = int(p.get("max_cells", 0))
+    workload += ("; cell tables with rows for %s cells" % format(rows, ",") if rows
+                 else "; cell tables with one row per lookup slot")
     line = {
         "metric": METRIC,
         "value": round(value, 1),

@@ -66,7 +66,7 @@ typedef struct rlc_config {
     float grid_hi[3];
     uint32_t grid_dims[3];
     uint32_t hashed;       /* 0: dense grid table; 1: open-addressing hash */
-    uint32_t capacity;     /* hash capacity in cells (rounded up to 2^k) */
+    uint32_t capacity;     /* hashed: lookup slots (rounded up to 2^k, at least 64) */
     uint32_t adapt;        /* 1: split-collapse at the end of every pass */
     uint32_t temporal;     /* 0: every pass restarts from the initial cut */
     uint32_t scene_id;     /* upper key bits and RNG stream of this scene */
@@ -93,6 +93,11 @@ typedef struct rlc_config {
                               smallest cell edge times 2^level) reaches footprint_tile
                               times its footprint (the coarsest if none does); > 0 when
                               footprint_levels > 1 */
+    uint32_t max_cells;    /* cells the tables hold rows for (section 3's bounded memory per
+                              cell: the per-cluster tables take max_cells * M * 32 bytes);
+                              0: one row per lookup slot (hashed) or per cell of the grid
+                              (dense); at most that many.  A cell created past it is not
+                              learned from and the pass reports RLC_ECAPACITY */
 } rlc_config;
 
 /* Per-sample records of rlc_sample (device arrays of n = P * spp entries,
@@ -100,7 +105,7 @@ typedef struct rlc_config {
  * do not need it (cell, slot, light and inv_pdf feed rlc_shade/rlc_learn). */
 typedef struct rlc_samples {
     uint64_t* d_key;       /* cell key: (scene_id << 32) | linear cell index */
-    uint32_t* d_cell;      /* internal table slot of the cell (0xFFFFFFFF: none) */
+    uint32_t* d_cell;      /* internal table row of the cell (0xFFFFFFFF: none) */
     uint32_t* d_ready;     /* 1 if the cell's learned table was used */
     uint32_t* d_slot;      /* cluster s drawn from the cell's cdf */
     uint32_t* d_light;     /* light index in tree order */
@@ -111,7 +116,9 @@ typedef struct rlc_samples {
 } rlc_samples;
 
 /* Create a context whose work goes to `stream` (hipStream_t).  Allocates
- * the cell tables: capacity * M * 32 bytes plus 12 bytes per cell. */
+ * the cell tables: 8 bytes per lookup slot (hashed: capacity; dense: every
+ * cell of the grid) and M * 32 + 8 bytes per row (max_cells rows).  Rows are
+ * handed out in creation order, so the rows in use are packed from row 0. */
 int rlc_create(const rlc_config* cfg, void* stream, rlc_ctx** out);
 int rlc_destroy(rlc_ctx* ctx);
 
@@ -334,6 +341,7 @@ int rlc_set_sample_log(rlc_ctx* ctx, uint32_t* d_pid, uint32_t* d_node, float* d
 /* ---- inspection, checkpoint and parity interface (synchronise) ---- */
 int rlc_sync(rlc_ctx* ctx);
 const char* rlc_last_error(const rlc_ctx* ctx);
+/* Cells created (at most the config's max_cells rows). */
 int rlc_num_cells(rlc_ctx* ctx, uint32_t* h_n);
 int rlc_meff(rlc_ctx* ctx, uint32_t* h_meff);
 /* All cells in increasing key order; per-cell arrays have Meff columns;

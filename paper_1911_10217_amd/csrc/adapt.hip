@@ -391,25 +391,31 @@ __device__ __forceinline__ void adapt_cell(const AdaptParams& ap, const CellIn<P
     adapt_back<PER>(ap, in.c, L);
 }
 
-// The cells of the live list from li on, with a stride of the grid: each
-// cell's loads are issued before the previous cell's work (with one slot per
-// lane; four slots per lane would hold too many registers).
+// Rows in use: the created cells, packed from row 0.
+__device__ __forceinline__ uint32_t rows_in_use(const DevCells& c) {
+    const uint32_t n = *c.n_live;
+    return n < c.rows ? n : c.rows;
+}
+
+// The cells of rows li, li + grid, ...: each cell's loads are issued before
+// the previous cell's work (with one slot per lane; four slots per lane
+// would hold too many registers).
 template <int PER>
 __device__ __forceinline__ void adapt_cells(const AdaptParams& ap, const AdaptLds& L) {
-    const uint32_t n_live = *ap.cells.n_live;
+    const uint32_t n_live = rows_in_use(ap.cells);
     uint32_t li = blockIdx.x;
     if (li >= n_live) return;
     CellIn<PER> cur, nxt;
-    load_cell<PER>(ap, ap.cells.live[li], cur);
+    load_cell<PER>(ap, li, cur);
     for (; li < n_live; li += gridDim.x) {
         const uint32_t ln = li + gridDim.x;
-        if (PER == 1 && ln < n_live) load_cell<PER>(ap, ap.cells.live[ln], nxt);
+        if (PER == 1 && ln < n_live) load_cell<PER>(ap, ln, nxt);
         adapt_cell<PER>(ap, cur, L);
         if (ln < n_live) {
             if (PER == 1)
                 cur = nxt;
             else
-                load_cell<PER>(ap, ap.cells.live[ln], cur);
+                load_cell<PER>(ap, ln, cur);
         }
     }
 }
@@ -452,20 +458,20 @@ __global__ void __launch_bounds__(kCellWaves * kWave, 8) k_adapt16(AdaptParams /
     __shared__ uint32_t s_active[kCellWaves];
     const uint32_t wave = threadIdx.x / kWave, lane = threadIdx.x % kWave;
     const AdaptLds L = lds_view(lds + wave * kCellRegion, kWave);
-    const uint32_t n_live = *ap.cells.n_live;
+    const uint32_t n_live = rows_in_use(ap.cells);
     const uint32_t per_round = gridDim.x * kCellWaves;
     const uint32_t rounds = (n_live + per_round - 1u) / per_round;
     // each round's cell is loaded during the round before (a launch
     // touches every cell once, so no round writes the next one's cell)
     CellIn<1> nxt;
     const uint32_t li0 = blockIdx.x * kCellWaves + wave;
-    if (li0 < n_live) load_cell<1>(ap, ap.cells.live[li0], nxt);
+    if (li0 < n_live) load_cell<1>(ap, li0, nxt);
     for (uint32_t rd = 0; rd < rounds; ++rd) {
         const uint32_t li = rd * per_round + li0;
         bool active = false;
         uint32_t c = 0;
         const CellIn<1> in = nxt;
-        if (li + per_round < n_live) load_cell<1>(ap, ap.cells.live[li + per_round], nxt);
+        if (li + per_round < n_live) load_cell<1>(ap, li + per_round, nxt);
         if (li < n_live) {
             c = in.c;
             active = adapt_front<1>(ap, in, L);
@@ -496,10 +502,10 @@ __global__ void __launch_bounds__(kWave) k_load_cells(AdaptParams /* read in pla
     const uint32_t Meff = ap.tmpl.Meff;
     for (uint32_t i = blockIdx.x; i < n; i += gridDim.x) {
         const unsigned long long key = keys[i];
-        uint32_t slot = RLC_NONE;
-        if (lane == 0) slot = find_or_create(ap.cells, key, (uint32_t)(key & 0xFFFFFFFFull), err);
-        slot = (uint32_t)__shfl((int)slot, 0, kWave);
-        if (slot == RLC_NONE) continue;
+        uint32_t row = RLC_NONE;
+        if (lane == 0) row = find_or_create(ap.cells, key, (uint32_t)(key & 0xFFFFFFFFull), err);
+        row = (uint32_t)__shfl((int)row, 0, kWave);
+        if (row == RLC_NONE) continue;
 #pragma unroll
         for (int j = 0; j < PER; ++j) {
             const uint32_t s = lane + kWave * j;
@@ -513,17 +519,17 @@ __global__ void __launch_bounds__(kWave) k_load_cells(AdaptParams /* read in pla
         wave_sync();
         if (lane == 0) eq2_one_lane(ap, L, Meff);
         wave_sync();
-        adapt_back<PER>(ap, slot, L);
+        adapt_back<PER>(ap, row, L);
     }
 }
 
-__global__ void k_gather_cells(DevCells c, uint32_t Meff, const uint32_t* __restrict__ slots, uint32_t n,
+__global__ void k_gather_cells(DevCells c, uint32_t Meff, const uint32_t* __restrict__ rows, uint32_t n,
                                uint32_t* node, uint32_t* end, float* Q, float* Qt, float* C,
                                unsigned long long* sum, uint32_t* cnt) {
     size_t i = (size_t)blockIdx.x * blockDim.x + threadIdx.x;
     if (i >= (size_t)n * Meff) return;
     size_t row = i / Meff, s = i % Meff;
-    size_t src = (size_t)slots[row] * c.M + s;
+    size_t src = (size_t)rows[row] * c.M + s;
     if (node) node[i] = c.node[src];
     if (end) end[i] = c.end[src];
     if (Q) Q[i] = c.Q[src];
@@ -572,12 +578,12 @@ hipError_t launch_load_cells(const AdaptParams& ap, const unsigned long long* ke
     return hipGetLastError();
 }
 
-hipError_t launch_gather_cells(DevCells c, uint32_t Meff, const uint32_t* slots, uint32_t n, uint32_t* node,
+hipError_t launch_gather_cells(DevCells c, uint32_t Meff, const uint32_t* rows, uint32_t n, uint32_t* node,
                                uint32_t* end, float* Q, float* Qt, float* C, unsigned long long* sum,
                                uint32_t* cnt, hipStream_t s) {
     size_t total = (size_t)n * Meff;
     if (total == 0) return hipSuccess;
-    hipLaunchKernelGGL(k_gather_cells, dim3((uint32_t)((total + 255) / 256)), dim3(256), 0, s, c, Meff, slots, n,
+    hipLaunchKernelGGL(k_gather_cells, dim3((uint32_t)((total + 255) / 256)), dim3(256), 0, s, c, Meff, rows, n,
                        node, end, Q, Qt, C, sum, cnt);
     return hipGetLastError();
 }

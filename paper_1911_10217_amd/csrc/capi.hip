@@ -199,11 +199,11 @@ uint32_t blocks_for(size_t n, uint32_t b = 256) { return (uint32_t)((n + b - 1) 
 
 int reset_cells(rlc_ctx* c) {
     DevCells& d = c->cells;
-    size_t rows = (size_t)d.capacity * d.M;
+    size_t bins = (size_t)d.rows * d.M;
     RLC_HIP(c, launch_fill_u64(d.keys, RLC_EMPTY_KEY, d.capacity, c->stream));
-    RLC_HIP(c, launch_fill_u32(d.ready, 0u, d.capacity, c->stream));
-    RLC_HIP(c, launch_fill_u64(d.sum, 0ull, rows, c->stream));
-    RLC_HIP(c, launch_fill_u32(d.cnt, 0u, rows, c->stream));
+    RLC_HIP(c, launch_fill_u32(d.ready, 0u, d.rows, c->stream));
+    RLC_HIP(c, launch_fill_u64(d.sum, 0ull, bins, c->stream));
+    RLC_HIP(c, launch_fill_u32(d.cnt, 0u, bins, c->stream));
     RLC_HIP(c, launch_fill_u32(d.n_live, 0u, 1, c->stream));
     return RLC_OK;
 }
@@ -382,8 +382,11 @@ int read_device_errors(rlc_ctx* c) {
         RLC_HIP(c, hipStreamSynchronize(c->stream));
         if (err & RLC_DERR_CAPACITY)
             return fail(c, RLC_ECAPACITY,
-                        "cell table full (capacity %u, or %u slots in a row taken); some samples were not learned from",
-                        c->cells.capacity, RLC_HASH_MAX_PROBES);
+                        "cell table full (rows for %u cells, %u lookup slots, or %u slots in a row taken); "
+                        "some samples were not learned from",
+                        c->cells.rows, c->cells.capacity, RLC_HASH_MAX_PROBES);
+        if (err & RLC_DERR_WAIT)
+            return fail(c, RLC_EHIP, "a cell lookup gave up waiting for the cell's row to be published");
         if (err & RLC_DERR_FX_OVERFLOW)
             return fail(c, RLC_ECAPACITY,
                         "a fixed-point reward sum of one (cell, cluster) exceeded 64 bits in one pass: "
@@ -540,7 +543,9 @@ int rlc_create(const rlc_config* cfg, void* stream, rlc_ctx** out) {
         if (dense > (1u << 28)) return RLC_EINVAL;
         capacity = dense;
     }
-    if (capacity * (uint64_t)k.M >= 0xFFFFFFFFull) return RLC_EINVAL;  // (cell, cluster) bins index with 32 bits
+    if (k.max_cells > capacity) return RLC_EINVAL;
+    const uint64_t pool = k.max_cells ? k.max_cells : capacity;
+    if (pool * (uint64_t)k.M >= 0xFFFFFFFFull) return RLC_EINVAL;  // (cell, cluster) bins index with 32 bits
     int dev = 0;
     if (hipGetDevice(&dev) != hipSuccess) return RLC_EHIP;
     float* noalloc = nullptr;
@@ -566,20 +571,21 @@ int rlc_create(const rlc_config* cfg, void* stream, rlc_ctx** out) {
     c->fx_inv = ldexpf(1.0f, -(int)k.fx_shift);
     DevCells& d = c->cells;
     d.capacity = (uint32_t)capacity;
+    d.rows = (uint32_t)pool;
     d.hashed = k.hashed ? 1u : 0u;
     d.M = k.M;
-    size_t rows = (size_t)capacity * k.M;
+    size_t bins = (size_t)pool * k.M;
     int r = RLC_OK;
     if (r == RLC_OK) r = dalloc(c, &d.keys, capacity);
-    if (r == RLC_OK) r = dalloc(c, &d.ready, capacity);
-    if (r == RLC_OK) r = dalloc(c, &d.node, rows);
-    if (r == RLC_OK) r = dalloc(c, &d.end, rows);
-    if (r == RLC_OK) r = dalloc(c, &d.Q, rows);
-    if (r == RLC_OK) r = dalloc(c, &d.Qt, rows);
-    if (r == RLC_OK) r = dalloc(c, &d.C, rows);
-    if (r == RLC_OK) r = dalloc(c, &d.sum, rows);
-    if (r == RLC_OK) r = dalloc(c, &d.cnt, rows);
-    if (r == RLC_OK) r = dalloc(c, &d.live, capacity);
+    if (r == RLC_OK) r = dalloc(c, &d.ready, pool);
+    if (r == RLC_OK) r = dalloc(c, &d.node, bins);
+    if (r == RLC_OK) r = dalloc(c, &d.end, bins);
+    if (r == RLC_OK) r = dalloc(c, &d.Q, bins);
+    if (r == RLC_OK) r = dalloc(c, &d.Qt, bins);
+    if (r == RLC_OK) r = dalloc(c, &d.C, bins);
+    if (r == RLC_OK) r = dalloc(c, &d.sum, bins);
+    if (r == RLC_OK) r = dalloc(c, &d.cnt, bins);
+    if (r == RLC_OK) r = dalloc(c, &d.live, pool);
     if (r == RLC_OK) r = dalloc(c, &d.n_live, 1);
     if (r == RLC_OK) r = dalloc(c, &c->d_err, 1);
     if (r == RLC_OK) r = dalloc(c, &c->d_partial, 6 * 1024);
@@ -976,8 +982,10 @@ int rlc_sync(rlc_ctx* c) {
 
 int rlc_num_cells(rlc_ctx* c, uint32_t* h_n) {
     if (!c || !h_n) return RLC_EINVAL;
-    RLC_HIP(c, hipMemcpyAsync(h_n, c->cells.n_live, sizeof(uint32_t), hipMemcpyDeviceToHost, c->stream));
+    uint32_t n = 0;
+    RLC_HIP(c, hipMemcpyAsync(&n, c->cells.n_live, sizeof(uint32_t), hipMemcpyDeviceToHost, c->stream));
     RLC_HIP(c, hipStreamSynchronize(c->stream));
+    *h_n = std::min(n, c->cells.rows);  // creations refused by a full pool count past it
     return RLC_OK;
 }
 
@@ -996,26 +1004,31 @@ int rlc_dump_cells(rlc_ctx* c, uint32_t max_cells, uint64_t* h_keys, uint32_t* h
     RLC_TRY(rlc_num_cells(c, &n));
     if (n == 0) return RLC_OK;
     const DevCells& d = c->cells;
-    std::vector<uint32_t> slots(n);
-    std::vector<unsigned long long> keys(d.capacity);
-    std::vector<uint32_t> ready(d.capacity);
-    RLC_HIP(c, hipMemcpy(slots.data(), d.live, sizeof(uint32_t) * n, hipMemcpyDeviceToHost));
-    RLC_HIP(c, hipMemcpy(keys.data(), d.keys, sizeof(unsigned long long) * d.capacity, hipMemcpyDeviceToHost));
-    RLC_HIP(c, hipMemcpy(ready.data(), d.ready, sizeof(uint32_t) * d.capacity, hipMemcpyDeviceToHost));
-    std::sort(slots.begin(), slots.end(), [&](uint32_t a, uint32_t b) { return keys[a] < keys[b]; });
+    // rows 0..n-1 hold the created cells; each row's slot holds its key
+    std::vector<uint32_t> slot_of(n), ready(n), order(n);
+    std::vector<unsigned long long> words(d.capacity);
+    RLC_HIP(c, hipMemcpy(slot_of.data(), d.live, sizeof(uint32_t) * n, hipMemcpyDeviceToHost));
+    RLC_HIP(c, hipMemcpy(ready.data(), d.ready, sizeof(uint32_t) * n, hipMemcpyDeviceToHost));
+    RLC_HIP(c, hipMemcpy(words.data(), d.keys, sizeof(unsigned long long) * d.capacity, hipMemcpyDeviceToHost));
+    std::vector<uint64_t> key(n);
+    for (uint32_t i = 0; i < n; ++i) {
+        key[i] = ((uint64_t)c->cfg.scene_id << 32) | (words[slot_of[i]] & 0xFFFFFFFFull);
+        order[i] = i;
+    }
+    std::sort(order.begin(), order.end(), [&](uint32_t a, uint32_t b) { return key[a] < key[b]; });
     uint32_t rows = std::min(n, max_cells);
     if (rows == 0) return RLC_OK;
     for (uint32_t i = 0; i < rows; ++i) {
-        if (h_keys) h_keys[i] = keys[slots[i]];
-        if (h_ready) h_ready[i] = ready[slots[i]];
+        if (h_keys) h_keys[i] = key[order[i]];
+        if (h_ready) h_ready[i] = ready[order[i]];
     }
     const uint32_t Meff = c->Meff;
     size_t cnt = (size_t)rows * Meff;
-    uint32_t* d_slots = nullptr;
+    uint32_t* d_rows = nullptr;
     uint32_t *dn = nullptr, *de = nullptr, *dc = nullptr;
     float *dq = nullptr, *dqt = nullptr, *dC = nullptr;
     unsigned long long* ds = nullptr;
-    int r = dalloc(c, &d_slots, rows);
+    int r = dalloc(c, &d_rows, rows);
     if (r == RLC_OK && h_node) r = dalloc(c, &dn, cnt);
     if (r == RLC_OK && h_end) r = dalloc(c, &de, cnt);
     if (r == RLC_OK && h_Q) r = dalloc(c, &dq, cnt);
@@ -1025,8 +1038,8 @@ int rlc_dump_cells(rlc_ctx* c, uint32_t max_cells, uint64_t* h_keys, uint32_t* h
     if (r == RLC_OK && h_cnt) r = dalloc(c, &dc, cnt);
     hipError_t e = hipSuccess;
     if (r == RLC_OK) {
-        e = hipMemcpy(d_slots, slots.data(), sizeof(uint32_t) * rows, hipMemcpyHostToDevice);
-        if (e == hipSuccess) e = launch_gather_cells(d, Meff, d_slots, rows, dn, de, dq, dqt, dC, ds, dc, c->stream);
+        e = hipMemcpy(d_rows, order.data(), sizeof(uint32_t) * rows, hipMemcpyHostToDevice);
+        if (e == hipSuccess) e = launch_gather_cells(d, Meff, d_rows, rows, dn, de, dq, dqt, dC, ds, dc, c->stream);
         if (e == hipSuccess) e = hipStreamSynchronize(c->stream);
         if (e == hipSuccess && h_node) e = hipMemcpy(h_node, dn, sizeof(uint32_t) * cnt, hipMemcpyDeviceToHost);
         if (e == hipSuccess && h_end) e = hipMemcpy(h_end, de, sizeof(uint32_t) * cnt, hipMemcpyDeviceToHost);
@@ -1036,7 +1049,7 @@ int rlc_dump_cells(rlc_ctx* c, uint32_t max_cells, uint64_t* h_keys, uint32_t* h
         if (e == hipSuccess && h_sum) e = hipMemcpy(h_sum, ds, sizeof(uint64_t) * cnt, hipMemcpyDeviceToHost);
         if (e == hipSuccess && h_cnt) e = hipMemcpy(h_cnt, dc, sizeof(uint32_t) * cnt, hipMemcpyDeviceToHost);
     }
-    dfree(d_slots);
+    dfree(d_rows);
     dfree(dn);
     dfree(de);
     dfree(dq);
@@ -1066,7 +1079,7 @@ int rlc_load_cells(rlc_ctx* c, uint32_t n, const uint64_t* h_keys, const uint32_
             return fail(c, RLC_EINVAL, "cell key %llu is not a cell of this scene", (unsigned long long)key);
         if (i && key == sorted[i - 1]) return fail(c, RLC_EINVAL, "cell key %llu given twice", (unsigned long long)key);
     }
-    if (!c->cfg.hashed && (uint64_t)n > c->cells.capacity) return fail(c, RLC_EINVAL, "more cells than the grid holds");
+    if (n > c->cells.rows) return fail(c, RLC_EINVAL, "more cells than the table holds rows for (%u)", c->cells.rows);
     for (uint32_t i = 0; i < n; ++i) {
         // the cut partitions the lights in range order: each node starts
         // right after the previous one ends, the first at 0, the last at N-1

@@ -17,6 +17,7 @@
 #define RLC_DERR_NONFINITE 2u
 #define RLC_DERR_INPUT 4u
 #define RLC_DERR_FX_OVERFLOW 8u   // a (cell, cluster) fixed-point reward sum wrapped 64 bits
+#define RLC_DERR_WAIT 16u         // a lookup gave up waiting for another wave to publish a cell's row
 #define RLC_HASH_MAX_PROBES 256u  // probes of the cell hash before a lookup reports the table full
 #define RLC_MIX_M 64u           // nodes of the learned proposal's fixed cut (row stride of its cdf)
 #define RLC_MAX_LEVELS 16u      // footprint-sized cells: levels of cell size
@@ -45,10 +46,14 @@ struct DevCut {
     uint32_t Meff;
 };
 
-// Cell tables.  Row c of every per-slot array starts at c * M.
+// Cell tables.  A created cell's tables live in a row taken from a pool in
+// creation order, so the rows in use are dense whatever the size of the
+// lookup table; row r of every per-row array starts at r * M.  A lookup slot
+// holds (row << 32) | the cell's linear index (RLC_EMPTY_KEY: free).  One
+// context holds the cells of one scene, so the linear index is the key.
 struct DevCells {
-    unsigned long long* keys;   // RLC_EMPTY_KEY = free
-    uint32_t* ready;            // 1 once the cell's own table exists
+    unsigned long long* keys;   // per lookup slot
+    uint32_t* ready;            // per row: 1 once the cell's own table exists
     uint32_t* node;
     uint32_t* end;
     float* Q;
@@ -56,9 +61,10 @@ struct DevCells {
     float* C;
     unsigned long long* sum;    // fixed-point reward sums of the pass
     uint32_t* cnt;              // sample counts of the pass
-    uint32_t* live;             // slots of all created cells
-    uint32_t* n_live;
-    uint32_t capacity;          // dense: cells of the grid; hashed: 2^k
+    uint32_t* live;             // per row: its lookup slot
+    uint32_t* n_live;           // rows taken (passes `rows` once the pool is full)
+    uint32_t capacity;          // lookup slots: dense, cells of the grid; hashed, 2^k
+    uint32_t rows;              // rows in the pool
     uint32_t hashed;
     uint32_t M;                 // row stride
 };
@@ -271,24 +277,110 @@ __device__ __forceinline__ unsigned long long mix64(unsigned long long x) {
     return x;
 }
 
-// Find the table slot of a cell key, creating the cell if it is absent
-// (RLC_NONE and the capacity error when RLC_HASH_MAX_PROBES slots in a row
-// are taken by other keys).
-// Creation only claims the slot and records it in the live list; the cell's
-// own table is filled at the end of the pass.  A slot's key changes once,
-// from empty to its key, by compare-and-swap, so the probe reads it with a
-// plain (cached) load: a stale "empty" only sends the lane to the CAS, whose
-// returned value is current.
+// Row field of a lookup slot while its cell is being created, and once the
+// row pool turned out to be full.
+#define RLC_ROW_PENDING 0xFFFFFFFEu
+#define RLC_ROW_FULL 0xFFFFFFFDu
+// polls of a pending slot before a lookup gives up (the creating wave
+// publishes the row a few instructions after taking the slot)
+#define RLC_CREATE_MAX_POLLS (1u << 16)
+
+__device__ __forceinline__ uint32_t slot_row(unsigned long long w) { return (uint32_t)(w >> 32); }
+__device__ __forceinline__ unsigned long long slot_word(uint32_t row, uint32_t lin) {
+    return ((unsigned long long)row << 32) | (unsigned long long)lin;
+}
+
+// The row of slot h, whose word w holds this lookup's cell: waits while
+// another wave publishes the row.  RLC_NONE (and an error bit) when the pool
+// was full or the wait ran out.
+__device__ __forceinline__ uint32_t resolve_row(const DevCells& c, uint32_t h, unsigned long long w, uint32_t* err) {
+    uint32_t r = slot_row(w);
+    for (uint32_t n = 0; r == RLC_ROW_PENDING && n < RLC_CREATE_MAX_POLLS; ++n) {
+        __builtin_amdgcn_s_sleep(1);
+        w = __hip_atomic_load(&c.keys[h], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+        r = slot_row(w);
+    }
+    if (r == RLC_ROW_PENDING) {
+        atomicOr(err, RLC_DERR_WAIT);
+        return RLC_NONE;
+    }
+    if (r == RLC_ROW_FULL) {
+        atomicOr(err, RLC_DERR_CAPACITY);
+        return RLC_NONE;
+    }
+    return r;
+}
+
+// Create the cell with linear index lin at slot h, read as free, for the
+// lanes of the wave that call this together (divergent code).  Lanes with
+// the same key have probed the same slots, so they are here at the same
+// slot, and one of them (the group's leader) acts for all: it claims the slot
+// by compare-and-swap to (pending, lin), takes the next row of the pool and
+// publishes (row, lin).  A slot meanwhile claimed by another wave for the
+// same cell gives its row once published; one claimed for another cell sets
+// `retry` (probe on).  Rows are taken only by successful claims, so the rows
+// in use are exactly 0 .. min(n_live, rows) - 1.  Groups are served one
+// after the other, so no lane waits on a claim of its own wave.
+__device__ __forceinline__ uint32_t create_at(const DevCells& c, uint32_t h, uint32_t lin, uint32_t* err,
+                                              bool& retry) {
+    const uint32_t lane = __lane_id();
+    unsigned long long pending = __ballot(1);
+    uint32_t res = RLC_NONE;
+    bool done = false;
+    retry = false;
+    while (pending) {
+        const uint32_t leader = (uint32_t)__ffsll((long long)pending) - 1u;
+        const uint32_t llin = (uint32_t)__builtin_amdgcn_readlane((int)lin, (int)leader);
+        const bool mine = !done && lin == llin;
+        pending &= ~__ballot(mine);
+        uint32_t r = RLC_NONE, st = 0u;  // st: 0 answered, 1 the slot holds another cell
+        if (lane == leader) {
+            const unsigned long long old = atomicCAS(&c.keys[h], RLC_EMPTY_KEY, slot_word(RLC_ROW_PENDING, lin));
+            if (old == RLC_EMPTY_KEY) {
+                r = atomicAdd(c.n_live, 1u);
+                if (r < c.rows) {
+                    c.live[r] = h;
+                } else {
+                    atomicOr(err, RLC_DERR_CAPACITY);
+                    r = RLC_NONE;
+                }
+                atomicExch(&c.keys[h], slot_word(r == RLC_NONE ? RLC_ROW_FULL : r, lin));
+            } else if ((uint32_t)old == lin) {
+                r = resolve_row(c, h, old, err);
+            } else {
+                st = 1u;
+            }
+        }
+        r = (uint32_t)__builtin_amdgcn_readlane((int)r, (int)leader);
+        st = (uint32_t)__builtin_amdgcn_readlane((int)st, (int)leader);
+        if (mine) {
+            res = r;
+            retry = st == 1u;
+            done = true;
+        }
+    }
+    return res;
+}
+
+// The row of a cell key, creating the cell if it is absent (RLC_NONE and the
+// capacity error when the row pool is full or, hashed, when
+// RLC_HASH_MAX_PROBES slots in a row hold other keys).  Creation only takes
+// the row and records its slot in the live list; the cell's own table is
+// filled at the end of the pass.  A slot changes from free to (pending, key)
+// by compare-and-swap and then once more to (row, key), so the probe reads
+// it with a plain (cached) load: a stale "free" only sends the lanes to the
+// compare-and-swap and a stale "pending" to the coherent polls, which both
+// see the current word.
 __device__ __forceinline__ uint32_t find_or_create(const DevCells& c, unsigned long long key, uint32_t lin,
                                                    uint32_t* err) {
     if (!c.hashed) {
         if (lin >= c.capacity) return RLC_NONE;
-        unsigned long long k = c.keys[lin];
-        if (k != key) {
-            unsigned long long old = atomicCAS(&c.keys[lin], RLC_EMPTY_KEY, key);
-            if (old == RLC_EMPTY_KEY) c.live[atomicAdd(c.n_live, 1u)] = lin;
+        const unsigned long long w = c.keys[lin];
+        if (w == RLC_EMPTY_KEY) {
+            bool retry;
+            return create_at(c, lin, lin, err, retry);
         }
-        return lin;
+        return slot_row(w) < c.rows ? slot_row(w) : resolve_row(c, lin, w, err);
     }
     uint32_t mask = c.capacity - 1u;
     uint32_t h = (uint32_t)mix64(key) & mask;
@@ -296,15 +388,13 @@ __device__ __forceinline__ uint32_t find_or_create(const DevCells& c, unsigned l
     // full table reports itself instead of walking all of its slots
     const uint32_t probes = c.capacity < RLC_HASH_MAX_PROBES ? c.capacity : RLC_HASH_MAX_PROBES;
     for (uint32_t probe = 0; probe < probes; ++probe) {
-        unsigned long long k = c.keys[h];
-        if (k == key) return h;
-        if (k == RLC_EMPTY_KEY) {
-            unsigned long long old = atomicCAS(&c.keys[h], RLC_EMPTY_KEY, key);
-            if (old == RLC_EMPTY_KEY) {
-                c.live[atomicAdd(c.n_live, 1u)] = h;
-                return h;
-            }
-            if (old == key) return h;
+        const unsigned long long w = c.keys[h];
+        if (w == RLC_EMPTY_KEY) {
+            bool retry;
+            const uint32_t r = create_at(c, h, lin, err, retry);
+            if (!retry) return r;
+        } else if ((uint32_t)w == lin) {
+            return slot_row(w) < c.rows ? slot_row(w) : resolve_row(c, h, w, err);
         }
         h = (h + 1u) & mask;
     }
@@ -313,11 +403,8 @@ __device__ __forceinline__ uint32_t find_or_create(const DevCells& c, unsigned l
 }
 
 // ---------------------------------------------------------------------------
-// One light sample (section 3): cluster from the cell's cdf, light inside
-// the cluster, point on the light.
-// ---------------------------------------------------------------------------
 struct Sample {
-    uint32_t cell;      // table slot or RLC_NONE
+    uint32_t cell;      // table row or RLC_NONE
     uint32_t ready;
     uint32_t comp;      // 1: drawn by the learned proposal
     uint32_t fnode;     // fixed-cut node holding the light (RLC_NONE if not needed)
@@ -628,7 +715,7 @@ hipError_t launch_batch_adapt(const AdaptParams* aps, uint32_t n_scenes, uint32_
 // Checkpoint load of n cells (keys, cuts and Q of Meff entries each).
 hipError_t launch_load_cells(const AdaptParams& ap, const unsigned long long* keys, const uint32_t* node,
                              const float* Q, uint32_t n, uint32_t* err, hipStream_t s);
-hipError_t launch_gather_cells(DevCells c, uint32_t Meff, const uint32_t* slots, uint32_t n, uint32_t* node,
+hipError_t launch_gather_cells(DevCells c, uint32_t Meff, const uint32_t* rows, uint32_t n, uint32_t* node,
                                uint32_t* end, float* Q, float* Qt, float* C, unsigned long long* sum,
                                uint32_t* cnt, hipStream_t s);
 

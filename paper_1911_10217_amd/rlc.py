@@ -77,6 +77,7 @@ class rlc_config(ctypes.Structure):
         ("jitter", ctypes.c_float),
         ("footprint_levels", ctypes.c_uint32),
         ("footprint_tile", ctypes.c_float),
+        ("max_cells", ctypes.c_uint32),
     ]
 
 
@@ -221,6 +222,7 @@ def make_config(params: dict) -> rlc_config:
     c.jitter = float(params.get("jitter", 0.0))
     c.footprint_levels = int(params.get("footprint_levels", 0))
     c.footprint_tile = float(params.get("footprint_tile", 0.0))
+    c.max_cells = int(params.get("max_cells", 0))
     return c
 
 

@@ -60,6 +60,7 @@ DEFAULT_PARAMS = dict(
     grid_dims=(8, 8, 8),
     hashed=0,
     capacity=0,
+    max_cells=0,
     adapt=1,
     temporal=1,
     split_steps=1,
@@ -285,7 +286,8 @@ def _clustered_lights(rng, n_clusters, per_cluster, centre_lo, centre_hi, sigma=
 # static: the large static workload (the headline throughput measurement)
 # --------------------------------------------------------------------------
 def make_static(width=1920, height=1080, n_clusters=256, per_cluster=256, n_boxes=4096,
-                M=64, spp=1, frames=32, seed=SEED_BASE + 2, capacity=1 << 19, **overrides) -> Scene:
+                M=64, spp=1, frames=32, seed=SEED_BASE + 2, capacity=1 << 19, max_cells=1 << 14,
+                **overrides) -> Scene:
     rng = np.random.default_rng(seed)
     tri, emit, _, _ = _clustered_lights(rng, n_clusters, per_cluster,
                                         [0.05, 0.90, 0.05], [0.95, 0.98, 0.95])
@@ -300,7 +302,7 @@ def make_static(width=1920, height=1080, n_clusters=256, per_cluster=256, n_boxe
     pos, nrm, fp = _primary_hits(boxes, width, height, cam=(0.1, 0.7, 0.05), look=(0.7, 0.1, 0.8))
     order = tiled_pixel_order(width, height)
     params = params_for(M=M, spp=spp, frames=frames, grid_dims=(64, 64, 64), hashed=1,
-                        capacity=capacity, seed=seed, occ_grid_res=64)
+                        capacity=capacity, max_cells=max_cells, seed=seed, occ_grid_res=64)
     params.update(overrides)
     return Scene("static", tri, emit, boxes, np.ascontiguousarray(pos[order]), np.ascontiguousarray(nrm[order]),
                  params, image_size=(height, width), pixel=order.astype(np.int64),
@@ -311,7 +313,7 @@ def make_static(width=1920, height=1080, n_clusters=256, per_cluster=256, n_boxe
 # dynamic: walled compartments, each with its own animated light
 # --------------------------------------------------------------------------
 def make_dynamic(n_points=1 << 20, per_cluster=65536, grid=4, n_bricks=16384, M=64, spp=1,
-                 frames=60, seed=SEED_BASE + 3, capacity=1 << 19, **overrides) -> Scene:
+                 frames=60, seed=SEED_BASE + 3, capacity=1 << 19, max_cells=1 << 17, **overrides) -> Scene:
     rng = np.random.default_rng(seed)
     n_comp = grid * grid
     cw = 1.0 / grid
@@ -388,7 +390,7 @@ def make_dynamic(n_points=1 << 20, per_cluster=65536, grid=4, n_bricks=16384, M=
     order = np.argsort(_morton_key(pos, 64), kind="stable")
     pos, nrm = pos[order], nrm[order]
     params = params_for(M=M, spp=spp, frames=frames, grid_dims=(64, 64, 64), hashed=1,
-                        capacity=capacity, seed=seed, occ_grid_res=64)
+                        capacity=capacity, max_cells=max_cells, seed=seed, occ_grid_res=64)
     params.update(overrides)
     return Scene("dynamic", tri, emit, boxes, _f32(pos), _f32(nrm), params, emission_at=emission_at)
 

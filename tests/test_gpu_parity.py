@@ -715,3 +715,101 @@ def test_static_mid_size_parity(torch):
     g = ctx.rlc_dump_cells()
     _assert_cells_equal(g, orc.cells())
     _assert_cells_equal(g, split.rlc_dump_cells())
+
+
+# --------------------------------------------------------------------------
+# the row pool: cell tables hold rows for max_cells cells, handed out in
+# creation order, whatever the size of the lookup table
+# --------------------------------------------------------------------------
+def _cells_after_passes(s, passes, spp):
+    o = oracle.Oracle(s.params, s.tri, s.emit, s.boxes if s.K else None)
+    for f in range(passes):
+        o.frame(s.pos, s.nrm, spp, f)
+        o.adapt()
+    return o.cells()["key"].size
+
+
+@pytest.mark.parametrize("hashed", [0, 1])
+def test_row_pool_of_exactly_the_cells_created(torch, hashed):
+    """Rows for exactly as many cells as the passes create: no error, every
+    row used, radiance and tables as the oracle's and as a context with one
+    row per lookup slot."""
+    s = scenes.make_tiny(n_points=3000, spp=4, M=16, hashed=hashed, capacity=4096)
+    n = _cells_after_passes(s, 4, 4)
+    assert 100 < n < 512
+    pos, nrm = _t(torch, s.pos), _t(torch, s.nrm)
+    ctx, orc = _make(torch, s, dict(s.params, max_cells=n))
+    full, _ = _make(torch, s)
+    for f in range(4):
+        rad = ctx.rlc_frame(pos, nrm, 4, f).cpu().numpy()
+        ref, _ = orc.frame(s.pos, s.nrm, 4, f)
+        orc.adapt()
+        assert np.array_equal(rad, ref), f
+        assert np.array_equal(full.rlc_frame(pos, nrm, 4, f).cpu().numpy(), rad), f
+    ctx.rlc_sync()
+    assert ctx.rlc_num_cells() == n
+    g = ctx.rlc_dump_cells()
+    _assert_cells_equal(g, orc.cells())
+    _assert_cells_equal(g, full.rlc_dump_cells())
+
+
+@pytest.mark.parametrize("hashed", [0, 1])
+def test_row_pool_full_keeps_its_cells_exact(torch, hashed):
+    """Rows for a third of the cells: every pass reports RLC_ECAPACITY and
+    ends normally; exactly max_cells cells hold rows, and since a cell gets
+    either all of its samples or none, each of them holds what the oracle
+    learns for it.  The first pass draws from the initial cut everywhere, so
+    its radiance is the oracle's bit for bit."""
+    from paper_1911_10217_amd import rlc
+    s = scenes.make_tiny(n_points=3000, spp=4, M=16, hashed=hashed, capacity=4096)
+    n = _cells_after_passes(s, 3, 4)
+    rows = n // 3
+    pos, nrm = _t(torch, s.pos), _t(torch, s.nrm)
+    ctx, orc = _make(torch, s, dict(s.params, max_cells=rows))
+    for f in range(3):
+        rad = ctx.rlc_frame(pos, nrm, 4, f).cpu().numpy()
+        ref, _ = orc.frame(s.pos, s.nrm, 4, f)
+        orc.adapt()
+        if f == 0:
+            assert np.array_equal(rad, ref)
+        assert np.isfinite(rad).all()
+        with pytest.raises(rlc.RLCError) as e:
+            ctx.rlc_sync()
+        assert e.value.code == rlc.RLC_ECAPACITY and "rows for %d cells" % rows in str(e.value)
+    assert ctx.rlc_num_cells() == rows
+    g = ctx.rlc_dump_cells()
+    assert g["key"].size == rows and np.all(g["ready"] == 1)
+    _assert_cells_equal(g, orc.cells(), keys=g["key"])
+    # a checkpoint of more cells than the rows is refused before any work
+    o = orc.cells()
+    with pytest.raises(rlc.RLCError) as e:
+        ctx.rlc_load_cells(o["key"], o["node"], o["Q"])
+    assert e.value.code == rlc.RLC_EINVAL
+
+
+def test_row_pool_bounds_are_refused(torch):
+    from paper_1911_10217_amd import rlc
+    s = scenes.make_tiny(n_points=64, hashed=1, capacity=4096)
+    with pytest.raises(rlc.RLCError):
+        rlc.Context(dict(s.params, max_cells=4097))
+    dense = scenes.make_tiny(n_points=64, grid_dims=(8, 8, 8))
+    with pytest.raises(rlc.RLCError):
+        rlc.Context(dict(dense.params, max_cells=513))
+    rlc.Context(dict(dense.params, max_cells=512)).close()
+    rlc.Context(dict(s.params, max_cells=1)).close()
+
+
+def test_row_pool_memory_follows_the_cells(torch):
+    """The static workload's tables: 2^19 lookup slots but rows for 16,384
+    cells, so the device memory a context takes is about 16,384 * 64 * 32
+    bytes of rows plus 8 bytes per slot, not 2^19 rows."""
+    from paper_1911_10217_amd import rlc
+    s = scenes.make_static(width=64, height=36)
+    torch.cuda.synchronize()
+    before = torch.cuda.mem_get_info()[0]
+    ctx = rlc.Context(s.params)
+    torch.cuda.synchronize()
+    taken = before - torch.cuda.mem_get_info()[0]
+    want = 16384 * 64 * 32 + 16384 * 8 + (1 << 19) * 8
+    assert taken < 2 * want + (64 << 20), taken
+    ctx.close()
