@@ -27,6 +27,7 @@ Prints ONE JSON line.  Extra fields:
 from __future__ import annotations
 
 import argparse
+import csv
 import hashlib
 import json
 import os
@@ -281,23 +282,39 @@ def _sum_counters(path, names):
     return {k: sum(v.values()) / len(v) for k, v in per.items()}
 
 
-def write_valu(valu_csv, wait_csv):
+SIMDS = 1024           # 256 CUs x 4 SIMDs
+CLOCK_HZ = 2.4e9       # peak engine clock
+VALU_ISSUE_CYCLES = 4  # a wave64 VALU instruction on a 16-lane SIMD
+
+
+def _mean_kernel_ns(stats_csv, name):
+    with open(stats_csv) as f:
+        for r in csv.DictReader(f):
+            if name in r["Name"]:
+                return float(r["AverageNs"])
+    raise SystemExit("no %s in %s" % (name, stats_csv))
+
+
+def write_valu(valu_csv, wait_csv, stats_csv):
     """VALU issue and waits of the fused kernel from two counter collections
-    (see profiles/k_frame_static_valu_counters.md): the lanes' share of VALU
-    work, the SIMDs' VALU occupancy, and their product, the useful-lane
-    fraction of the chip's VALU issue capacity while the kernel runs."""
+    and the kernel trace of the same configuration (see
+    profiles/k_frame_static_valu_counters.md): the lanes' share of VALU work,
+    the SIMDs' VALU issue time over the kernel's mean duration, and their
+    product, the useful-lane fraction of the chip's VALU issue capacity."""
     a = _sum_counters(valu_csv, {"SQ_ACTIVE_INST_VALU", "SQ_THREAD_CYCLES_VALU", "SQ_WAVES", "SQ_WAVE_CYCLES",
                                  "SQ_INSTS_VALU", "SQ_INSTS_SALU"})
     b = _sum_counters(wait_csv, {"SQ_WAIT_ANY", "SQ_WAVE_CYCLES"})
     waves = a["SQ_WAVES"]
     lane_util = a["SQ_THREAD_CYCLES_VALU"] / (64.0 * a["SQ_ACTIVE_INST_VALU"])
-    # 8 waves per SIMD; counters in quad-cycles (a wave64 VALU instruction takes one)
-    simd_busy = 8.0 * a["SQ_ACTIVE_INST_VALU"] / a["SQ_WAVE_CYCLES"]
+    # VALU instructions issued per SIMD, 4 cycles each, over the kernel's
+    # mean duration at the peak clock
+    kernel_ns = _mean_kernel_ns(stats_csv, "k_frame")
+    simd_busy = a["SQ_ACTIVE_INST_VALU"] * VALU_ISSUE_CYCLES / SIMDS / (kernel_ns * 1e-9 * CLOCK_HZ)
     out = {"kernel": "k_frame", "kernel_source_hash": kernel_source_hash(),
            "valu_insts_per_wave": round(a["SQ_INSTS_VALU"] / waves, 1),
            "salu_insts_per_wave": round(a["SQ_INSTS_SALU"] / waves, 1),
            "lane_utilisation": round(lane_util, 4), "simd_valu_busy": round(simd_busy, 4),
-           "useful_lane_valu_frac": round(lane_util * simd_busy, 4),
+           "useful_lane_valu_frac": round(lane_util * simd_busy, 4), "kernel_ns": round(kernel_ns, 1),
            "wait_any_frac": round(b["SQ_WAIT_ANY"] / b["SQ_WAVE_CYCLES"], 4)}
     with open(VALU_FILE, "w") as f:
         json.dump(out, f, indent=1)
@@ -681,7 +698,7 @@ def main():
                          "5-D cells default to 0)")
     ap.add_argument("--copy-calib-mib", type=int, default=0,
                     help="also run a plain device copy of this many MiB (counter calibration)")
-    ap.add_argument("--write-valu", nargs=2, metavar=("VALU_CSV", "WAIT_CSV"),
+    ap.add_argument("--write-valu", nargs=3, metavar=("VALU_CSV", "WAIT_CSV", "KERNEL_STATS_CSV"),
                     help="turn the two VALU / wait counter collections of the fused kernel into "
                          "profiles/valu_frame_static.json")
     ap.add_argument("--write-traffic", nargs=2, metavar=("FETCH_CSV", "WRITE_CSV"),
