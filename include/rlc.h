@@ -316,6 +316,12 @@ int rlc_mlp_forward(rlc_ctx* ctx, const float* d_pos, const float* d_nrm, uint32
  * Synchronises; bad tuples give RLC_EINVAL. */
 int rlc_mlp_grad(rlc_ctx* ctx, const float* d_pos, const float* d_nrm, uint32_t P, const uint32_t* d_pid,
                  const uint32_t* d_node, const float* d_w, uint32_t n, float* d_grad, float* h_loss);
+/* The order in which epoch `epoch` of rlc_mlp_train visits n tuples (the
+ * paper does not fix one): d_order[i] (device, n entries) is the tuple at
+ * position i, a permutation of 0..n-1 keyed by the context's seed, scene
+ * id and the epoch (an eight-round Feistel network with cycle walking over
+ * Philox round keys).  Enqueued on the context's stream. */
+int rlc_mlp_order(rlc_ctx* ctx, uint32_t n, uint32_t epoch, uint32_t* d_order);
 /* `epochs` epochs of minibatch Adam at learning rate lr over the n tuples.
  * With h_loss non-NULL the call synchronises, reports bad tuples and
  * returns the last batch's loss; with h_loss NULL it only enqueues, and bad

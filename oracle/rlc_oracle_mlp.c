@@ -276,29 +276,58 @@ int orc_mlp_adam(double* params, double* m, double* v, const double* grad, uint3
     return 0;
 }
 
-/* Training order: for epoch e, tuple i gets the key x0 of Philox at counter
- * (i, e, 0, scene << 16 | 2); the order is ascending (key, i). */
+/* Training order (not fixed by the paper; a reading): batch position i of
+ * epoch e takes tuple pi_e(i), where pi_e is a keyed pseudo-random
+ * permutation of 0..n-1 that needs no sort.  pi_e is a balanced Feistel
+ * network of eight rounds on 2h-bit words (h the smallest with 4^h >= n, at
+ * least 1; Luby and Rackoff 1988): round r maps the halves (L, R) to
+ * (R, L xor (F(R xor k_r) mod 2^h)), with F the 32-bit finaliser of
+ * MurmurHash3 (Appleby) and k_{4j+w} word w of Philox at counter
+ * (j, e, 0, scene << 16 | 2), j = 0, 1.  (Four rounds leave neighbouring
+ * positions visibly correlated when the halves are a few bits wide.)  The
+ * network permutes 0..4^h-1; a value of n or more is sent through it again
+ * until one falls below n (cycle walking, Black and Rogaway 2002), which
+ * keeps the map a permutation of 0..n-1. */
 int orc_philox(const uint32_t* ctr, const uint32_t* key, uint32_t* out, uint32_t n);
 
-static int cmp_u64_asc(const void* a, const void* b)
+static uint32_t murmur3_fmix32(uint32_t h)
 {
-    uint64_t x = *(const uint64_t*)a, y = *(const uint64_t*)b;
-    return x < y ? -1 : (x > y ? 1 : 0);
+    h ^= h >> 16;
+    h *= 0x85EBCA6Bu;
+    h ^= h >> 13;
+    h *= 0xC2B2AE35u;
+    h ^= h >> 16;
+    return h;
+}
+
+static uint32_t feistel_rounds(uint32_t x, uint32_t h, const uint32_t k[8])
+{
+    const uint32_t mask = (uint32_t)((1ull << h) - 1ull);
+    uint32_t left = (uint32_t)((uint64_t)x >> h), right = x & mask;
+    for (int r = 0; r < 8; ++r) {
+        uint32_t next = left ^ (murmur3_fmix32(right ^ k[r]) & mask);
+        left = right;
+        right = next;
+    }
+    return (uint32_t)(((uint64_t)left << h) | right);
 }
 
 int orc_mlp_shuffle(uint32_t n, uint32_t epoch, uint32_t scene_id, uint64_t seed, uint32_t* perm)
 {
-    uint64_t* k = (uint64_t*)malloc(sizeof(uint64_t) * (n ? n : 1u));
-    if (!k) return -2;
-    uint32_t key[2] = {(uint32_t)(seed & 0xFFFFFFFFull), (uint32_t)(seed >> 32)};
-    for (uint32_t i = 0; i < n; ++i) {
-        uint32_t ctr[4] = {i, epoch, 0u, (scene_id << 16) | 2u}, o[4];
-        orc_philox(ctr, key, o, 1);
-        k[i] = ((uint64_t)o[0] << 32) | i;
+    uint32_t h = 1;
+    while ((1ull << (2u * h)) < (uint64_t)n) ++h;
+    uint32_t key[2] = {(uint32_t)(seed & 0xFFFFFFFFull), (uint32_t)(seed >> 32)}, k[8];
+    for (uint32_t j = 0; j < 2; ++j) {
+        uint32_t ctr[4] = {j, epoch, 0u, (scene_id << 16) | 2u};
+        orc_philox(ctr, key, k + 4 * j, 1);
     }
-    qsort(k, n, sizeof(uint64_t), cmp_u64_asc);
-    for (uint32_t i = 0; i < n; ++i) perm[i] = (uint32_t)(k[i] & 0xFFFFFFFFull);
-    free(k);
+    for (uint32_t i = 0; i < n; ++i) {
+        uint32_t x = i;
+        do
+            x = feistel_rounds(x, h, k);
+        while (x >= n);
+        perm[i] = x;
+    }
     return 0;
 }
 

@@ -108,17 +108,12 @@ struct rlc_ctx {
     float* mlp_v = nullptr;
     uint16_t* mlp_frag = nullptr;
     uint32_t mlp_step = 0;
+    double mlp_b1t = 1.0, mlp_b2t = 1.0;  // beta1^t, beta2^t after mlp_step steps
     float* mlp_partial = nullptr;
     uint32_t mlp_partial_blocks = 0;
     float* mlp_part_w = nullptr;
     float* mlp_part_loss = nullptr;
     float* mlp_loss = nullptr;
-    uint32_t* mlp_keys = nullptr;
-    uint32_t* mlp_vals = nullptr;
-    uint32_t* mlp_ktmp = nullptr;
-    uint32_t* mlp_vtmp = nullptr;
-    uint32_t* mlp_hist = nullptr;
-    uint32_t mlp_order_cap = 0;
     uint16_t* mlp_xenc = nullptr;      // encoded inputs of the training call's points
     uint32_t mlp_xenc_cap = 0;
     // mixture with the learned proposal, and per-sample training records
@@ -241,15 +236,9 @@ void free_mlp(rlc_ctx* c) {
     dfree(c->mlp_part_w);
     dfree(c->mlp_part_loss);
     dfree(c->mlp_loss);
-    dfree(c->mlp_keys);
-    dfree(c->mlp_vals);
-    dfree(c->mlp_ktmp);
-    dfree(c->mlp_vtmp);
-    dfree(c->mlp_hist);
     dfree(c->mlp_xenc);
     c->mlp_xenc_cap = 0;
     c->mlp_partial_blocks = 0;
-    c->mlp_order_cap = 0;
     c->mlp_ready = false;
 }
 
@@ -433,6 +422,8 @@ int mlp_reset_optimizer(rlc_ctx* c) {
     RLC_HIP(c, hipMemsetAsync(c->mlp_v, 0, sizeof(float) * kMlpParams, c->stream));
     RLC_HIP(c, launch_mlp_refresh(c->mlp_master, c->mlp_frag, c->stream));
     c->mlp_step = 0;
+    c->mlp_b1t = 1.0;
+    c->mlp_b2t = 1.0;
     c->mlp_ready = true;
     return RLC_OK;
 }
@@ -447,23 +438,6 @@ int mlp_partials(rlc_ctx* c, uint32_t nblocks) {
     RLC_TRY(dalloc(c, &c->mlp_part_w, nblocks));
     RLC_TRY(dalloc(c, &c->mlp_part_loss, nblocks));
     c->mlp_partial_blocks = nblocks;
-    return RLC_OK;
-}
-
-int mlp_order_buffers(rlc_ctx* c, uint32_t n) {
-    if (n <= c->mlp_order_cap) return RLC_OK;
-    dfree(c->mlp_keys);
-    dfree(c->mlp_vals);
-    dfree(c->mlp_ktmp);
-    dfree(c->mlp_vtmp);
-    dfree(c->mlp_hist);
-    c->mlp_order_cap = 0;
-    RLC_TRY(dalloc(c, &c->mlp_keys, n));
-    RLC_TRY(dalloc(c, &c->mlp_vals, n));
-    RLC_TRY(dalloc(c, &c->mlp_ktmp, n));
-    RLC_TRY(dalloc(c, &c->mlp_vtmp, n));
-    RLC_TRY(dalloc(c, &c->mlp_hist, radix_sort_hist_entries(n)));
-    c->mlp_order_cap = n;
     return RLC_OK;
 }
 
@@ -1207,9 +1181,10 @@ int rlc_mlp_grad(rlc_ctx* c, const float* d_pos, const float* d_nrm, uint32_t P,
     }
     const uint16_t* xenc = nullptr;
     if (n) RLC_TRY(mlp_encoded_inputs(c, d_pos, d_nrm, P, &xenc));
-    RLC_HIP(c, launch_mlp_fwd_bwd(c->mlp_frag, c->mlp_master, mlp_encode_params(c), d_pos, d_nrm, P, xenc, nullptr, d_pid,
-                                  d_node, d_w, n, c->mlp_partial, c->mlp_part_w, c->mlp_part_loss, c->d_err,
-                                  c->stream));
+    const MlpOrder identity{};
+    RLC_HIP(c, launch_mlp_fwd_bwd(c->mlp_frag, c->mlp_master, mlp_encode_params(c), d_pos, d_nrm, P, xenc, identity,
+                                  0u, d_pid, d_node, d_w, n, c->mlp_partial, c->mlp_part_w, c->mlp_part_loss,
+                                  c->d_err, c->stream));
     RLC_HIP(c, launch_mlp_reduce(c->mlp_partial, c->mlp_part_w, c->mlp_part_loss, nb, 0u, d_grad, nullptr, nullptr,
                                  nullptr, nullptr, 0.0f, 0.0f, 0.0f, 0.0f, 1.0f, 1.0f, c->mlp_loss, c->stream));
     float loss = 0.0f;
@@ -1230,43 +1205,50 @@ int rlc_mlp_train(rlc_ctx* c, const float* d_pos, const float* d_nrm, uint32_t P
     const uint32_t bmax = std::min(batch, n);
     const uint32_t nb = (bmax + kMlpTuplesPerBlock - 1u) / kMlpTuplesPerBlock;
     RLC_TRY(mlp_partials(c, nb));
-    RLC_TRY(mlp_order_buffers(c, n));
     RLC_HIP(c, launch_fill_u32(c->d_err, 0u, 1, c->stream));
     const MlpEncode enc = mlp_encode_params(c);
     const uint16_t* xenc = nullptr;
     RLC_TRY(mlp_encoded_inputs(c, d_pos, d_nrm, P, &xenc));
-    const uint32_t seed_lo = (uint32_t)(c->cfg.seed & 0xFFFFFFFFull), seed_hi = (uint32_t)(c->cfg.seed >> 32);
+    // a training step's two launches, with HIP events around and between
+    // them while timing is on
+    auto timed = [&](auto&& launch) -> int {
+        hipEvent_t ev[3] = {nullptr, nullptr, nullptr};
+        if (c->timing) {
+            for (auto& x : ev) {
+                x = take_event(c);
+                if (!x) return fail(c, RLC_EHIP, "hipEventCreate failed");
+            }
+            RLC_HIP(c, hipEventRecord(ev[0], c->stream));
+        }
+        RLC_TRY(launch(ev[1]));
+        if (c->timing) {
+            RLC_HIP(c, hipEventRecord(ev[2], c->stream));
+            for (auto& x : ev) c->mlp_pending.push_back(x);
+        }
+        return RLC_OK;
+    };
     for (uint32_t e = 0; e < epochs; ++e) {
-        RLC_HIP(c, launch_mlp_shuffle_keys(n, e, c->cfg.scene_id, seed_lo, seed_hi, c->mlp_keys, c->mlp_vals,
-                                           c->stream));
-        RLC_HIP(c, radix_sort_pairs(c->mlp_keys, c->mlp_vals, c->mlp_ktmp, c->mlp_vtmp, c->mlp_hist, n, 32,
-                                    c->stream));
+        const MlpOrder ord = mlp_epoch_order(n, e, c->cfg.scene_id, c->cfg.seed);
         for (uint32_t b0 = 0; b0 < n; b0 += batch) {
             const uint32_t nbat = std::min(batch, n - b0);
             const uint32_t blocks = (nbat + kMlpTuplesPerBlock - 1u) / kMlpTuplesPerBlock;
-            hipEvent_t ev[3] = {nullptr, nullptr, nullptr};
-            if (c->timing) {
-                for (auto& x : ev) {
-                    x = take_event(c);
-                    if (!x) return fail(c, RLC_EHIP, "hipEventCreate failed");
-                }
-                RLC_HIP(c, hipEventRecord(ev[0], c->stream));
-            }
-            RLC_HIP(c, launch_mlp_fwd_bwd(c->mlp_frag, c->mlp_master, enc, d_pos, d_nrm, P, xenc, c->mlp_vals + b0, d_pid,
-                                          d_node, d_w, nbat, c->mlp_partial, c->mlp_part_w, c->mlp_part_loss,
-                                          c->d_err, c->stream));
-            if (c->timing) RLC_HIP(c, hipEventRecord(ev[1], c->stream));
             c->mlp_step += 1u;
-            const double t = (double)c->mlp_step;
-            const float c1 = (float)(1.0 - std::pow((double)kAdamBeta1, t));
-            const float c2 = (float)(1.0 - std::pow((double)kAdamBeta2, t));
-            RLC_HIP(c, launch_mlp_reduce(c->mlp_partial, c->mlp_part_w, c->mlp_part_loss, blocks, 1u, nullptr,
-                                         c->mlp_master, c->mlp_m, c->mlp_v, c->mlp_frag, lr, kAdamBeta1,
-                                         kAdamBeta2, kAdamEps, c1, c2, c->mlp_loss, c->stream));
-            if (c->timing) {
-                RLC_HIP(c, hipEventRecord(ev[2], c->stream));
-                for (auto& x : ev) c->mlp_pending.push_back(x);
-            }
+            c->mlp_b1t *= (double)kAdamBeta1;
+            c->mlp_b2t *= (double)kAdamBeta2;
+            const float c1 = (float)(1.0 - c->mlp_b1t);
+            const float c2 = (float)(1.0 - c->mlp_b2t);
+            RLC_TRY(timed(
+                [&](hipEvent_t mid) -> int {
+                    RLC_HIP(c, launch_mlp_fwd_bwd(c->mlp_frag, c->mlp_master, enc, d_pos, d_nrm, P, xenc, ord, b0,
+                                                  d_pid, d_node, d_w, nbat, c->mlp_partial, c->mlp_part_w,
+                                                  c->mlp_part_loss, c->d_err, c->stream));
+                    if (c->timing) RLC_HIP(c, hipEventRecord(mid, c->stream));
+                    RLC_HIP(c, launch_mlp_reduce(c->mlp_partial, c->mlp_part_w, c->mlp_part_loss, blocks, 1u,
+                                                 nullptr, c->mlp_master, c->mlp_m, c->mlp_v, c->mlp_frag, lr,
+                                                 kAdamBeta1, kAdamBeta2, kAdamEps, c1, c2, c->mlp_loss,
+                                                 c->stream));
+                    return RLC_OK;
+                }));
         }
     }
     if (!h_loss) return RLC_OK;  // asynchronous: bad tuples are reported by the next synchronising call
@@ -1274,6 +1256,14 @@ int rlc_mlp_train(rlc_ctx* c, const float* d_pos, const float* d_nrm, uint32_t P
     RLC_HIP(c, hipMemcpyAsync(&loss, c->mlp_loss, sizeof(float), hipMemcpyDeviceToHost, c->stream));
     RLC_TRY(read_device_errors(c));
     *h_loss = loss;
+    return RLC_OK;
+}
+
+int rlc_mlp_order(rlc_ctx* c, uint32_t n, uint32_t epoch, uint32_t* d_order) {
+    if (!c) return RLC_EINVAL;
+    if (n == 0) return RLC_OK;
+    if (!d_order) return fail(c, RLC_EINVAL, "null array");
+    RLC_HIP(c, launch_mlp_order(mlp_epoch_order(n, epoch, c->cfg.scene_id, c->cfg.seed), d_order, c->stream));
     return RLC_OK;
 }
 

@@ -373,38 +373,59 @@ __device__ __forceinline__ uint32_t hidden_layer(const bf16x8* __restrict__ frag
     return mask;
 }
 
-__global__ void __launch_bounds__(kTrainThreads) k_mlp_fwd_bwd(const bf16x8* __restrict__ frag,
-                                                               const float* __restrict__ master, MlpEncode enc,
-                                                               const float* __restrict__ pos,
-                                                               const float* __restrict__ nrm, uint32_t P,
-                                                               const bf16x8* __restrict__ xenc,
-                                                               const uint32_t* __restrict__ order,
-                                                               const uint32_t* __restrict__ pid,
-                                                               const uint32_t* __restrict__ node,
-                                                               const float* __restrict__ w, uint32_t n,
-                                                               float* __restrict__ partial,
-                                                               float* __restrict__ part_w,
-                                                               float* __restrict__ part_loss,
-                                                               uint32_t* __restrict__ err) {
+// The work of training block blk (its kTrainTuples tuples of the n given):
+// forward, backward, and its row of partial sums.
+__device__ __forceinline__ void train_block(uint32_t blk, const bf16x8* frag, const float* master,
+                                            const MlpEncode& enc, const float* __restrict__ pos,
+                                            const float* __restrict__ nrm, uint32_t P,
+                                            const bf16x8* __restrict__ xenc, const MlpOrder& ord, uint32_t base,
+                                            const uint32_t* __restrict__ pid, const uint32_t* __restrict__ node,
+                                            const float* __restrict__ w, uint32_t n, float* partial, float* part_w,
+                                            float* part_loss, uint32_t* err) {
     __shared__ __attribute__((aligned(16))) uint16_t sG[kH * kLdsT];
     __shared__ __attribute__((aligned(16))) uint16_t sA[kIn * kLdsT];
     __shared__ float s_w[kTrainTuples], s_l[kTrainTuples];
+    // the block's copy of every weight operand (forward and transposed) and
+    // of the biases: each wave reads its operands from LDS instead of
+    // fetching the same 70 KB from L2
+    __shared__ bf16x8 s_frag[kMlpFragVecs];
+    __shared__ float s_bias[4u * kH];
     const uint32_t lane = threadIdx.x & 63u, wave = threadIdx.x >> 6, i16 = lane & 15u, g = lane >> 4;
     const uint32_t col = wave * 16u + i16;
-    const uint32_t tb = blockIdx.x * kTrainTuples + col;
+    const uint32_t tb = blk * kTrainTuples + col;
+    // the staging loads are issued first; the tuple's place in the epoch
+    // order is computed and its record fetched while they are in flight
+    constexpr uint32_t kPer = (kMlpFragVecs + kTrainThreads - 1u) / kTrainThreads;
+    bf16x8 v[kPer];
+#pragma unroll
+    for (uint32_t k = 0; k < kPer; ++k) {
+        const uint32_t j = threadIdx.x + k * kTrainThreads;
+        if (j < kMlpFragVecs) v[k] = frag[j];
+    }
+    float bv = 0.0f;
+    if (threadIdx.x < 4u * kH) {
+        const uint32_t L = threadIdx.x / kH;
+        bv = master[(L == 0u ? ob1 : (L == 1u ? ob2 : (L == 2u ? ob3 : ob4))) + threadIdx.x % kH];
+    }
     uint32_t pt = 0, nd = 0;
     float wt = 0.0f;
     if (tb < n) {
-        const uint32_t t = order ? order[tb] : tb;
+        const uint32_t t = ord.n ? mlp_order_at(ord, base + tb) : tb;
         pt = pid[t];
         nd = node[t];
         wt = w[t];
-        if (pt >= P || nd >= 64u || !(wt >= 0.0f && wt <= 3.402823466e38f)) {
-            if (g == 0u) atomicOr(err, RLC_DERR_INPUT);
-            pt = 0;
-            nd = 0;
-            wt = 0.0f;
-        }
+    }
+#pragma unroll
+    for (uint32_t k = 0; k < kPer; ++k) {
+        const uint32_t j = threadIdx.x + k * kTrainThreads;
+        if (j < kMlpFragVecs) s_frag[j] = v[k];
+    }
+    if (threadIdx.x < 4u * kH) s_bias[threadIdx.x] = bv;
+    if (tb < n && (pt >= P || nd >= 64u || !(wt >= 0.0f && wt <= 3.402823466e38f))) {
+        if (g == 0u) atomicOr(err, RLC_DERR_INPUT);
+        pt = 0;
+        nd = 0;
+        wt = 0.0f;
     }
     // the point's encoded inputs (computed once per call, or here)
     auto load_x = [&](bf16x8 (&x)[5]) {
@@ -420,14 +441,14 @@ __global__ void __launch_bounds__(kTrainThreads) k_mlp_fwd_bwd(const bf16x8* __r
     bf16x8 a1[2], a2[2], a3[2];
     uint32_t m1, m2, m3;
     f32x4 z[4];
-    {
-        bf16x8 x[5];
-        load_x(x);
-        m1 = hidden_layer<5>(frag + fF1, x, master + ob1, lane, a1);
-    }
-    m2 = hidden_layer<2>(frag + fF2, a1, master + ob2, lane, a2);
-    m3 = hidden_layer<2>(frag + fF3, a2, master + ob3, lane, a3);
-    dense<2>(frag + fF4, a3, master + ob4, lane, z);
+    // the encoded inputs stay in registers for layer 1's weight gradient
+    bf16x8 x[5];
+    load_x(x);
+    __syncthreads();  // the staged operands
+    m1 = hidden_layer<5>(s_frag + fF1, x, s_bias, lane, a1);
+    m2 = hidden_layer<2>(s_frag + fF2, a1, s_bias + kH, lane, a2);
+    m3 = hidden_layer<2>(s_frag + fF3, a2, s_bias + 2u * kH, lane, a3);
+    dense<2>(s_frag + fF4, a3, s_bias + 3u * kH, lane, z);
     // the target's logit, from the lane that holds it (before the softmax
     // replaces the logits by probabilities)
     const uint32_t tn = nd >> 4, gn = (nd & 15u) >> 2, rn = nd & 3u;
@@ -479,7 +500,7 @@ __global__ void __launch_bounds__(kTrainThreads) k_mlp_fwd_bwd(const bf16x8* __r
             gout[kb] = pack8(val);
         }
     };
-    float* prow = partial + (size_t)blockIdx.x * kNP;
+    float* prow = partial + (size_t)blk * kNP;
     // layers 4, 3, 2, each in turn: G_L and the previous activations staged
     // in LDS, G_{L-1} propagated from G_L, then the layer's weight gradient
     // (16 tiles over the waves) and bias gradient; a layer's operands are not
@@ -498,87 +519,96 @@ __global__ void __launch_bounds__(kTrainThreads) k_mlp_fwd_bwd(const bf16x8* __r
         bias_grad(sG, prow + ob_);
         __syncthreads();
     };
-    layer_grad(a3, frag + fT4, m3, oW4, ob4);
-    layer_grad(a2, frag + fT3, m2, oW3, ob3);
-    layer_grad(a1, frag + fT2, m1, oW2, ob2);
+    layer_grad(a3, s_frag + fT4, m3, oW4, ob4);
+    layer_grad(a2, s_frag + fT3, m2, oW3, ob3);
+    layer_grad(a1, s_frag + fT2, m1, oW2, ob2);
     // layer 1: G_1 against the encoded inputs (144 rows): 36 tiles
     stage_hidden(sG, gB, g, col);
-    {
-        bf16x8 x[5];
-        load_x(x);
 #pragma unroll
-        for (uint32_t kb = 0; kb < 5u; ++kb)
+    for (uint32_t kb = 0; kb < 5u; ++kb)
 #pragma unroll
-            for (uint32_t e = 0; e < 8u; ++e) {
-                const uint32_t j = 32u * kb + 8u * g + e;
-                if (j < kIn) sA[j * kLdsT + col] = elem(x[kb], (int)e);
-            }
-    }
+        for (uint32_t e = 0; e < 8u; ++e) {
+            const uint32_t j = 32u * kb + 8u * g + e;
+            if (j < kIn) sA[j * kLdsT + col] = elem(x[kb], (int)e);
+        }
     __syncthreads();
     for (uint32_t tile = wave; tile < 36u; tile += kTrainWaves)  // 4 output x 9 input tiles
         wgrad_tile(sG, sA, tile / 9u, tile % 9u, kIn, lane, prow + oW1);
     bias_grad(sG, prow + ob1);
-    if (threadIdx.x == 0) {
+    // the block's sums of weights and of weighted losses, by wave 0 in a
+    // fixed order: each lane adds its kTrainTuples / 64 entries, then a
+    // butterfly across the lanes
+    if (wave == 0u) {
         float sw = 0.0f, sl = 0.0f;
-        for (uint32_t c = 0; c < kTrainTuples; ++c) {
+#pragma unroll
+        for (uint32_t c = lane; c < kTrainTuples; c += 64u) {
             sw += s_w[c];
             sl += s_l[c];
         }
-        part_w[blockIdx.x] = sw;
-        part_loss[blockIdx.x] = sl;
+#pragma unroll
+        for (int off = 32; off >= 1; off >>= 1) {
+            sw += __shfl_xor(sw, off, 64);
+            sl += __shfl_xor(sl, off, 64);
+        }
+        if (lane == 0u) {
+            part_w[blk] = sw;
+            part_loss[blk] = sl;
+        }
     }
 }
 
-// Sum of the blocks' partial rows, divided by the batch's sum of weights;
-// then either stored (mode 0) or applied by Adam (mode 1, with the bias
-// corrections c1 = 1 - beta1^t, c2 = 1 - beta2^t) with the BF16 operands
-// refreshed from the new FP32 weights.  A block covers 32 parameters with 8
-// row groups: group r sums rows r, r + 8, ... in order, and the 8 group sums
-// are added in group order, so the result does not depend on scheduling.
+__global__ void __launch_bounds__(kTrainThreads) k_mlp_fwd_bwd(const bf16x8* __restrict__ frag,
+                                                               const float* __restrict__ master, MlpEncode enc,
+                                                               const float* __restrict__ pos,
+                                                               const float* __restrict__ nrm, uint32_t P,
+                                                               const bf16x8* __restrict__ xenc, MlpOrder ord,
+                                                               uint32_t base, const uint32_t* __restrict__ pid,
+                                                               const uint32_t* __restrict__ node,
+                                                               const float* __restrict__ w, uint32_t n,
+                                                               float* __restrict__ partial,
+                                                               float* __restrict__ part_w,
+                                                               float* __restrict__ part_loss,
+                                                               uint32_t* __restrict__ err) {
+    train_block(blockIdx.x, frag, master, enc, pos, nrm, P, xenc, ord, base, pid, node, w, n, partial, part_w,
+                part_loss, err);
+}
+
 constexpr uint32_t kRedCols = 32, kRedGroups = kBlock / kRedCols;
 
-__global__ void __launch_bounds__(kBlock) k_mlp_reduce(const float* __restrict__ partial,
-                                                       const float* __restrict__ part_w,
-                                                       const float* __restrict__ part_loss, uint32_t nblocks,
-                                                       uint32_t mode, float* __restrict__ out,
-                                                       float* __restrict__ master, float* __restrict__ m,
-                                                       float* __restrict__ v, uint16_t* __restrict__ frag, float lr,
-                                                       float beta1, float beta2, float eps, float c1, float c2,
-                                                       float* __restrict__ loss) {
-    __shared__ float s_part[kRedGroups][kRedCols];
-    __shared__ float s_stage[kBlock];
-    __shared__ float s_inv;
-    const uint32_t col = threadIdx.x % kRedCols, grp = threadIdx.x / kRedCols;
-    const uint32_t p = blockIdx.x * kRedCols + col;
+// Column p of the blocks' partial rows, the rows of group grp (grp, grp +
+// kRedGroups, ...) added in that order; the loads of a run of 32 (then 8)
+// rows are issued before their additions.
+__device__ __forceinline__ float column_sum(const float* partial, uint32_t p, uint32_t grp, uint32_t nblocks) {
     float acc = 0.0f;
-    if (p < kNP) {
-        // rows grp, grp + 8, ... added in that order; the loads of a run of
-        // 32 (then 8) rows are issued before their additions
-        uint32_t b = grp;
-        for (; b + 31u * kRedGroups < nblocks; b += 32u * kRedGroups) {
-            float v[32];
+    uint32_t b = grp;
+    for (; b + 31u * kRedGroups < nblocks; b += 32u * kRedGroups) {
+        float v[32];
 #pragma unroll
-            for (uint32_t j = 0; j < 32u; ++j) v[j] = partial[(size_t)(b + j * kRedGroups) * kNP + p];
+        for (uint32_t j = 0; j < 32u; ++j) v[j] = partial[(size_t)(b + j * kRedGroups) * kNP + p];
 #pragma unroll
-            for (uint32_t j = 0; j < 32u; ++j) acc += v[j];
-        }
-        for (; b + 7u * kRedGroups < nblocks; b += 8u * kRedGroups) {
-            float v[8];
-#pragma unroll
-            for (uint32_t j = 0; j < 8u; ++j) v[j] = partial[(size_t)(b + j * kRedGroups) * kNP + p];
-#pragma unroll
-            for (uint32_t j = 0; j < 8u; ++j) acc += v[j];
-        }
-        for (; b < nblocks; b += kRedGroups) acc += partial[(size_t)b * kNP + p];
+        for (uint32_t j = 0; j < 32u; ++j) acc += v[j];
     }
-    s_part[grp][col] = acc;
-    // the blocks' weight sums (and, in block 0, loss sums) added in block
-    // order by one thread, after every thread has staged 256 of them in LDS
-    float sw = 0.0f, sl = 0.0f;
-    const bool want_loss = blockIdx.x == 0 && loss;
-    for (uint32_t base = 0; base < nblocks; base += kBlock) {
+    for (; b + 7u * kRedGroups < nblocks; b += 8u * kRedGroups) {
+        float v[8];
+#pragma unroll
+        for (uint32_t j = 0; j < 8u; ++j) v[j] = partial[(size_t)(b + j * kRedGroups) * kNP + p];
+#pragma unroll
+        for (uint32_t j = 0; j < 8u; ++j) acc += v[j];
+    }
+    for (; b < nblocks; b += kRedGroups) acc += partial[(size_t)b * kNP + p];
+    return acc;
+}
+
+// The blocks' weight sums (and, with want_loss, loss sums) added in block
+// order by thread 0, after the block's threads have staged them in LDS.
+// Every thread must call it; thread 0 gets the sums.
+__device__ __forceinline__ void block_sums(const float* part_w, const float* part_loss, uint32_t nblocks,
+                                           bool want_loss, float* s_stage, float& sw, float& sl) {
+    sw = 0.0f;
+    sl = 0.0f;
+    for (uint32_t base = 0; base < nblocks; base += blockDim.x) {
         const uint32_t i = base + threadIdx.x;
-        const uint32_t cnt = nblocks - base < kBlock ? nblocks - base : kBlock;
+        const uint32_t cnt = nblocks - base < blockDim.x ? nblocks - base : blockDim.x;
         s_stage[threadIdx.x] = i < nblocks ? part_w[i] : 0.0f;
         __syncthreads();
         if (threadIdx.x == 0)
@@ -592,6 +622,51 @@ __global__ void __launch_bounds__(kBlock) k_mlp_reduce(const float* __restrict__
             __syncthreads();
         }
     }
+}
+
+// Adam on parameter p (weight w0, moments m0, v0) with gradient gr (bias
+// corrections c1 = 1 - beta1^t, c2 = 1 - beta2^t), then its BF16 operands
+// refreshed.
+__device__ __forceinline__ void adam_apply(uint32_t p, float gr, float w0, float m0, float v0, float* master,
+                                           float* m, float* v, uint16_t* frag, float lr, float beta1, float beta2,
+                                           float eps, float c1, float c2) {
+    const float mm = beta1 * m0 + (1.0f - beta1) * gr;
+    const float vv = beta2 * v0 + (1.0f - beta2) * (gr * gr);
+    m[p] = mm;
+    v[p] = vv;
+    const float mh = mm / c1, vh = vv / c2;
+    const float np = w0 - lr * mh / (sqrtf(vh) + eps);
+    master[p] = np;
+    write_frag(frag, p, np);
+}
+
+__device__ __forceinline__ void adam_update(uint32_t p, float gr, float* master, float* m, float* v, uint16_t* frag,
+                                            float lr, float beta1, float beta2, float eps, float c1, float c2) {
+    adam_apply(p, gr, master[p], m[p], v[p], master, m, v, frag, lr, beta1, beta2, eps, c1, c2);
+}
+
+// Sum of the blocks' partial rows, divided by the batch's sum of weights;
+// then either stored (mode 0) or applied by Adam (mode 1).  A block covers
+// 32 parameters with 8 row groups: group r sums rows r, r + 8, ... in order,
+// and the 8 group sums are added in group order, so the result does not
+// depend on scheduling.
+__global__ void __launch_bounds__(kBlock) k_mlp_reduce(const float* __restrict__ partial,
+                                                       const float* __restrict__ part_w,
+                                                       const float* __restrict__ part_loss, uint32_t nblocks,
+                                                       uint32_t mode, float* __restrict__ out,
+                                                       float* __restrict__ master, float* __restrict__ m,
+                                                       float* __restrict__ v, uint16_t* __restrict__ frag, float lr,
+                                                       float beta1, float beta2, float eps, float c1, float c2,
+                                                       float* __restrict__ loss) {
+    __shared__ float s_part[kRedGroups][kRedCols];
+    __shared__ float s_stage[kBlock];
+    __shared__ float s_inv;
+    const uint32_t col = threadIdx.x % kRedCols, grp = threadIdx.x / kRedCols;
+    const uint32_t p = blockIdx.x * kRedCols + col;
+    s_part[grp][col] = p < kNP ? column_sum(partial, p, grp, nblocks) : 0.0f;
+    const bool want_loss = blockIdx.x == 0 && loss;
+    float sw, sl;
+    block_sums(part_w, part_loss, nblocks, want_loss, s_stage, sw, sl);
     if (threadIdx.x == 0) {
         const float inv = sw > 0.0f ? 1.0f / sw : 0.0f;
         s_inv = inv;
@@ -606,14 +681,7 @@ __global__ void __launch_bounds__(kBlock) k_mlp_reduce(const float* __restrict__
         out[p] = gr;
         return;
     }
-    const float mm = beta1 * m[p] + (1.0f - beta1) * gr;
-    const float vv = beta2 * v[p] + (1.0f - beta2) * (gr * gr);
-    m[p] = mm;
-    v[p] = vv;
-    const float mh = mm / c1, vh = vv / c2;
-    const float np = master[p] - lr * mh / (sqrtf(vh) + eps);
-    master[p] = np;
-    write_frag(frag, p, np);
+    adam_update(p, gr, master, m, v, frag, lr, beta1, beta2, eps, c1, c2);
 }
 
 __global__ void __launch_bounds__(kBlock) k_mlp_refresh(const float* __restrict__ master,
@@ -641,16 +709,9 @@ __global__ void __launch_bounds__(kBlock) k_mlp_encode(MlpEncode enc, const floa
 
 // Training order of an epoch: key of tuple i = first word of Philox at
 // counter (i, epoch, 0, scene << 16 | 2); sorted (stably) by key.
-__global__ void __launch_bounds__(kBlock) k_mlp_shuffle_keys(uint32_t n, uint32_t epoch, uint32_t scene_id,
-                                                             uint32_t seed_lo, uint32_t seed_hi,
-                                                             uint32_t* __restrict__ keys,
-                                                             uint32_t* __restrict__ vals) {
+__global__ void __launch_bounds__(kBlock) k_mlp_order(MlpOrder ord, uint32_t* __restrict__ out) {
     const uint32_t i = blockIdx.x * kBlock + threadIdx.x;
-    if (i >= n) return;
-    uint32_t x0 = i, x1 = epoch, x2 = 0u, x3 = (scene_id << 16) | 2u;
-    philox4x32_10(x0, x1, x2, x3, seed_lo, seed_hi);
-    keys[i] = x0;
-    vals[i] = i;
+    if (i < ord.n) out[i] = mlp_order_at(ord, i);
 }
 
 // Initial weights: uniform in +-sqrt(6 / fan_in) (He et al. 2015, uniform
@@ -699,13 +760,13 @@ hipError_t launch_mlp_encode(MlpEncode enc, const float* pos, const float* nrm, 
 }
 
 hipError_t launch_mlp_fwd_bwd(const uint16_t* frag, const float* master, MlpEncode enc, const float* pos,
-                              const float* nrm, uint32_t P, const uint16_t* xenc, const uint32_t* order,
+                              const float* nrm, uint32_t P, const uint16_t* xenc, const MlpOrder& ord, uint32_t base,
                               const uint32_t* pid, const uint32_t* node, const float* w, uint32_t n, float* partial,
                               float* part_w, float* part_loss, uint32_t* err, hipStream_t s) {
     if (n == 0) return hipSuccess;
     const uint32_t grid = (n + kMlpTuplesPerBlock - 1u) / kMlpTuplesPerBlock;
     hipLaunchKernelGGL(k_mlp_fwd_bwd, dim3(grid), dim3(kTrainThreads), 0, s, reinterpret_cast<const bf16x8*>(frag),
-                       master, enc, pos, nrm, P, reinterpret_cast<const bf16x8*>(xenc), order, pid, node, w, n,
+                       master, enc, pos, nrm, P, reinterpret_cast<const bf16x8*>(xenc), ord, base, pid, node, w, n,
                        partial, part_w, part_loss, err);
     return hipGetLastError();
 }
@@ -720,11 +781,9 @@ hipError_t launch_mlp_reduce(const float* partial, const float* part_w, const fl
     return hipGetLastError();
 }
 
-hipError_t launch_mlp_shuffle_keys(uint32_t n, uint32_t epoch, uint32_t scene_id, uint32_t seed_lo,
-                                   uint32_t seed_hi, uint32_t* keys, uint32_t* vals, hipStream_t s) {
-    if (n == 0) return hipSuccess;
-    hipLaunchKernelGGL(k_mlp_shuffle_keys, dim3(blocks_for(n)), dim3(kBlock), 0, s, n, epoch, scene_id, seed_lo,
-                       seed_hi, keys, vals);
+hipError_t launch_mlp_order(const MlpOrder& ord, uint32_t* out, hipStream_t s) {
+    if (ord.n == 0) return hipSuccess;
+    hipLaunchKernelGGL(k_mlp_order, dim3(blocks_for(ord.n)), dim3(kBlock), 0, s, ord, out);
     return hipGetLastError();
 }
 

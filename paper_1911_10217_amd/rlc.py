@@ -37,7 +37,8 @@ EXPORTS = (
     "rlc_batch_create", "rlc_batch_destroy", "rlc_batch_set_schedule", "rlc_batch_get_schedule",
     "rlc_batch_autotune", "rlc_batch_frame",
     "rlc_mlp_fixed_cut", "rlc_mlp_init", "rlc_mlp_set_params", "rlc_mlp_get_params", "rlc_mlp_forward",
-    "rlc_mlp_grad", "rlc_mlp_train", "rlc_set_mixture", "rlc_set_sample_log", "rlc_get_mlp_timing",
+    "rlc_mlp_grad", "rlc_mlp_train", "rlc_mlp_order", "rlc_set_mixture", "rlc_set_sample_log",
+    "rlc_get_mlp_timing",
     "rlc_set_footprints",
 )
 RLC_MLP_PARAMS = 21760
@@ -165,6 +166,7 @@ def _declare(L):
     L.rlc_set_footprints.argtypes = [_vp, _vp, _u32]
     L.rlc_set_sample_log.argtypes = [_vp, _vp, _vp, _vp, ctypes.c_uint64]
     L.rlc_get_mlp_timing.argtypes = [_vp, _vp, _vp, _vp]
+    L.rlc_mlp_order.argtypes = [_vp, _u32, _u32, _vp]
     for name in EXPORTS:
         if name != "rlc_last_error":
             getattr(L, name).restype = i
@@ -471,6 +473,14 @@ class Context:
         return float(f[0]), float(u[0]), int(n[0])
 
     # -- learned proposal ------------------------------------------------------------
+    def rlc_mlp_order(self, n: int, epoch: int, out=None):
+        """Tuple order of a training epoch (device uint32 tensor of n)."""
+        import torch
+        if out is None:
+            out = torch.empty(n, dtype=torch.int32, device="cuda")
+        self._check(lib().rlc_mlp_order(self._h, n, epoch, _ptr(out)), "rlc_mlp_order")
+        return out
+
     def rlc_mlp_fixed_cut(self):
         node = np.zeros(RLC_MLP_NODES, np.uint32)
         end = np.zeros(RLC_MLP_NODES, np.uint32)

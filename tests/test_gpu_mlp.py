@@ -172,6 +172,19 @@ def test_training_matches_oracle(torch, orc):
     assert np.mean(np.abs(d_gpu - d_orc) > 3e-3) < 0.02
 
 
+@pytest.mark.parametrize("n", [1, 5, 16, 17, 700, 65537, 524288])
+def test_epoch_order_matches_oracle(torch, orc, n):
+    """The tuple order of training epochs, bit for bit: sizes that need no
+    cycle walk (powers of four), sizes just past one, a ragged size, the
+    learned workload's 524,288 tuples."""
+    s = scenes.make_tiny(n_lights=64, n_points=16, scene_id=5)
+    ctx, _, _ = _ctx(torch, s)
+    for e in (0, 3):
+        got = ctx.rlc_mlp_order(n, e).cpu().numpy().astype(np.uint32)
+        want = orc.mlp_shuffle(n, e, s.params["scene_id"], s.params["seed"])
+        assert np.array_equal(got, want), e
+
+
 def test_training_is_deterministic_and_can_be_asynchronous(torch):
     s = scenes.make_tiny(n_lights=300, n_points=100)
     ctx, pos, nrm = _ctx(torch, s)

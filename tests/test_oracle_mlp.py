@@ -9,6 +9,7 @@ PyTorch's own float32 -> bfloat16 conversion."""
 import math
 
 import numpy as np
+from scipy import stats
 import pytest
 import torch
 
@@ -295,15 +296,48 @@ def test_adam_first_step_is_lr_times_sign(orc):
     assert np.allclose(p, -0.1 * g / (np.abs(g) + 1e-8), rtol=1e-14)
 
 
-def test_shuffle_is_a_permutation_sorted_by_philox_keys(orc):
-    n = 1000
+@pytest.mark.parametrize("n", [1, 2, 3, 4, 5, 15, 16, 17, 63, 64, 65, 1000, 4096, 4097, 65537])
+def test_shuffle_is_a_permutation_for_every_size(orc, n):
+    """Sizes at, just below and just above powers of four (where the
+    Feistel domain grows and the walk starts or stops being needed)."""
+    perm = orc.mlp_shuffle(n, 3, 7, scenes.SEED_BASE + 5)
+    assert np.array_equal(np.sort(perm), np.arange(n))
+
+
+def test_shuffle_changes_with_epoch_scene_and_seed(orc):
     seed = scenes.SEED_BASE + 5
-    perm = orc.mlp_shuffle(n, 3, 7, seed)
-    assert sorted(perm.tolist()) == list(range(n))
-    ctr = np.stack([np.arange(n), np.full(n, 3), np.zeros(n), np.full(n, (7 << 16) | 2)], 1)
-    keys = orc.philox(ctr, [seed & 0xFFFFFFFF, seed >> 32])[:, 0]
-    assert np.array_equal(perm, np.lexsort((np.arange(n), keys)))
-    assert not np.array_equal(perm, orc.mlp_shuffle(n, 4, 7, seed))
+    base = orc.mlp_shuffle(1000, 3, 7, seed)
+    for other in (orc.mlp_shuffle(1000, 4, 7, seed), orc.mlp_shuffle(1000, 3, 8, seed),
+                  orc.mlp_shuffle(1000, 3, 7, seed + 1)):
+        assert np.mean(other != base) > 0.9
+    assert np.array_equal(base, orc.mlp_shuffle(1000, 3, 7, seed))
+
+
+def test_shuffle_positions_are_uniform(orc):
+    """Over epochs, the first two positions of a 10-tuple order (its domain
+    has 16 values, so most maps walk) take every ordered pair of distinct
+    tuples equally often, as a uniformly random order would."""
+    n, epochs = 10, 9000
+    first = np.empty((epochs, 2), np.int64)
+    for e in range(epochs):
+        first[e] = orc.mlp_shuffle(n, e, 1, scenes.SEED_BASE + 6)[:2]
+    assert np.all(first[:, 0] != first[:, 1])
+    cnt = np.bincount(first[:, 0] * n + first[:, 1], minlength=n * n).reshape(n, n)
+    off = cnt[~np.eye(n, dtype=bool)]
+    assert stats.chisquare(off).pvalue > 1e-4
+    assert stats.chisquare(np.bincount(first[:, 0], minlength=n)).pvalue > 1e-4
+
+
+def test_shuffle_moves_low_and_high_bits(orc):
+    """With n = 4^5 no value walks; a round that left either half of the
+    word in place would keep it: about 1/32 of the tuples keep their low
+    (or high) 5 bits, and about one keeps its place."""
+    n = 1024
+    perm = orc.mlp_shuffle(n, 0, 2, scenes.SEED_BASE + 7).astype(np.int64)
+    i = np.arange(n)
+    assert np.mean((perm & 31) == (i & 31)) < 0.1
+    assert np.mean((perm >> 5) == (i >> 5)) < 0.1
+    assert np.sum(perm == i) < 8
 
 
 def test_training_single_full_batch_is_one_adam_step(orc):
