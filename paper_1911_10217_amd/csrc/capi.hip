@@ -10,7 +10,7 @@
 #include <new>
 #include <vector>
 
-#include "rlc_internal.h"
+#include "mlp_internal.h"
 
 using namespace rlc;
 

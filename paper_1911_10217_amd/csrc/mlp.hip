@@ -20,7 +20,7 @@
 // lane contributes to the next layer's B operand if the next layer's
 // weights are stored with their input units in the matching order
 // (hidden_pos below), so activations never leave registers.
-#include "rlc_internal.h"
+#include "mlp_internal.h"
 
 namespace rlc {
 
