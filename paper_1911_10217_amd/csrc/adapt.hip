@@ -148,16 +148,29 @@ __device__ __forceinline__ bool adapt_front(const AdaptParams& ap, const CellIn<
     if (!__any(any)) return false;  // no samples this pass: the cell is left as it is
 
     const bool fresh = in.ready == 0u || ap.temporal == 0u;
+    // the children and split point of each cluster's node, for the first
+    // step's split (they come with the parent in one load)
+    uint32_t pre_l[PER], pre_r[PER], pre_sp[PER];
     // the cut and Q (a fresh cell starts from the initial cut, Q = 0)
 #pragma unroll
     for (int j = 0; j < PER; ++j) {
         uint32_t s = lane + kWave * j;
+        pre_l[j] = pre_r[j] = pre_sp[j] = 0u;
         if (s < Meff) {
             const uint32_t nd = fresh ? in.tnode[j] : in.node[j];
             const uint32_t en = fresh ? in.tend[j] : in.end[j];
             float q = fresh ? 0.0f : in.q[j];
-            // the one tree lookup the step needs for every cluster: its parent
-            L.par[s] = ap.tree.parent[nd];
+            // the tree lookup the step needs for every cluster: its parent,
+            // and for an internal node its children and split point
+            if (nd + 1u < ap.tree.N) {
+                const uint4 nr = ap.tree.inode[nd];
+                pre_l[j] = nr.x;
+                pre_r[j] = nr.y;
+                pre_sp[j] = nr.z;
+                L.par[s] = nr.w;
+            } else {
+                L.par[s] = ap.tree.parent[nd];
+            }
             L.end[s] = en;
             if (ap.temporal && in.cnt[j]) {
                 // Eq. 1 applied to the n samples of the pass at once
@@ -264,12 +277,15 @@ __device__ __forceinline__ bool adapt_front(const AdaptParams& ap, const CellIn<
                         L.nQ[dst] = qpmin;
                         if (more) L.npar[dst] = ap.tree.parent[L.par[s]];
                     } else if (s == smax) {
+                        // the first step splits a node of the loaded cut,
+                        // whose children and split point came with it
                         float h = 0.5f * q;
-                        const uint32_t lc = ap.tree.left[nd];
+                        const bool pre = step == 0u;
+                        const uint32_t lc = pre ? pre_l[j] : ap.tree.left[nd];
                         L.nnode[dst] = lc;
-                        L.nend[dst] = ap.tree.last[lc] + 1u;
+                        L.nend[dst] = pre ? pre_sp[j] : ap.tree.last[lc] + 1u;
                         L.nQ[dst] = h;
-                        L.nnode[dst + 1u] = ap.tree.right[nd];
+                        L.nnode[dst + 1u] = pre ? pre_r[j] : ap.tree.right[nd];
                         L.nend[dst + 1u] = L.end[s];
                         L.nQ[dst + 1u] = h;
                         if (more) L.npar[dst] = L.npar[dst + 1u] = nd;

@@ -64,6 +64,7 @@ struct rlc_ctx {
     uint32_t* parent = nullptr;
     uint32_t* first = nullptr;
     uint32_t* last = nullptr;
+    uint32_t* inode = nullptr;  // 4 words per internal node (left, right, split, parent)
     uint32_t* tmpl_node = nullptr;
     uint32_t* tmpl_end = nullptr;
     float* tmpl_Qt = nullptr;
@@ -212,6 +213,7 @@ void free_tree(rlc_ctx* c) {
     dfree(c->parent);
     dfree(c->first);
     dfree(c->last);
+    dfree(c->inode);
     dfree(c->tmpl_node);
     dfree(c->tmpl_end);
     dfree(c->tmpl_Qt);
@@ -260,6 +262,7 @@ DevTree dev_tree(const rlc_ctx* c) {
     t.parent = c->parent;
     t.first = c->first;
     t.last = c->last;
+    t.inode = reinterpret_cast<const uint4*>(c->inode);
     t.N = c->N;
     return t;
 }
@@ -624,6 +627,7 @@ int rlc_build_light_tree(rlc_ctx* c, const float* d_tri, const float* d_emit, ui
     RLC_TRY(dalloc(c, &c->parent, nn));
     RLC_TRY(dalloc(c, &c->first, nn));
     RLC_TRY(dalloc(c, &c->last, nn));
+    RLC_TRY(dalloc(c, &c->inode, 4 * (size_t)(N > 1 ? N - 1 : 1)));
     RLC_TRY(dalloc(c, &c->tmpl_node, M));
     RLC_TRY(dalloc(c, &c->tmpl_end, M));
     RLC_TRY(dalloc(c, &c->tmpl_Qt, M));
@@ -659,7 +663,8 @@ int rlc_build_light_tree(rlc_ctx* c, const float* d_tri, const float* d_emit, ui
         step(launch_morton(sums, bbox, N, c->morton, c->perm, c->stream));
         step(radix_sort_pairs(c->morton, c->perm, ktmp, vtmp, hist, N, 30, c->stream));
         step(launch_gather_records(d_tri, d_emit, c->perm, N, c->rec, c->stream));
-        step(launch_radix_tree(c->morton, c->perm, N, c->left, c->right, c->parent, c->first, c->last, c->stream));
+        step(launch_radix_tree(c->morton, c->perm, N, c->left, c->right, c->parent, c->first, c->last, c->inode,
+                               c->stream));
         c->N = N;
         c->Meff = std::min(M, N);
         step(launch_initial_cut(dev_tree(c), M, c->tmpl_node, c->tmpl_end, c->tmpl_Qt, c->tmpl_C, c->stream));

@@ -33,6 +33,10 @@ struct DevTree {
     const uint32_t* parent;
     const uint32_t* first;
     const uint32_t* last;
+    // per internal node i: (left, right, split, parent) with split the first
+    // light of the right child, so one load gives all a split-collapse step
+    // needs to know about a cut node
+    const uint4* inode;
     uint32_t N;
 };
 
@@ -664,7 +668,7 @@ hipError_t launch_gather_records(const float* tri, const float* emit, const uint
 hipError_t launch_scatter_emission(const float* emit, const uint32_t* perm, uint32_t N, float4* rec,
                                    hipStream_t s);
 hipError_t launch_radix_tree(const uint32_t* morton, const uint32_t* perm, uint32_t N, uint32_t* left,
-                             uint32_t* right, uint32_t* parent, uint32_t* first, uint32_t* last,
+                             uint32_t* right, uint32_t* parent, uint32_t* first, uint32_t* last, uint32_t* inode,
                              hipStream_t s);
 hipError_t launch_initial_cut(DevTree tree, uint32_t M, uint32_t* node, uint32_t* end, float* Qt, float* C,
                               hipStream_t s);

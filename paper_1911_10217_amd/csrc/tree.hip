@@ -292,14 +292,17 @@ __global__ void __launch_bounds__(kBlock) k_radix_tree(const uint32_t* __restric
                                                        const uint32_t* __restrict__ perm, uint32_t N,
                                                        uint32_t* __restrict__ left, uint32_t* __restrict__ right,
                                                        uint32_t* __restrict__ parent, uint32_t* __restrict__ first,
-                                                       uint32_t* __restrict__ last) {
+                                                       uint32_t* __restrict__ last, uint32_t* __restrict__ inode) {
     size_t gi = (size_t)blockIdx.x * kBlock + threadIdx.x;
     const int n = (int)N;
     if (gi < N) {  // leaves
         first[N - 1 + gi] = (uint32_t)gi;
         last[N - 1 + gi] = (uint32_t)gi;
     }
-    if (gi == 0) parent[0] = RLC_NONE;
+    if (gi == 0) {
+        parent[0] = RLC_NONE;
+        if (N > 1) inode[3] = RLC_NONE;
+    }
     if (gi + 1 >= N) return;
     const int i = (int)gi;
     // direction of the range from the larger common prefix
@@ -328,6 +331,11 @@ __global__ void __launch_bounds__(kBlock) k_radix_tree(const uint32_t* __restric
     parent[rc] = (uint32_t)i;
     first[i] = (uint32_t)lo;
     last[i] = (uint32_t)hi;
+    inode[4 * i] = lc;
+    inode[4 * i + 1] = rc;
+    inode[4 * i + 2] = (uint32_t)(gamma + 1);
+    if (lc + 1u < N) inode[4 * lc + 3] = (uint32_t)i;
+    if (rc + 1u < N) inode[4 * rc + 3] = (uint32_t)i;
 }
 
 // Breadth-first initial cut, built once by one thread (setup).
@@ -486,10 +494,10 @@ hipError_t launch_scatter_emission(const float* emit, const uint32_t* perm, uint
 }
 
 hipError_t launch_radix_tree(const uint32_t* morton, const uint32_t* perm, uint32_t N, uint32_t* left,
-                             uint32_t* right, uint32_t* parent, uint32_t* first, uint32_t* last,
+                             uint32_t* right, uint32_t* parent, uint32_t* first, uint32_t* last, uint32_t* inode,
                              hipStream_t s) {
     hipLaunchKernelGGL(k_radix_tree, dim3(blocks_for(N)), dim3(kBlock), 0, s, morton, perm, N, left, right, parent,
-                       first, last);
+                       first, last, inode);
     return hipGetLastError();
 }
 
