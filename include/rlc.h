@@ -127,6 +127,10 @@ int rlc_destroy(rlc_ctx* ctx);
  * build the binary radix tree over them, then the breadth-first initial cut
  * of min(M, N) nodes.  Resets every cell.  Synchronises (validates input). */
 int rlc_build_light_tree(rlc_ctx* ctx, const float* d_tri, const float* d_emit, uint32_t N);
+/* The tree's light order (section 3.1): d_perm[j] (device, N entries) is
+ * the input index of the light at position j, the order of the leaves and
+ * of every node's light range.  Enqueued on the context's stream. */
+int rlc_get_light_order(rlc_ctx* ctx, uint32_t* d_perm);
 
 /* Forget every cell (keys, cuts, Q, statistics): the next pass starts from
  * the initial cut everywhere, as after rlc_build_light_tree. */

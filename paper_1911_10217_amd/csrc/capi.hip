@@ -1097,6 +1097,13 @@ int rlc_load_cells(rlc_ctx* c, uint32_t n, const uint64_t* h_keys, const uint32_
     return read_device_errors(c);
 }
 
+int rlc_get_light_order(rlc_ctx* c, uint32_t* d_perm) {
+    RLC_TRY(need_tree(c));
+    if (!d_perm) return fail(c, RLC_EINVAL, "null array");
+    RLC_HIP(c, hipMemcpyAsync(d_perm, c->perm, sizeof(uint32_t) * c->N, hipMemcpyDeviceToDevice, c->stream));
+    return RLC_OK;
+}
+
 int rlc_dump_tree(rlc_ctx* c, uint32_t* h_perm, uint32_t* h_left, uint32_t* h_right, uint32_t* h_parent,
                   uint32_t* h_first, uint32_t* h_last, float* h_rec) {
     RLC_TRY(need_tree(c));

@@ -33,7 +33,8 @@ EXPORTS = (
     "rlc_set_occluders",
     "rlc_sample", "rlc_shade", "rlc_learn", "rlc_adapt_cuts", "rlc_frame", "rlc_frame_sub", "rlc_frame_sub_noalloc", "rlc_visible",
     "rlc_cell_keys", "rlc_image_error", "rlc_sync", "rlc_last_error", "rlc_num_cells", "rlc_meff",
-    "rlc_dump_cells", "rlc_load_cells", "rlc_dump_tree", "rlc_get_template", "rlc_set_timing", "rlc_get_timing",
+    "rlc_dump_cells", "rlc_load_cells", "rlc_dump_tree", "rlc_get_light_order", "rlc_get_template",
+    "rlc_set_timing", "rlc_get_timing",
     "rlc_batch_create", "rlc_batch_destroy", "rlc_batch_set_schedule", "rlc_batch_get_schedule",
     "rlc_batch_autotune", "rlc_batch_frame",
     "rlc_mlp_fixed_cut", "rlc_mlp_init", "rlc_mlp_set_params", "rlc_mlp_get_params", "rlc_mlp_forward",
@@ -167,6 +168,7 @@ def _declare(L):
     L.rlc_set_sample_log.argtypes = [_vp, _vp, _vp, _vp, ctypes.c_uint64]
     L.rlc_get_mlp_timing.argtypes = [_vp, _vp, _vp, _vp]
     L.rlc_mlp_order.argtypes = [_vp, _u32, _u32, _vp]
+    L.rlc_get_light_order.argtypes = [_vp, _vp]
     for name in EXPORTS:
         if name != "rlc_last_error":
             getattr(L, name).restype = i
@@ -445,6 +447,14 @@ class Context:
         d["left"] = d["left"][:N - 1]
         d["right"] = d["right"][:N - 1]
         return d
+
+    def rlc_get_light_order(self, out=None):
+        """Input index of the light at each tree position (device int32 tensor of N)."""
+        import torch
+        if out is None:
+            out = torch.empty(self.N, dtype=torch.int32, device="cuda")
+        self._check(lib().rlc_get_light_order(self._h, _ptr(out)), "rlc_get_light_order")
+        return out
 
     def rlc_get_template(self):
         node = np.zeros(RLC_MMAX, np.uint32)

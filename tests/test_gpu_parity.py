@@ -85,6 +85,18 @@ def test_tree_parity_random(torch, N):
     assert np.array_equal(gn, on) and np.array_equal(ge, oe)
 
 
+def test_light_order_matches_oracle(torch):
+    rng = np.random.default_rng(12)
+    tri = rng.random((3000, 9)).astype(np.float32)
+    emit = rng.random((3000, 3)).astype(np.float32)
+    s = scenes.Scene("t", tri, emit, np.zeros((0, 6), np.float32), np.zeros((0, 3), np.float32),
+                     np.zeros((0, 3), np.float32), scenes.params_for(M=16))
+    ctx, orc = _make(torch, s)
+    got = ctx.rlc_get_light_order().cpu().numpy().astype(np.uint32)
+    assert np.array_equal(got, orc.tree()["perm"])
+    assert np.array_equal(got, ctx.rlc_dump_tree()["perm"])
+
+
 def test_tree_parity_duplicates_and_flat(torch):
     # many equal positions (ties broken by input index) and a flat axis
     rng = np.random.default_rng(3)
