@@ -332,13 +332,17 @@ def run_learned(args, np, torch, rlc, scenes, dev):
     Workload: the tiny scene (1,024 emissive triangles, 4,096 points, 64 box
     occluders, 8^3 cells, cut size 16, 16 spp per pass).  Plain: passes of
     the method from a fresh cell table.  Learned: 8 passes of the method that
-    log (point, fixed-cut node, weight) for every sample, training of the MLP
-    (epochs x minibatch Adam over the 524,288 logged tuples), one forward pass
-    for the per-point cdf, then passes that draw from the 50/50 mixture.  A
+    log (point, fixed-cut node, weight) for every sample; training of the MLP
+    (epochs x minibatch Adam over the 524,288 logged tuples) in a second
+    context on a side stream, while passes of the method go on in the first
+    (as many as a trial run shows end before the training does); the trained
+    weights taken over without a host synchronisation, one forward pass for
+    the per-point cdf, then passes that draw from the 50/50 mixture.  The
+    same with training first and rendering after is reported beside it.  A
     GPU-time budget is the plain method's time for n passes; each form's
-    image is the mean of the passes that fit in it.  MSE against the FP64
-    oracle truth at every 16th point (a stored table written by the oracle).
-    All times are HIP events on the library's stream, training included."""
+    image is the mean of the passes that end within it.  MSE against the
+    FP64 oracle truth at every 16th point (a stored table written by the
+    oracle).  All times are HIP events, training included."""
     s = scenes.make_tiny()
     p = dict(s.params)
     spp = int(p["spp"])
@@ -410,32 +414,81 @@ def run_learned(args, np, torch, rlc, scenes, dev):
     plain_mse, plain_mse_b = mse_curve(nmax)
 
     # ---- learned: log, train, forward, mixture passes ----
-    ctx.rlc_reset_cells()
-    ctx.rlc_mlp_init(p["seed"])
+    # Training runs in a second context on a side stream (default priority),
+    # fed by the logged tuples: the training kernels occupy half of the
+    # compute units, so the method's passes go on beside them until the
+    # network is trained; the rendering context then takes the weights
+    # (rlc_mlp_copy_params joins the streams) and switches to the mixture.
+    side = torch.cuda.Stream()
+    side.wait_stream(torch.cuda.current_stream())
+    with torch.cuda.stream(side):
+        trainer = rlc.Context(p)
+        trainer.rlc_build_light_tree(t(s.tri), t(s.emit))
+        trainer.rlc_set_occluders(t(s.boxes))
+    torch.cuda.synchronize()
     k_mix = nmax
-    ev = events(log_passes + 1)
-    ev_train, ev_fwd = events(2)
-    ev_mix = events(k_mix)
-    torch.cuda.synchronize()
-    ev[0].record()
-    for f in range(log_passes):
-        sl = slice(f * P * spp, (f + 1) * P * spp)
-        ctx.rlc_set_sample_log(lp[sl], ln[sl], lw[sl])
-        ctx.rlc_frame(pos, nrm, spp, f, rad[f])
-        ev[f + 1].record()
-    ctx.rlc_set_sample_log()
-    ctx.rlc_mlp_train(pos, nrm, lp, ln, lw, args.mlp_epochs, args.mlp_batch, args.mlp_lr, sync=False)
-    ev_train.record()
-    ctx.rlc_mlp_forward(pos, nrm, cdf=cdf)
-    ctx.rlc_set_mixture(cdf, 0.5)
-    ev_fwd.record()
-    for j in range(k_mix - log_passes):
-        ctx.rlc_frame(pos, nrm, spp, log_passes + j, rad[log_passes + j])
-        ev_mix[j].record()
-    torch.cuda.synchronize()
-    ctx.rlc_set_mixture()
-    ctx.rlc_sync()
+
+    def learned_run(k_ov, passes=k_mix):
+        """k_ov None: train on the rendering context's stream, then render;
+        otherwise k_ov passes of the method beside the training."""
+        ctx.rlc_reset_cells()
+        ctx.rlc_mlp_init(p["seed"])
+        trainer.rlc_mlp_init(p["seed"])
+        ev = events(passes + 1)
+        ev_train, ev_fwd = events(2)
+        torch.cuda.synchronize()
+        ev[0].record()
+        for f in range(log_passes):
+            sl = slice(f * P * spp, (f + 1) * P * spp)
+            ctx.rlc_set_sample_log(lp[sl], ln[sl], lw[sl])
+            ctx.rlc_frame(pos, nrm, spp, f, rad[f])
+            ev[f + 1].record()
+        ctx.rlc_set_sample_log()
+        done = log_passes
+        if k_ov is None:
+            ctx.rlc_mlp_train(pos, nrm, lp, ln, lw, args.mlp_epochs, args.mlp_batch, args.mlp_lr, sync=False)
+            ev_train.record()
+        else:
+            side.wait_event(ev[log_passes])
+            trainer.rlc_mlp_train(pos, nrm, lp, ln, lw, args.mlp_epochs, args.mlp_batch, args.mlp_lr, sync=False)
+            ev_train.record(side)
+            for f in range(log_passes, min(log_passes + k_ov, passes)):
+                ctx.rlc_frame(pos, nrm, spp, f, rad[f])
+                ev[f + 1].record()
+                done = f + 1
+            ctx.rlc_mlp_copy_params(trainer)
+        if done < passes:
+            ctx.rlc_mlp_forward(pos, nrm, cdf=cdf)
+            ctx.rlc_set_mixture(cdf, 0.5)
+            ev_fwd.record()
+            for f in range(done, passes):
+                ctx.rlc_frame(pos, nrm, spp, f, rad[f])
+                ev[f + 1].record()
+        torch.cuda.synchronize()
+        ctx.rlc_set_mixture()
+        ctx.rlc_sync()
+        trainer.rlc_sync()
+        ends = np.array([ev[0].elapsed_time(e) for e in ev[1:]])
+        out = {"ends": ends, "done": done, "t_log": ev[0].elapsed_time(ev[log_passes]),
+               "t_train": ev[log_passes].elapsed_time(ev_train), "t_train_end": ev[0].elapsed_time(ev_train)}
+        if done < passes:
+            fwd_end = ev[0].elapsed_time(ev_fwd)
+            out["t_fwd"] = fwd_end - max(ends[done - 1], out["t_train_end"])
+            out["mix_ms"] = ev_fwd.elapsed_time(ev[passes])
+            out["n_mix"] = passes - done
+        return out
+
+    # how many passes of the method fit beside the training: a trial run
+    # with more than enough of them, counted by their end times
+    trial = learned_run(256, passes=log_passes + 256)
+    k_ov = int(np.sum(trial["ends"][log_passes:] <= trial["t_train_end"]))
+    serial = learned_run(None)
+    serial_mse, serial_mse_b = mse_curve(k_mix)
+    lrun = learned_run(k_ov)
     learned_mse, learned_mse_b = mse_curve(k_mix)
+    mix_t = lrun["ends"]
+    t_log, t_train, t_fwd = lrun["t_log"], lrun["t_train"], lrun["t_fwd"]
+    trainer.close()
     # per-kernel durations of the training steps, in a separate run with HIP
     # events around each launch (the same training from the same weights)
     ctx.rlc_mlp_init(p["seed"])
@@ -443,17 +496,18 @@ def run_learned(args, np, torch, rlc, scenes, dev):
     loss = ctx.rlc_mlp_train(pos, nrm, lp, ln, lw, args.mlp_epochs, args.mlp_batch, args.mlp_lr)
     ctx.rlc_set_timing(False)
     fb_ms, upd_ms, steps = ctx.rlc_get_mlp_timing()
-    t_log = ev[0].elapsed_time(ev[log_passes])
-    t_train = ev[log_passes].elapsed_time(ev_train)
-    t_fwd = ev_train.elapsed_time(ev_fwd)
-    mix_t = np.array([ev[0].elapsed_time(ev[f + 1]) for f in range(log_passes)] +
-                     [ev[0].elapsed_time(e) for e in ev_mix[:k_mix - log_passes]])
+
+    def serial_ratio(n):
+        budget = float(plain_t[n - 1])
+        fit = int(np.searchsorted(serial["ends"], budget, side="right"))
+        return round(float(serial_mse[fit - 1] / plain_mse[n - 1]), 4) if fit >= 1 else None
 
     rows = []
     for n in budgets:
         budget = float(plain_t[n - 1])
         fit = int(np.searchsorted(mix_t, budget, side="right"))
-        # the logged passes always count; mixture passes only after training
+        # every pass that ends within the budget counts: logged, beside the
+        # training, mixture
         m = learned_mse[fit - 1] if fit >= 1 else float("nan")
         mb = learned_mse_b[fit - 1] if fit >= 1 else float("nan")
         rows.append({"budget_passes_plain": n, "budget_ms": round(budget, 4),
@@ -461,7 +515,8 @@ def run_learned(args, np, torch, rlc, scenes, dev):
                      "learned_passes": fit, "learned_mse": float(m),
                      "ratio_learned_to_plain": round(float(m / plain_mse[n - 1]), 4) if fit >= 1 else None,
                      "plain_mse_below_band": float(plain_mse_b[n - 1]), "learned_mse_below_band": float(mb),
-                     "ratio_below_band": round(float(mb / plain_mse_b[n - 1]), 4) if fit >= 1 else None})
+                     "ratio_below_band": round(float(mb / plain_mse_b[n - 1]), 4) if fit >= 1 else None,
+                     "ratio_learned_to_plain_train_then_render": serial_ratio(n)})
     equal_samples = {"passes": nmax, "plain_mse": float(plain_mse[nmax - 1]),
                      "learned_mse": float(learned_mse[nmax - 1]),
                      "ratio_learned_to_plain": round(float(learned_mse[nmax - 1] / plain_mse[nmax - 1]), 4),
@@ -469,8 +524,8 @@ def run_learned(args, np, torch, rlc, scenes, dev):
                      "learned_mse_below_band": float(learned_mse_b[nmax - 1]),
                      "ratio_below_band": round(float(learned_mse_b[nmax - 1] / plain_mse_b[nmax - 1]), 4)}
 
-    mix_ms = ev_fwd.elapsed_time(ev_mix[k_mix - log_passes - 1]) if k_mix > log_passes else 0.0
-    n_mix = k_mix - log_passes
+    mix_ms = lrun.get("mix_ms", 0.0)
+    n_mix = lrun.get("n_mix", 0)
     value = P * spp * n_mix / (mix_ms * 1e-3) if mix_ms > 0 else 0.0
     fb_avg = fb_ms / max(steps, 1)
     flop = MLP_FLOP_PER_TUPLE * min(args.mlp_batch, n_log)
@@ -491,8 +546,9 @@ def run_learned(args, np, torch, rlc, scenes, dev):
         "config": {
             "workload": ("learned: tiny scene (1,024 emissive triangles, 4,096 points, 64 box occluders, "
                          "8^3 cells, cut size 16, 16 spp); 8 logged passes, MLP 144-64-64-64-64 trained "
-                         "%d epochs (batch %d, lr %g), then 50/50 mixture passes"
-                         % (args.mlp_epochs, args.mlp_batch, args.mlp_lr)),
+                         "%d epochs (batch %d, lr %g) in a second context on a side stream while %d passes "
+                         "of the method go on, then 50/50 mixture passes"
+                         % (args.mlp_epochs, args.mlp_batch, args.mlp_lr, k_ov)),
             "samples_per_step": P * spp,
             "parallelism": "1 GPU",
         },
@@ -503,7 +559,10 @@ def run_learned(args, np, torch, rlc, scenes, dev):
             "equal_samples": equal_samples,
             "plain_ms_per_pass": round(float(plain_t[-1] / nmax), 4),
             "learned_ms": {"log_passes": round(t_log, 4), "train": round(t_train, 4),
-                           "forward": round(t_fwd, 4), "mixture_per_pass": round(mix_ms / max(n_mix, 1), 4)},
+                           "passes_beside_training": k_ov,
+                           "forward": round(t_fwd, 4), "mixture_per_pass": round(mix_ms / max(n_mix, 1), 4),
+                           "train_then_render": {"train": round(serial["t_train"], 4),
+                                                 "forward": round(serial.get("t_fwd", 0.0), 4)}},
             "train_steps": steps,
             "train_last_loss": loss,
         },

@@ -309,6 +309,12 @@ int rlc_mlp_init(rlc_ctx* ctx, uint64_t seed);
  * non-finite values) or out. */
 int rlc_mlp_set_params(rlc_ctx* ctx, const float* d_params);
 int rlc_mlp_get_params(rlc_ctx* ctx, float* d_params);
+/* dst takes src's network weights, without synchronising: on dst's stream,
+ * after all work enqueued so far on src's stream (an event joins the two
+ * streams when they differ), so a network trained on one context's stream
+ * can serve another's passes while those go on.  Resets dst's Adam state.
+ * RLC_ESTATE if src has no weights. */
+int rlc_mlp_copy_params(rlc_ctx* dst, rlc_ctx* src);
 /* Forward pass for P points: d_cdf (P x 64, may be NULL) the inclusive
  * running sums of the 64 probabilities, left to right in FP32 (the table
  * the mixture draws from); d_logits (P x 64, may be NULL). */

@@ -144,6 +144,7 @@ struct rlc_ctx {
     std::vector<hipEvent_t> pending;   // 3 per timed frame
     std::vector<hipEvent_t> mlp_pending;  // 3 per timed training step
     std::vector<hipEvent_t> spare;
+    hipEvent_t join = nullptr;  // marks this stream's work for another context's stream to wait on
 };
 
 namespace {
@@ -606,6 +607,7 @@ int rlc_destroy(rlc_ctx* c) {
     for (hipEvent_t e : c->pending) (void)hipEventDestroy(e);
     for (hipEvent_t e : c->mlp_pending) (void)hipEventDestroy(e);
     for (hipEvent_t e : c->spare) (void)hipEventDestroy(e);
+    if (c->join) (void)hipEventDestroy(c->join);
     delete c;
     return RLC_OK;
 }
@@ -1155,6 +1157,22 @@ int rlc_mlp_set_params(rlc_ctx* c, const float* d_params) {
     RLC_HIP(c, launch_check_finite(c->mlp_master, kMlpParams, c->d_err, c->stream));
     RLC_TRY(read_device_errors(c));
     return mlp_reset_optimizer(c);
+}
+
+int rlc_mlp_copy_params(rlc_ctx* dst, rlc_ctx* src) {
+    if (!dst || !src) return RLC_EINVAL;
+    if (dst == src) return fail(dst, RLC_EINVAL, "a context takes weights from another context");
+    if (!src->mlp_ready) return fail(dst, RLC_ESTATE, "the source network has no weights");
+    RLC_TRY(mlp_alloc(dst));
+    if (src->stream != dst->stream) {
+        // dst's stream waits for the work enqueued so far on src's
+        if (!src->join) RLC_HIP(dst, hipEventCreateWithFlags(&src->join, hipEventDisableTiming));
+        RLC_HIP(dst, hipEventRecord(src->join, src->stream));
+        RLC_HIP(dst, hipStreamWaitEvent(dst->stream, src->join, 0));
+    }
+    RLC_HIP(dst, hipMemcpyAsync(dst->mlp_master, src->mlp_master, sizeof(float) * kMlpParams,
+                                hipMemcpyDeviceToDevice, dst->stream));
+    return mlp_reset_optimizer(dst);
 }
 
 int rlc_mlp_get_params(rlc_ctx* c, float* d_params) {

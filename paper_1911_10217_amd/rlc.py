@@ -37,7 +37,8 @@ EXPORTS = (
     "rlc_set_timing", "rlc_get_timing",
     "rlc_batch_create", "rlc_batch_destroy", "rlc_batch_set_schedule", "rlc_batch_get_schedule",
     "rlc_batch_autotune", "rlc_batch_frame",
-    "rlc_mlp_fixed_cut", "rlc_mlp_init", "rlc_mlp_set_params", "rlc_mlp_get_params", "rlc_mlp_forward",
+    "rlc_mlp_fixed_cut", "rlc_mlp_init", "rlc_mlp_set_params", "rlc_mlp_get_params", "rlc_mlp_copy_params",
+    "rlc_mlp_forward",
     "rlc_mlp_grad", "rlc_mlp_train", "rlc_mlp_order", "rlc_set_mixture", "rlc_set_sample_log",
     "rlc_get_mlp_timing",
     "rlc_set_footprints",
@@ -169,6 +170,7 @@ def _declare(L):
     L.rlc_get_mlp_timing.argtypes = [_vp, _vp, _vp, _vp]
     L.rlc_mlp_order.argtypes = [_vp, _u32, _u32, _vp]
     L.rlc_get_light_order.argtypes = [_vp, _vp]
+    L.rlc_mlp_copy_params.argtypes = [_vp, _vp]
     for name in EXPORTS:
         if name != "rlc_last_error":
             getattr(L, name).restype = i
@@ -514,6 +516,11 @@ class Context:
         out = torch.empty(RLC_MLP_PARAMS, dtype=torch.float32, device="cuda")
         self._check(lib().rlc_mlp_get_params(self._h, _ptr(out)), "rlc_mlp_get_params")
         return out
+
+    def rlc_mlp_copy_params(self, src: "Context"):
+        """Take src's network weights on this context's stream, after the work
+        enqueued so far on src's stream (no host synchronisation)."""
+        self._check(lib().rlc_mlp_copy_params(self._h, src._h), "rlc_mlp_copy_params")
 
     def rlc_mlp_forward(self, pos, nrm, cdf=True, logits=False):
         """cdf / logits: True to allocate the output, a (P, 64) float32 tensor

@@ -211,6 +211,43 @@ def test_training_is_deterministic_and_can_be_asynchronous(torch):
     ctx.rlc_sync()
 
 
+def test_copy_params_from_a_context_on_another_stream(torch):
+    """A network trained on a side stream serves a context on the main
+    stream: the copy waits for the training without a host synchronisation
+    and gives the same weights and the same forward pass."""
+    from paper_1911_10217_amd import rlc
+    s = scenes.make_tiny(n_lights=300, n_points=200)
+    a, pos, nrm = _ctx(torch, s)
+    rng = np.random.default_rng(8)
+    n = 3000
+    g = lambda x: torch.from_numpy(x).cuda()
+    pid = g(rng.integers(0, s.P, n).astype(np.int32))
+    node = g(rng.integers(0, 64, n).astype(np.int32))
+    w = g(rng.exponential(size=n).astype(np.float32))
+    side = torch.cuda.Stream()
+    side.wait_stream(torch.cuda.current_stream())
+    with torch.cuda.stream(side):
+        b, _, _ = _ctx(torch, s)
+        b.rlc_mlp_init(7)
+        b.rlc_mlp_train(pos, nrm, pid, node, w, epochs=3, batch=512, lr=1e-2, sync=False)
+    with pytest.raises(rlc.RLCError) as e:
+        a.rlc_mlp_copy_params(a)
+    assert e.value.code == rlc.RLC_EINVAL
+    a.rlc_mlp_copy_params(b)
+    qa = a.rlc_mlp_forward(pos, nrm, cdf=True)[0]
+    pa = a.rlc_mlp_get_params()
+    torch.cuda.synchronize()
+    with torch.cuda.stream(side):
+        pb = b.rlc_mlp_get_params()
+        qb = b.rlc_mlp_forward(pos, nrm, cdf=True)[0]
+    torch.cuda.synchronize()
+    assert torch.equal(pa, pb) and torch.equal(qa, qb)
+    fresh, _, _ = _ctx(torch, s)
+    with pytest.raises(rlc.RLCError) as e:
+        a.rlc_mlp_copy_params(fresh)
+    assert e.value.code == rlc.RLC_ESTATE
+
+
 def test_init_is_seeded_and_bounded(torch):
     s = scenes.make_tiny(n_lights=100, n_points=50)
     ctx, pos, nrm = _ctx(torch, s)
