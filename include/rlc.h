@@ -293,9 +293,9 @@ int rlc_batch_frame(rlc_batch* b, uint32_t frame);
  * Training: minibatch Adam (beta1 0.9, beta2 0.999, eps 1e-8) on the
  * weighted cross-entropy -sum_i w_i log q(x_i)[node_i] / sum_i w_i over
  * logged tuples (point, fixed-cut node, w = (c_l summed over RGB) / p(l)).
- * Epoch e visits the tuples in ascending order of the first Philox word at
- * counter (i, e, 0, scene_id << 16 | 2) (ties by i), in batches of `batch`;
- * each batch is one Adam step. */
+ * Epoch e visits the tuples in the order rlc_mlp_order gives (a keyed
+ * permutation computed per position), in batches of `batch`; each batch is
+ * one Adam step. */
 #define RLC_MLP_PARAMS 21760u
 #define RLC_MLP_NODES 64u
 

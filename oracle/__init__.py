@@ -22,26 +22,35 @@ _HERE = os.path.dirname(os.path.abspath(__file__))
 _SRC = os.path.join(_HERE, "rlc_oracle.c")
 _SRC_MLP = os.path.join(_HERE, "rlc_oracle_mlp.c")
 _SO = os.path.join(_HERE, "liboracle.so")
+# a prebuilt oracle library to load instead (the sanitizer test builds one
+# with AddressSanitizer and UBSan and runs the oracle's pins against it)
+_SO_OVERRIDE = os.environ.get("RLC_ORACLE_LIB")
 _lib = None
 
 MMAX = 256
 MIX_M = 64
 
 
-def build(force: bool = True) -> str:
+FLAGS = ["-std=c11", "-Wall", "-ffp-contract=off", "-fno-fast-math", "-fexcess-precision=standard", "-fPIC",
+         "-shared"]
+
+
+def build(force: bool = True, out: str = _SO, extra=("-O2",)) -> str:
     """Compile the oracle library (always recompiles when force is true)."""
-    if force or not os.path.exists(_SO):
-        tmp = _SO + ".tmp%d" % os.getpid()
-        subprocess.check_call(["gcc", "-O2", "-std=c11", "-Wall", "-ffp-contract=off",
-                               "-fno-fast-math", "-fexcess-precision=standard", "-fPIC",
-                               "-shared", "-o", tmp, _SRC, _SRC_MLP, "-lm"])
-        os.replace(tmp, _SO)
-    return _SO
+    if force or not os.path.exists(out):
+        tmp = out + ".tmp%d" % os.getpid()
+        subprocess.check_call(["gcc", *extra, *FLAGS, "-o", tmp, _SRC, _SRC_MLP, "-lm"])
+        os.replace(tmp, out)
+    return out
 
 
 def lib():
     global _lib
     if _lib is None:
+        if _SO_OVERRIDE:
+            _lib = ctypes.CDLL(_SO_OVERRIDE)
+            _declare(_lib)
+            return _lib
         if not os.path.exists(_SO) or os.path.getmtime(_SO) < max(os.path.getmtime(_SRC),
                                                                     os.path.getmtime(_SRC_MLP)):
             build()
