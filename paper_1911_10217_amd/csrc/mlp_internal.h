@@ -40,6 +40,7 @@ __host__ __device__ __forceinline__ uint32_t fmix32(uint32_t v) {
 }
 
 __host__ __device__ __forceinline__ uint32_t mlp_order_at(const MlpOrder& o, uint32_t i) {
+    if (o.n == 0u) return i;  // the identity
     const uint32_t h = o.h, mask = (uint32_t)((1ull << h) - 1ull);
     uint32_t x = i;
     do {
