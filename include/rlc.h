@@ -96,8 +96,11 @@ typedef struct rlc_config {
     uint32_t max_cells;    /* cells the tables hold rows for (section 3's bounded memory per
                               cell: the per-cluster tables take max_cells * M * 32 bytes);
                               0: one row per lookup slot (hashed) or per cell of the grid
-                              (dense); at most that many.  A cell created past it is not
-                              learned from and the pass reports RLC_ECAPACITY */
+                              (dense); at most that many.  From 4,096 rows on, the pool is
+                              cut into stripes of about 1,024 rows (up to 64), a cell taking
+                              its row from the stripe its lookup slot selects.  A cell whose
+                              stripe is full is not learned from, and the pass reports
+                              RLC_ECAPACITY */
 } rlc_config;
 
 /* Per-sample records of rlc_sample (device arrays of n = P * spp entries,

@@ -407,33 +407,72 @@ __device__ __forceinline__ void adapt_cell(const AdaptParams& ap, const CellIn<P
     adapt_back<PER>(ap, in.c, L);
 }
 
-// Rows in use: the created cells, packed from row 0.
-__device__ __forceinline__ uint32_t rows_in_use(const DevCells& c) {
-    const uint32_t n = *c.n_live;
-    return n < c.rows ? n : c.rows;
+// The rows in use: row k * stripes + s for k below stripe s's count.  They
+// lie in rows 0 .. span - 1 (span: the largest count times the stripes),
+// with a few unused rows where a stripe has fewer cells than the fullest.
+// Built by one wave (lane s reads stripe s's counter, then a maximum across
+// the lanes).
+struct RowMap {
+    uint32_t used[RLC_ROW_STRIPES_MAX];
+    uint32_t span;
+    uint32_t shift;  // log2(stripes)
+};
+
+__device__ __forceinline__ void row_map_build(const DevCells& c, RowMap& m) {
+    const uint32_t lane = threadIdx.x & (kWave - 1u);
+    uint32_t v = 0;
+    if (lane < c.stripes) {
+        const uint32_t n = c.n_live[lane];
+        v = n < c.stripe_rows ? n : c.stripe_rows;
+        m.used[lane] = v;
+    }
+    uint32_t mx = v;
+#pragma unroll
+    for (int off = 1; off < (int)kWave; off <<= 1) {
+        const uint32_t t = (uint32_t)__shfl_xor((int)mx, off, kWave);
+        mx = t > mx ? t : mx;
+    }
+    if (lane == 0) {
+        m.span = mx * c.stripes;
+        m.shift = (uint32_t)__builtin_ctz(c.stripes);
+    }
+}
+
+__device__ __forceinline__ bool row_used(const DevCells& c, const RowMap& m, uint32_t r) {
+    return r < m.span && (r >> m.shift) < m.used[r & (c.stripes - 1u)];
 }
 
 // The cells of rows li, li + grid, ...: each cell's loads are issued before
 // the previous cell's work (with one slot per lane; four slots per lane
 // would hold too many registers).
 template <int PER>
-__device__ __forceinline__ void adapt_cells(const AdaptParams& ap, const AdaptLds& L) {
-    const uint32_t n_live = rows_in_use(ap.cells);
-    uint32_t li = blockIdx.x;
-    if (li >= n_live) return;
-    CellIn<PER> cur, nxt;
-    load_cell<PER>(ap, li, cur);
-    for (; li < n_live; li += gridDim.x) {
-        const uint32_t ln = li + gridDim.x;
-        if (PER == 1 && ln < n_live) load_cell<PER>(ap, ln, nxt);
-        adapt_cell<PER>(ap, cur, L);
-        if (ln < n_live) {
-            if (PER == 1)
-                cur = nxt;
-            else
-                load_cell<PER>(ap, ln, cur);
+__device__ __forceinline__ void adapt_cells(const AdaptParams& ap, const AdaptLds& L, RowMap& map) {
+    row_map_build(ap.cells, map);
+    wave_sync();
+    const uint32_t span = map.span;
+    // the rows this block visits (stride: the grid), unused ones skipped
+    auto next_row = [&](uint32_t r) {
+        while (r < span && !row_used(ap.cells, map, r)) r += gridDim.x;
+        return r;
+    };
+    uint32_t li = next_row(blockIdx.x);
+    if (li < span) {
+        CellIn<PER> cur, nxt;
+        load_cell<PER>(ap, li, cur);
+        while (li < span) {
+            const uint32_t ln = next_row(li + gridDim.x);
+            if (PER == 1 && ln < span) load_cell<PER>(ap, ln, nxt);
+            adapt_cell<PER>(ap, cur, L);
+            if (ln < span) {
+                if (PER == 1)
+                    cur = nxt;
+                else
+                    load_cell<PER>(ap, ln, cur);
+            }
+            li = ln;
         }
     }
+    wave_sync();  // the map is rebuilt by the next call (the batch's next scene)
 }
 
 // One block = one wavefront; it walks the list of created cells.  The LDS
@@ -442,19 +481,21 @@ template <int PER>
 __global__ void __launch_bounds__(kWave, PER == 1 ? 8 : 4) k_adapt(AdaptParams /* read in place */) {
     const AdaptParams& ap = first_kernel_arg<AdaptParams>();
     extern __shared__ uint32_t lds[];
+    __shared__ RowMap s_map;
     const AdaptLds L = lds_view(lds, kWave * PER);
-    adapt_cells<PER>(ap, L);
+    adapt_cells<PER>(ap, L, s_map);
 }
 
 // The same over every scene of a batch.
 template <int PER>
 __global__ void __launch_bounds__(kWave, PER == 1 ? 8 : 4) k_batch_adapt(const AdaptParams* __restrict__ aps, uint32_t n_scenes) {
     extern __shared__ uint32_t lds[];
+    __shared__ RowMap s_map;
     const AdaptLds L = lds_view(lds, kWave * PER);
     typedef const __attribute__((address_space(4))) AdaptParams* ConstAdaptParams;
     for (uint32_t sc = 0; sc < n_scenes; ++sc) {
         const AdaptParams& ap = opaque_const((ConstAdaptParams)uniform_u64((uint64_t)&aps[sc]));
-        adapt_cells<PER>(ap, L);
+        adapt_cells<PER>(ap, L, s_map);
     }
 }
 
@@ -472,23 +513,26 @@ __global__ void __launch_bounds__(kCellWaves * kWave, 8) k_adapt16(AdaptParams /
     const AdaptParams& ap = first_kernel_arg<AdaptParams>();
     extern __shared__ uint32_t lds[];
     __shared__ uint32_t s_active[kCellWaves];
+    __shared__ RowMap s_map;
     const uint32_t wave = threadIdx.x / kWave, lane = threadIdx.x % kWave;
     const AdaptLds L = lds_view(lds + wave * kCellRegion, kWave);
-    const uint32_t n_live = rows_in_use(ap.cells);
+    if (wave == 0) row_map_build(ap.cells, s_map);
+    __syncthreads();
+    const uint32_t n_live = s_map.span;
     const uint32_t per_round = gridDim.x * kCellWaves;
     const uint32_t rounds = (n_live + per_round - 1u) / per_round;
     // each round's cell is loaded during the round before (a launch
     // touches every cell once, so no round writes the next one's cell)
     CellIn<1> nxt;
     const uint32_t li0 = blockIdx.x * kCellWaves + wave;
-    if (li0 < n_live) load_cell<1>(ap, li0, nxt);
+    if (row_used(ap.cells, s_map, li0)) load_cell<1>(ap, li0, nxt);
     for (uint32_t rd = 0; rd < rounds; ++rd) {
         const uint32_t li = rd * per_round + li0;
         bool active = false;
         uint32_t c = 0;
         const CellIn<1> in = nxt;
-        if (li + per_round < n_live) load_cell<1>(ap, li + per_round, nxt);
-        if (li < n_live) {
+        if (row_used(ap.cells, s_map, li + per_round)) load_cell<1>(ap, li + per_round, nxt);
+        if (row_used(ap.cells, s_map, li)) {
             c = in.c;
             active = adapt_front<1>(ap, in, L);
         }

@@ -201,7 +201,7 @@ int reset_cells(rlc_ctx* c) {
     RLC_HIP(c, launch_fill_u32(d.ready, 0u, d.rows, c->stream));
     RLC_HIP(c, launch_fill_u64(d.sum, 0ull, bins, c->stream));
     RLC_HIP(c, launch_fill_u32(d.cnt, 0u, bins, c->stream));
-    RLC_HIP(c, launch_fill_u32(d.n_live, 0u, 1, c->stream));
+    RLC_HIP(c, launch_fill_u32(d.n_live, 0u, d.stripes, c->stream));
     return RLC_OK;
 }
 
@@ -375,9 +375,10 @@ int read_device_errors(rlc_ctx* c) {
         RLC_HIP(c, hipStreamSynchronize(c->stream));
         if (err & RLC_DERR_CAPACITY)
             return fail(c, RLC_ECAPACITY,
-                        "cell table full (rows for %u cells, %u lookup slots, or %u slots in a row taken); "
-                        "some samples were not learned from",
-                        c->cells.rows, c->cells.capacity, RLC_HASH_MAX_PROBES);
+                        "cell table full (rows for %u cells in %u stripes, %u lookup slots, or %u slots in a "
+                        "row taken); some samples were not learned from",
+                        c->cells.stripes * c->cells.stripe_rows, c->cells.stripes, c->cells.capacity,
+                        RLC_HASH_MAX_PROBES);
         if (err & RLC_DERR_WAIT)
             return fail(c, RLC_EHIP, "a cell lookup gave up waiting for the cell's row to be published");
         if (err & RLC_DERR_FX_OVERFLOW)
@@ -550,6 +551,12 @@ int rlc_create(const rlc_config* cfg, void* stream, rlc_ctx** out) {
     DevCells& d = c->cells;
     d.capacity = (uint32_t)capacity;
     d.rows = (uint32_t)pool;
+    // a pool of 4,096 rows or more is cut into stripes of about 1,024 rows
+    // (a power of two of them, at most RLC_ROW_STRIPES_MAX), each with its
+    // own row counter
+    d.stripes = 1;
+    while (d.stripes < RLC_ROW_STRIPES_MAX && pool >= 4096 && pool / (2u * d.stripes) >= 1024) d.stripes *= 2u;
+    d.stripe_rows = (uint32_t)(pool / d.stripes);
     d.hashed = k.hashed ? 1u : 0u;
     d.M = k.M;
     size_t bins = (size_t)pool * k.M;
@@ -564,7 +571,7 @@ int rlc_create(const rlc_config* cfg, void* stream, rlc_ctx** out) {
     if (r == RLC_OK) r = dalloc(c, &d.sum, bins);
     if (r == RLC_OK) r = dalloc(c, &d.cnt, bins);
     if (r == RLC_OK) r = dalloc(c, &d.live, pool);
-    if (r == RLC_OK) r = dalloc(c, &d.n_live, 1);
+    if (r == RLC_OK) r = dalloc(c, &d.n_live, RLC_ROW_STRIPES_MAX);
     if (r == RLC_OK) r = dalloc(c, &c->d_err, 1);
     if (r == RLC_OK) r = dalloc(c, &c->d_partial, 6 * 1024);
     if (r == RLC_OK) r = reset_cells(c);
@@ -961,13 +968,27 @@ int rlc_sync(rlc_ctx* c) {
     return read_device_errors(c);
 }
 
+// The rows in use, stripe by stripe (a stripe's counter passes its rows
+// once the stripe is full: the refused creations count too).
+int rows_in_use(rlc_ctx* c, std::vector<uint32_t>* rows_out, uint32_t* h_n) {
+    const DevCells& d = c->cells;
+    uint32_t cnt[RLC_ROW_STRIPES_MAX] = {0};
+    RLC_HIP(c, hipMemcpyAsync(cnt, d.n_live, sizeof(uint32_t) * d.stripes, hipMemcpyDeviceToHost, c->stream));
+    RLC_HIP(c, hipStreamSynchronize(c->stream));
+    uint32_t n = 0;
+    for (uint32_t s = 0; s < d.stripes; ++s) {
+        const uint32_t used = std::min(cnt[s], d.stripe_rows);
+        if (rows_out)
+            for (uint32_t k = 0; k < used; ++k) rows_out->push_back(k * d.stripes + s);
+        n += used;
+    }
+    *h_n = n;
+    return RLC_OK;
+}
+
 int rlc_num_cells(rlc_ctx* c, uint32_t* h_n) {
     if (!c || !h_n) return RLC_EINVAL;
-    uint32_t n = 0;
-    RLC_HIP(c, hipMemcpyAsync(&n, c->cells.n_live, sizeof(uint32_t), hipMemcpyDeviceToHost, c->stream));
-    RLC_HIP(c, hipStreamSynchronize(c->stream));
-    *h_n = std::min(n, c->cells.rows);  // creations refused by a full pool count past it
-    return RLC_OK;
+    return rows_in_use(c, nullptr, h_n);
 }
 
 int rlc_meff(rlc_ctx* c, uint32_t* h_meff) {
@@ -982,26 +1003,42 @@ int rlc_dump_cells(rlc_ctx* c, uint32_t max_cells, uint64_t* h_keys, uint32_t* h
     RLC_TRY(need_tree(c));
     RLC_TRY(rlc_sync(c));
     uint32_t n = 0;
-    RLC_TRY(rlc_num_cells(c, &n));
+    std::vector<uint32_t> used;
+    RLC_TRY(rows_in_use(c, &used, &n));
     if (n == 0) return RLC_OK;
     const DevCells& d = c->cells;
-    // rows 0..n-1 hold the created cells; each row's slot holds its key
-    std::vector<uint32_t> slot_of(n), ready(n), order(n);
+    // the rows in use hold the created cells; each row's slot holds its key
+    std::vector<uint32_t> slot_of(d.rows), ready_all(d.rows), ready(n), order(n);
     std::vector<unsigned long long> words(d.capacity);
-    RLC_HIP(c, hipMemcpy(slot_of.data(), d.live, sizeof(uint32_t) * n, hipMemcpyDeviceToHost));
-    RLC_HIP(c, hipMemcpy(ready.data(), d.ready, sizeof(uint32_t) * n, hipMemcpyDeviceToHost));
+    RLC_HIP(c, hipMemcpy(slot_of.data(), d.live, sizeof(uint32_t) * d.rows, hipMemcpyDeviceToHost));
+    RLC_HIP(c, hipMemcpy(ready_all.data(), d.ready, sizeof(uint32_t) * d.rows, hipMemcpyDeviceToHost));
     RLC_HIP(c, hipMemcpy(words.data(), d.keys, sizeof(unsigned long long) * d.capacity, hipMemcpyDeviceToHost));
     std::vector<uint64_t> key(n);
     for (uint32_t i = 0; i < n; ++i) {
-        key[i] = ((uint64_t)c->cfg.scene_id << 32) | (words[slot_of[i]] & 0xFFFFFFFFull);
-        order[i] = i;
+        key[i] = ((uint64_t)c->cfg.scene_id << 32) | (words[slot_of[used[i]]] & 0xFFFFFFFFull);
+        ready[i] = ready_all[used[i]];
+        order[i] = used[i];
     }
-    std::sort(order.begin(), order.end(), [&](uint32_t a, uint32_t b) { return key[a] < key[b]; });
+    std::vector<uint32_t> idx(n);
+    for (uint32_t i = 0; i < n; ++i) idx[i] = i;
+    std::sort(idx.begin(), idx.end(), [&](uint32_t a, uint32_t b) { return key[a] < key[b]; });
+    {
+        std::vector<uint64_t> k2(n);
+        std::vector<uint32_t> r2(n), o2(n);
+        for (uint32_t i = 0; i < n; ++i) {
+            k2[i] = key[idx[i]];
+            r2[i] = ready[idx[i]];
+            o2[i] = order[idx[i]];
+        }
+        key.swap(k2);
+        ready.swap(r2);
+        order.swap(o2);
+    }
     uint32_t rows = std::min(n, max_cells);
     if (rows == 0) return RLC_OK;
     for (uint32_t i = 0; i < rows; ++i) {
-        if (h_keys) h_keys[i] = key[order[i]];
-        if (h_ready) h_ready[i] = ready[order[i]];
+        if (h_keys) h_keys[i] = key[i];
+        if (h_ready) h_ready[i] = ready[i];
     }
     const uint32_t Meff = c->Meff;
     size_t cnt = (size_t)rows * Meff;
@@ -1060,7 +1097,9 @@ int rlc_load_cells(rlc_ctx* c, uint32_t n, const uint64_t* h_keys, const uint32_
             return fail(c, RLC_EINVAL, "cell key %llu is not a cell of this scene", (unsigned long long)key);
         if (i && key == sorted[i - 1]) return fail(c, RLC_EINVAL, "cell key %llu given twice", (unsigned long long)key);
     }
-    if (n > c->cells.rows) return fail(c, RLC_EINVAL, "more cells than the table holds rows for (%u)", c->cells.rows);
+    if (n > c->cells.stripes * c->cells.stripe_rows)
+        return fail(c, RLC_EINVAL, "more cells than the table holds rows for (%u)",
+                    c->cells.stripes * c->cells.stripe_rows);
     for (uint32_t i = 0; i < n; ++i) {
         // the cut partitions the lights in range order: each node starts
         // right after the previous one ends, the first at 0, the last at N-1

@@ -66,12 +66,15 @@ struct DevCells {
     unsigned long long* sum;    // fixed-point reward sums of the pass
     uint32_t* cnt;              // sample counts of the pass
     uint32_t* live;             // per row: its lookup slot
-    uint32_t* n_live;           // rows taken (passes `rows` once the pool is full)
+    uint32_t* n_live;           // per stripe: rows taken (passes stripe_rows once the stripe is full)
     uint32_t capacity;          // lookup slots: dense, cells of the grid; hashed, 2^k
     uint32_t rows;              // rows in the pool
+    uint32_t stripes;           // stripes of the pool, a power of two up to RLC_ROW_STRIPES_MAX
+    uint32_t stripe_rows;       // rows per stripe: stripe s holds rows s, s + stripes, s + 2 stripes, ...
     uint32_t hashed;
     uint32_t M;                 // row stride
 };
+#define RLC_ROW_STRIPES_MAX 64u
 
 struct FrameParams {
     DevTree tree;
@@ -319,12 +322,17 @@ __device__ __forceinline__ uint32_t resolve_row(const DevCells& c, uint32_t h, u
 // lanes of the wave that call this together (divergent code).  Lanes with
 // the same key have probed the same slots, so they are here at the same
 // slot, and one of them (the group's leader) acts for all: it claims the slot
-// by compare-and-swap to (pending, lin), takes the next row of the pool and
-// publishes (row, lin).  A slot meanwhile claimed by another wave for the
-// same cell gives its row once published; one claimed for another cell sets
-// `retry` (probe on).  Rows are taken only by successful claims, so the rows
-// in use are exactly 0 .. min(n_live, rows) - 1.  Groups are served one
-// after the other, so no lane waits on a claim of its own wave.
+// by compare-and-swap to (pending, lin), takes the next row of the slot's
+// stripe of the pool and publishes (row, lin).  A slot meanwhile claimed by
+// another wave for the same cell gives its row once published; one claimed
+// for another cell sets `retry` (probe on).  Rows are taken only by
+// successful claims, so the rows in use are each stripe's first
+// min(n_live[s], stripe_rows).  The stripes (chosen by slot) each have their
+// own counter, so the creations of a pass do not all queue on one atomic,
+// and are interleaved row by row, so the rows in use stay packed at the
+// start of the pool.
+// Groups are served one after the other, so no lane waits on a claim of its
+// own wave.
 __device__ __forceinline__ uint32_t create_at(const DevCells& c, uint32_t h, uint32_t lin, uint32_t* err,
                                               bool& retry) {
     const uint32_t lane = __lane_id();
@@ -341,8 +349,10 @@ __device__ __forceinline__ uint32_t create_at(const DevCells& c, uint32_t h, uin
         if (lane == leader) {
             const unsigned long long old = atomicCAS(&c.keys[h], RLC_EMPTY_KEY, slot_word(RLC_ROW_PENDING, lin));
             if (old == RLC_EMPTY_KEY) {
-                r = atomicAdd(c.n_live, 1u);
-                if (r < c.rows) {
+                const uint32_t st = h & (c.stripes - 1u);
+                const uint32_t k = atomicAdd(&c.n_live[st], 1u);
+                if (k < c.stripe_rows) {
+                    r = k * c.stripes + st;
                     c.live[r] = h;
                 } else {
                     atomicOr(err, RLC_DERR_CAPACITY);
