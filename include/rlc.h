@@ -70,7 +70,7 @@ typedef struct rlc_config {
     uint32_t adapt;        /* 1: split-collapse at the end of every pass */
     uint32_t temporal;     /* 0: every pass restarts from the initial cut */
     uint32_t scene_id;     /* upper key bits and RNG stream of this scene */
-    uint32_t occ_grid_res; /* 0: test every box per shadow ray; n: n^3 grid */
+    uint32_t occ_grid_res; /* 0: test every box per shadow ray; n: n^3 grid, n <= 256 */
     uint32_t split_steps;  /* split-collapse steps per pass (section 3): 0 or 1, one
                               step (the basic algorithm); n > 1, repeated until a
                               step changes nothing, at most n times (with T >= 1

@@ -491,7 +491,7 @@ int rlc_create(const rlc_config* cfg, void* stream, rlc_ctx** out) {
               finite_f(k.T) && k.T >= 0.0f && finite_f(k.eps) && k.eps >= 0.0f && k.fx_shift <= 40 &&
               finite_f(k.reward_max) && k.reward_max > 0.0f && finite_f(k.t_lo) && k.t_lo >= 0.0f &&
               k.t_lo < 0.5f && k.reward_mode <= 1 && finite_f(k.albedo) && k.albedo >= 0.0f &&
-              k.occ_grid_res <= 1024 && k.split_steps <= RLC_SPLIT_STEPS_MAX && k.normal_bits <= 8 &&
+              k.occ_grid_res <= RLC_OCC_RES_MAX && k.split_steps <= RLC_SPLIT_STEPS_MAX && k.normal_bits <= 8 &&
               finite_f(k.jitter) && k.jitter >= 0.0f && k.jitter <= 1.0f && k.footprint_levels <= RLC_MAX_LEVELS &&
               (k.footprint_levels <= 1u || (finite_f(k.footprint_tile) && k.footprint_tile > 0.0f));
     for (int a = 0; a < 3; ++a)

@@ -237,8 +237,13 @@ __device__ __forceinline__ void frame_block(const FrameParams& fp, const float* 
     float e[3] = {0.0f, 0.0f, 0.0f};
     uint32_t p = 0, k = 0;
     if (valid) {
-        const uint32_t q = (uint32_t)(i / spp);
-        k = (uint32_t)(i % spp);
+        // a valid i is below P * spp < 2^32; spp is the same for every lane
+        const uint32_t i32 = (uint32_t)i;
+        uint32_t q = i32;
+        if (spp != 1u) {
+            q = i32 / spp;
+            k = i32 - q * spp;
+        }
         p = perm ? perm[q] : q;
         float x[3] = {pos[3 * (size_t)p], pos[3 * (size_t)p + 1], pos[3 * (size_t)p + 2]};
         float nn[3] = {nrm[3 * (size_t)p], nrm[3 * (size_t)p + 1], nrm[3 * (size_t)p + 2]};

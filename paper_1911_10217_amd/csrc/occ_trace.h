@@ -34,6 +34,8 @@ namespace rlc {
 #define RLC_OCC_LIST 0x80000000u
 #define RLC_OCC_PAYLOAD 0x3FFFFFFFu
 #define RLC_OCC_SKIP_MAX 7u
+// Largest grid resolution (the walk's offsets are exact in FP32 up to it).
+#define RLC_OCC_RES_MAX 256u
 
 struct DevOcc {
     const float4* box;
@@ -201,13 +203,21 @@ struct WalkState {
     float t1;
     float tx, ty, tz, dtx, dty, dtz, itx, ity, itz;
     float rx, ry, rz;            // cells left before the grid's face, per axis (whole numbers)
-    int sx, sy, sz;              // byte steps of the header offset
-    uint32_t lin;                // byte offset of the current cell's header (< 2^32 for res <= 1024)
+    // byte offset of the current cell's header as a function of the counts
+    // above: lin0 + rx fx + ry fy + rz fz.  Every term and partial sum is a
+    // multiple of 4 below 4 res^3 <= 2^26 (res <= RLC_OCC_RES_MAX), so FP32
+    // holds them exactly and the fused multiply-adds are exact.
+    float lin0, fx, fy, fz;
     uint32_t osh;                // 3 x the segment's octant: shift of its radius in a header
     int it;                      // steps taken (a guard: the counts above already bound them)
     uint32_t last0, last1;
     uint32_t h;                  // header of the current cell, loaded one step ahead
 };
+
+// Byte offset of the current cell's header (see WalkState).
+RLC_WALK_INLINE uint32_t walk_offset(const WalkState& w) {
+    return (uint32_t)fmaf(w.rx, w.fx, fmaf(w.ry, w.fy, fmaf(w.rz, w.fz, w.lin0)));
+}
 
 // false: the segment misses the grid (nothing to test).
 RLC_WALK_INLINE bool walk_begin(const DevOcc& occ, const float o[3], const float d[3],
@@ -249,7 +259,15 @@ RLC_WALK_INLINE bool walk_begin(const DevOcc& occ, const float o[3], const float
         }
     }
     w.t1 = t1;
-    w.lin = 4u * (uint32_t)(c[0] + res * (c[1] + res * c[2]));
+    // cell coordinate c = (res - 1) - rem on an axis walked upwards, rem
+    // otherwise (a zero direction leaves rem at 0)
+    const int stride[3] = {4, 4 * res, 4 * res * res};
+    int lin0 = 0;
+    for (int a = 0; a < 3; ++a) lin0 += stride[a] * (c[a] + st[a] * rem[a]);
+    w.lin0 = (float)lin0;
+    w.fx = (float)(-st[0] * stride[0]);
+    w.fy = (float)(-st[1] * stride[1]);
+    w.fz = (float)(-st[2] * stride[2]);
     w.tx = tn[0];
     w.ty = tn[1];
     w.tz = tn[2];
@@ -262,14 +280,11 @@ RLC_WALK_INLINE bool walk_begin(const DevOcc& occ, const float o[3], const float
     w.rx = (float)rem[0];
     w.ry = (float)rem[1];
     w.rz = (float)rem[2];
-    w.sx = 4 * st[0];
-    w.sy = 4 * st[1] * res;
-    w.sz = 4 * st[2] * res * res;
     w.osh = 3u * ((d[0] < 0.0f ? 1u : 0u) | (d[1] < 0.0f ? 2u : 0u) | (d[2] < 0.0f ? 4u : 0u));
     w.it = 0;
     w.last0 = 0xFFFFFFFFu;
     w.last1 = 0xFFFFFFFFu;
-    w.h = *(const uint32_t*)((const char*)occ.head + w.lin);
+    w.h = *(const uint32_t*)((const char*)occ.head + walk_offset(w));
     return true;
 }
 
@@ -306,14 +321,6 @@ RLC_WALK_INLINE float walk_min(float a, float b) {
     return __builtin_amdgcn_fmed3f(a, b, -3.0e38f);
 #else
     return a < b ? a : b;
-#endif
-}
-
-RLC_WALK_INLINE int walk_mul24(int a, int b) {
-#if defined(__HIP_DEVICE_COMPILE__)
-    return __mul24(a, b);
-#else
-    return a * b;
 #endif
 }
 
@@ -356,15 +363,13 @@ RLC_WALK_INLINE int walk_step(const DevOcc& occ, WalkState& w, const float o[3],
     ++w.it;
     const bool ends = (tm > w.t1) | (rm <= r) | (w.it >= 3 * (int)occ.res + 3);
     if (!ends) {
-        const int kx = (int)fkx, ky = (int)fky, kz = (int)fkz;
-        w.lin += (uint32_t)(walk_mul24(kx, w.sx) + walk_mul24(ky, w.sy) + walk_mul24(kz, w.sz));
         w.tx = walk_advance<FAST>(w.tx, fkx, w.dtx);
         w.ty = walk_advance<FAST>(w.ty, fky, w.dty);
         w.tz = walk_advance<FAST>(w.tz, fkz, w.dtz);
         w.rx -= fkx;
         w.ry -= fky;
         w.rz -= fkz;
-        w.h = *(const uint32_t*)((const char*)occ.head + w.lin);
+        w.h = *(const uint32_t*)((const char*)occ.head + walk_offset(w));
     }
     if (occupied && cell_blocks<FAST>(occ, h, w.last0, w.last1, o, d, invd, t_lo)) return 1;
     return ends ? 2 : 0;

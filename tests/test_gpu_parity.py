@@ -393,7 +393,8 @@ def test_errors(torch):
         rlc.Context(dict(s.params, M=300))
     with pytest.raises(rlc.RLCError):
         rlc.Context(dict(s.params, split_steps=65537))
-    for bad in (dict(normal_bits=9), dict(jitter=1.5), dict(jitter=-0.1), dict(normal_bits=1, grid_dims=(1024, 1024, 1024), hashed=1, capacity=4096)):
+    for bad in (dict(normal_bits=9), dict(jitter=1.5), dict(jitter=-0.1), dict(normal_bits=1, grid_dims=(1024, 1024, 1024), hashed=1, capacity=4096),
+                dict(occ_grid_res=257)):
         with pytest.raises(rlc.RLCError):
             rlc.Context(dict(s.params, **bad))
     # hash table too small: reported at the next sync, samples still shaded
