@@ -732,8 +732,10 @@ def main():
                          "learned: the tiny scene, plain method against the MLP mixture at equal GPU time; "
                          "batched: 16 uneven scenes, per-scene launches against one batched graph launch")
     ap.add_argument("--mlp-epochs", type=int, default=1)
-    ap.add_argument("--mlp-batch", type=int, default=16384)
-    ap.add_argument("--mlp-lr", type=float, default=1e-2)
+    # 32,768 tuples per step give 256 training blocks, one per compute unit;
+    # the rate follows the square-root rule for Adam from 0.01 at 16,384
+    ap.add_argument("--mlp-batch", type=int, default=32768)
+    ap.add_argument("--mlp-lr", type=float, default=0.014)
     ap.add_argument("--budgets", default="32,128,512,2048",
                     help="learned: GPU-time budgets, as the plain method's time for this many passes")
     ap.add_argument("--split-steps", type=int, default=1,

@@ -599,28 +599,45 @@ __device__ __forceinline__ float column_sum(const float* partial, uint32_t p, ui
     return acc;
 }
 
-// The blocks' weight sums (and, with want_loss, loss sums) added in block
-// order by thread 0, after the block's threads have staged them in LDS.
-// Every thread must call it; thread 0 gets the sums.
-__device__ __forceinline__ void block_sums(const float* part_w, const float* part_loss, uint32_t nblocks,
-                                           bool want_loss, float* s_stage, float& sw, float& sl) {
+// The blocks' weight sums (and, with want_loss, loss sums), by the first
+// wave in a fixed order: lane l adds entries l, l + 64, l + 128, ... in
+// turn, then a butterfly across the lanes gives every lane the totals.  The
+// first kBlockSumPer entries of each lane are loaded by block_sums_begin,
+// which the caller issues before its other loads so that the latencies
+// overlap.
+constexpr uint32_t kBlockSumPer = 4;
+
+struct BlockSums {
+    float w[kBlockSumPer], l[kBlockSumPer];
+};
+
+__device__ __forceinline__ void block_sums_begin(const float* part_w, const float* part_loss, uint32_t nblocks,
+                                                 bool want_loss, BlockSums& b) {
+#pragma unroll
+    for (uint32_t k = 0; k < kBlockSumPer; ++k) {
+        const uint32_t i = threadIdx.x + 64u * k;
+        b.w[k] = i < nblocks ? part_w[i] : 0.0f;
+        b.l[k] = want_loss && i < nblocks ? part_loss[i] : 0.0f;
+    }
+}
+
+__device__ __forceinline__ void block_sums_end(const float* part_w, const float* part_loss, uint32_t nblocks,
+                                               bool want_loss, const BlockSums& b, float& sw, float& sl) {
     sw = 0.0f;
     sl = 0.0f;
-    for (uint32_t base = 0; base < nblocks; base += blockDim.x) {
-        const uint32_t i = base + threadIdx.x;
-        const uint32_t cnt = nblocks - base < blockDim.x ? nblocks - base : blockDim.x;
-        s_stage[threadIdx.x] = i < nblocks ? part_w[i] : 0.0f;
-        __syncthreads();
-        if (threadIdx.x == 0)
-            for (uint32_t j = 0; j < cnt; ++j) sw += s_stage[j];
-        __syncthreads();
-        if (want_loss) {
-            s_stage[threadIdx.x] = i < nblocks ? part_loss[i] : 0.0f;
-            __syncthreads();
-            if (threadIdx.x == 0)
-                for (uint32_t j = 0; j < cnt; ++j) sl += s_stage[j];
-            __syncthreads();
-        }
+#pragma unroll
+    for (uint32_t k = 0; k < kBlockSumPer; ++k) {
+        sw += b.w[k];
+        sl += b.l[k];
+    }
+    for (uint32_t i = threadIdx.x + 64u * kBlockSumPer; i < nblocks; i += 64u) {
+        sw += part_w[i];
+        if (want_loss) sl += part_loss[i];
+    }
+#pragma unroll
+    for (int off = 32; off >= 1; off >>= 1) {
+        sw += __shfl_xor(sw, off, 64);
+        sl += __shfl_xor(sl, off, 64);
     }
 }
 
@@ -640,11 +657,6 @@ __device__ __forceinline__ void adam_apply(uint32_t p, float gr, float w0, float
     write_frag(frag, p, np);
 }
 
-__device__ __forceinline__ void adam_update(uint32_t p, float gr, float* master, float* m, float* v, uint16_t* frag,
-                                            float lr, float beta1, float beta2, float eps, float c1, float c2) {
-    adam_apply(p, gr, master[p], m[p], v[p], master, m, v, frag, lr, beta1, beta2, eps, c1, c2);
-}
-
 // Sum of the blocks' partial rows, divided by the batch's sum of weights;
 // then either stored (mode 0) or applied by Adam (mode 1).  A block covers
 // 32 parameters with 8 row groups: group r sums rows r, r + 8, ... in order,
@@ -659,14 +671,24 @@ __global__ void __launch_bounds__(kBlock) k_mlp_reduce(const float* __restrict__
                                                        float beta1, float beta2, float eps, float c1, float c2,
                                                        float* __restrict__ loss) {
     __shared__ float s_part[kRedGroups][kRedCols];
-    __shared__ float s_stage[kBlock];
     __shared__ float s_inv;
     const uint32_t col = threadIdx.x % kRedCols, grp = threadIdx.x / kRedCols;
     const uint32_t p = blockIdx.x * kRedCols + col;
-    s_part[grp][col] = p < kNP ? column_sum(partial, p, grp, nblocks) : 0.0f;
     const bool want_loss = blockIdx.x == 0 && loss;
-    float sw, sl;
-    block_sums(part_w, part_loss, nblocks, want_loss, s_stage, sw, sl);
+    const bool sums = threadIdx.x < 64u;
+    BlockSums bs;
+    if (sums) block_sums_begin(part_w, part_loss, nblocks, want_loss, bs);
+    // the parameter's weight and moments, loaded ahead for Adam
+    const bool upd = grp == 0u && p < kNP && mode != 0u;
+    float w0 = 0.0f, m0 = 0.0f, v0 = 0.0f;
+    if (upd) {
+        w0 = master[p];
+        m0 = m[p];
+        v0 = v[p];
+    }
+    s_part[grp][col] = p < kNP ? column_sum(partial, p, grp, nblocks) : 0.0f;
+    float sw = 0.0f, sl = 0.0f;
+    if (sums) block_sums_end(part_w, part_loss, nblocks, want_loss, bs, sw, sl);
     if (threadIdx.x == 0) {
         const float inv = sw > 0.0f ? 1.0f / sw : 0.0f;
         s_inv = inv;
@@ -681,7 +703,7 @@ __global__ void __launch_bounds__(kBlock) k_mlp_reduce(const float* __restrict__
         out[p] = gr;
         return;
     }
-    adam_update(p, gr, master, m, v, frag, lr, beta1, beta2, eps, c1, c2);
+    adam_apply(p, gr, w0, m0, v0, master, m, v, frag, lr, beta1, beta2, eps, c1, c2);
 }
 
 __global__ void __launch_bounds__(kBlock) k_mlp_refresh(const float* __restrict__ master,
