@@ -516,16 +516,18 @@ __global__ void __launch_bounds__(kCellWaves * kWave, 8) k_adapt16(AdaptParams /
     __shared__ RowMap s_map;
     const uint32_t wave = threadIdx.x / kWave, lane = threadIdx.x % kWave;
     const AdaptLds L = lds_view(lds + wave * kCellRegion, kWave);
+    // each round's cell is loaded during the round before (a launch
+    // touches every cell once, so no round writes the next one's cell); the
+    // first round's row before the row map says whether it is in use (every
+    // row of the pool is allocated, and an unused row's data is not used)
+    CellIn<1> nxt;
+    const uint32_t li0 = blockIdx.x * kCellWaves + wave;
+    if (li0 < ap.cells.rows) load_cell<1>(ap, li0, nxt);
     if (wave == 0) row_map_build(ap.cells, s_map);
     __syncthreads();
     const uint32_t n_live = s_map.span;
     const uint32_t per_round = gridDim.x * kCellWaves;
     const uint32_t rounds = (n_live + per_round - 1u) / per_round;
-    // each round's cell is loaded during the round before (a launch
-    // touches every cell once, so no round writes the next one's cell)
-    CellIn<1> nxt;
-    const uint32_t li0 = blockIdx.x * kCellWaves + wave;
-    if (row_used(ap.cells, s_map, li0)) load_cell<1>(ap, li0, nxt);
     for (uint32_t rd = 0; rd < rounds; ++rd) {
         const uint32_t li = rd * per_round + li0;
         bool active = false;
