@@ -106,6 +106,9 @@ struct CellIn {
     uint32_t cnt[PER], node[PER], end[PER], tnode[PER], tend[PER];
     float q[PER];
     unsigned long long sum[PER];
+    // each slot's node record (children, split point, parent; a leaf: its
+    // parent alone), by load_cell_nodes
+    uint4 nrec[PER];
 };
 
 template <int PER>
@@ -128,6 +131,29 @@ __device__ __forceinline__ void load_cell(const AdaptParams& ap, uint32_t c, Cel
         in.sum[j] = cells.sum[i];
         in.tnode[j] = ap.tmpl.node[st];
         in.tend[j] = ap.tmpl.end[st];
+    }
+}
+
+// The node record of each slot's cluster, for the cut the pass starts from
+// (the stored one, or the initial cut for a fresh cell).  Issued once the
+// cell's row has arrived, ahead of the cell's work.  A node outside the tree
+// (only in a row that is not in use) reads nothing.
+template <int PER>
+__device__ __forceinline__ void load_cell_nodes(const AdaptParams& ap, CellIn<PER>& in) {
+    const uint32_t Meff = ap.tmpl.Meff;
+    const bool fresh = in.ready == 0u || ap.temporal == 0u;
+    const uint32_t n_nodes = 2u * ap.tree.N - 1u;
+#pragma unroll
+    for (int j = 0; j < PER; ++j) {
+        const uint32_t s = (threadIdx.x & (kWave - 1u)) + kWave * j;
+        in.nrec[j] = make_uint4(0u, 0u, 0u, RLC_NONE);
+        if (s < Meff) {
+            const uint32_t nd = fresh ? in.tnode[j] : in.node[j];
+            if (nd + 1u < ap.tree.N)
+                in.nrec[j] = ap.tree.inode[nd];
+            else if (nd < n_nodes)
+                in.nrec[j].w = ap.tree.parent[nd];
+        }
     }
 }
 
@@ -162,15 +188,10 @@ __device__ __forceinline__ bool adapt_front(const AdaptParams& ap, const CellIn<
             float q = fresh ? 0.0f : in.q[j];
             // the tree lookup the step needs for every cluster: its parent,
             // and for an internal node its children and split point
-            if (nd + 1u < ap.tree.N) {
-                const uint4 nr = ap.tree.inode[nd];
-                pre_l[j] = nr.x;
-                pre_r[j] = nr.y;
-                pre_sp[j] = nr.z;
-                L.par[s] = nr.w;
-            } else {
-                L.par[s] = ap.tree.parent[nd];
-            }
+            pre_l[j] = in.nrec[j].x;
+            pre_r[j] = in.nrec[j].y;
+            pre_sp[j] = in.nrec[j].z;
+            L.par[s] = in.nrec[j].w;
             L.end[s] = en;
             if (ap.temporal && in.cnt[j]) {
                 // Eq. 1 applied to the n samples of the pass at once
@@ -459,6 +480,7 @@ __device__ __forceinline__ void adapt_cells(const AdaptParams& ap, const AdaptLd
     if (li < span) {
         CellIn<PER> cur, nxt;
         load_cell<PER>(ap, li, cur);
+        load_cell_nodes<PER>(ap, cur);
         while (li < span) {
             const uint32_t ln = next_row(li + gridDim.x);
             if (PER == 1 && ln < span) load_cell<PER>(ap, ln, nxt);
@@ -468,6 +490,7 @@ __device__ __forceinline__ void adapt_cells(const AdaptParams& ap, const AdaptLd
                     cur = nxt;
                 else
                     load_cell<PER>(ap, ln, cur);
+                load_cell_nodes<PER>(ap, cur);
             }
             li = ln;
         }
@@ -525,6 +548,7 @@ __global__ void __launch_bounds__(kCellWaves * kWave, 8) k_adapt16(AdaptParams /
     if (li0 < ap.cells.rows) load_cell<1>(ap, li0, nxt);
     if (wave == 0) row_map_build(ap.cells, s_map);
     __syncthreads();
+    if (row_used(ap.cells, s_map, li0)) load_cell_nodes<1>(ap, nxt);
     const uint32_t n_live = s_map.span;
     const uint32_t per_round = gridDim.x * kCellWaves;
     const uint32_t rounds = (n_live + per_round - 1u) / per_round;
@@ -538,6 +562,8 @@ __global__ void __launch_bounds__(kCellWaves * kWave, 8) k_adapt16(AdaptParams /
             c = in.c;
             active = adapt_front<1>(ap, in, L);
         }
+        // the next round's node records, once its row has arrived
+        if (row_used(ap.cells, s_map, li + per_round)) load_cell_nodes<1>(ap, nxt);
         if (lane == 0) s_active[wave] = active ? 1u : 0u;
         __syncthreads();
         if (wave == 0 && lane < kCellWaves && s_active[lane])
