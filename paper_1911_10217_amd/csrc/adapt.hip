@@ -420,14 +420,6 @@ __device__ __forceinline__ void adapt_back(const AdaptParams& ap, uint32_t c, co
     wave_sync();
 }
 
-// The whole end of pass of one cell by one wavefront.
-template <int PER>
-__device__ __forceinline__ void adapt_cell(const AdaptParams& ap, const CellIn<PER>& in, const AdaptLds& L) {
-    if (!adapt_front<PER>(ap, in, L)) return;
-    adapt_eq2<PER>(ap, L);
-    adapt_back<PER>(ap, in.c, L);
-}
-
 // The rows in use: row k * stripes + s for k below stripe s's count.  They
 // lie in rows 0 .. span - 1 (span: the largest count times the stripes),
 // with a few unused rows where a stripe has fewer cells than the fullest.
@@ -484,13 +476,20 @@ __device__ __forceinline__ void adapt_cells(const AdaptParams& ap, const AdaptLd
         while (li < span) {
             const uint32_t ln = next_row(li + gridDim.x);
             if (PER == 1 && ln < span) load_cell<PER>(ap, ln, nxt);
-            adapt_cell<PER>(ap, cur, L);
+            const bool active = adapt_front<PER>(ap, cur, L);
+            // the next cell's node records, once its row has arrived
+            if (PER == 1 && ln < span) load_cell_nodes<PER>(ap, nxt);
+            if (active) {
+                adapt_eq2<PER>(ap, L);
+                adapt_back<PER>(ap, cur.c, L);
+            }
             if (ln < span) {
-                if (PER == 1)
+                if (PER == 1) {
                     cur = nxt;
-                else
+                } else {
                     load_cell<PER>(ap, ln, cur);
-                load_cell_nodes<PER>(ap, cur);
+                    load_cell_nodes<PER>(ap, cur);
+                }
             }
             li = ln;
         }
