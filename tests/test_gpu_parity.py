@@ -171,10 +171,11 @@ def test_visibility_parity_grid(torch, static_scene):
     assert np.array_equal(vis, ref), int((vis != ref).sum())
 
 
-@pytest.mark.parametrize("res", [16, 64, 100, 128])
+@pytest.mark.parametrize("res", [16, 64, 100, 128, 256])
 def test_visibility_parity_sparse_grid(torch, res):
     """Few small boxes in a fine grid: most cells are empty and the walk
-    leaves whole empty cubes at a time.  Segments run across the room and
+    leaves whole empty cubes at a time (256: the largest grid, where the
+    walk's FP32 header offsets reach 4 res^3 = 2^26).  Segments run across the room and
     to points just inside and just outside the boxes' faces."""
     import dataclasses
     rng = np.random.default_rng(20 + res)

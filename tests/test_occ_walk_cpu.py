@@ -98,7 +98,7 @@ def test_walk_subnormal_and_touching_cases(walker):
         assert np.array_equal(_walk(walker, box, res, X, Y), o.visible(X, Y))
 
 
-@pytest.mark.parametrize("res", [16, 64, 100])
+@pytest.mark.parametrize("res", [16, 64, 100, 256])
 def test_walk_skips_empty_cubes_sparse_boxes(walker, res):
     """Few small boxes in a fine grid, so that most cells carry a skip radius;
     segments end just inside or just outside box faces."""
