@@ -435,7 +435,7 @@ __device__ __forceinline__ void row_map_build(const DevCells& c, RowMap& m) {
     const uint32_t lane = threadIdx.x & (kWave - 1u);
     uint32_t v = 0;
     if (lane < c.stripes) {
-        const uint32_t n = c.n_live[lane];
+        const uint32_t n = c.n_live[lane * RLC_NLIVE_STRIDE];
         v = n < c.stripe_rows ? n : c.stripe_rows;
         m.used[lane] = v;
     }

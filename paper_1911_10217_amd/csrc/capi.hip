@@ -201,7 +201,7 @@ int reset_cells(rlc_ctx* c) {
     RLC_HIP(c, launch_fill_u32(d.ready, 0u, d.rows, c->stream));
     RLC_HIP(c, launch_fill_u64(d.sum, 0ull, bins, c->stream));
     RLC_HIP(c, launch_fill_u32(d.cnt, 0u, bins, c->stream));
-    RLC_HIP(c, launch_fill_u32(d.n_live, 0u, d.stripes, c->stream));
+    RLC_HIP(c, launch_fill_u32(d.n_live, 0u, d.stripes * RLC_NLIVE_STRIDE, c->stream));
     return RLC_OK;
 }
 
@@ -571,7 +571,7 @@ int rlc_create(const rlc_config* cfg, void* stream, rlc_ctx** out) {
     if (r == RLC_OK) r = dalloc(c, &d.sum, bins);
     if (r == RLC_OK) r = dalloc(c, &d.cnt, bins);
     if (r == RLC_OK) r = dalloc(c, &d.live, pool);
-    if (r == RLC_OK) r = dalloc(c, &d.n_live, RLC_ROW_STRIPES_MAX);
+    if (r == RLC_OK) r = dalloc(c, &d.n_live, RLC_ROW_STRIPES_MAX * RLC_NLIVE_STRIDE);
     if (r == RLC_OK) r = dalloc(c, &c->d_err, 1);
     if (r == RLC_OK) r = dalloc(c, &c->d_partial, 6 * 1024);
     if (r == RLC_OK) r = reset_cells(c);
@@ -972,12 +972,12 @@ int rlc_sync(rlc_ctx* c) {
 // once the stripe is full: the refused creations count too).
 int rows_in_use(rlc_ctx* c, std::vector<uint32_t>* rows_out, uint32_t* h_n) {
     const DevCells& d = c->cells;
-    uint32_t cnt[RLC_ROW_STRIPES_MAX] = {0};
-    RLC_HIP(c, hipMemcpyAsync(cnt, d.n_live, sizeof(uint32_t) * d.stripes, hipMemcpyDeviceToHost, c->stream));
+    std::vector<uint32_t> cnt((size_t)d.stripes * RLC_NLIVE_STRIDE);
+    RLC_HIP(c, hipMemcpyAsync(cnt.data(), d.n_live, sizeof(uint32_t) * cnt.size(), hipMemcpyDeviceToHost, c->stream));
     RLC_HIP(c, hipStreamSynchronize(c->stream));
     uint32_t n = 0;
     for (uint32_t s = 0; s < d.stripes; ++s) {
-        const uint32_t used = std::min(cnt[s], d.stripe_rows);
+        const uint32_t used = std::min(cnt[(size_t)s * RLC_NLIVE_STRIDE], d.stripe_rows);
         if (rows_out)
             for (uint32_t k = 0; k < used; ++k) rows_out->push_back(k * d.stripes + s);
         n += used;

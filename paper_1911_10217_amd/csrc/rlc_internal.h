@@ -66,7 +66,7 @@ struct DevCells {
     unsigned long long* sum;    // fixed-point reward sums of the pass
     uint32_t* cnt;              // sample counts of the pass
     uint32_t* live;             // per row: its lookup slot
-    uint32_t* n_live;           // per stripe: rows taken (passes stripe_rows once the stripe is full)
+    uint32_t* n_live;           // per stripe, RLC_NLIVE_STRIDE words apart: rows taken (passes stripe_rows once full)
     uint32_t capacity;          // lookup slots: dense, cells of the grid; hashed, 2^k
     uint32_t rows;              // rows in the pool
     uint32_t stripes;           // stripes of the pool, a power of two up to RLC_ROW_STRIPES_MAX
@@ -75,6 +75,10 @@ struct DevCells {
     uint32_t M;                 // row stride
 };
 #define RLC_ROW_STRIPES_MAX 64u
+// Words between two stripes' row counters: each counter in a 256-byte
+// block of its own, so that the atomics of different stripes do not queue on
+// one cache line.
+#define RLC_NLIVE_STRIDE 64u
 
 struct FrameParams {
     DevTree tree;
@@ -350,7 +354,7 @@ __device__ __forceinline__ uint32_t create_at(const DevCells& c, uint32_t h, uin
             const unsigned long long old = atomicCAS(&c.keys[h], RLC_EMPTY_KEY, slot_word(RLC_ROW_PENDING, lin));
             if (old == RLC_EMPTY_KEY) {
                 const uint32_t st = h & (c.stripes - 1u);
-                const uint32_t k = atomicAdd(&c.n_live[st], 1u);
+                const uint32_t k = atomicAdd(&c.n_live[st * RLC_NLIVE_STRIDE], 1u);
                 if (k < c.stripe_rows) {
                     r = k * c.stripes + st;
                     c.live[r] = h;
