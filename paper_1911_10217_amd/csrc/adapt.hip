@@ -572,6 +572,136 @@ __global__ void __launch_bounds__(kCellWaves * kWave, 8) k_adapt16(AdaptParams /
     }
 }
 
+// The end of pass of a batch's cells (up to kBatchScenes16 scenes), 16 per
+// block as in k_adapt16, over one index space of all scenes' rows in use:
+// entry j is scene sc's entry j - off[sc], and a scene's entries run
+// through its stripes in turn (stripe s's rows k * stripes + s, k below its
+// count).  Every block stages the scenes' per-stripe prefix sums in LDS;
+// each wave maps its next cell's entry during the current round.  A round's
+// 16 cells may belong to different scenes, so each wave reads its own
+// scene's parameters, and in the serial phase each lane its cell's scene's.
+// The same arithmetic as k_adapt16, cell for cell.
+constexpr uint32_t kBatchScenes16 = 16;
+
+__global__ void __launch_bounds__(kCellWaves * kWave, 8) k_batch_adapt16(const AdaptParams* __restrict__ aps,
+                                                                        uint32_t n_scenes) {
+    extern __shared__ uint32_t lds[];
+    __shared__ uint32_t s_active[kCellWaves];
+    __shared__ uint32_t s_scene[kCellWaves];
+    // per scene: the rows in use before each stripe, and the total at [64]
+    __shared__ uint32_t s_pref[kBatchScenes16][RLC_ROW_STRIPES_MAX + 1];
+    __shared__ uint32_t s_off[kBatchScenes16 + 1];
+    typedef const __attribute__((address_space(4))) AdaptParams* ConstAdaptParams;
+    const uint32_t wave = threadIdx.x / kWave, lane = threadIdx.x % kWave;
+    const AdaptLds L = lds_view(lds + wave * kCellRegion, kWave);
+    auto params = [&](uint32_t sc) -> const AdaptParams& {
+        return opaque_const((ConstAdaptParams)uniform_u64((uint64_t)&aps[sc]));
+    };
+    if (wave < n_scenes) {
+        // wave w: scene w's counts, scanned across the lanes (lane = stripe)
+        const DevCells& c = params(wave).cells;
+        uint32_t v = 0;
+        if (lane < c.stripes) {
+            const uint32_t nl = c.n_live[lane * RLC_NLIVE_STRIDE];
+            v = nl < c.stripe_rows ? nl : c.stripe_rows;
+        }
+#pragma unroll
+        for (int off = 1; off < (int)kWave; off <<= 1) {
+            const uint32_t t = (uint32_t)__shfl_up((int)v, off, kWave);
+            if (lane >= (uint32_t)off) v += t;
+        }
+        s_pref[wave][lane + 1u] = v;
+        if (lane == 0) s_pref[wave][0] = 0u;
+    }
+    __syncthreads();
+    if (wave == 0) {
+        uint32_t v = lane < n_scenes ? s_pref[lane][RLC_ROW_STRIPES_MAX] : 0u;
+#pragma unroll
+        for (int off = 1; off < (int)kBatchScenes16; off <<= 1) {
+            const uint32_t t = (uint32_t)__shfl_up((int)v, off, kWave);
+            if (lane >= (uint32_t)off) v += t;
+        }
+        if (lane < kBatchScenes16) s_off[lane + 1u] = v;
+        if (lane == 0) s_off[0] = 0u;
+    }
+    __syncthreads();
+    const uint32_t n = s_off[n_scenes];
+    // entry j -> (scene, row) by two binary searches in LDS (the last scene,
+    // then the last stripe, whose offset is at most j: empty ones are
+    // passed over); j is the same for every lane of the wave
+    auto locate = [&](uint32_t j, uint32_t& sc, uint32_t& row) {
+        uint32_t lo = 0, hi = n_scenes - 1u;
+        while (lo < hi) {
+            const uint32_t mid = (lo + hi + 1u) >> 1;
+            if (s_off[mid] <= j)
+                lo = mid;
+            else
+                hi = mid - 1u;
+        }
+        sc = lo;
+        const uint32_t jj = j - s_off[sc];
+        lo = 0;
+        hi = RLC_ROW_STRIPES_MAX - 1u;
+        while (lo < hi) {
+            const uint32_t mid = (lo + hi + 1u) >> 1;
+            if (s_pref[sc][mid] <= jj)
+                lo = mid;
+            else
+                hi = mid - 1u;
+        }
+        row = (jj - s_pref[sc][lo]) * params(sc).cells.stripes + lo;
+    };
+    const uint32_t per_round = gridDim.x * kCellWaves;
+    const uint32_t rounds = (n + per_round - 1u) / per_round;
+    const uint32_t li0 = blockIdx.x * kCellWaves + wave;
+    // each round's cell is loaded during the round before, as in k_adapt16,
+    // and the entry after it located in the round before that, while the
+    // block waits for the serial sums
+    CellIn<1> nxt;
+    uint32_t sc_nxt = 0, sc_far = 0, row_far = 0;
+    if (li0 < n) {
+        uint32_t row;
+        locate(li0, sc_nxt, row);
+        load_cell<1>(params(sc_nxt), row, nxt);
+        load_cell_nodes<1>(params(sc_nxt), nxt);
+    }
+    if (li0 + per_round < n) locate(li0 + per_round, sc_far, row_far);
+    for (uint32_t rd = 0; rd < rounds; ++rd) {
+        const uint32_t li = rd * per_round + li0;
+        const uint32_t ln = li + per_round, lf = ln + per_round;
+        bool active = false;
+        uint32_t c = 0;
+        const CellIn<1> in = nxt;
+        const uint32_t sc = sc_nxt;
+        if (ln < n) {
+            sc_nxt = sc_far;
+            load_cell<1>(params(sc_nxt), row_far, nxt);
+        }
+        if (li < n) {
+            c = in.c;
+            active = adapt_front<1>(params(sc), in, L);
+        }
+        // the next round's node records, once its row has arrived
+        if (ln < n) load_cell_nodes<1>(params(sc_nxt), nxt);
+        if (lane == 0) {
+            s_active[wave] = active ? 1u : 0u;
+            s_scene[wave] = sc;
+        }
+        __syncthreads();
+        if (wave == 0) {
+            if (lane < kCellWaves && s_active[lane]) {
+                const AdaptParams& apl = aps[s_scene[lane]];
+                eq2_one_lane(apl, lds_view(lds + lane * kCellRegion, kWave), apl.tmpl.Meff);
+            }
+        } else if (lf < n) {
+            locate(lf, sc_far, row_far);
+        }
+        __syncthreads();
+        if (wave == 0 && lf < n) locate(lf, sc_far, row_far);
+        if (active) adapt_back<1>(params(sc), c, L);
+    }
+}
+
 // Checkpoint load: one wavefront per cell.  The cell is found (or created)
 // by its key, its cut and Q are taken as given, the ends follow from the
 // tree, Q~ and C from Eq. 2 as at the end of a pass, and the write-back
@@ -627,6 +757,13 @@ __global__ void k_gather_cells(DevCells c, uint32_t Meff, const uint32_t* __rest
 }
 
 }  // namespace
+
+hipError_t launch_batch_adapt16(const AdaptParams* aps, uint32_t n_scenes, hipStream_t s) {
+    if (n_scenes == 0 || n_scenes > kBatchScenes16) return hipErrorInvalidValue;
+    hipLaunchKernelGGL(k_batch_adapt16, dim3(512), dim3(kCellWaves * kWave), kCellWaves * kCellRegion * 4, s, aps,
+                       n_scenes);
+    return hipGetLastError();
+}
 
 hipError_t launch_batch_adapt(const AdaptParams* aps, uint32_t n_scenes, uint32_t Meff, hipStream_t s) {
     if (Meff <= (uint32_t)kWave)

@@ -1552,9 +1552,18 @@ int batch_capture(rlc_batch* b) {
     if (e == hipSuccess)
         e = launch_batch_frame(b->d_scenes, (uint32_t)b->scenes.size(), b->total_items, rounds, b->sched.dynamic,
                                grid, b->d_counter, b->d_frame, b->stream);
-    uint32_t meff_max = 1;
-    for (const auto& sc : b->scenes) meff_max = std::max(meff_max, sc.ctx->Meff);
-    if (e == hipSuccess) e = launch_batch_adapt(b->d_adapt, (uint32_t)b->scenes.size(), meff_max, b->stream);
+    uint32_t meff_max = 1, steps_max = 0;
+    for (const auto& sc : b->scenes) {
+        meff_max = std::max(meff_max, sc.ctx->Meff);
+        steps_max = std::max(steps_max, sc.ctx->cfg.split_steps);
+    }
+    // up to 16 scenes whose cuts have up to 64 clusters, one split-collapse
+    // step: 16 cells per block over all scenes' rows in use (as k_adapt16
+    // does for one scene); otherwise one wave per cell, scene after scene
+    if (e == hipSuccess && meff_max <= 64u && steps_max <= 1u && b->scenes.size() <= 16u)
+        e = launch_batch_adapt16(b->d_adapt, (uint32_t)b->scenes.size(), b->stream);
+    else if (e == hipSuccess)
+        e = launch_batch_adapt(b->d_adapt, (uint32_t)b->scenes.size(), meff_max, b->stream);
     if (e == hipSuccess) e = launch_batch_end(b->d_frame, b->stream);
     hipGraph_t g = nullptr;
     hipError_t e2 = hipStreamEndCapture(b->stream, &g);

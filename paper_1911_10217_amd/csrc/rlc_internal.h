@@ -730,6 +730,9 @@ hipError_t launch_batch_frame(const BatchScene* scenes, uint32_t n_scenes, uint3
 hipError_t launch_adapt(const AdaptParams& ap, hipStream_t s);
 // Meff: the largest cut size of the batch's scenes.
 hipError_t launch_batch_adapt(const AdaptParams* aps, uint32_t n_scenes, uint32_t Meff, hipStream_t s);
+// The batch's cells with cuts of up to 64 clusters and one split-collapse
+// step, 16 cells per block over all scenes' rows in use (1 to 16 scenes).
+hipError_t launch_batch_adapt16(const AdaptParams* aps, uint32_t n_scenes, hipStream_t s);
 // Checkpoint load of n cells (keys, cuts and Q of Meff entries each).
 hipError_t launch_load_cells(const AdaptParams& ap, const unsigned long long* keys, const uint32_t* node,
                              const float* Q, uint32_t n, uint32_t* err, hipStream_t s);
