@@ -58,6 +58,7 @@ struct rlc_ctx {
     uint32_t N = 0, Meff = 0;
     float4* rec = nullptr;
     uint32_t* perm = nullptr;
+    uint32_t* rank = nullptr;  // sorted position of each input light
     uint32_t* morton = nullptr;
     uint32_t* left = nullptr;
     uint32_t* right = nullptr;
@@ -208,6 +209,7 @@ int reset_cells(rlc_ctx* c) {
 void free_tree(rlc_ctx* c) {
     dfree(c->rec);
     dfree(c->perm);
+    dfree(c->rank);
     dfree(c->morton);
     dfree(c->left);
     dfree(c->right);
@@ -630,6 +632,7 @@ int rlc_build_light_tree(rlc_ctx* c, const float* d_tri, const float* d_emit, ui
     const uint32_t M = c->cfg.M;
     RLC_TRY(dalloc(c, &c->rec, 4 * (size_t)N));
     RLC_TRY(dalloc(c, &c->perm, N));
+    RLC_TRY(dalloc(c, &c->rank, N));
     RLC_TRY(dalloc(c, &c->morton, N));
     RLC_TRY(dalloc(c, &c->left, N > 1 ? N - 1 : 1));
     RLC_TRY(dalloc(c, &c->right, N > 1 ? N - 1 : 1));
@@ -672,6 +675,7 @@ int rlc_build_light_tree(rlc_ctx* c, const float* d_tri, const float* d_emit, ui
         step(launch_morton(sums, bbox, N, c->morton, c->perm, c->stream));
         step(radix_sort_pairs(c->morton, c->perm, ktmp, vtmp, hist, N, 30, c->stream));
         step(launch_gather_records(d_tri, d_emit, c->perm, N, c->rec, c->stream));
+        step(launch_invert_perm(c->perm, N, c->rank, c->stream));
         step(launch_radix_tree(c->morton, c->perm, N, c->left, c->right, c->parent, c->first, c->last, c->inode,
                                c->stream));
         c->N = N;
@@ -705,7 +709,7 @@ int rlc_set_emission(rlc_ctx* c, const float* d_emit, uint32_t N) {
     RLC_TRY(need_tree(c));
     if (!d_emit) return fail(c, RLC_EINVAL, "null emission array");
     if (N != c->N) return fail(c, RLC_EINVAL, "emission for %u lights, tree has %u", N, c->N);
-    RLC_HIP(c, launch_scatter_emission(d_emit, c->perm, N, c->rec, c->stream));
+    RLC_HIP(c, launch_scatter_emission(d_emit, c->rank, N, c->rec, c->stream));
     return RLC_OK;
 }
 

@@ -679,7 +679,8 @@ size_t scan_scratch_entries(size_t n);
 hipError_t launch_exclusive_scan(uint32_t* data, uint32_t n, uint32_t* scratch, hipStream_t s);
 hipError_t launch_gather_records(const float* tri, const float* emit, const uint32_t* perm, uint32_t N,
                                  float4* rec, hipStream_t s);
-hipError_t launch_scatter_emission(const float* emit, const uint32_t* perm, uint32_t N, float4* rec,
+hipError_t launch_invert_perm(const uint32_t* perm, uint32_t N, uint32_t* rank, hipStream_t s);
+hipError_t launch_scatter_emission(const float* emit, const uint32_t* rank, uint32_t N, float4* rec,
                                    hipStream_t s);
 hipError_t launch_radix_tree(const uint32_t* morton, const uint32_t* perm, uint32_t N, uint32_t* left,
                              uint32_t* right, uint32_t* parent, uint32_t* first, uint32_t* last, uint32_t* inode,

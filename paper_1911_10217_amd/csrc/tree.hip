@@ -267,17 +267,26 @@ __global__ void __launch_bounds__(kBlock) k_gather_records(const float* __restri
     rec[4 * j + 3] = make_float4(area, nx, ny, nz);
 }
 
+// rank[perm[j]] = j: the sorted position of each input light.
+__global__ void __launch_bounds__(kBlock) k_invert_perm(const uint32_t* __restrict__ perm, uint32_t N,
+                                                        uint32_t* __restrict__ rank) {
+    const size_t j = (size_t)blockIdx.x * kBlock + threadIdx.x;
+    if (j < N) rank[perm[j]] = (uint32_t)j;
+}
+
+// New emission of every light: input light i (read in input order, so the
+// loads are coalesced and independent) into its record at sorted position
+// rank[i] (one 12-byte store per light).
 __global__ void __launch_bounds__(kBlock) k_scatter_emission(const float* __restrict__ emit,
-                                                             const uint32_t* __restrict__ perm, uint32_t N,
+                                                             const uint32_t* __restrict__ rank, uint32_t N,
                                                              float4* __restrict__ rec) {
-    size_t j = (size_t)blockIdx.x * kBlock + threadIdx.x;
-    if (j >= N) return;
-    size_t i = perm[j];
-    float4 r = rec[4 * j + 2];
-    r.y = emit[3 * i];
-    r.z = emit[3 * i + 1];
-    r.w = emit[3 * i + 2];
-    rec[4 * j + 2] = r;
+    const size_t i = (size_t)blockIdx.x * kBlock + threadIdx.x;
+    if (i >= N) return;
+    const size_t j = rank[i];
+    float* r = reinterpret_cast<float*>(rec + 4 * j + 2);
+    r[1] = emit[3 * i];
+    r[2] = emit[3 * i + 1];
+    r[3] = emit[3 * i + 2];
 }
 
 // 64-bit key of sorted position j: (Morton << 32) | input index, all distinct
@@ -487,9 +496,14 @@ hipError_t launch_gather_records(const float* tri, const float* emit, const uint
     return hipGetLastError();
 }
 
-hipError_t launch_scatter_emission(const float* emit, const uint32_t* perm, uint32_t N, float4* rec,
+hipError_t launch_invert_perm(const uint32_t* perm, uint32_t N, uint32_t* rank, hipStream_t s) {
+    hipLaunchKernelGGL(k_invert_perm, dim3(blocks_for(N)), dim3(kBlock), 0, s, perm, N, rank);
+    return hipGetLastError();
+}
+
+hipError_t launch_scatter_emission(const float* emit, const uint32_t* rank, uint32_t N, float4* rec,
                                    hipStream_t s) {
-    hipLaunchKernelGGL(k_scatter_emission, dim3(blocks_for(N)), dim3(kBlock), 0, s, emit, perm, N, rec);
+    hipLaunchKernelGGL(k_scatter_emission, dim3(blocks_for(N)), dim3(kBlock), 0, s, emit, rank, N, rec);
     return hipGetLastError();
 }
 
