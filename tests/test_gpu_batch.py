@@ -132,6 +132,39 @@ def test_batch_frames_out_of_order_and_emission_changes(torch):
         batch.close()
 
 
+@pytest.mark.parametrize("n_scenes", [16, 17])
+def test_batch_of_many_small_scenes(torch, n_scenes):
+    """Batches at the edge of the 16-cell end-of-pass kernel (cells of up to
+    16 scenes over one index space; cuts of 16, 32 and 64 clusters side by
+    side, so the serial phase's lanes run cuts of different lengths; row
+    pools of one stripe and of eight) and one scene past it, which takes the
+    one-wave kernel scene after scene; one scene has few points and seven
+    lights.  Every scene equals the oracle after every pass."""
+    from paper_1911_10217_amd import rlc
+    sc = []
+    for i in range(n_scenes):
+        M = (16, 32, 64)[i % 3]
+        n_lights = 7 if i == 5 else 200 + 37 * i
+        sc.append(scenes.make_tiny(n_lights=n_lights, n_points=64 if i == 5 else 400 + 50 * i, n_boxes=8, M=M,
+                                   spp=1, seed=scenes.SEED_BASE + 100 + i, scene_id=i, hashed=1,
+                                   capacity=8192 if i % 2 == 0 else 1024, max_cells=8192 if i % 2 == 0 else 512))
+    st = torch.cuda.Stream()
+    with torch.cuda.stream(st):
+        a = [_ctx(torch, s) for s in sc]
+        orcs = [oracle.Oracle(s.params, s.tri, s.emit, s.boxes) for s in sc]
+        batch = rlc.Batch([(c, p, n, 1) for c, p, n in a], st)
+        for f in range(3):
+            rads = batch.rlc_batch_frame(f)
+            for i, (s, o) in enumerate(zip(sc, orcs)):
+                ref, _ = o.frame(s.pos, s.nrm, 1, f)
+                o.adapt()
+                assert np.array_equal(rads[i].cpu().numpy(), ref), (n_scenes, f, i)
+                _assert_cells(a[i][0].rlc_dump_cells(), o.cells(), (n_scenes, f, i))
+        batch.close()
+        for c, _, _ in a:
+            c.close()
+
+
 def test_batch_recaptures_after_rebuilds_and_guards_destroy(torch):
     """Rebuilding a scene's occluders or light tree frees the buffers the
     captured graph points at: the next batch pass captures again from the
