@@ -521,6 +521,101 @@ __global__ void __launch_bounds__(kWave, PER == 1 ? 8 : 4) k_batch_adapt(const A
     }
 }
 
+// The fused kernel's blocks for the next pass, longest first: a counting
+// sort of the n blocks' recorded durations into kOrderBuckets equal ranges
+// between the shortest and the longest, by one workgroup of kOrderThreads
+// threads (blocks in one range in no particular order).  Each wave counts
+// into its own histogram, so the LDS atomics of a range queue only within a
+// wave.  s: kOrderLds words of LDS.
+constexpr uint32_t kOrderBuckets = 256;
+constexpr uint32_t kOrderThreads = 1024;
+constexpr uint32_t kOrderWaves = kOrderThreads / kWave;
+constexpr uint32_t kOrderLds = (kOrderWaves + 1u) * kOrderBuckets + 2u;
+
+__device__ __forceinline__ uint32_t order_key(uint32_t c, uint32_t lo, unsigned long long range) {
+    return kOrderBuckets - 1u - (uint32_t)(((unsigned long long)(c - lo) * kOrderBuckets) / range);
+}
+
+__device__ __forceinline__ void block_order(const uint32_t* __restrict__ cost, uint32_t* __restrict__ order,
+                                            uint32_t n, uint32_t* s) {
+    const uint32_t t = threadIdx.x, lane = t % kWave, wave = t / kWave;
+    uint32_t* hist = s;                                  // [wave][bucket]
+    uint32_t* tot = s + kOrderWaves * kOrderBuckets;     // per bucket: count, then first position
+    uint32_t* ext = tot + kOrderBuckets;                 // [0] shortest, [1] longest
+    for (uint32_t j = t; j < kOrderWaves * kOrderBuckets; j += kOrderThreads) hist[j] = 0u;
+    if (t == 0) {
+        ext[0] = 0xFFFFFFFFu;
+        ext[1] = 0u;
+    }
+    __syncthreads();
+    uint32_t lo = 0xFFFFFFFFu, hi = 0u;
+    for (uint32_t i = t; i < n; i += kOrderThreads) {
+        const uint32_t c = cost[i];
+        lo = c < lo ? c : lo;
+        hi = c > hi ? c : hi;
+    }
+#pragma unroll
+    for (int off = 1; off < (int)kWave; off <<= 1) {
+        const uint32_t a = (uint32_t)__shfl_xor((int)lo, off, kWave), b = (uint32_t)__shfl_xor((int)hi, off, kWave);
+        lo = a < lo ? a : lo;
+        hi = b > hi ? b : hi;
+    }
+    if (lane == 0) {
+        atomicMin(&ext[0], lo);
+        atomicMax(&ext[1], hi);
+    }
+    __syncthreads();
+    lo = ext[0];
+    const unsigned long long range = (unsigned long long)(ext[1] - lo) + 1ull;
+    uint32_t* mine = hist + wave * kOrderBuckets;
+    for (uint32_t i = t; i < n; i += kOrderThreads) atomicAdd(&mine[order_key(cost[i], lo, range)], 1u);
+    __syncthreads();
+    // per bucket: each wave's count becomes the count of the waves before it
+    if (t < kOrderBuckets) {
+        uint32_t run = 0;
+        for (uint32_t w = 0; w < kOrderWaves; ++w) {
+            const uint32_t v = hist[w * kOrderBuckets + t];
+            hist[w * kOrderBuckets + t] = run;
+            run += v;
+        }
+        tot[t] = run;
+    }
+    __syncthreads();
+    if (t < kWave) {
+        // exclusive scan of the buckets' counts, four buckets per lane
+        constexpr uint32_t kPer = kOrderBuckets / kWave;
+        uint32_t v[kPer], sum = 0;
+#pragma unroll
+        for (uint32_t k = 0; k < kPer; ++k) {
+            v[k] = tot[t * kPer + k];
+            sum += v[k];
+        }
+        uint32_t incl = sum;
+#pragma unroll
+        for (int off = 1; off < (int)kWave; off <<= 1) {
+            const uint32_t u = (uint32_t)__shfl_up((int)incl, off, kWave);
+            if (t >= (uint32_t)off) incl += u;
+        }
+        uint32_t at = incl - sum;
+#pragma unroll
+        for (uint32_t k = 0; k < kPer; ++k) {
+            tot[t * kPer + k] = at;
+            at += v[k];
+        }
+    }
+    __syncthreads();
+    if (t < kOrderBuckets)
+        for (uint32_t w = 0; w < kOrderWaves; ++w) hist[w * kOrderBuckets + t] += tot[t];
+    __syncthreads();
+    for (uint32_t i = t; i < n; i += kOrderThreads) order[atomicAdd(&mine[order_key(cost[i], lo, range)], 1u)] = i;
+}
+
+__global__ void __launch_bounds__(kOrderThreads) k_block_order(const uint32_t* __restrict__ cost,
+                                                               uint32_t* __restrict__ order, uint32_t n) {
+    __shared__ uint32_t s[kOrderLds];
+    block_order(cost, order, n, s);
+}
+
 // Cuts of up to 64 clusters, 16 cells per block: one wavefront per cell
 // for Eq. 1, split-collapse and the write-back, and, between two block
 // barriers, one lane per cell for the serial sums of Eq. 2, so those sums
@@ -530,12 +625,27 @@ constexpr uint32_t kCellWaves = 16;
 // words of one wave's scratch, padded by one so that the serial phase's 16
 // lanes, each in its own cell's scratch, read different LDS banks
 constexpr uint32_t kCellRegion = kLdsArrays * kWave + 1u;
+// blocks of the 16-cell kernels (the chip holds them all at once: two per
+// compute unit)
+constexpr uint32_t kAdaptBlocks = 512;
+static_assert(kCellWaves * kWave == kOrderThreads, "the ordering block is one of the 16-cell kernel's");
+static_assert(kCellWaves * kCellRegion >= kOrderLds, "LDS for the ordering block");
 
+// With ap.blk_n > 0 the first block orders the fused kernel's blocks for the
+// next pass, beside the cells' work (it is dispatched first, and the launch
+// fits the chip at once, so it does not wait for a free compute unit), and
+// the others take the cells.
 __global__ void __launch_bounds__(kCellWaves * kWave, 8) k_adapt16(AdaptParams /* read in place */) {
     const AdaptParams& ap = first_kernel_arg<AdaptParams>();
     extern __shared__ uint32_t lds[];
     __shared__ uint32_t s_active[kCellWaves];
     __shared__ RowMap s_map;
+    const uint32_t first = ap.blk_n > 0u && ap.blk_n <= RLC_ORDER_MAX_BLOCKS ? 1u : 0u;
+    if (blockIdx.x < first) {
+        block_order(ap.blk_cost, ap.blk_order, ap.blk_n, lds);
+        return;
+    }
+    const uint32_t blk = blockIdx.x - first, n_blk = kAdaptBlocks - first;
     const uint32_t wave = threadIdx.x / kWave, lane = threadIdx.x % kWave;
     const AdaptLds L = lds_view(lds + wave * kCellRegion, kWave);
     // each round's cell is loaded during the round before (a launch
@@ -543,13 +653,13 @@ __global__ void __launch_bounds__(kCellWaves * kWave, 8) k_adapt16(AdaptParams /
     // first round's row before the row map says whether it is in use (every
     // row of the pool is allocated, and an unused row's data is not used)
     CellIn<1> nxt;
-    const uint32_t li0 = blockIdx.x * kCellWaves + wave;
+    const uint32_t li0 = blk * kCellWaves + wave;
     if (li0 < ap.cells.rows) load_cell<1>(ap, li0, nxt);
     if (wave == 0) row_map_build(ap.cells, s_map);
     __syncthreads();
     if (row_used(ap.cells, s_map, li0)) load_cell_nodes<1>(ap, nxt);
     const uint32_t n_live = s_map.span;
-    const uint32_t per_round = gridDim.x * kCellWaves;
+    const uint32_t per_round = n_blk * kCellWaves;
     const uint32_t rounds = (n_live + per_round - 1u) / per_round;
     for (uint32_t rd = 0; rd < rounds; ++rd) {
         const uint32_t li = rd * per_round + li0;
@@ -780,9 +890,15 @@ hipError_t launch_adapt(const AdaptParams& ap, hipStream_t s) {
     // split-collapse steps the cells of a 16-cell block take different
     // numbers of steps and the block waits for its slowest, so those passes
     // take the one-wave kernel.
-    if (ap.tmpl.Meff <= (uint32_t)kWave && ap.split_steps <= 1u)
-        hipLaunchKernelGGL(k_adapt16, dim3(512), dim3(kCellWaves * kWave), kCellWaves * kCellRegion * 4, s, ap);
-    else if (ap.tmpl.Meff <= (uint32_t)kWave)
+    const bool order = ap.blk_n > 0u && ap.blk_n <= RLC_ORDER_MAX_BLOCKS;
+    if (ap.tmpl.Meff <= (uint32_t)kWave && ap.split_steps <= 1u) {
+        // the ordering block rides along with the cells' blocks
+        hipLaunchKernelGGL(k_adapt16, dim3(kAdaptBlocks), dim3(kCellWaves * kWave), kCellWaves * kCellRegion * 4, s,
+                           ap);
+        return hipGetLastError();
+    }
+    if (order) hipLaunchKernelGGL(k_block_order, dim3(1), dim3(kOrderThreads), 0, s, ap.blk_cost, ap.blk_order, ap.blk_n);
+    if (ap.tmpl.Meff <= (uint32_t)kWave)
         hipLaunchKernelGGL(k_adapt<1>, dim3(8192), dim3(kWave), kLdsArrays * kWave * 4, s, ap);
     else
         hipLaunchKernelGGL(k_adapt<kMaxPerLane>, dim3(8192), dim3(kWave), kLdsArrays * RLC_MMAX * 4, s, ap);

@@ -85,6 +85,13 @@ struct rlc_ctx {
     // the same for rlc_frame_sub_noalloc: this device's scratch array
     float* noalloc_scratch = nullptr;
 
+    // fused-kernel block scheduling: each block's duration in the last pass,
+    // the longest-first order built from it, and the block count that order
+    // is for (0: none yet)
+    uint32_t* blk_cost = nullptr;
+    uint32_t* blk_order = nullptr;
+    uint32_t blk_ordered = 0;
+
     // cells
     DevCells cells{};
     uint32_t* d_err = nullptr;
@@ -282,6 +289,8 @@ DevCut dev_tmpl(const rlc_ctx* c) {
 
 FrameParams frame_params(const rlc_ctx* c) {
     FrameParams fp;
+    fp.blk_order = nullptr;
+    fp.blk_cost = nullptr;
     fp.tree = dev_tree(c);
     fp.tmpl = dev_tmpl(c);
     fp.cells = c->cells;
@@ -332,6 +341,9 @@ AdaptParams adapt_params(const rlc_ctx* c) {
     ap.adapt = c->cfg.adapt;
     ap.temporal = c->cfg.temporal;
     ap.split_steps = c->cfg.split_steps;
+    ap.blk_cost = nullptr;
+    ap.blk_order = nullptr;
+    ap.blk_n = 0;
     return ap;
 }
 
@@ -576,6 +588,8 @@ int rlc_create(const rlc_config* cfg, void* stream, rlc_ctx** out) {
     if (r == RLC_OK) r = dalloc(c, &d.n_live, RLC_ROW_STRIPES_MAX * RLC_NLIVE_STRIDE);
     if (r == RLC_OK) r = dalloc(c, &c->d_err, 1);
     if (r == RLC_OK) r = dalloc(c, &c->d_partial, 6 * 1024);
+    if (r == RLC_OK) r = dalloc(c, &c->blk_cost, RLC_ORDER_MAX_BLOCKS);
+    if (r == RLC_OK) r = dalloc(c, &c->blk_order, RLC_ORDER_MAX_BLOCKS);
     if (r == RLC_OK) r = reset_cells(c);
     if (r == RLC_OK) {
         hipError_t e = launch_fill_u32(c->d_err, 0u, 1, c->stream);
@@ -612,6 +626,8 @@ int rlc_destroy(rlc_ctx* c) {
     dfree(d.n_live);
     dfree(c->d_err);
     dfree(c->d_partial);
+    dfree(c->blk_cost);
+    dfree(c->blk_order);
     dfree(c->sub_buf);
     for (hipEvent_t e : c->pending) (void)hipEventDestroy(e);
     for (hipEvent_t e : c->mlp_pending) (void)hipEventDestroy(e);
@@ -848,9 +864,26 @@ int frame_pass(rlc_ctx* c, const float* d_pos, const float* d_nrm, uint32_t P, u
         }
         RLC_HIP(c, hipEventRecord(ev[0], c->stream));
     }
-    RLC_HIP(c, launch_frame(frame_params(c), d_pos, d_nrm, P, spp, frame, d_radiance, c->stream));
+    // the fused kernel's blocks run longest first when the pass before had
+    // as many blocks (its durations ordered them); every pass records its
+    // blocks' durations, and the end-of-pass launch orders them for the next
+    const uint64_t nb = ((uint64_t)P * spp + RLC_FRAME_BLOCK - 1u) / RLC_FRAME_BLOCK;
+    const bool sched = nb > 0 && nb <= RLC_ORDER_MAX_BLOCKS;
+    FrameParams fp = frame_params(c);
+    if (sched) {
+        fp.blk_cost = c->blk_cost;
+        fp.blk_order = c->blk_ordered == nb ? c->blk_order : nullptr;
+    }
+    RLC_HIP(c, launch_frame(fp, d_pos, d_nrm, P, spp, frame, d_radiance, c->stream));
     if (timed) RLC_HIP(c, hipEventRecord(ev[1], c->stream));
-    RLC_HIP(c, launch_adapt(adapt_params(c), c->stream));
+    AdaptParams ap = adapt_params(c);
+    if (sched) {
+        ap.blk_cost = c->blk_cost;
+        ap.blk_order = c->blk_order;
+        ap.blk_n = (uint32_t)nb;
+    }
+    c->blk_ordered = sched ? (uint32_t)nb : 0u;
+    RLC_HIP(c, launch_adapt(ap, c->stream));
     if (timed) {
         RLC_HIP(c, hipEventRecord(ev[2], c->stream));
         for (auto& e : ev) c->pending.push_back(e);

@@ -9,6 +9,7 @@ namespace rlc {
 namespace {
 
 constexpr int kBlock = 256;
+static_assert(kBlock == (int)RLC_FRAME_BLOCK, "fused kernel block size");
 
 __device__ __forceinline__ bool pow2_le64(uint32_t spp) { return spp <= 64u && (spp & (spp - 1u)) == 0u; }
 
@@ -315,17 +316,29 @@ __device__ __forceinline__ uint32_t xcd_chunk_block(uint32_t b, uint32_t nb) {
 }
 
 // Fused pass: one lane per sample.  The parameters (the first argument,
-// kept first) are read in place in the kernarg segment.
+// kept first) are read in place in the kernarg segment.  With an order, the
+// launched blocks take the logical blocks longest first (the costliest
+// blocks of the pass before start first, so that the pass does not end on a
+// few of them running alone); each logical block records its duration.
 __global__ void __launch_bounds__(kBlock, 8) k_frame(FrameParams /* read in place */, const float* __restrict__ pos,
                                                   const float* __restrict__ nrm, uint32_t P, uint32_t spp,
                                                   uint32_t frame, float* __restrict__ radiance) {
     __shared__ AggTable agg;
     __shared__ float s_e[kBlock][3];
+    const FrameParams& fp = first_kernel_arg<FrameParams>();
+    const unsigned long long t0 = wall_clock64();
     agg_clear(agg);
     __syncthreads();
-    const uint32_t b = xcd_chunk_block(blockIdx.x, gridDim.x);
-    const FrameParams& fp = first_kernel_arg<FrameParams>();
+    uint32_t b = xcd_chunk_block(blockIdx.x, gridDim.x);
+    if (fp.blk_order) {
+        const uint32_t o = fp.blk_order[blockIdx.x];
+        b = o < gridDim.x ? o : b;
+    }
     frame_block(fp, pos, nrm, nullptr, P, spp, frame, radiance, (size_t)b * kBlock, agg, s_e);
+    if (fp.blk_cost && threadIdx.x == 0) {
+        const unsigned long long d = wall_clock64() - t0;
+        fp.blk_cost[b] = d < 0xFFFFFFFFull ? (uint32_t)d : 0xFFFFFFFFu;
+    }
 }
 
 // Batched pass over several scenes: persistent blocks take work items of

@@ -118,7 +118,17 @@ struct FrameParams {
     uint32_t* log_pid;
     uint32_t* log_node;
     float* log_w;
+    // block scheduling of the fused kernel (both optional): the logical
+    // block each launched block runs (longest first, from the costs of the
+    // pass before), and where each logical block records its duration
+    const uint32_t* blk_order;
+    uint32_t* blk_cost;
 };
+
+// Samples per block of the fused kernel, and the largest block count whose
+// blocks are ordered longest first.
+#define RLC_FRAME_BLOCK 256u
+#define RLC_ORDER_MAX_BLOCKS 65536u
 
 // One scene of a batched pass: its parameters, inputs and output, and the
 // first work item that belongs to it.
@@ -145,6 +155,11 @@ struct AdaptParams {
     uint32_t adapt;
     uint32_t temporal;
     uint32_t split_steps;       // split-collapse steps per pass, at most (0 and 1: one)
+    // with blk_n > 0, the end-of-pass launch also orders the fused kernel's
+    // blk_n blocks for the next pass, longest first by blk_cost
+    const uint32_t* blk_cost;
+    uint32_t* blk_order;
+    uint32_t blk_n;
 };
 
 // ---------------------------------------------------------------------------
