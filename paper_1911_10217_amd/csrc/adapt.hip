@@ -532,8 +532,11 @@ constexpr uint32_t kOrderThreads = 1024;
 constexpr uint32_t kOrderWaves = kOrderThreads / kWave;
 constexpr uint32_t kOrderLds = (kOrderWaves + 1u) * kOrderBuckets + 2u;
 
-__device__ __forceinline__ uint32_t order_key(uint32_t c, uint32_t lo, unsigned long long range) {
-    return kOrderBuckets - 1u - (uint32_t)(((unsigned long long)(c - lo) * kOrderBuckets) / range);
+// Range of duration c, counted from the longest (a float product: the same
+// key wherever it is computed, which is all the sort needs).
+__device__ __forceinline__ uint32_t order_key(uint32_t c, uint32_t lo, float scale) {
+    const uint32_t k = (uint32_t)((float)(c - lo) * scale);
+    return kOrderBuckets - 1u - (k < kOrderBuckets - 1u ? k : kOrderBuckets - 1u);
 }
 
 __device__ __forceinline__ void block_order(const uint32_t* __restrict__ cost, uint32_t* __restrict__ order,
@@ -566,9 +569,9 @@ __device__ __forceinline__ void block_order(const uint32_t* __restrict__ cost, u
     }
     __syncthreads();
     lo = ext[0];
-    const unsigned long long range = (unsigned long long)(ext[1] - lo) + 1ull;
+    const float scale = (float)kOrderBuckets / ((float)(ext[1] - lo) + 1.0f);
     uint32_t* mine = hist + wave * kOrderBuckets;
-    for (uint32_t i = t; i < n; i += kOrderThreads) atomicAdd(&mine[order_key(cost[i], lo, range)], 1u);
+    for (uint32_t i = t; i < n; i += kOrderThreads) atomicAdd(&mine[order_key(cost[i], lo, scale)], 1u);
     __syncthreads();
     // per bucket: each wave's count becomes the count of the waves before it
     if (t < kOrderBuckets) {
@@ -607,7 +610,7 @@ __device__ __forceinline__ void block_order(const uint32_t* __restrict__ cost, u
     if (t < kOrderBuckets)
         for (uint32_t w = 0; w < kOrderWaves; ++w) hist[w * kOrderBuckets + t] += tot[t];
     __syncthreads();
-    for (uint32_t i = t; i < n; i += kOrderThreads) order[atomicAdd(&mine[order_key(cost[i], lo, range)], 1u)] = i;
+    for (uint32_t i = t; i < n; i += kOrderThreads) order[atomicAdd(&mine[order_key(cost[i], lo, scale)], 1u)] = i;
 }
 
 __global__ void __launch_bounds__(kOrderThreads) k_block_order(const uint32_t* __restrict__ cost,
