@@ -882,8 +882,10 @@ int frame_pass(rlc_ctx* c, const float* d_pos, const float* d_nrm, uint32_t P, u
         ap.blk_order = c->blk_order;
         ap.blk_n = (uint32_t)nb;
     }
-    c->blk_ordered = sched ? (uint32_t)nb : 0u;
     RLC_HIP(c, launch_adapt(ap, c->stream));
+    // (after a failed launch the order from an earlier pass stays, still a
+    // permutation of its blocks)
+    c->blk_ordered = sched ? (uint32_t)nb : 0u;
     if (timed) {
         RLC_HIP(c, hipEventRecord(ev[2], c->stream));
         for (auto& e : ev) c->pending.push_back(e);
