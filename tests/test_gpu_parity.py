@@ -307,6 +307,28 @@ def test_ragged_and_empty(torch):
     _assert_cells_equal(ctx.rlc_dump_cells(), orc.cells())
 
 
+def test_point_sets_change_between_passes(torch):
+    """One context, passes over changing point sets: the fused kernel runs
+    its blocks longest first by the durations of the pass before when that
+    pass had as many blocks, and in the plain order otherwise.  The sequence
+    switches between a set of 16 blocks, a shuffled set of the same size
+    (same block count, other points) and one of 5 blocks; each pass equals
+    the oracle run through the same sequence."""
+    s = scenes.make_tiny(n_points=4096, spp=1)
+    ctx, orc = _make(torch, s)
+    rng = np.random.default_rng(77)
+    perm = rng.permutation(s.P)
+    sets = {"all": np.arange(s.P), "shuffled": perm, "few": perm[:1111]}
+    for f, name in enumerate(["all", "all", "all", "shuffled", "shuffled", "few", "few", "all", "few", "all"]):
+        idx = sets[name]
+        x, n = s.pos[idx], s.nrm[idx]
+        rad = ctx.rlc_frame(_t(torch, x), _t(torch, n), 1, f).cpu().numpy()
+        ref, _ = orc.frame(x, n, 1, f)
+        orc.adapt()
+        assert np.array_equal(rad, ref), (f, name)
+    _assert_cells_equal(ctx.rlc_dump_cells(), orc.cells())
+
+
 def test_fused_matches_split_and_is_deterministic(torch):
     s = scenes.make_tiny(spp=4)
     p = s.params
